@@ -52,6 +52,8 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
+        # libgomp reads this when it loads; an unset value can oversubscribe a container
+        os.environ.setdefault("OMP_NUM_THREADS", str(max(1, min(16, len(os.sched_getaffinity(0))))))
         if not os.path.exists(_LIB):
             build()
         lib = ctypes.CDLL(_LIB)

@@ -1,0 +1,274 @@
+/*
+ * pyst -- per-GPU relational hot path of a tensor-runtime OLAP engine, for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operators are those of the distributed hash join and the queries built
+ * on it in PystachIO (arXiv 2512.02862): a pushed-down filter (Sec. 4,
+ * introduction), the hash partition that splits a table by join key into
+ * per-destination buffers, i.e. the send side of the shuffle (Sec. 3.1,
+ * "Anatomy of a Distributed Hash Join"), the hash-table build and probe
+ * (same paragraph; Sec. 3.2 builds the table once over the fully
+ * materialized build side), and the group-by SUM aggregation (Sec. 6.3,
+ * observation (5)).  Chunked streaming follows Sec. 3.2 ("Partial Overlap
+ * Using Chunking") and the queue-based, memory-regulated scheduling of
+ * Sec. 5.4 ("Queue-Based Scheduling", "Adaptive Regulation").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Column data pointers are DEVICE pointers unless a parameter says "host".
+ *   They are borrowed: the caller owns them and keeps them alive until the
+ *   work enqueued on `stream` has completed.
+ * - Every call only ENQUEUES work on `stream` and returns without waiting for
+ *   the device, except those documented as blocking (pyst_ctx_check,
+ *   pyst_ctx_destroy, pyst_table_destroy, the server calls).  Data-dependent
+ *   sizes (selected rows, join matches, groups, partition offsets) are written
+ *   to device memory and consumed from there by later calls: no host-side
+ *   sizing, which is what forces stream synchronizations in a tensor runtime
+ *   (Sec. 3.2, "Stream-Synchronizing Operations Limit Overlap").
+ * - A selection is the pair (sel, d_nsel): an ascending int32 row-id vector and
+ *   a device int64 count.  Passing NULL, NULL means "all rows".
+ * - Row ids are int32, so a column passed to one call has fewer than 2^31 rows.
+ * - Argument errors are returned synchronously.  Errors found by a kernel
+ *   (an EMPTY-sentinel key, a full table, an output over capacity, a duplicate
+ *   key under a unique-key promise) are latched in the context and returned by
+ *   the next pyst_ctx_check.
+ * - Integer sums wrap modulo 2^64 (two's complement), so results do not depend
+ *   on the order in which the device adds them.
+ * - A context is not thread-safe; use one per host thread.  Its arena
+ *   allocations are stream ordered: memory freed by work on one stream is
+ *   reused by another stream only after that work has completed.
+ */
+#ifndef PYST_H
+#define PYST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pyst_status {
+  PYST_OK = 0,
+  PYST_ERR_ARG = 1,         /* invalid argument (returned synchronously)              */
+  PYST_ERR_NOMEM = 2,       /* the context's device-memory budget cannot hold the call */
+  PYST_ERR_HIP = 3,         /* a HIP runtime call failed                              */
+  PYST_ERR_CAPACITY = 4,    /* output capacity exceeded; the count holds the need     */
+  PYST_ERR_KEY = 5,         /* a key equal to the EMPTY sentinel was seen              */
+  PYST_ERR_TABLE_FULL = 6,  /* a hash table had no free slot                          */
+  PYST_ERR_UNSUPPORTED = 7, /* a valid but unsupported combination                    */
+  PYST_ERR_DUP_KEY = 8      /* duplicate build key although unique_keys was promised  */
+} pyst_status;
+
+typedef enum pyst_dtype { PYST_I32 = 0, PYST_I64 = 1 } pyst_dtype;
+
+/* One column: `n` values of `dtype` at device address `data` (contiguous). */
+typedef struct pyst_col {
+  const void *data;
+  int64_t n;
+  int32_t dtype; /* pyst_dtype */
+  int32_t reserved;
+} pyst_col;
+
+typedef enum pyst_cmp { PYST_EQ = 0, PYST_NE = 1, PYST_LT = 2, PYST_LE = 3, PYST_GT = 4, PYST_GE = 5 } pyst_cmp;
+
+/* One predicate term `cols[col] <cmp> value`; the value is compared as int64
+   after sign extension.  A predicate list is the AND of its terms. */
+typedef struct pyst_pred {
+  int32_t col;
+  int32_t cmp; /* pyst_cmp */
+  int64_t value;
+} pyst_pred;
+
+#define PYST_MAX_COLS 8
+#define PYST_MAX_PREDS 8
+#define PYST_MAX_FANOUT 1024
+
+typedef struct pyst_ctx pyst_ctx;
+typedef struct pyst_table pyst_table;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on `device` with a device arena of `budget_bytes`
+   (allocated once; every internal table and scratch buffer comes from it, the
+   analog of the pooled allocator of Sec. 3.1 "(2) Runtime Memory Allocation").
+   On success *out owns the arena.  Errors: PYST_ERR_ARG (bad device, NULL
+   out), PYST_ERR_NOMEM (the arena cannot be allocated), PYST_ERR_HIP. */
+pyst_status pyst_ctx_create(int device, size_t budget_bytes, pyst_ctx **out);
+
+/* Wait for all device work, then free the arena and the context.  NULL is a no-op. */
+void pyst_ctx_destroy(pyst_ctx *ctx);
+
+/* Synchronize `stream`, then return and clear the errors latched by kernels
+   (PYST_OK if none).  This is the only place device-detected errors surface. */
+pyst_status pyst_ctx_check(pyst_ctx *ctx, hipStream_t stream);
+
+/* Bytes of the arena currently allocated, and its total size. */
+size_t pyst_ctx_used(const pyst_ctx *ctx);
+size_t pyst_ctx_budget(const pyst_ctx *ctx);
+
+/* Message describing the last error returned on the calling thread. */
+const char *pyst_last_error(void);
+
+/* Kernel timing for measurement.  When enabled, the library records a pair of
+   HIP events on the launch stream around its timed regions: "fact_pass" (the
+   fused probe + aggregation kernel of pyst_query), "partition" (the whole of
+   pyst_partition) and "part_scatter" (its scatter kernel).
+   pyst_ctx_kernel_time waits for the recorded events of region `name`, returns
+   their summed duration in milliseconds and the number of launches, and
+   forgets them.  Errors: PYST_ERR_ARG, PYST_ERR_HIP. */
+pyst_status pyst_ctx_timing(pyst_ctx *ctx, int enable);
+pyst_status pyst_ctx_kernel_time(pyst_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+
+/* ---------------------------------------------------------------- filter */
+
+/* Filter pushdown (Sec. 4, introduction): select the rows i < n of
+   cols[0..ncols) (all of n rows) for which every predicate holds.
+   sel_out: device int32[n], receives the ascending row ids.
+   d_nsel: device int64, receives the number selected.
+   Errors: PYST_ERR_ARG (column counts or lengths disagree, ncols or np over
+   the maxima, a predicate names a missing column). */
+pyst_status pyst_filter(pyst_ctx *ctx, const pyst_col *cols, int ncols, const pyst_pred *preds,
+                        int npreds, int32_t *sel_out, int64_t *d_nsel, hipStream_t stream);
+
+/* ---------------------------------------------------------------- partition */
+
+/* Hash partition, the send side of the shuffle (Sec. 3.1, "Anatomy of a
+   Distributed Hash Join": the local table is partitioned by join key before
+   it is shuffled).  Destination of a row: h(key) mod fanout, with
+   h = MurmurHash3 fmix32(uint32 key) for int32 keys and the low 32 bits of
+   fmix64(uint64 key) for int64 keys.
+   Rows (all n, or the selection) are written STABLY into `fanout` contiguous
+   segments: out_cols[0] receives the key column, out_cols[1 + j] payload j;
+   each output has room for key->n values of its column's dtype.
+   d_offsets: device int64[fanout + 1]; segment p is [d_offsets[p], d_offsets[p+1]).
+   Errors: PYST_ERR_ARG (fanout outside 1..PYST_MAX_FANOUT, npay over
+   PYST_MAX_COLS - 1, lengths disagree), PYST_ERR_NOMEM. */
+pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payloads, int npay,
+                           const int32_t *sel, const int64_t *d_nsel, uint32_t fanout,
+                           void *const *out_cols, int64_t *d_offsets, hipStream_t stream);
+
+/* ---------------------------------------------------------------- join */
+
+/* Hash-join build (Sec. 3.1 "Anatomy..."; the table is built over the fully
+   materialized build side, Sec. 3.2 "Scheduling Overlap With GPU Streams").
+   Inserts the selected rows of the int32 `key` column into a power-of-two
+   open-addressing table with linear probing and atomic compare-and-swap.
+   payload: int32 column stored with each key, or NULL to store the row id.
+   max_load in (0, 0.95]: the capacity is the smallest power of two with
+   load <= max_load for the number of rows actually selected (read on the
+   device, so no host synchronization is needed; memory is reserved for the
+   unfiltered n).  unique_keys != 0 promises distinct keys: probes stop at
+   the first match, and a duplicate latches PYST_ERR_DUP_KEY.
+   The key INT32_MIN is reserved as EMPTY and latches PYST_ERR_KEY.
+   *out receives a table owned by the caller (pyst_table_destroy).
+   Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED (int64 keys), PYST_ERR_NOMEM. */
+pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payload,
+                            const int32_t *sel, const int64_t *d_nsel, double max_load,
+                            int unique_keys, pyst_table **out, hipStream_t stream);
+
+/* Hash-join probe: for every selected row of the int32 `key` column, in
+   ascending row order, emit one (probe row, stored payload) pair per matching
+   build row.  out_probe_row / out_payload: device int32[out_cap].
+   d_nout: device int64, receives the number of matches; when it exceeds
+   out_cap only the first out_cap pairs are written and PYST_ERR_CAPACITY is
+   latched.  With duplicate build keys the matches of one probe row come in
+   table order.  Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED (int64 keys). */
+pyst_status pyst_join_probe(pyst_ctx *ctx, const pyst_table *table, const pyst_col *key,
+                            const int32_t *sel, const int64_t *d_nsel, int32_t *out_probe_row,
+                            int32_t *out_payload, int64_t out_cap, int64_t *d_nout,
+                            hipStream_t stream);
+
+/* Enqueue a copy of the table's header into d_out (device int64[2]):
+   [0] the effective capacity chosen on the device, [1] the number of rows
+   offered for insertion.  For tests and diagnostics.  Errors: PYST_ERR_ARG. */
+pyst_status pyst_table_info(const pyst_table *table, int64_t *d_out, hipStream_t stream);
+
+/* Free a table.  Blocks until the work enqueued on `stream` (the last stream
+   that used it) has completed.  NULL is a no-op. */
+void pyst_table_destroy(pyst_table *table, hipStream_t stream);
+
+/* ---------------------------------------------------------------- group-by */
+
+/* GROUP BY key SUM(val) (the aggregation of Sec. 6.3, observation (5)).
+   key: int32 or int64; val: int32 or int64; both sign-extended to int64.
+   A group exists for every key that occurs (no zero rows).
+   max_groups: upper bound on distinct keys (<= 0 means the row count).
+   Output: out_keys / out_sums: device int64[max_groups]; d_ngroups: device
+   int64.  Groups come out in table order, or ascending by key when
+   sort_by_key != 0.  The key INT64_MIN is reserved (PYST_ERR_KEY); more than
+   max_groups groups latch PYST_ERR_CAPACITY.
+   Errors: PYST_ERR_ARG, PYST_ERR_NOMEM. */
+pyst_status pyst_groupby_sum(pyst_ctx *ctx, const pyst_col *key, const pyst_col *val,
+                             const int32_t *sel, const int64_t *d_nsel, int64_t max_groups,
+                             double max_load, int64_t *out_keys, int64_t *out_sums,
+                             int64_t *d_ngroups, int sort_by_key, hipStream_t stream);
+
+/* ---------------------------------------------------------------- fused query */
+
+/* A join step of a query plan: the dimension side is built into a hash table
+   over int32 `key`, restricted by `preds` over `cols`; `payload` (int32, or
+   data == NULL for none) is stored with each key.  The fact rows probe it
+   with fact column `probe_col`. */
+typedef struct pyst_join_spec {
+  pyst_col key;
+  pyst_col payload;
+  const pyst_col *cols;
+  int32_t ncols;
+  int32_t npreds;
+  const pyst_pred *preds;
+  int32_t probe_col;
+  int32_t reserved;
+  double max_load;
+} pyst_join_spec;
+
+/* Source of one half of the group key. */
+typedef enum pyst_gsrc {
+  PYST_G_NONE = 0,
+  PYST_G_JOIN_KEY = 1,     /* the matched build key of join `index`      */
+  PYST_G_JOIN_PAYLOAD = 2, /* the stored payload of join `index`         */
+  PYST_G_FACT_COL = 3      /* fact column `index`                        */
+} pyst_gsrc;
+
+typedef enum pyst_vexpr {
+  PYST_V_COL = 0,              /* fact[v0]                                */
+  PYST_V_COL_TIMES_C_MINUS = 1 /* fact[v0] * (vconst - fact[v1])          */
+} pyst_vexpr;
+
+/* Query: filter the fact table by `preds`, inner-join it with 1 or 2
+   dimensions (a row survives if every join matches), then
+   GROUP BY key SUM(value).  The group key is (int64(hi) << 32) | uint32(lo)
+   when hi is set, else lo sign-extended.  Dimensions must have unique keys. */
+typedef struct pyst_plan {
+  int32_t njoins; /* 1 or 2 */
+  int32_t npreds;
+  pyst_join_spec joins[2];
+  const pyst_pred *preds;
+  int32_t hi_src, hi_index; /* pyst_gsrc */
+  int32_t lo_src, lo_index;
+  int32_t vexpr; /* pyst_vexpr */
+  int32_t v0, v1;
+  int32_t reserved;
+  int64_t vconst;
+  int64_t max_groups; /* <= 0: bounded by the rows reaching the aggregation */
+  double group_max_load;
+} pyst_plan;
+
+/* Fused filter + join + group-by over the fact columns fact[0..nfact).  One
+   build pass per dimension, then ONE pass over the fact table.  When the
+   group key is the key of the single join, sums accumulate in the join
+   table's slots (no second table).  out_keys / out_sums: device
+   int64[out_cap]; d_ngroups: device int64; more than out_cap groups latch
+   PYST_ERR_CAPACITY.  Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED,
+   PYST_ERR_NOMEM. */
+pyst_status pyst_query(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col *fact, int nfact,
+                       int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                       hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYST_H */

@@ -1,0 +1,283 @@
+// Context: device selection, the device-memory arena, and the error latch.
+//
+// The arena is one hipMalloc of the whole budget made at context creation;
+// every table and scratch buffer is carved out of it (first fit, coalescing
+// free list).  This is the pooled-allocation remedy for per-operator
+// allocation cost (Sec. 3.1, "(2) Runtime Memory Allocation in PyTorch"),
+// and the hard budget is what admission control and backpressure account
+// against (Sec. 5.4, "Adaptive Regulation").
+//
+// Frees are stream ordered: a freed block carries an event recorded on the
+// freeing stream and is reused by another stream only after that event has
+// completed; the same stream may reuse it at once, because its later work is
+// ordered after the earlier work.
+#include <deque>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "pyst_internal.h"
+
+struct pyst_ctx {
+  int device = 0;
+  int cus = 0;
+  char *base = nullptr;
+  size_t budget = 0;
+  size_t used = 0;
+  uint32_t *d_err = nullptr;    // device error word (first 256 B of the arena)
+  uint32_t *h_err = nullptr;    // pinned host copy
+  std::map<size_t, size_t> free_blocks;          // offset -> size
+  std::unordered_map<size_t, size_t> live;       // offset -> size
+  struct Pending {
+    size_t off, size;
+    hipStream_t stream;
+    hipEvent_t ev;
+  };
+  std::deque<Pending> pending;
+  std::vector<hipEvent_t> events;
+  // optional per-kernel timing: name -> (start, stop) event pairs of each launch
+  bool timing = false;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> timed;
+};
+
+namespace pyst {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr size_t kAlign = 256;
+
+hipEvent_t take_event(pyst_ctx *c) {
+  if (!c->events.empty()) {
+    hipEvent_t e = c->events.back();
+    c->events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+void insert_free(pyst_ctx *c, size_t off, size_t size) {
+  auto it = c->free_blocks.emplace(off, size).first;
+  auto next = std::next(it);
+  if (next != c->free_blocks.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    c->free_blocks.erase(next);
+  }
+  if (it != c->free_blocks.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      c->free_blocks.erase(it);
+    }
+  }
+}
+
+void reap(pyst_ctx *c) {
+  for (auto it = c->pending.begin(); it != c->pending.end();) {
+    if (hipEventQuery(it->ev) == hipSuccess) {
+      insert_free(c, it->off, it->size);
+      c->events.push_back(it->ev);
+      it = c->pending.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+bool take_first_fit(pyst_ctx *c, size_t bytes, size_t *off) {
+  for (auto it = c->free_blocks.begin(); it != c->free_blocks.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t rest_off = it->first + bytes;
+      c->free_blocks.erase(it);
+      if (rest) c->free_blocks.emplace(rest_off, rest);
+      c->live[*off] = bytes;
+      return true;
+    }
+  }
+  return false;
+}
+}  // namespace
+
+pyst_status set_error(pyst_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+pyst_status hip_error(hipError_t e, const char *what) {
+  return set_error(PYST_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *ctx_alloc(pyst_ctx *c, size_t bytes, hipStream_t stream) {
+  bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+  if (bytes == 0) bytes = kAlign;
+  size_t off = 0;
+  while (true) {
+    reap(c);
+    if (take_first_fit(c, bytes, &off)) break;
+    // Same-stream reuse of a pending block is safe without waiting.
+    bool got = false;
+    for (auto it = c->pending.begin(); it != c->pending.end(); ++it) {
+      if (it->stream == stream && it->size >= bytes) {
+        off = it->off;
+        c->live[off] = it->size;
+        c->events.push_back(it->ev);
+        bytes = it->size;
+        c->pending.erase(it);
+        got = true;
+        break;
+      }
+    }
+    if (got) break;
+    if (c->pending.empty()) return nullptr;
+    // Backpressure: wait for the oldest outstanding free, then retry.
+    (void)hipEventSynchronize(c->pending.front().ev);
+  }
+  c->used += c->live[off];
+  return c->base + off;
+}
+
+void ctx_free(pyst_ctx *c, void *p, hipStream_t stream) {
+  if (!p) return;
+  const size_t off = static_cast<size_t>(static_cast<char *>(p) - c->base);
+  auto it = c->live.find(off);
+  if (it == c->live.end()) return;
+  const size_t size = it->second;
+  c->live.erase(it);
+  c->used -= size;
+  hipEvent_t ev = take_event(c);
+  if (ev && hipEventRecord(ev, stream) == hipSuccess) {
+    c->pending.push_back({off, size, stream, ev});
+  } else {
+    if (ev) c->events.push_back(ev);
+    (void)hipStreamSynchronize(stream);
+    insert_free(c, off, size);
+  }
+}
+
+uint32_t *ctx_err_word(pyst_ctx *c) { return c->d_err; }
+
+TimedRegion::TimedRegion(pyst_ctx *c, const char *name, hipStream_t s) : ctx(c), stream(s), label(name) {
+  if (!c->timing) return;
+  if (hipEventCreate(&start) != hipSuccess || hipEventCreate(&stop) != hipSuccess) return;
+  (void)hipEventRecord(start, stream);
+}
+
+TimedRegion::~TimedRegion() {
+  if (!start || !stop) return;
+  (void)hipEventRecord(stop, stream);
+  ctx->timed[label].emplace_back(start, stop);
+}
+int ctx_device(const pyst_ctx *c) { return c->device; }
+int ctx_num_cus(const pyst_ctx *c) { return c->cus; }
+
+}  // namespace pyst
+
+using namespace pyst;
+
+extern "C" {
+
+const char *pyst_last_error(void) { return g_last_error.c_str(); }
+
+pyst_status pyst_ctx_create(int device, size_t budget_bytes, pyst_ctx **out) {
+  if (!out) return set_error(PYST_ERR_ARG, "pyst_ctx_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return set_error(PYST_ERR_ARG, "pyst_ctx_create: no such device");
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_error(e, "hipSetDevice");
+  auto *c = new pyst_ctx();
+  c->device = device;
+  (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (c->cus <= 0) c->cus = 256;
+  const size_t total = (budget_bytes + kAlign - 1) / kAlign * kAlign + kAlign;
+  if ((e = hipMalloc(reinterpret_cast<void **>(&c->base), total)) != hipSuccess) {
+    delete c;
+    (void)hipGetLastError();
+    return set_error(PYST_ERR_NOMEM, std::string("pyst_ctx_create: arena allocation failed: ") + hipGetErrorString(e));
+  }
+  if ((e = hipHostMalloc(reinterpret_cast<void **>(&c->h_err), sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) {
+    (void)hipFree(c->base);
+    delete c;
+    return hip_error(e, "hipHostMalloc");
+  }
+  c->d_err = reinterpret_cast<uint32_t *>(c->base);
+  c->base += kAlign;  // block offsets are relative to the first usable byte
+  c->budget = total - kAlign;
+  c->free_blocks.emplace(0, c->budget);
+  pyst_status st = fill_u32(c->d_err, 1, 0u, nullptr);
+  if (st == PYST_OK && (e = hipDeviceSynchronize()) != hipSuccess) st = hip_error(e, "hipDeviceSynchronize");
+  if (st != PYST_OK) {
+    pyst_ctx_destroy(c);
+    return st;
+  }
+  *out = c;
+  return PYST_OK;
+}
+
+void pyst_ctx_destroy(pyst_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto &p : c->pending) (void)hipEventDestroy(p.ev);
+  for (auto e : c->events) (void)hipEventDestroy(e);
+  for (auto &kv : c->timed)
+    for (auto &pr : kv.second) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  if (c->base) (void)hipFree(c->base - kAlign);
+  if (c->h_err) (void)hipHostFree(c->h_err);
+  delete c;
+}
+
+size_t pyst_ctx_used(const pyst_ctx *c) { return c ? c->used : 0; }
+
+pyst_status pyst_ctx_timing(pyst_ctx *c, int enable) {
+  if (!c) return set_error(PYST_ERR_ARG, "pyst_ctx_timing: ctx is NULL");
+  c->timing = enable != 0;
+  return PYST_OK;
+}
+
+pyst_status pyst_ctx_kernel_time(pyst_ctx *c, const char *name, double *total_ms, int64_t *launches) {
+  if (!c || !name || !total_ms || !launches) return set_error(PYST_ERR_ARG, "pyst_ctx_kernel_time: NULL argument");
+  *total_ms = 0.0;
+  *launches = 0;
+  auto it = c->timed.find(name);
+  if (it == c->timed.end()) return PYST_OK;
+  for (auto &pr : it->second) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_error(e, "hipEventElapsedTime");
+    *total_ms += ms;
+    ++*launches;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  c->timed.erase(it);
+  return PYST_OK;
+}
+size_t pyst_ctx_budget(const pyst_ctx *c) { return c ? c->budget : 0; }
+
+pyst_status pyst_ctx_check(pyst_ctx *c, hipStream_t stream) {
+  if (!c) return set_error(PYST_ERR_ARG, "pyst_ctx_check: ctx is NULL");
+  hipError_t e = hipMemcpyAsync(c->h_err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(error word)");
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  const uint32_t bits = *c->h_err;
+  if (bits == 0) return PYST_OK;
+  pyst_status st = fill_u32(c->d_err, 1, 0u, stream);
+  if (st != PYST_OK) return st;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  if (bits & kErrKey) return set_error(PYST_ERR_KEY, "a key equal to the reserved EMPTY sentinel was seen");
+  if (bits & kErrDup) return set_error(PYST_ERR_DUP_KEY, "duplicate build key under a unique-key promise");
+  if (bits & kErrTableFull) return set_error(PYST_ERR_TABLE_FULL, "hash table full");
+  return set_error(PYST_ERR_CAPACITY, "output capacity exceeded");
+}
+
+}  // extern "C"

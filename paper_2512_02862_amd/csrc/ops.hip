@@ -1,0 +1,897 @@
+// Relational operators for gfx950: filter, hash partition, hash-join build and
+// probe, hash group-by SUM.  Every data-dependent size stays in device memory.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "pyst_internal.h"
+#include "table.h"
+
+namespace pyst {
+
+// ============================================================== fill kernels
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+pyst_status fill_u64(void *p, int64_t n, uint64_t v, hipStream_t stream) {
+  if (n <= 0) return PYST_OK;
+  const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(n, 256), 8192));
+  k_fill_u64<<<blocks, 256, 0, stream>>>(static_cast<uint64_t *>(p), n, v);
+  PYST_LAUNCH_CHECK("k_fill_u64");
+  return PYST_OK;
+}
+pyst_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t stream) {
+  if (n <= 0) return PYST_OK;
+  const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(n, 256), 8192));
+  k_fill_u32<<<blocks, 256, 0, stream>>>(static_cast<uint32_t *>(p), n, v);
+  PYST_LAUNCH_CHECK("k_fill_u32");
+  return PYST_OK;
+}
+
+// ============================================================== argument helpers
+namespace {
+
+bool col_ok(const pyst_col *c) {
+  return c && (c->dtype == PYST_I32 || c->dtype == PYST_I64) && c->n >= 0 && (c->data || c->n == 0) &&
+         c->n < (int64_t{1} << 31);
+}
+
+pyst_status build_predset(const pyst_col *cols, int ncols, const pyst_pred *preds, int np, PredSet *ps,
+                          const char *who) {
+  if (np < 0 || np > PYST_MAX_PREDS) return set_error(PYST_ERR_ARG, std::string(who) + ": too many predicates");
+  if (np > 0 && !preds) return set_error(PYST_ERR_ARG, std::string(who) + ": preds is NULL");
+  std::memset(ps, 0, sizeof(*ps));
+  ps->n = np;
+  for (int k = 0; k < np; ++k) {
+    const int c = preds[k].col;
+    if (c < 0 || c >= ncols) return set_error(PYST_ERR_ARG, std::string(who) + ": predicate names a missing column");
+    if (preds[k].cmp < PYST_EQ || preds[k].cmp > PYST_GE) return set_error(PYST_ERR_ARG, std::string(who) + ": bad comparison");
+    ps->col[k] = cols[c].data;
+    ps->is64[k] = cols[c].dtype == PYST_I64;
+    ps->op[k] = preds[k].cmp;
+    ps->val[k] = preds[k].value;
+  }
+  return PYST_OK;
+}
+
+// Rows [tile*TILE, (tile+1)*TILE) of a selection (or of all rows): row id of position i.
+__device__ __forceinline__ int64_t row_of(const int32_t *sel, int64_t i) { return sel ? static_cast<int64_t>(sel[i]) : i; }
+__device__ __forceinline__ int64_t count_of(const int64_t *d_nsel, int64_t n) { return d_nsel ? *d_nsel : n; }
+
+// In-place exclusive scan of arr[0..len) by one block (len <= BLOCK * 8).
+template <int BLOCK>
+__device__ void block_exclusive_scan(int32_t *arr, int len, int32_t *s_wave) {
+  constexpr int NW = BLOCK / kWave;
+  const int per = (len + BLOCK - 1) / BLOCK;
+  const int lo = threadIdx.x * per;
+  int32_t local = 0;
+  for (int k = 0; k < per; ++k)
+    if (lo + k < len) local += arr[lo + k];
+  const int32_t incl = wave_inclusive_scan(local);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) s_wave[w] = incl;
+  __syncthreads();
+  int32_t wave_off = 0;
+  for (int k = 0; k < w; ++k) wave_off += s_wave[k];
+  int32_t run = wave_off + incl - local;
+  __syncthreads();
+  for (int k = 0; k < per; ++k) {
+    if (lo + k < len) {
+      const int32_t v = arr[lo + k];
+      arr[lo + k] = run;
+      run += v;
+    }
+  }
+  (void)NW;
+}
+
+}  // namespace
+
+// ============================================================== filter
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_filter(PredSet ps, int64_t n, int32_t *sel_out, int64_t *d_nsel,
+                                                 uint64_t *status, unsigned long long *ticket, int64_t ntiles) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  __shared__ int64_t s_tile, s_prefix;
+  __shared__ int32_t s_cnt[NW];
+  if (threadIdx.x == 0) s_tile = static_cast<int64_t>(atomicAdd(ticket, 1ull));
+  __syncthreads();
+  const int64_t t = s_tile;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t wbase = t * TILE + int64_t{w} * kWave * ITEMS;
+  uint64_t m[ITEMS];
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t row = wbase + int64_t{j} * kWave + lane;
+    const bool keep = row < n && eval_preds(ps, row);
+    m[j] = __ballot(keep);
+    cnt += __popcll(m[j]);
+  }
+  if (lane == 0) s_cnt[w] = cnt;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t c = lane < NW ? s_cnt[lane] : 0;
+    const int64_t agg = wave_sum(c);
+    const int64_t ex = lookback_exclusive(status, t, agg);
+    if (lane == 0) {
+      s_prefix = ex;
+      if (t == ntiles - 1) *d_nsel = ex + agg;
+    }
+  }
+  __syncthreads();
+  int64_t pos = s_prefix;
+  for (int k = 0; k < w; ++k) pos += s_cnt[k];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if ((m[j] >> lane) & 1ull) sel_out[pos + mbcnt(m[j])] = static_cast<int32_t>(wbase + int64_t{j} * kWave + lane);
+    pos += __popcll(m[j]);
+  }
+}
+
+pyst_status filter_impl(pyst_ctx *ctx, const PredSet &ps, int64_t n, int32_t *sel_out, int64_t *d_nsel,
+                        hipStream_t stream) {
+  constexpr int BLOCK = 256, ITEMS = 16;
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, int64_t{BLOCK} * ITEMS));
+  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "pyst_filter: arena exhausted");
+  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+  if (st != PYST_OK) return st;
+  uint64_t *status = sc.as<uint64_t>();
+  k_filter<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
+      ps, n, sel_out, d_nsel, status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles);
+  PYST_LAUNCH_CHECK("k_filter");
+  return PYST_OK;
+}
+
+// ============================================================== partition
+struct PartArgs {
+  const void *key;
+  int32_t key64;
+  int32_t npay;
+  const void *pay[PYST_MAX_COLS - 1];
+  int32_t pay64[PYST_MAX_COLS - 1];
+  void *out[PYST_MAX_COLS];
+  const int32_t *sel;
+  const int64_t *d_nsel;
+  int64_t n;
+  uint32_t fanout;
+  int32_t fbits;        // bits needed to hold fanout - 1
+  int32_t radix_shift;  // >= 0: destination = byte of (key ^ sign bit) at this shift (sort pass); < 0: hash
+};
+
+__device__ __forceinline__ uint32_t part_dest(const PartArgs &a, int64_t row) {
+  if (a.radix_shift >= 0) {
+    const uint64_t k = static_cast<uint64_t>(load_as_i64(a.key, a.key64, row)) ^ (1ull << 63);
+    return static_cast<uint32_t>((k >> a.radix_shift) & 0xffu);
+  }
+  uint32_t h;
+  if (a.key64) h = static_cast<uint32_t>(fmix64(static_cast<uint64_t>(static_cast<const int64_t *>(a.key)[row])));
+  else h = fmix32(static_cast<uint32_t>(static_cast<const int32_t *>(a.key)[row]));
+  return (a.fanout & (a.fanout - 1)) == 0 ? (h & (a.fanout - 1)) : (h % a.fanout);
+}
+
+// Lanes of `valid` holding the same destination as the calling lane (AMD has no
+// match instruction: intersect one ballot per destination bit).
+__device__ __forceinline__ uint64_t match_peers(uint32_t d, uint64_t valid, int fbits) {
+  uint64_t peers = valid;
+  for (int b = 0; b < fbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t ones = __ballot(bit);
+    peers &= bit ? ones : ~ones;
+  }
+  return peers;
+}
+
+constexpr int kPartBlock = 256;
+constexpr int kPartItems = 16;
+constexpr int64_t kPartTile = int64_t{kPartBlock} * kPartItems;
+
+// Pass 1: per-tile destination histogram, stored destination-major so that one
+// exclusive scan of the flat array yields every (destination, tile) offset.
+template <int BLOCK, int ITEMS, int FMAX>
+__global__ __launch_bounds__(BLOCK) void k_part_hist(PartArgs a, int32_t *hist, int64_t ntiles) {
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  __shared__ int32_t s_h[FMAX];
+  for (int p = threadIdx.x; p < static_cast<int>(a.fanout); p += BLOCK) s_h[p] = 0;
+  __syncthreads();
+  const int64_t cnt = count_of(a.d_nsel, a.n);
+  const int64_t t = blockIdx.x;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t wbase = t * TILE + int64_t{w} * kWave * ITEMS;
+#pragma unroll 4
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t i = wbase + int64_t{j} * kWave + lane;
+    const bool valid = i < cnt;
+    const uint32_t d = valid ? part_dest(a, row_of(a.sel, i)) : 0u;
+    const uint64_t vm = __ballot(valid);
+    const uint64_t peers = match_peers(d, vm, a.fbits);
+    if (valid && lane == __ffsll(static_cast<unsigned long long>(peers)) - 1) atomicAdd(&s_h[d], __popcll(peers));
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < static_cast<int>(a.fanout); p += BLOCK) hist[int64_t{p} * ntiles + t] = s_h[p];
+}
+
+// Exclusive scan of an int32 array (decoupled look-back); total -> *d_total.
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_scan_excl_i32(const int32_t *in, int32_t *out, int64_t len,
+                                                        uint64_t *status, unsigned long long *ticket, int64_t ntiles,
+                                                        int64_t *d_total) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  __shared__ int64_t s_tile, s_prefix;
+  __shared__ int32_t s_w[NW];
+  if (threadIdx.x == 0) s_tile = static_cast<int64_t>(atomicAdd(ticket, 1ull));
+  __syncthreads();
+  const int64_t t = s_tile;
+  const int64_t base = t * TILE + int64_t{threadIdx.x} * ITEMS;
+  int32_t v[ITEMS];
+  int32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    v[k] = base + k < len ? in[base + k] : 0;
+    local += v[k];
+  }
+  const int32_t incl = wave_inclusive_scan(local);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) s_w[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t c = lane_id() < NW ? s_w[lane_id()] : 0;
+    const int64_t agg = wave_sum(c);
+    const int64_t ex = lookback_exclusive(status, t, agg);
+    if (lane_id() == 0) {
+      s_prefix = ex;
+      if (t == ntiles - 1 && d_total) *d_total = ex + agg;
+    }
+  }
+  __syncthreads();
+  int64_t run = s_prefix + incl - local;
+  for (int k = 0; k < w; ++k) run += s_w[k];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    if (base + k < len) out[base + k] = static_cast<int32_t>(run);
+    run += v[k];
+  }
+}
+
+__global__ void k_part_offsets(const int32_t *scan, uint32_t fanout, int64_t ntiles, const int64_t *d_nsel, int64_t n,
+                               int64_t *d_offsets) {
+  const int64_t cnt = count_of(d_nsel, n);
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p <= fanout; p += gridDim.x * blockDim.x)
+    d_offsets[p] = p < fanout ? static_cast<int64_t>(scan[int64_t{p} * ntiles]) : cnt;
+}
+
+// Pass 3: stable scatter.  Each wave ranks its rows per destination with
+// ballots; the block lays the tile out destination-major in LDS, then writes
+// every destination's run with consecutive threads on consecutive addresses
+// (software write combining: whole lines per destination, not scattered words).
+template <int BLOCK, int ITEMS, int FMAX>
+__global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_t *scan, int64_t ntiles) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int TILE = BLOCK * ITEMS;
+  __shared__ int32_t s_cnt[NW][FMAX];
+  __shared__ int32_t s_start[FMAX];
+  __shared__ int32_t s_goff[FMAX];
+  __shared__ int32_t s_wave[NW];
+  __shared__ uint16_t s_dest[TILE];
+  __shared__ int64_t s_stage[TILE];
+
+  const int F = static_cast<int>(a.fanout);
+  const int64_t t = blockIdx.x;
+  const int64_t cnt = count_of(a.d_nsel, a.n);
+  for (int p = threadIdx.x; p < F; p += BLOCK) {
+    for (int w = 0; w < NW; ++w) s_cnt[w][p] = 0;
+    s_goff[p] = scan[int64_t{p} * ntiles + t];
+  }
+  __syncthreads();
+
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t wbase = t * TILE + int64_t{w} * kWave * ITEMS;
+  int32_t rowv[ITEMS];
+  int32_t pos[ITEMS];
+  uint16_t dst[ITEMS];
+  int64_t keyv[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t i = wbase + int64_t{j} * kWave + lane;
+    const bool valid = i < cnt;
+    const int64_t row = valid ? row_of(a.sel, i) : 0;
+    rowv[j] = static_cast<int32_t>(row);
+    keyv[j] = valid ? load_as_i64(a.key, a.key64, row) : 0;
+    const uint32_t d = valid ? part_dest(a, row) : 0u;
+    dst[j] = static_cast<uint16_t>(d);
+    const uint64_t vm = __ballot(valid);
+    const uint64_t peers = match_peers(d, vm, a.fbits);
+    const int32_t base = valid ? s_cnt[w][d] : 0;
+    pos[j] = valid ? base + static_cast<int32_t>(mbcnt(peers)) : -1;
+    if (valid && lane == __ffsll(static_cast<unsigned long long>(peers)) - 1) s_cnt[w][d] = base + __popcll(peers);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < F; p += BLOCK) {
+    int32_t run = 0;
+    for (int k = 0; k < NW; ++k) {
+      const int32_t c = s_cnt[k][p];
+      s_cnt[k][p] = run;
+      run += c;
+    }
+    s_start[p] = run;
+  }
+  __syncthreads();
+  block_exclusive_scan<BLOCK>(s_start, F, s_wave);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (pos[j] >= 0) {
+      pos[j] += s_start[dst[j]] + s_cnt[w][dst[j]];
+      s_dest[pos[j]] = dst[j];
+    }
+  }
+  const int tile_rows = static_cast<int>(std::min<int64_t>(TILE, std::max<int64_t>(0, cnt - t * TILE)));
+  for (int c = 0; c <= a.npay; ++c) {
+    const void *src = c == 0 ? a.key : a.pay[c - 1];
+    const int is64 = c == 0 ? a.key64 : a.pay64[c - 1];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (pos[j] >= 0) s_stage[pos[j]] = c == 0 ? keyv[j] : load_as_i64(src, is64, rowv[j]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < tile_rows; i += BLOCK) {
+      const int d = s_dest[i];
+      const int64_t g = int64_t{s_goff[d]} + (i - s_start[d]);
+      if (is64) static_cast<int64_t *>(a.out[c])[g] = s_stage[i];
+      else static_cast<int32_t *>(a.out[c])[g] = static_cast<int32_t>(s_stage[i]);
+    }
+    __syncthreads();
+  }
+}
+
+template <int FMAX>
+static void launch_partition(const PartArgs &a, int32_t *hist, int32_t *scan, int64_t ntiles, hipStream_t stream,
+                             bool hist_phase) {
+  if (hist_phase)
+    k_part_hist<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, hist, ntiles);
+  else
+    k_part_scatter<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, scan, ntiles);
+}
+
+pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_t len, int64_t *d_total,
+                          hipStream_t stream);
+
+// histogram -> scan -> (offsets) -> stable scatter
+static pyst_status partition_run(pyst_ctx *ctx, const PartArgs &a, int64_t *d_offsets, hipStream_t stream) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(a.n, kPartTile));
+  const int64_t hlen = ntiles * a.fanout;
+  Scratch sc(ctx, 2 * hlen * sizeof(int32_t) + 256, stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "partition: arena exhausted");
+  int32_t *hist = sc.as<int32_t>();
+  int32_t *scan = hist + hlen + 64;
+  if (a.fanout <= 64) launch_partition<64>(a, hist, scan, ntiles, stream, true);
+  else if (a.fanout <= 256) launch_partition<256>(a, hist, scan, ntiles, stream, true);
+  else launch_partition<1024>(a, hist, scan, ntiles, stream, true);
+  PYST_LAUNCH_CHECK("k_part_hist");
+  pyst_status st = scan_excl_i32(ctx, hist, scan, hlen, nullptr, stream);
+  if (st != PYST_OK) return st;
+  if (d_offsets) {
+    k_part_offsets<<<static_cast<unsigned>(ceil_div(a.fanout + 1, 256)), 256, 0, stream>>>(scan, a.fanout, ntiles,
+                                                                                          a.d_nsel, a.n, d_offsets);
+    PYST_LAUNCH_CHECK("k_part_offsets");
+  }
+  TimedRegion timed(ctx, "part_scatter", stream);
+  if (a.fanout <= 64) launch_partition<64>(a, hist, scan, ntiles, stream, false);
+  else if (a.fanout <= 256) launch_partition<256>(a, hist, scan, ntiles, stream, false);
+  else launch_partition<1024>(a, hist, scan, ntiles, stream, false);
+  PYST_LAUNCH_CHECK("k_part_scatter");
+  return PYST_OK;
+}
+
+// LSD radix sort of (key, value) int64 pairs, 8 stable byte passes; the first
+// *d_count of `cap` entries are sorted in place (ping-pong through scratch).
+pyst_status sort_pairs_by_key(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *d_count, int64_t cap,
+                              hipStream_t stream) {
+  if (cap <= 0) return PYST_OK;
+  Scratch tmp(ctx, 2 * cap * sizeof(int64_t), stream);
+  if (!tmp.p) return set_error(PYST_ERR_NOMEM, "sort: arena exhausted");
+  int64_t *bk[2] = {keys, tmp.as<int64_t>()};
+  int64_t *bv[2] = {vals, tmp.as<int64_t>() + cap};
+  for (int pass = 0; pass < 8; ++pass) {
+    const int src = pass & 1, dst = src ^ 1;
+    PartArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.key = bk[src];
+    a.key64 = 1;
+    a.npay = 1;
+    a.pay[0] = bv[src];
+    a.pay64[0] = 1;
+    a.out[0] = bk[dst];
+    a.out[1] = bv[dst];
+    a.d_nsel = d_count;
+    a.n = cap;
+    a.fanout = 256;
+    a.fbits = 8;
+    a.radix_shift = 8 * pass;
+    pyst_status st = partition_run(ctx, a, nullptr, stream);
+    if (st != PYST_OK) return st;
+  }
+  return PYST_OK;
+}
+
+pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_t len, int64_t *d_total,
+                          hipStream_t stream) {
+  constexpr int BLOCK = 256, ITEMS = 8;
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(len, int64_t{BLOCK} * ITEMS));
+  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "scan: arena exhausted");
+  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+  if (st != PYST_OK) return st;
+  uint64_t *status = sc.as<uint64_t>();
+  k_scan_excl_i32<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
+      in, out, len, status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles, d_total);
+  PYST_LAUNCH_CHECK("k_scan_excl_i32");
+  return PYST_OK;
+}
+
+// ============================================================== join build / probe
+// Key + payload table: 8-byte slots, (uint32 key) | (uint32 payload) << 32.
+constexpr uint64_t kEmptySlot = static_cast<uint32_t>(kEmpty32);
+
+__global__ void k_table_init(TableDev t, const int64_t *d_nsel, int64_t n, double max_load) {
+  const int64_t cnt = count_of(d_nsel, n);
+  const int64_t cap = table_capacity(cnt, max_load, t.cap_alloc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    t.hdr[0] = cap;
+    t.hdr[1] = cnt;
+  }
+  const int64_t words = t.slot_bytes == 4 ? cap / 2 : cap;  // in 8-byte words
+  const uint64_t fillv = t.slot_bytes == 4 ? (uint64_t{static_cast<uint32_t>(kEmpty32)} * 0x100000001ull) : kEmptySlot;
+  uint64_t *p = static_cast<uint64_t *>(t.slots);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = fillv;
+  if (t.sums)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+      t.sums[i] = 0;
+      t.flags[i] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_join_build(const int32_t *key, const int32_t *payload, const int32_t *sel,
+                                                    const int64_t *d_nsel, int64_t n, TableDev t, int unique,
+                                                    uint32_t *err) {
+  const int64_t cnt = count_of(d_nsel, n);
+  const int64_t mask = t.hdr[0] - 1;
+  uint64_t *slots = static_cast<uint64_t *>(t.slots);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = row_of(sel, i);
+    const int32_t k = key[row];
+    if (k == kEmpty32) {
+      latch(err, kErrKey);
+      continue;
+    }
+    const uint32_t pl = payload ? static_cast<uint32_t>(payload[row]) : static_cast<uint32_t>(row);
+    const uint64_t packed = uint64_t{static_cast<uint32_t>(k)} | (uint64_t{pl} << 32);
+    int64_t s = (table_hash32(k) & mask) & ~int64_t{1};
+    bool done = false;
+    for (int64_t step = 0; step <= mask; ++step) {
+      uint64_t cur = slots[s];
+      if (static_cast<int32_t>(cur) == kEmpty32) {
+        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&slots[s]), kEmptySlot, packed);
+        if (old == kEmptySlot) {
+          done = true;
+          break;
+        }
+        cur = old;
+      }
+      if (unique && static_cast<int32_t>(cur) == k) {
+        latch(err, kErrDup);
+        done = true;
+        break;
+      }
+      s = (s + 1) & mask;
+    }
+    if (!done) latch(err, kErrTableFull);
+  }
+}
+
+// Probe the key+payload table two slots (16 bytes) per load; calls on_match(payload)
+// for each match in table order until on_match returns false or an EMPTY slot ends the run.
+template <typename F>
+__device__ __forceinline__ void probe_kp(const uint64_t *slots, int64_t mask, int32_t k, F &&on_match) {
+  int64_t s = (table_hash32(k) & mask) & ~int64_t{1};
+  for (int64_t step = 0; step <= mask; step += 2) {
+    const ulonglong2 pair = *reinterpret_cast<const ulonglong2 *>(&slots[s]);
+    const int32_t k0 = static_cast<int32_t>(pair.x), k1 = static_cast<int32_t>(pair.y);
+    if (k0 == k) {
+      if (!on_match(static_cast<int32_t>(pair.x >> 32))) return;
+    } else if (k0 == kEmpty32) {
+      return;
+    }
+    if (k1 == k) {
+      if (!on_match(static_cast<int32_t>(pair.y >> 32))) return;
+    } else if (k1 == kEmpty32) {
+      return;
+    }
+    s = (s + 2) & mask;
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_join_probe(const int32_t *key, const int32_t *sel, const int64_t *d_nsel,
+                                                     int64_t n, TableDev t, int unique, int32_t *out_row,
+                                                     int32_t *out_pay, int64_t out_cap, int64_t *d_nout,
+                                                     uint64_t *status, unsigned long long *ticket, int64_t ntiles,
+                                                     uint32_t *err) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  __shared__ int64_t s_tile, s_prefix;
+  __shared__ int64_t s_w[NW];
+  if (threadIdx.x == 0) s_tile = static_cast<int64_t>(atomicAdd(ticket, 1ull));
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t cnt = count_of(d_nsel, n);
+  const int64_t mask = t.hdr[0] - 1;
+  const uint64_t *slots = static_cast<const uint64_t *>(t.slots);
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t wbase = tile * TILE + int64_t{w} * kWave * ITEMS;
+  int32_t c[ITEMS];
+  int32_t first_pay[ITEMS];
+  int64_t wave_total = 0;
+  int64_t lane_off[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t i = wbase + int64_t{j} * kWave + lane;
+    c[j] = 0;
+    first_pay[j] = 0;
+    if (i < cnt) {
+      const int32_t k = key[row_of(sel, i)];
+      int32_t m = 0, fp = 0;
+      probe_kp(slots, mask, k, [&](int32_t pl) {
+        if (m == 0) fp = pl;
+        ++m;
+        return !unique;
+      });
+      c[j] = m;
+      first_pay[j] = fp;
+    }
+    const int64_t incl = wave_inclusive_scan<int64_t>(c[j]);
+    lane_off[j] = wave_total + incl - c[j];
+    wave_total += __shfl(incl, kWave - 1);
+  }
+  if (lane == 0) s_w[w] = wave_total;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t v = lane < NW ? s_w[lane] : 0;
+    const int64_t agg = wave_sum(v);
+    const int64_t ex = lookback_exclusive(status, tile, agg);
+    if (lane == 0) {
+      s_prefix = ex;
+      if (tile == ntiles - 1) {
+        *d_nout = ex + agg;
+        if (ex + agg > out_cap) latch(err, kErrCapacity);
+      }
+    }
+  }
+  __syncthreads();
+  int64_t base = s_prefix;
+  for (int k = 0; k < w; ++k) base += s_w[k];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (c[j] == 0) continue;
+    const int64_t i = wbase + int64_t{j} * kWave + lane;
+    const int32_t row = static_cast<int32_t>(row_of(sel, i));
+    int64_t p = base + lane_off[j];
+    if (c[j] == 1) {
+      if (p < out_cap) {
+        out_row[p] = row;
+        out_pay[p] = first_pay[j];
+      }
+    } else {
+      probe_kp(slots, mask, key[row], [&](int32_t pl) {
+        if (p < out_cap) {
+          out_row[p] = row;
+          out_pay[p] = pl;
+        }
+        ++p;
+        return true;
+      });
+    }
+  }
+}
+
+// ============================================================== group-by SUM
+// 16-byte slots {int64 key, uint64 sum}; EMPTY key = INT64_MIN.
+__global__ void k_gb_init(GroupDev g, const int64_t *d_nsel, int64_t n, int64_t max_groups, double max_load) {
+  int64_t cnt = count_of(d_nsel, n);
+  if (max_groups > 0 && max_groups < cnt) cnt = max_groups;
+  const int64_t cap = table_capacity(cnt, max_load, g.cap_alloc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) g.hdr[0] = cap;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+    g.slots[2 * i] = static_cast<uint64_t>(kEmpty64);
+    g.slots[2 * i + 1] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gb_insert(const void *key, int key64, const void *val, int val64,
+                                                   const int32_t *sel, const int64_t *d_nsel, int64_t n, GroupDev g,
+                                                   uint32_t *err) {
+  const int64_t cnt = count_of(d_nsel, n);
+  const int64_t mask = g.hdr[0] - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = row_of(sel, i);
+    const int64_t k = load_as_i64(key, key64, row);
+    const int64_t v = load_as_i64(val, val64, row);
+    if (k == kEmpty64) {
+      latch(err, kErrKey);
+      continue;
+    }
+    if (!group_add(g.slots, mask, k, static_cast<uint64_t>(v))) latch(err, kErrTableFull);
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_gb_compact(GroupDev g, int64_t *out_keys, int64_t *out_sums,
+                                                     int64_t out_cap, int64_t *d_ngroups, uint64_t *status,
+                                                     unsigned long long *ticket, int64_t ntiles, uint32_t *err) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  __shared__ int64_t s_tile, s_prefix;
+  __shared__ int32_t s_cnt[NW];
+  if (threadIdx.x == 0) s_tile = static_cast<int64_t>(atomicAdd(ticket, 1ull));
+  __syncthreads();
+  const int64_t t = s_tile;
+  const int64_t cap = g.hdr[0];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t wbase = t * TILE + int64_t{w} * kWave * ITEMS;
+  uint64_t m[ITEMS];
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t s = wbase + int64_t{j} * kWave + lane;
+    const bool keep = s < cap && static_cast<int64_t>(g.slots[2 * s]) != kEmpty64;
+    m[j] = __ballot(keep);
+    cnt += __popcll(m[j]);
+  }
+  if (lane == 0) s_cnt[w] = cnt;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t c = lane < NW ? s_cnt[lane] : 0;
+    const int64_t agg = wave_sum(c);
+    const int64_t ex = lookback_exclusive(status, t, agg);
+    if (lane == 0) {
+      s_prefix = ex;
+      if (t == ntiles - 1) {
+        *d_ngroups = ex + agg;
+        if (ex + agg > out_cap) latch(err, kErrCapacity);
+      }
+    }
+  }
+  __syncthreads();
+  int64_t pos = s_prefix;
+  for (int k = 0; k < w; ++k) pos += s_cnt[k];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t s = wbase + int64_t{j} * kWave + lane;
+    if ((m[j] >> lane) & 1ull) {
+      const int64_t p = pos + mbcnt(m[j]);
+      if (p < out_cap) {
+        out_keys[p] = static_cast<int64_t>(g.slots[2 * s]);
+        out_sums[p] = static_cast<int64_t>(g.slots[2 * s + 1]);
+      }
+    }
+    pos += __popcll(m[j]);
+  }
+}
+
+pyst_status group_compact(pyst_ctx *ctx, const GroupDev &g, int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
+                          int64_t *d_ngroups, hipStream_t stream) {
+  constexpr int BLOCK = 256, ITEMS = 8;
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(g.cap_alloc, int64_t{BLOCK} * ITEMS));
+  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "group compaction: arena exhausted");
+  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+  if (st != PYST_OK) return st;
+  uint64_t *status = sc.as<uint64_t>();
+  k_gb_compact<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
+      g, out_keys, out_sums, out_cap, d_ngroups, status, reinterpret_cast<unsigned long long *>(status + ntiles),
+      ntiles, ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_gb_compact");
+  return PYST_OK;
+}
+
+pyst_status group_init(const GroupDev &g, const int64_t *d_nsel, int64_t n, int64_t max_groups, double max_load,
+                       hipStream_t stream) {
+  const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(g.cap_alloc, 256), 4096));
+  k_gb_init<<<blocks, 256, 0, stream>>>(g, d_nsel, n, max_groups, max_load);
+  PYST_LAUNCH_CHECK("k_gb_init");
+  return PYST_OK;
+}
+
+int grid_for(pyst_ctx *ctx, int64_t work, int block, int per_cu) {
+  const int64_t want = ceil_div(std::max<int64_t>(work, 1), block);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, int64_t{ctx_num_cus(ctx)} * per_cu)));
+}
+
+pyst_status table_init(const TableDev &t, const int64_t *d_nsel, int64_t n, double max_load, hipStream_t stream) {
+  const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(t.cap_alloc, 256), 4096));
+  k_table_init<<<blocks, 256, 0, stream>>>(t, d_nsel, n, max_load);
+  PYST_LAUNCH_CHECK("k_table_init");
+  return PYST_OK;
+}
+
+}  // namespace pyst
+
+// ============================================================== C ABI
+using namespace pyst;
+
+struct pyst_table {
+  pyst_ctx *ctx;
+  void *mem;
+  TableDev dev;
+  int unique;
+  hipStream_t stream;
+};
+
+extern "C" {
+
+pyst_status pyst_filter(pyst_ctx *ctx, const pyst_col *cols, int ncols, const pyst_pred *preds, int npreds,
+                        int32_t *sel_out, int64_t *d_nsel, hipStream_t stream) {
+  if (!ctx || !d_nsel) return set_error(PYST_ERR_ARG, "pyst_filter: NULL ctx or d_nsel");
+  if (ncols < 1 || ncols > PYST_MAX_COLS || !cols) return set_error(PYST_ERR_ARG, "pyst_filter: 1..8 columns required");
+  const int64_t n = cols[0].n;
+  for (int c = 0; c < ncols; ++c)
+    if (!col_ok(&cols[c]) || cols[c].n != n) return set_error(PYST_ERR_ARG, "pyst_filter: bad column or length mismatch");
+  if (n > 0 && !sel_out) return set_error(PYST_ERR_ARG, "pyst_filter: sel_out is NULL");
+  PredSet ps;
+  pyst_status st = build_predset(cols, ncols, preds, npreds, &ps, "pyst_filter");
+  if (st != PYST_OK) return st;
+  return filter_impl(ctx, ps, n, sel_out, d_nsel, stream);
+}
+
+pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payloads, int npay, const int32_t *sel,
+                           const int64_t *d_nsel, uint32_t fanout, void *const *out_cols, int64_t *d_offsets,
+                           hipStream_t stream) {
+  if (!ctx || !key || !out_cols || !d_offsets) return set_error(PYST_ERR_ARG, "pyst_partition: NULL argument");
+  if (fanout < 1 || fanout > PYST_MAX_FANOUT) return set_error(PYST_ERR_ARG, "pyst_partition: fanout must be 1..1024");
+  if (npay < 0 || npay > PYST_MAX_COLS - 1 || (npay > 0 && !payloads))
+    return set_error(PYST_ERR_ARG, "pyst_partition: 0..7 payload columns");
+  if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_partition: sel and d_nsel go together");
+  if (!col_ok(key)) return set_error(PYST_ERR_ARG, "pyst_partition: bad key column");
+  for (int j = 0; j < npay; ++j)
+    if (!col_ok(&payloads[j]) || payloads[j].n != key->n)
+      return set_error(PYST_ERR_ARG, "pyst_partition: payload length mismatch");
+  for (int j = 0; j <= npay; ++j)
+    if (!out_cols[j] && key->n > 0) return set_error(PYST_ERR_ARG, "pyst_partition: NULL output column");
+  TimedRegion timed(ctx, "partition", stream);
+  PartArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.key = key->data;
+  a.key64 = key->dtype == PYST_I64;
+  a.npay = npay;
+  for (int j = 0; j < npay; ++j) {
+    a.pay[j] = payloads[j].data;
+    a.pay64[j] = payloads[j].dtype == PYST_I64;
+  }
+  for (int j = 0; j <= npay; ++j) a.out[j] = out_cols[j];
+  a.sel = sel;
+  a.d_nsel = d_nsel;
+  a.n = key->n;
+  a.fanout = fanout;
+  int bits = 0;
+  while ((1u << bits) < fanout) ++bits;
+  a.fbits = bits;
+  a.radix_shift = -1;
+  return partition_run(ctx, a, d_offsets, stream);
+}
+
+pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payload, const int32_t *sel,
+                            const int64_t *d_nsel, double max_load, int unique_keys, pyst_table **out,
+                            hipStream_t stream) {
+  if (!ctx || !key || !out) return set_error(PYST_ERR_ARG, "pyst_join_build: NULL argument");
+  *out = nullptr;
+  if (!col_ok(key)) return set_error(PYST_ERR_ARG, "pyst_join_build: bad key column");
+  if (key->dtype != PYST_I32) return set_error(PYST_ERR_UNSUPPORTED, "pyst_join_build: join keys are int32");
+  if (payload && (!col_ok(payload) || payload->dtype != PYST_I32 || payload->n != key->n))
+    return set_error(PYST_ERR_ARG, "pyst_join_build: payload must be int32 with the key's length");
+  if (!(max_load > 0.0 && max_load <= 0.95)) return set_error(PYST_ERR_ARG, "pyst_join_build: max_load in (0, 0.95]");
+  if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_join_build: sel and d_nsel go together");
+  const int64_t cap_alloc = table_capacity_host(key->n, max_load);
+  const size_t bytes = table_bytes(cap_alloc, 8, false);
+  void *mem = ctx_alloc(ctx, bytes, stream);
+  if (!mem) return set_error(PYST_ERR_NOMEM, "pyst_join_build: arena exhausted");
+  auto *t = new pyst_table();
+  t->ctx = ctx;
+  t->mem = mem;
+  t->dev = table_view(mem, cap_alloc, 8, false);
+  t->unique = unique_keys != 0;
+  t->stream = stream;
+  pyst_status st = table_init(t->dev, d_nsel, key->n, max_load, stream);
+  if (st == PYST_OK && key->n > 0) {
+    const int blocks = grid_for(ctx, key->n, 256, 8);
+    k_join_build<<<blocks, 256, 0, stream>>>(static_cast<const int32_t *>(key->data),
+                                             payload ? static_cast<const int32_t *>(payload->data) : nullptr, sel,
+                                             d_nsel, key->n, t->dev, t->unique, ctx_err_word(ctx));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) st = hip_error(e, "k_join_build");
+  }
+  if (st != PYST_OK) {
+    pyst_table_destroy(t, stream);
+    return st;
+  }
+  *out = t;
+  return PYST_OK;
+}
+
+pyst_status pyst_join_probe(pyst_ctx *ctx, const pyst_table *table, const pyst_col *key, const int32_t *sel,
+                            const int64_t *d_nsel, int32_t *out_probe_row, int32_t *out_payload, int64_t out_cap,
+                            int64_t *d_nout, hipStream_t stream) {
+  if (!ctx || !table || !key || !d_nout) return set_error(PYST_ERR_ARG, "pyst_join_probe: NULL argument");
+  if (!col_ok(key)) return set_error(PYST_ERR_ARG, "pyst_join_probe: bad key column");
+  if (key->dtype != PYST_I32) return set_error(PYST_ERR_UNSUPPORTED, "pyst_join_probe: join keys are int32");
+  if (out_cap < 0 || (out_cap > 0 && (!out_probe_row || !out_payload)))
+    return set_error(PYST_ERR_ARG, "pyst_join_probe: bad output");
+  if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_join_probe: sel and d_nsel go together");
+  constexpr int BLOCK = 256, ITEMS = 8;
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(key->n, int64_t{BLOCK} * ITEMS));
+  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "pyst_join_probe: arena exhausted");
+  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+  if (st != PYST_OK) return st;
+  uint64_t *status = sc.as<uint64_t>();
+  k_join_probe<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
+      static_cast<const int32_t *>(key->data), sel, d_nsel, key->n, table->dev, table->unique, out_probe_row,
+      out_payload, out_cap, d_nout, status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles,
+      ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_join_probe");
+  const_cast<pyst_table *>(table)->stream = stream;
+  return PYST_OK;
+}
+
+pyst_status pyst_table_info(const pyst_table *table, int64_t *d_out, hipStream_t stream) {
+  if (!table || !d_out) return set_error(PYST_ERR_ARG, "pyst_table_info: NULL argument");
+  hipError_t e = hipMemcpyAsync(d_out, table->dev.hdr, 2 * sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(table header)");
+  return PYST_OK;
+}
+
+void pyst_table_destroy(pyst_table *table, hipStream_t stream) {
+  if (!table) return;
+  (void)hipStreamSynchronize(stream);
+  if (table->stream && table->stream != stream) (void)hipStreamSynchronize(table->stream);
+  ctx_free(table->ctx, table->mem, stream);
+  delete table;
+}
+
+pyst_status pyst_groupby_sum(pyst_ctx *ctx, const pyst_col *key, const pyst_col *val, const int32_t *sel,
+                             const int64_t *d_nsel, int64_t max_groups, double max_load, int64_t *out_keys,
+                             int64_t *out_sums, int64_t *d_ngroups, int sort_by_key, hipStream_t stream) {
+  if (!ctx || !key || !val || !d_ngroups) return set_error(PYST_ERR_ARG, "pyst_groupby_sum: NULL argument");
+  if (!col_ok(key) || !col_ok(val) || key->n != val->n)
+    return set_error(PYST_ERR_ARG, "pyst_groupby_sum: bad columns or length mismatch");
+  if (!(max_load > 0.0 && max_load <= 0.95)) return set_error(PYST_ERR_ARG, "pyst_groupby_sum: max_load in (0, 0.95]");
+  if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_groupby_sum: sel and d_nsel go together");
+  const int64_t bound = max_groups > 0 ? std::min<int64_t>(max_groups, key->n) : key->n;
+  const int64_t out_cap = max_groups > 0 ? max_groups : key->n;
+  if (out_cap > 0 && (!out_keys || !out_sums)) return set_error(PYST_ERR_ARG, "pyst_groupby_sum: NULL outputs");
+  const int64_t cap_alloc = table_capacity_host(bound, max_load);
+  Scratch mem(ctx, group_bytes(cap_alloc), stream);
+  if (!mem.p) return set_error(PYST_ERR_NOMEM, "pyst_groupby_sum: arena exhausted");
+  GroupDev g = group_view(mem.p, cap_alloc);
+  pyst_status st = group_init(g, d_nsel, key->n, max_groups, max_load, stream);
+  if (st != PYST_OK) return st;
+  if (key->n > 0) {
+    const int blocks = grid_for(ctx, key->n, 256, 8);
+    k_gb_insert<<<blocks, 256, 0, stream>>>(key->data, key->dtype == PYST_I64, val->data, val->dtype == PYST_I64, sel,
+                                            d_nsel, key->n, g, ctx_err_word(ctx));
+    PYST_LAUNCH_CHECK("k_gb_insert");
+  }
+  st = group_compact(ctx, g, out_keys, out_sums, out_cap, d_ngroups, stream);
+  if (st != PYST_OK) return st;
+  if (sort_by_key) return sort_pairs_by_key(ctx, out_keys, out_sums, d_ngroups, out_cap, stream);
+  return PYST_OK;
+}
+
+}  // extern "C"

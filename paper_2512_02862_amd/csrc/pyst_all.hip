@@ -1,0 +1,5 @@
+// Single translation unit of libpyst (device helpers are shared inline, and one
+// unit keeps kernel launches and their definitions together).
+#include "ctx.hip"
+#include "ops.hip"
+#include "query.hip"

@@ -1,0 +1,372 @@
+"""Python binding of libpyst: argument marshalling only.
+
+Every step of the relational path runs in the HIP kernels of libpyst.so; this
+module converts torch tensors (device memory) and the current torch stream to
+the plain pointers and sizes of the C ABI declared in include/pyst.h.  There is
+no fallback: if the library is missing or no GPU is visible, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpyst.so")
+
+OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_CAPACITY, ERR_KEY, ERR_TABLE_FULL, ERR_UNSUPPORTED, ERR_DUP_KEY = range(9)
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_CAPACITY", 5: "ERR_KEY",
+                6: "ERR_TABLE_FULL", 7: "ERR_UNSUPPORTED", 8: "ERR_DUP_KEY"}
+CMP = {"==": 0, "!=": 1, "<": 2, "<=": 3, ">": 4, ">=": 5}
+I32, I64 = 0, 1
+G_NONE, G_JOIN_KEY, G_JOIN_PAYLOAD, G_FACT_COL = 0, 1, 2, 3
+V_COL, V_COL_TIMES_C_MINUS = 0, 1
+
+EXPORTS = [
+    "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
+    "pyst_last_error", "pyst_filter", "pyst_partition", "pyst_join_build", "pyst_join_probe",
+    "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
+    "pyst_ctx_kernel_time",
+]
+
+
+class PystError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Col(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("cmp", ctypes.c_int32), ("value", ctypes.c_int64)]
+
+
+class JoinSpec(ctypes.Structure):
+    _fields_ = [("key", Col), ("payload", Col), ("cols", ctypes.POINTER(Col)), ("ncols", ctypes.c_int32),
+                ("npreds", ctypes.c_int32), ("preds", ctypes.POINTER(Pred)), ("probe_col", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_load", ctypes.c_double)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("njoins", ctypes.c_int32), ("npreds", ctypes.c_int32), ("joins", JoinSpec * 2),
+                ("preds", ctypes.POINTER(Pred)), ("hi_src", ctypes.c_int32), ("hi_index", ctypes.c_int32),
+                ("lo_src", ctypes.c_int32), ("lo_index", ctypes.c_int32), ("vexpr", ctypes.c_int32),
+                ("v0", ctypes.c_int32), ("v1", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("vconst", ctypes.c_int64), ("max_groups", ctypes.c_int64), ("group_max_load", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpyst.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libpyst.so is not built: run __graft_entry__.build() or "
+                           "python -m paper_2512_02862_amd.build")
+    lib = ctypes.CDLL(path)
+    p, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "pyst_ctx_create": ([i32, sz, P(p)], i32),
+        "pyst_ctx_destroy": ([p], None),
+        "pyst_ctx_check": ([p, p], i32),
+        "pyst_ctx_used": ([p], sz),
+        "pyst_ctx_budget": ([p], sz),
+        "pyst_last_error": ([], ctypes.c_char_p),
+        "pyst_filter": ([p, P(Col), i32, P(Pred), i32, p, p, p], i32),
+        "pyst_partition": ([p, P(Col), P(Col), i32, p, p, u32, P(p), p, p], i32),
+        "pyst_join_build": ([p, P(Col), P(Col), p, p, ctypes.c_double, i32, P(p), p], i32),
+        "pyst_join_probe": ([p, p, P(Col), p, p, p, p, i64, p, p], i32),
+        "pyst_table_info": ([p, p, p], i32),
+        "pyst_table_destroy": ([p, p], None),
+        "pyst_groupby_sum": ([p, P(Col), P(Col), p, p, i64, ctypes.c_double, p, p, p, i32, p], i32),
+        "pyst_query": ([p, P(Plan), P(Col), i32, p, p, i64, p, p], i32),
+        "pyst_ctx_timing": ([p, i32], i32),
+        "pyst_ctx_kernel_time": ([p, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != OK:
+        raise PystError(status, _lib.pyst_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _sel_ptr(t):
+    """Selection vector pointer; an empty selection still needs a valid address."""
+    if t is None:
+        return None
+    if t.numel() == 0:
+        if t.device not in _EMPTY_SEL:
+            _EMPTY_SEL[t.device] = torch.zeros(1, dtype=torch.int32, device=t.device)
+        t = _EMPTY_SEL[t.device]
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_EMPTY_SEL = {}
+
+
+def col(t: torch.Tensor) -> Col:
+    if not t.is_cuda or not t.is_contiguous() or t.dtype not in (torch.int32, torch.int64):
+        raise ValueError("columns are contiguous int32/int64 device tensors")
+    return Col(t.data_ptr(), t.numel(), I64 if t.dtype == torch.int64 else I32, 0)
+
+
+def _null_col():
+    return Col(None, 0, I32, 0)
+
+
+def _preds(preds):
+    preds = list(preds or [])
+    arr = (Pred * max(1, len(preds)))(*[Pred(c, CMP[o], int(v)) for c, o, v in preds])
+    return arr, len(preds)
+
+
+class Ctx:
+    """A device context with a fixed device-memory arena (the budget)."""
+
+    def __init__(self, device: int = 0, budget: int = 1 << 30):
+        load()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.pyst_ctx_create(device, budget, ctypes.byref(h)))
+        self.h = h
+
+    def check(self, stream=None):
+        """Synchronize the stream and raise on any error latched by a kernel."""
+        _check(_lib.pyst_ctx_check(self.h, _stream(stream)))
+
+    def timing(self, enable: bool):
+        """Record HIP events around the library's timed kernels (see kernel_time)."""
+        _check(_lib.pyst_ctx_timing(self.h, int(bool(enable))))
+
+    def kernel_time(self, name: str):
+        """(total milliseconds, launches) of the timed region `name` since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.pyst_ctx_kernel_time(self.h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def used(self):
+        return _lib.pyst_ctx_used(self.h)
+
+    @property
+    def budget(self):
+        return _lib.pyst_ctx_budget(self.h)
+
+    def close(self):
+        if self.h:
+            _lib.pyst_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev(ctx):
+    return torch.device("cuda", ctx.device)
+
+
+def filter(ctx: Ctx, cols, preds, stream=None):
+    """Ascending selection vector (int32, capacity n) and device count (int64[1])."""
+    cols = list(cols)
+    n = cols[0].numel()
+    carr = (Col * len(cols))(*[col(c) for c in cols])
+    parr, npred = _preds(preds)
+    sel = torch.empty(max(n, 1), dtype=torch.int32, device=_dev(ctx))
+    nsel = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+    _check(_lib.pyst_filter(ctx.h, carr, len(cols), parr, npred, _sel_ptr(sel), _ptr(nsel), _stream(stream)))
+    return sel, nsel
+
+
+def partition(ctx: Ctx, key, payloads, fanout: int, sel=None, nsel=None, stream=None):
+    """Stable hash partition: (out_key, [out_payloads], offsets int64[F+1])."""
+    payloads = list(payloads)
+    n = key.numel()
+    outs = [torch.empty(max(n, 1), dtype=t.dtype, device=_dev(ctx)) for t in [key] + payloads]
+    offsets = torch.empty(fanout + 1, dtype=torch.int64, device=_dev(ctx))
+    kc = col(key)
+    parr = (Col * max(1, len(payloads)))(*[col(t) for t in payloads])
+    oarr = (ctypes.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    _check(_lib.pyst_partition(ctx.h, ctypes.byref(kc), parr, len(payloads), _sel_ptr(sel), _ptr(nsel), fanout, oarr,
+                               _ptr(offsets), _stream(stream)))
+    return outs[0][:n], [o[:n] for o in outs[1:]], offsets
+
+
+class Table:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def info(self, stream=None):
+        """(effective capacity, rows offered for insertion), read from the device."""
+        out = torch.empty(2, dtype=torch.int64, device=_dev(self.ctx))
+        _check(_lib.pyst_table_info(self.h, _ptr(out), _stream(stream)))
+        return tuple(int(x) for x in out.cpu())
+
+    def destroy(self, stream=None):
+        if self.h:
+            _lib.pyst_table_destroy(self.h, _stream(stream))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def join_build(ctx: Ctx, key, payload=None, sel=None, nsel=None, max_load=0.5, unique_keys=True, stream=None):
+    kc = col(key)
+    pc = col(payload) if payload is not None else None
+    h = ctypes.c_void_p()
+    _check(_lib.pyst_join_build(ctx.h, ctypes.byref(kc), ctypes.byref(pc) if pc is not None else None,
+                                _sel_ptr(sel), _ptr(nsel), float(max_load), int(bool(unique_keys)), ctypes.byref(h),
+                                _stream(stream)))
+    return Table(ctx, h)
+
+
+def join_probe(ctx: Ctx, table: Table, key, sel=None, nsel=None, out_cap=None, stream=None):
+    """(probe rows int32, payloads int32, count int64[1]); outputs have out_cap entries."""
+    n = key.numel()
+    cap = n if out_cap is None else out_cap
+    rows = torch.empty(max(cap, 1), dtype=torch.int32, device=_dev(ctx))
+    pays = torch.empty(max(cap, 1), dtype=torch.int32, device=_dev(ctx))
+    nout = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+    kc = col(key)
+    _check(_lib.pyst_join_probe(ctx.h, table.h, ctypes.byref(kc), _sel_ptr(sel), _ptr(nsel), _ptr(rows), _ptr(pays),
+                                cap, _ptr(nout), _stream(stream)))
+    return rows, pays, nout
+
+
+def groupby_sum(ctx: Ctx, key, val, sel=None, nsel=None, max_groups=0, max_load=0.5, sort_by_key=False,
+                stream=None):
+    """(keys int64, sums int64, count int64[1]); outputs have max_groups (or n) entries."""
+    n = key.numel()
+    cap = max_groups if max_groups > 0 else n
+    ok = torch.empty(max(cap, 1), dtype=torch.int64, device=_dev(ctx))
+    osum = torch.empty(max(cap, 1), dtype=torch.int64, device=_dev(ctx))
+    ng = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+    kc, vc = col(key), col(val)
+    _check(_lib.pyst_groupby_sum(ctx.h, ctypes.byref(kc), ctypes.byref(vc), _sel_ptr(sel), _ptr(nsel), int(max_groups),
+                                 float(max_load), _ptr(ok), _ptr(osum), _ptr(ng), int(bool(sort_by_key)),
+                                 _stream(stream)))
+    return ok, osum, ng
+
+
+_GSRC = {None: G_NONE, "join_key": G_JOIN_KEY, "join_payload": G_JOIN_PAYLOAD, "fact": G_FACT_COL}
+
+
+class QueryPlan:
+    """A fused query plan (see pyst_plan in include/pyst.h).
+
+    joins: list of dicts {key, payload (or None), cols (list), preds, probe_col, max_load}
+    preds: fact predicates [(fact column index, op, constant)]
+    hi, lo: group-key halves, each None or (source, index) with source in
+            'join_key' | 'join_payload' | 'fact'
+    value: ('col', c) or ('col_times_c_minus', c0, c1, const)
+    """
+
+    def __init__(self, joins, preds, lo, hi=None, value=("col", 2), max_groups=0, group_max_load=0.5):
+        self.joins, self.preds, self.lo, self.hi = joins, preds, lo, hi
+        self.value, self.max_groups, self.group_max_load = value, max_groups, group_max_load
+
+    def to_c(self):
+        keep = []
+        p = Plan()
+        p.njoins = len(self.joins)
+        parr, npred = _preds(self.preds)
+        keep.append(parr)
+        p.preds = ctypes.cast(parr, ctypes.POINTER(Pred))
+        p.npreds = npred
+        for j, js in enumerate(self.joins):
+            s = p.joins[j]
+            s.key = col(js["key"])
+            s.payload = col(js["payload"]) if js.get("payload") is not None else _null_col()
+            dcols = list(js.get("cols", []))
+            carr = (Col * max(1, len(dcols)))(*[col(t) for t in dcols])
+            dp, ndp = _preds(js.get("preds", []))
+            keep += [carr, dp]
+            s.cols = ctypes.cast(carr, ctypes.POINTER(Col))
+            s.ncols = len(dcols)
+            s.preds = ctypes.cast(dp, ctypes.POINTER(Pred))
+            s.npreds = ndp
+            s.probe_col = js["probe_col"]
+            s.max_load = float(js.get("max_load", 0.5))
+        p.lo_src, p.lo_index = (_GSRC[self.lo[0]], self.lo[1])
+        p.hi_src, p.hi_index = (G_NONE, 0) if self.hi is None else (_GSRC[self.hi[0]], self.hi[1])
+        if self.value[0] == "col":
+            p.vexpr, p.v0, p.v1, p.vconst = V_COL, self.value[1], 0, 0
+        else:
+            p.vexpr, p.v0, p.v1, p.vconst = V_COL_TIMES_C_MINUS, self.value[1], self.value[2], self.value[3]
+        p.max_groups = int(self.max_groups)
+        p.group_max_load = float(self.group_max_load)
+        return p, keep
+
+
+def query(ctx: Ctx, plan: QueryPlan, fact, out_cap=None, stream=None):
+    """Fused filter + join + group-by: (keys int64, sums int64, count int64[1])."""
+    fact = list(fact)
+    cp, keep = plan.to_c()
+    if out_cap is None:
+        out_cap = plan.joins[0]["key"].numel() if plan.hi is None and plan.lo == ("join_key", 0) \
+            and len(plan.joins) == 1 else fact[0].numel()
+    ok = torch.empty(max(out_cap, 1), dtype=torch.int64, device=_dev(ctx))
+    osum = torch.empty(max(out_cap, 1), dtype=torch.int64, device=_dev(ctx))
+    ng = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+    farr = (Col * len(fact))(*[col(t) for t in fact])
+    _check(_lib.pyst_query(ctx.h, ctypes.byref(cp), farr, len(fact), _ptr(ok), _ptr(osum), int(out_cap), _ptr(ng),
+                           _stream(stream)))
+    del keep
+    return ok, osum, ng
+
+
+# ------------------------------------------------------------------ plans of the measured workloads
+
+def star_plan(build, seg_eq=1, date_lt=1200, max_load=0.5):
+    """SELECT key, SUM(price) ... WHERE segment == seg_eq AND date < date_lt GROUP BY key.
+
+    build: {key, segment} device tensors; fact columns are [fk, date, price].
+    """
+    return QueryPlan(
+        joins=[{"key": build["key"], "payload": None, "cols": [build["key"], build["segment"]],
+                "preds": [(1, "==", seg_eq)], "probe_col": 0, "max_load": max_load}],
+        preds=[(1, "<", date_lt)], lo=("join_key", 0), value=("col", 2))
+
+
+def chain_plan(a, b, seg_eq=1, date_lt=1200, max_load=0.5, group_max_load=0.5, max_groups=0):
+    """Two-join chain: fact JOIN B (filtered) JOIN A, GROUP BY (B.key, A.date) SUM(price*(100-discount)).
+
+    Fact columns are [a_fk, b_fk, date, price, discount]; B is probed first (more selective).
+    """
+    return QueryPlan(
+        joins=[{"key": b["key"], "payload": None, "cols": [b["key"], b["segment"]], "preds": [(1, "==", seg_eq)],
+                "probe_col": 1, "max_load": max_load},
+               {"key": a["key"], "payload": a["date"], "cols": [], "preds": [], "probe_col": 0,
+                "max_load": max_load}],
+        preds=[(2, "<", date_lt)], hi=("join_key", 0), lo=("join_payload", 1),
+        value=("col_times_c_minus", 3, 4, 100), max_groups=max_groups, group_max_load=group_max_load)
