@@ -120,6 +120,12 @@ const char *pyst_last_error(void);
    their summed duration in milliseconds and the number of launches, and
    forgets them.  Errors: PYST_ERR_ARG, PYST_ERR_HIP. */
 pyst_status pyst_ctx_timing(pyst_ctx *ctx, int enable);
+
+/* Context options.  PYST_OPT_GENERIC_ONLY != 0 makes pyst_query use its
+   generic fact pass even where a plan-shape-specialized kernel exists (both
+   compute the same result; tests compare them).  Errors: PYST_ERR_ARG. */
+#define PYST_OPT_GENERIC_ONLY 1
+pyst_status pyst_ctx_option(pyst_ctx *ctx, int key, int64_t value);
 pyst_status pyst_ctx_kernel_time(pyst_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------- filter */
@@ -266,6 +272,146 @@ typedef struct pyst_plan {
 pyst_status pyst_query(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col *fact, int nfact,
                        int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                        hipStream_t stream);
+
+/* ---------------------------------------------------------------- streamed query */
+
+/* pyst_query over a fact table held in PINNED HOST memory (hipHostMalloc or
+   pinned torch tensors), streamed to the device in chunks (Sec. 3.2,
+   "Partial Overlap Using Chunking"; memory relief of Sec. 3.4).
+   host_fact[c].data are host pointers (16-byte aligned, total rows < 2^31);
+   the plan's dimension columns are device pointers as in pyst_query.
+   chunk_rows (a positive multiple of 4) rows of every fact column are copied
+   on the context's copy stream into a ring of nbuf (2..8) device buffers
+   taken from the arena, and the fused fact pass runs per chunk on `stream`;
+   buffer reuse is ordered by device events, so the call only enqueues work and
+   returns (no host synchronization between chunks).  The host buffers must
+   stay alive and unchanged until `stream` completes.
+   Only plans served by the specialized fact pass can be streamed, and group
+   keys other than the single join key need plan->max_groups > 0 (the group
+   table must exist before the first chunk).
+   Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED, PYST_ERR_NOMEM, PYST_ERR_HIP. */
+pyst_status pyst_query_streamed(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col *host_fact, int nfact,
+                                int64_t chunk_rows, int nbuf, int64_t *out_keys, int64_t *out_sums,
+                                int64_t out_cap, int64_t *d_ngroups, hipStream_t stream);
+
+/* ---------------------------------------------------------------- batched fragments */
+
+/* One independent query fragment: a plan (its own dimension columns), its own
+   device fact columns, and its outputs (as for pyst_query). */
+typedef struct pyst_fragment {
+  const pyst_plan *plan;
+  const pyst_col *fact;
+  int32_t nfact;
+  int32_t reserved;
+  int64_t *out_keys;
+  int64_t *out_sums;
+  int64_t out_cap;
+  int64_t *d_ngroups;
+} pyst_fragment;
+
+/* Batch execution parameters.
+   fanout   : the number of work units each fragment's fact table is split into
+              (at least 4 * block rows per unit), i.e. how finely large
+              fragments spread over the chip next to small ones;
+   block    : threads per block of the fact pass (256, 512 or 1024);
+   max_load : hash-table load bound of every fragment (0: the plan's). */
+typedef struct pyst_tuning {
+  int32_t fanout;
+  int32_t block;
+  double max_load;
+} pyst_tuning;
+
+/* Run nfrag fragments as one batch: five launches in total (dimension filter,
+   table init, build, fact pass, compaction), each covering every fragment, in
+   place of a launch sequence and a host round trip per fragment -- the
+   small-work inefficiency the paper counters by buffering small chunks into
+   larger units (Sec. 5.3, "Dynamic Buffering").  Every fragment must be a
+   single-join star query grouped by the join key on int32 columns with the
+   same value dtype; each gets exactly the result pyst_query gives it.
+   tuning may be NULL (defaults {64, 512, 0}).  Errors: PYST_ERR_ARG,
+   PYST_ERR_UNSUPPORTED, PYST_ERR_NOMEM, PYST_ERR_HIP. */
+pyst_status pyst_query_batch(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, const pyst_tuning *tuning,
+                             hipStream_t stream);
+
+/* Search fanout {16,32,64,128,256} x block {256,512,1024} x max_load
+   {0.5,0.7} for the fastest pyst_query_batch of these fragments (mean of
+   `reps` timed runs after one warm-up, HIP events on a private stream).
+   Blocks until done; writes the winner to *out and its time to *best_ms
+   (may be NULL).  Errors: as pyst_query_batch. */
+pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, int reps, pyst_tuning *out,
+                          double *best_ms);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A query server over one fact table in pinned host memory, after the
+   queue-based scheduling of Sec. 5.4: client threads submit requests into a
+   multi-producer queue; one scheduler thread issues all GPU work.  It admits
+   requests while stream slots and device memory allow (adaptive regulation:
+   excess load waits in the queue), keeps built dimension tables resident
+   across requests, and runs every active request on one shared circular scan
+   of the fact table -- each chunk is copied to the device once and consumed
+   by every active request that still needs it (the reader combining of
+   Sec. 5.2).  Requests arriving while others run join the scan at its current
+   position (continuous batching).  max_active = 1 gives one-at-a-time FIFO
+   service over the same machinery. */
+typedef struct pyst_server pyst_server;
+
+typedef struct pyst_server_cfg {
+  size_t budget_bytes; /* device memory for dimension tables and aggregation state */
+  int32_t max_active;  /* concurrently served requests (1..64), one stream each      */
+  int32_t nbuf;        /* chunk buffers in the device ring (2..8)                   */
+  int64_t chunk_rows;  /* fact rows per chunk (a positive multiple of 4)            */
+} pyst_server_cfg;
+
+/* A request: plan over the server's fact columns (same column order as at
+   creation; dimension columns are device pointers that must stay alive until
+   the request completes), scanning fact rows [0, rows).  The plan is copied at
+   submit.  Outputs are device buffers as in pyst_query. */
+typedef struct pyst_request {
+  const pyst_plan *plan;
+  int64_t rows;
+  int64_t *out_keys;
+  int64_t *out_sums;
+  int64_t out_cap;
+  int64_t *d_ngroups;
+} pyst_request;
+
+typedef struct pyst_server_stats {
+  int64_t submitted;
+  int64_t completed;
+  int64_t chunks_copied;
+  int64_t admission_waits;  /* times the queue head waited for memory or a slot */
+  int64_t max_active_seen;
+  double bytes_copied;      /* host-to-device bytes of fact chunks       */
+  double fact_rows_processed; /* sum over requests of fact rows consumed  */
+} pyst_server_stats;
+
+/* Create a server on `device` over host_fact[0..nfact) (pinned host columns,
+   kept alive by the caller until pyst_server_destroy).  Allocates its own
+   context (arena = cfg->budget_bytes plus the chunk ring) and starts the
+   scheduler thread.  Errors: PYST_ERR_ARG, PYST_ERR_NOMEM, PYST_ERR_HIP. */
+pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pyst_col *host_fact, int nfact,
+                               pyst_server **out);
+
+/* Queue a request (thread-safe, never blocks on the GPU); *ticket identifies
+   it.  Only plans served by the specialized fact pass are accepted, and group
+   keys other than the single join key need plan->max_groups > 0.
+   Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED. */
+pyst_status pyst_server_submit(pyst_server *server, const pyst_request *req, uint64_t *ticket);
+
+/* Block until request `ticket` has completed (its outputs are then final);
+   *latency_ms = completion - submission.  Returns the request's status
+   (PYST_ERR_NOMEM if it can never fit the budget).  A ticket is waited once. */
+pyst_status pyst_server_wait(pyst_server *server, uint64_t ticket, double *latency_ms);
+
+/* Counters since creation.  Errors: PYST_ERR_ARG. */
+pyst_status pyst_server_get_stats(pyst_server *server, pyst_server_stats *out);
+
+/* Wait for the device and return the errors latched by the server's kernels. */
+pyst_status pyst_server_check(pyst_server *server);
+
+/* Finish every submitted request, stop the scheduler and free everything. */
+void pyst_server_destroy(pyst_server *server);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,385 @@
+// Batched execution of many independent query fragments.
+//
+// Small inputs lose efficiency when each is processed by its own sequence of
+// launches and host round trips; the paper accumulates small chunks before
+// size-sensitive operators for the same reason (Sec. 5.3, "Dynamic
+// Buffering").  Here all fragments of a batch run through five launches in
+// total -- dimension filter, table init, build, fact pass, compaction -- each
+// launch covering every fragment.  A block finds its fragment by binary search
+// over per-kernel block prefixes held in device memory.
+//
+// The batch path serves star-shaped fragments (one join, group by the join
+// key, slot sums); every fragment has its own dimension, fact and outputs.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "pyst_internal.h"
+#include "query.h"
+#include "table.h"
+
+namespace pyst {
+
+struct BatFrag {
+  PredSet bpred;           // dimension predicates
+  const int32_t *bkey;     // dimension keys
+  int64_t nb;
+  int32_t *sel;            // block-local selection (nblk * kDimTile)
+  int32_t *cnt;            // per-block selected counts
+  int64_t nblk;
+  TableDev t;              // keys-only table with slot sums
+  double max_load;
+  FastArgs fa;             // fact side (single join)
+  int64_t rows_per_unit;   // rows of one fact work unit (multiple of 4)
+  int64_t *out_keys, *out_sums;
+  int64_t out_cap;
+  int64_t *d_ngroups;
+};
+
+// Per-kernel block prefixes: blocks of fragment f are [pre[f], pre[f+1]).
+enum { kPreFilter = 0, kPreInit = 1, kPreBuild = 2, kPreFact = 3, kPreCompact = 4, kPreKinds = 5 };
+
+__device__ __forceinline__ int frag_of(const int64_t *pre, int nfrag, int64_t b) {
+  int lo = 0, hi = nfrag - 1;  // largest f with pre[f] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+#define PYST_BLOCK_FRAG(kind)                                              \
+  __shared__ int s_frag;                                                   \
+  if (threadIdx.x == 0) s_frag = frag_of(pre + (kind) * (nfrag + 1), nfrag, blockIdx.x); \
+  __syncthreads();                                                         \
+  const int f = s_frag;                                                    \
+  const BatFrag &fr = frags[f];                                            \
+  const int64_t local = blockIdx.x - pre[(kind) * (nfrag + 1) + f];        \
+  const int64_t nloc = pre[(kind) * (nfrag + 1) + f + 1] - pre[(kind) * (nfrag + 1) + f];
+
+__global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const int64_t *pre, int nfrag) {
+  PYST_BLOCK_FRAG(kPreFilter)
+  (void)nloc;
+  constexpr int NW = 256 / kWave, ITEMS = kDimTile / 256;
+  __shared__ int32_t s_cnt[NW];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t wbase = local * kDimTile + int64_t{w} * kWave * ITEMS;
+  uint64_t m[ITEMS];
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t row = wbase + int64_t{j} * kWave + lane;
+    m[j] = __ballot(row < fr.nb && eval_preds(fr.bpred, row));
+    c += __popcll(m[j]);
+  }
+  if (lane == 0) s_cnt[w] = c;
+  __syncthreads();
+  int pos = 0;
+  for (int k = 0; k < w; ++k) pos += s_cnt[k];
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < NW; ++k) tot += s_cnt[k];
+    fr.cnt[local] = tot;
+  }
+  int32_t *out = fr.sel + local * kDimTile;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if ((m[j] >> lane) & 1ull) out[pos + mbcnt(m[j])] = static_cast<int32_t>(wbase + int64_t{j} * kWave + lane);
+    pos += __popcll(m[j]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const int64_t *pre, int nfrag) {
+  PYST_BLOCK_FRAG(kPreInit)
+  __shared__ int64_t s_total;
+  if (threadIdx.x < kWave) {
+    int64_t part = 0;
+    for (int64_t b = threadIdx.x; b < fr.nblk; b += kWave) part += fr.cnt[b];
+    part = wave_sum(part);
+    if (threadIdx.x == 0) s_total = part;
+  }
+  __syncthreads();
+  const TableDev &t = fr.t;
+  const int64_t cap = table_capacity(s_total, fr.max_load, t.cap_alloc);
+  const int64_t tid = local * 256 + threadIdx.x, nthr = nloc * 256;
+  if (tid == 0) {
+    t.hdr[0] = cap;
+    t.hdr[1] = s_total;
+    *fr.d_ngroups = 0;
+  }
+  int32_t *keys = static_cast<int32_t *>(t.slots);
+  for (int64_t i = tid; i < cap; i += nthr) {
+    keys[i] = kEmpty32;
+    t.sums[i] = 0;
+    t.flags[i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
+  PYST_BLOCK_FRAG(kPreBuild)
+  const TableDev &t = fr.t;
+  const int64_t mask = t.hdr[0] - 1;
+  int32_t *keys = static_cast<int32_t *>(t.slots);
+  for (int64_t i = local * 256 + threadIdx.x; i < fr.nb; i += nloc * 256) {
+    if ((i % kDimTile) >= fr.cnt[i / kDimTile]) continue;
+    const int32_t k = fr.bkey[fr.sel[i]];
+    if (k == kEmpty32) {
+      latch(err, kErrKey);
+      continue;
+    }
+    int64_t s = (table_hash32(k) & mask) & ~int64_t{3};
+    bool done = false;
+    for (int64_t step = 0; step <= mask; ++step) {
+      int32_t cur = keys[s];
+      if (cur == kEmpty32) {
+        const int32_t old = atomicCAS(&keys[s], kEmpty32, k);
+        if (old == kEmpty32) {
+          done = true;
+          break;
+        }
+        cur = old;
+      }
+      if (cur == k) {
+        latch(err, kErrDup);
+        done = true;
+        break;
+      }
+      s = (s + 1) & mask;
+    }
+    if (!done) latch(err, kErrTableFull);
+  }
+}
+
+template <int BS, bool V64>
+__global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
+  PYST_BLOCK_FRAG(kPreFact)
+  (void)nloc;
+  const int64_t begin = local * fr.rows_per_unit;
+  const int64_t end = begin + fr.rows_per_unit < fr.fa.n ? begin + fr.rows_per_unit : fr.fa.n;
+  fact_range<1, 4, 0, V64>(fr.fa, fr.t, fr.t, GroupDev{}, PairsOut{}, err, nullptr, false, begin, int64_t{BS} * 4, end);
+}
+
+__global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
+  PYST_BLOCK_FRAG(kPreCompact)
+  const TableDev &t = fr.t;
+  const int64_t cap = t.hdr[0];
+  for (int64_t s0 = local * 256; s0 < cap; s0 += nloc * 256) {
+    const int64_t s = s0 + threadIdx.x;
+    const bool keep = s < cap && t.flags[s] != 0;
+    const uint64_t m = __ballot(keep);
+    if (!m) continue;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    unsigned long long wb = 0;
+    if (lane_id() == leader)
+      wb = atomicAdd(reinterpret_cast<unsigned long long *>(fr.d_ngroups), static_cast<unsigned long long>(__popcll(m)));
+    wb = __shfl(wb, leader);
+    if (keep) {
+      const int64_t p = static_cast<int64_t>(wb) + mbcnt(m);
+      if (p < fr.out_cap) {
+        fr.out_keys[p] = static_cast<const int32_t *>(t.slots)[s];
+        fr.out_sums[p] = static_cast<int64_t>(t.sums[s]);
+      } else {
+        latch(err, kErrCapacity);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host side
+struct BatchPlan {
+  std::vector<BatFrag> frags;
+  std::vector<int64_t> pre;  // kPreKinds * (nfrag + 1)
+  size_t table_bytes_total = 0, sel_bytes_total = 0;
+};
+
+static bool batch_shape(const pyst_fragment &fg, QueryShape *q, FastArgs *fa) {
+  if (prepare_query(fg.plan, fg.fact, fg.nfact, q) != PYST_OK) return false;
+  if (fg.plan->njoins != 1 || !q->slot_agg) return false;
+  return fast_shape(fg.plan, fg.fact, *q, fa);
+}
+
+static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu, BatchPlan *bp) {
+  bp->frags.resize(nfrag);
+  bp->pre.assign(static_cast<size_t>(kPreKinds) * (nfrag + 1), 0);
+  const int64_t cus = ctx_num_cus(ctx);
+  for (int f = 0; f < nfrag; ++f) {
+    QueryShape q;
+    FastArgs fa;
+    if (!batch_shape(fr[f], &q, &fa))
+      return set_error(PYST_ERR_UNSUPPORTED, "pyst_query_batch: fragments must be single-join star queries on int32 columns");
+    const pyst_join_spec &js = fr[f].plan->joins[0];
+    BatFrag &b = bp->frags[f];
+    std::memset(&b, 0, sizeof(b));
+    b.bkey = static_cast<const int32_t *>(js.key.data);
+    b.nb = js.key.n;
+    b.nblk = std::max<int64_t>(1, ceil_div(b.nb, kDimTile));
+    b.bpred.n = js.npreds;
+    for (int k = 0; k < js.npreds; ++k) {
+      const int c = js.preds[k].col;
+      if (c < 0 || c >= js.ncols) return set_error(PYST_ERR_ARG, "pyst_query_batch: dimension predicate names a missing column");
+      b.bpred.col[k] = js.cols[c].data;
+      b.bpred.is64[k] = js.cols[c].dtype == PYST_I64;
+      b.bpred.op[k] = js.preds[k].cmp;
+      b.bpred.val[k] = js.preds[k].value;
+    }
+    b.max_load = tu.max_load > 0 ? tu.max_load : js.max_load;
+    b.fa = fa;
+    const int64_t units = std::max<int64_t>(1, std::min<int64_t>(tu.fanout, ceil_div(fa.n, int64_t{4} * tu.block)));
+    b.rows_per_unit = std::max<int64_t>(4, ceil_div(ceil_div(fa.n, units), 4) * 4);
+    b.out_keys = fr[f].out_keys;
+    b.out_sums = fr[f].out_sums;
+    b.out_cap = fr[f].out_cap;
+    b.d_ngroups = fr[f].d_ngroups;
+    const int64_t cap_alloc = table_capacity_host(b.nb, b.max_load);
+    b.t.cap_alloc = cap_alloc;
+    b.t.slot_bytes = 4;
+    bp->table_bytes_total += (table_bytes(cap_alloc, 4, true) + 255) / 256 * 256;
+    bp->sel_bytes_total += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
+    const int64_t blocks[kPreKinds] = {
+        b.nblk,
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus)),
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(b.nb, 256 * 4), 4 * cus)),
+        ceil_div(std::max<int64_t>(fa.n, 1), b.rows_per_unit),
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus))};
+    for (int k = 0; k < kPreKinds; ++k) bp->pre[k * (nfrag + 1) + f + 1] = bp->pre[k * (nfrag + 1) + f] + blocks[k];
+  }
+  return PYST_OK;
+}
+
+static pyst_status batch_run(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu,
+                             hipStream_t stream) {
+  BatchPlan bp;
+  pyst_status st = batch_layout(ctx, fr, nfrag, tu, &bp);
+  if (st != PYST_OK) return st;
+  const size_t desc_bytes = sizeof(BatFrag) * nfrag;
+  const size_t pre_bytes = sizeof(int64_t) * bp.pre.size();
+  const size_t meta = (desc_bytes + 255) / 256 * 256 + (pre_bytes + 255) / 256 * 256;
+  char *mem = static_cast<char *>(ctx_alloc(ctx, meta + bp.table_bytes_total + bp.sel_bytes_total, stream));
+  if (!mem) return set_error(PYST_ERR_NOMEM, "pyst_query_batch: arena cannot hold the batch");
+  char *p = mem + meta;
+  for (int f = 0; f < nfrag; ++f) {
+    BatFrag &b = bp.frags[f];
+    b.t = table_view(p, b.t.cap_alloc, 4, true);
+    p += (table_bytes(b.t.cap_alloc, 4, true) + 255) / 256 * 256;
+  }
+  for (int f = 0; f < nfrag; ++f) {
+    BatFrag &b = bp.frags[f];
+    b.cnt = reinterpret_cast<int32_t *>(p);
+    b.sel = b.cnt + (b.nblk + 63) / 64 * 64;
+    p += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
+  }
+  // Descriptors go up through pinned staging (a pageable copy would stall other streams).
+  char *stage = ctx_pinned_staging(ctx, meta);
+  if (!stage) {
+    ctx_free(ctx, mem, stream);
+    return set_error(PYST_ERR_NOMEM, "pyst_query_batch: pinned staging");
+  }
+  std::memcpy(stage, bp.frags.data(), desc_bytes);
+  std::memcpy(stage + (desc_bytes + 255) / 256 * 256, bp.pre.data(), pre_bytes);
+  hipError_t e = hipMemcpyAsync(mem, stage, meta, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = ctx_staging_record(ctx, stream);
+  if (e != hipSuccess) {
+    ctx_free(ctx, mem, stream);
+    return hip_error(e, "pyst_query_batch: descriptor upload");
+  }
+  const BatFrag *d_frags = reinterpret_cast<const BatFrag *>(mem);
+  const int64_t *d_pre = reinterpret_cast<const int64_t *>(mem + (desc_bytes + 255) / 256 * 256);
+  auto total = [&](int k) { return static_cast<unsigned>(bp.pre[k * (nfrag + 1) + nfrag]); };
+  uint32_t *err = ctx_err_word(ctx);
+  {
+    TimedRegion timed(ctx, "batch", stream);
+    k_bat_filter<<<total(kPreFilter), 256, 0, stream>>>(d_frags, d_pre, nfrag);
+    k_bat_init<<<total(kPreInit), 256, 0, stream>>>(d_frags, d_pre, nfrag);
+    k_bat_build<<<total(kPreBuild), 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
+    const bool v64 = bp.frags[0].fa.v0_64 != 0;
+    for (int f = 1; f < nfrag; ++f)
+      if ((bp.frags[f].fa.v0_64 != 0) != v64) {
+        ctx_free(ctx, mem, stream);
+        return set_error(PYST_ERR_UNSUPPORTED, "pyst_query_batch: value columns must share one dtype");
+      }
+#define PYST_BAT_FACT(BS_)                                                                                      \
+  if (tu.block == BS_) {                                                                                      \
+    if (v64) k_bat_fact<BS_, true><<<total(kPreFact), BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);           \
+    else k_bat_fact<BS_, false><<<total(kPreFact), BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);              \
+  }
+    PYST_BAT_FACT(256)
+    PYST_BAT_FACT(512)
+    PYST_BAT_FACT(1024)
+#undef PYST_BAT_FACT
+    k_bat_compact<<<total(kPreCompact), 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
+    e = hipGetLastError();
+  }
+  ctx_free(ctx, mem, stream);
+  if (e != hipSuccess) return hip_error(e, "pyst_query_batch: launch");
+  return PYST_OK;
+}
+
+static bool tuning_ok(const pyst_tuning &t) {
+  return (t.block == 256 || t.block == 512 || t.block == 1024) && t.fanout >= 1 && t.fanout <= 65536 &&
+         (t.max_load == 0.0 || (t.max_load > 0.0 && t.max_load <= 0.95));
+}
+
+}  // namespace pyst
+
+using namespace pyst;
+
+extern "C" {
+
+pyst_status pyst_query_batch(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, const pyst_tuning *tuning,
+                             hipStream_t stream) {
+  if (!ctx || (!frags && nfrag > 0) || nfrag < 0) return set_error(PYST_ERR_ARG, "pyst_query_batch: NULL argument");
+  if (nfrag == 0) return PYST_OK;
+  pyst_tuning tu = tuning ? *tuning : pyst_tuning{64, 512, 0.0};
+  if (!tuning_ok(tu)) return set_error(PYST_ERR_ARG, "pyst_query_batch: tuning fanout 1..65536, block 256/512/1024, max_load 0 or (0, 0.95]");
+  for (int f = 0; f < nfrag; ++f)
+    if (!frags[f].plan || !frags[f].fact || !frags[f].d_ngroups || frags[f].out_cap < 0 ||
+        (frags[f].out_cap > 0 && (!frags[f].out_keys || !frags[f].out_sums)))
+      return set_error(PYST_ERR_ARG, "pyst_query_batch: bad fragment");
+  return batch_run(ctx, frags, nfrag, tu, stream);
+}
+
+pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, int reps, pyst_tuning *out,
+                          double *best_ms) {
+  if (!ctx || !frags || nfrag <= 0 || !out) return set_error(PYST_ERR_ARG, "pyst_autotune: NULL argument");
+  if (reps < 1) reps = 1;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return set_error(PYST_ERR_HIP, "pyst_autotune: stream");
+  hipEvent_t a = nullptr, b = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  const int fanouts[] = {16, 32, 64, 128, 256};
+  const int blocks[] = {256, 512, 1024};
+  const double loads[] = {0.5, 0.7};
+  double best = 1e30;
+  pyst_tuning best_t{64, 512, 0.5};
+  pyst_status st = PYST_OK;
+  for (double ld : loads)
+    for (int bs : blocks)
+      for (int fo : fanouts) {
+        const pyst_tuning t{fo, bs, ld};
+        st = batch_run(ctx, frags, nfrag, t, s);  // warm-up
+        if (st != PYST_OK) break;
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < reps && st == PYST_OK; ++r) st = batch_run(ctx, frags, nfrag, t, s);
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (st == PYST_OK && ms / reps < best) {
+          best = ms / reps;
+          best_t = t;
+        }
+      }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
+  if (st != PYST_OK) return st;
+  *out = best_t;
+  if (best_ms) *best_ms = best;
+  return PYST_OK;
+}
+
+}  // extern "C"

@@ -38,6 +38,11 @@ struct pyst_ctx {
   std::vector<hipEvent_t> events;
   // optional per-kernel timing: name -> (start, stop) event pairs of each launch
   bool timing = false;
+  bool generic_only = false;  // PYST_OPT_GENERIC_ONLY
+  hipStream_t copy_stream = nullptr;  // host-to-device chunk copies (created on first use)
+  char *staging = nullptr;            // pinned host staging for descriptor uploads
+  size_t staging_bytes = 0;
+  hipEvent_t staging_done = nullptr;  // recorded after the last copy out of `staging`
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> timed;
 };
 
@@ -159,6 +164,41 @@ void ctx_free(pyst_ctx *c, void *p, hipStream_t stream) {
 }
 
 uint32_t *ctx_err_word(pyst_ctx *c) { return c->d_err; }
+bool ctx_generic_only(const pyst_ctx *c) { return c->generic_only; }
+
+// Bytes not currently allocated (free or pending reuse); an allocation of this
+// size may still fail when the space is fragmented.
+size_t ctx_budget_free(const pyst_ctx *c) { return c->budget - c->used; }
+
+// Pinned staging area for small host-to-device uploads; waits until the copy
+// issued from its previous contents has finished before handing it out again.
+char *ctx_pinned_staging(pyst_ctx *c, size_t bytes) {
+  if (c->staging_done) (void)hipEventSynchronize(c->staging_done);
+  if (bytes > c->staging_bytes) {
+    if (c->staging) (void)hipHostFree(c->staging);
+    c->staging = nullptr;
+    c->staging_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, size_t{1} << 20);
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->staging), want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    c->staging_bytes = want;
+  }
+  return c->staging;
+}
+
+hipError_t ctx_staging_record(pyst_ctx *c, hipStream_t stream) {
+  if (!c->staging_done) {
+    hipError_t e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(c->staging_done, stream);
+}
+
+hipStream_t ctx_copy_stream(pyst_ctx *c) {
+  if (!c->copy_stream &&
+      hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess)  // default priority
+    c->copy_stream = nullptr;
+  return c->copy_stream;
+}
 
 TimedRegion::TimedRegion(pyst_ctx *c, const char *name, hipStream_t s) : ctx(c), stream(s), label(name) {
   if (!c->timing) return;
@@ -230,12 +270,23 @@ void pyst_ctx_destroy(pyst_ctx *c) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+  if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+  if (c->staging) (void)hipHostFree(c->staging);
   if (c->base) (void)hipFree(c->base - kAlign);
   if (c->h_err) (void)hipHostFree(c->h_err);
   delete c;
 }
 
 size_t pyst_ctx_used(const pyst_ctx *c) { return c ? c->used : 0; }
+
+pyst_status pyst_ctx_option(pyst_ctx *c, int key, int64_t value) {
+  if (!c) return set_error(PYST_ERR_ARG, "pyst_ctx_option: ctx is NULL");
+  switch (key) {
+    case PYST_OPT_GENERIC_ONLY: c->generic_only = value != 0; return PYST_OK;
+  }
+  return set_error(PYST_ERR_ARG, "pyst_ctx_option: unknown option");
+}
 
 pyst_status pyst_ctx_timing(pyst_ctx *c, int enable) {
   if (!c) return set_error(PYST_ERR_ARG, "pyst_ctx_timing: ctx is NULL");

@@ -3,3 +3,7 @@
 #include "ctx.hip"
 #include "ops.hip"
 #include "query.hip"
+#include "fast.hip"
+#include "stream.hip"
+#include "batch.hip"
+#include "server.hip"

@@ -52,7 +52,41 @@ struct AggState {
   PairsOut po;
 };
 
+// Kernel arguments of the specialized fact pass (int32 keys and predicate
+// columns, group key from join keys / the payload of join 1).
+struct FastArgs {
+  const int32_t *fk[2];
+  const void *v0;
+  const int32_t *v1;
+  int32_t v0_64;
+  int32_t vexpr;
+  int64_t vconst;
+  int32_t npred;
+  int32_t psrc[2];  // 0: own column pcol, 1: fk[0], 2: fk[1], 3: v1
+  const int32_t *pcol[2];
+  int32_t pop[2];
+  int64_t pval[2];
+  int32_t hi_src, hi_idx, lo_src, lo_idx;
+  int64_t n;
+};
+
 pyst_status prepare_query(const pyst_plan *plan, const pyst_col *fact, int nfact, QueryShape *q);
+bool fast_shape(const pyst_plan *plan, const pyst_col *fact, const QueryShape &q, FastArgs *fa);
+pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const FastArgs &fa,
+                       int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                       hipStream_t stream);
+pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
+                                  int64_t *zero0, int64_t *zero1, hipStream_t stream);
+pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastArgs &a, const DimTables &d,
+                           const GroupDev &g, const PairsOut &po, hipStream_t stream);
+pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const DimTables &d, AggState *s,
+                        int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                        hipStream_t stream);
+bool ctx_generic_only(const pyst_ctx *ctx);
+hipStream_t ctx_copy_stream(pyst_ctx *ctx);
+char *ctx_pinned_staging(pyst_ctx *ctx, size_t bytes);
+size_t ctx_budget_free(const pyst_ctx *ctx);
+hipError_t ctx_staging_record(pyst_ctx *ctx, hipStream_t stream);
 pyst_status build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
                              hipStream_t stream);
 void free_dimensions(pyst_ctx *ctx, DimTables *d, hipStream_t stream);

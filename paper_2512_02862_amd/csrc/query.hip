@@ -547,6 +547,9 @@ extern "C" pyst_status pyst_query(pyst_ctx *ctx, const pyst_plan *plan, const py
   QueryShape q;
   pyst_status st = prepare_query(plan, fact, nfact, &q);
   if (st != PYST_OK) return st;
+  FastArgs fa;
+  if (!ctx_generic_only(ctx) && fast_shape(plan, fact, q, &fa))
+    return fast_query(ctx, plan, q, fa, out_keys, out_sums, out_cap, d_ngroups, stream);
   DimTables d;
   std::memset(&d, 0, sizeof(d));
   st = build_dimensions(ctx, plan, q, &d, stream);

@@ -1,0 +1,488 @@
+// Serving loop: continuous batching of queries over one fact table held in
+// pinned host memory.
+//
+// Structure after the paper's queue-based scheduling (Sec. 5.4): client
+// threads push requests into a multi-producer queue; one scheduler thread
+// consumes it and is the only thread that issues GPU work.  Admission is
+// regulated by device memory (Sec. 5.4, "Adaptive Regulation"): a request
+// starts only when its aggregation state fits in the server's arena, so load
+// beyond the budget waits in the queue instead of failing.  All active
+// requests share one circular scan of the fact table -- each chunk is copied
+// once and consumed by every request that still needs it, the analog of one
+// I/O pool serving every scan of a plan (Sec. 5.2, "Reader Combining").
+// Dimension tables are built once and stay resident for later requests.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pyst_internal.h"
+#include "query.h"
+#include "table.h"
+
+namespace pyst {
+
+__global__ void k_req_init(TableDev t, int64_t *d_ngroups) {
+  const int64_t cap = t.hdr[0];
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (tid == 0) *d_ngroups = 0;
+  if (t.sums)
+    for (int64_t i = tid; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+      t.sums[i] = 0;
+      t.flags[i] = 0;
+    }
+}
+
+// A deep copy of a plan (the caller's arrays may go away after submit).
+struct PlanCopy {
+  pyst_plan plan;
+  std::vector<pyst_pred> preds;
+  std::vector<pyst_pred> jpreds[2];
+  std::vector<pyst_col> jcols[2];
+  void take(const pyst_plan &p) {
+    plan = p;
+    preds.assign(p.preds, p.preds + std::max(0, p.npreds));
+    plan.preds = preds.data();
+    for (int j = 0; j < p.njoins && j < 2; ++j) {
+      jpreds[j].assign(p.joins[j].preds, p.joins[j].preds + std::max(0, p.joins[j].npreds));
+      jcols[j].assign(p.joins[j].cols, p.joins[j].cols + std::max(0, p.joins[j].ncols));
+      plan.joins[j].preds = jpreds[j].data();
+      plan.joins[j].cols = jcols[j].data();
+    }
+  }
+  std::string dim_signature() const {
+    std::string s;
+    char buf[160];
+    for (int j = 0; j < plan.njoins; ++j) {
+      const pyst_join_spec &js = plan.joins[j];
+      snprintf(buf, sizeof buf, "j%d:%p:%lld:%p:%g:", j, js.key.data, static_cast<long long>(js.key.n), js.payload.data,
+               js.max_load);
+      s += buf;
+      for (const auto &pr : jpreds[j]) {
+        const void *cp = pr.col >= 0 && pr.col < static_cast<int>(jcols[j].size()) ? jcols[j][pr.col].data : nullptr;
+        snprintf(buf, sizeof buf, "%p,%d,%lld;", cp, pr.cmp, static_cast<long long>(pr.value));
+        s += buf;
+      }
+    }
+    // payload needs depend on the group key
+    snprintf(buf, sizeof buf, "g%d,%d,%d,%d", plan.hi_src, plan.hi_index, plan.lo_src, plan.lo_index);
+    return s + buf;
+  }
+};
+
+struct DimEntry {
+  DimTables d;
+  hipEvent_t ready = nullptr;
+  int64_t cap_alloc0 = 0;
+};
+
+struct Request {
+  uint64_t id = 0;
+  PlanCopy pc;
+  int64_t rows = 0;
+  int64_t *out_keys = nullptr, *out_sums = nullptr, *d_ngroups = nullptr;
+  int64_t out_cap = 0;
+  QueryShape q;
+  int slot = -1;
+  DimEntry *dims = nullptr;
+  DimTables d;      // the cached tables with this request's own sums
+  AggState s;
+  void *sums_mem = nullptr;
+  int64_t nchunks = 0, remaining = 0;
+  std::vector<char> done;
+  hipEvent_t finish = nullptr;
+  std::chrono::steady_clock::time_point t_submit, t_done;
+  pyst_status status = PYST_OK;
+  bool completed = false;
+};
+
+}  // namespace pyst
+
+struct pyst_server {
+  pyst_ctx *ctx = nullptr;
+  pyst_server_cfg cfg{};
+  std::vector<pyst_col> fact;
+  int64_t fact_rows = 0;
+  size_t row_bytes = 0;
+  std::vector<hipStream_t> slots;
+  std::vector<int> slot_free;
+  // ring of chunk buffers
+  void *ring = nullptr;
+  std::vector<std::vector<char *>> buf;
+  std::vector<hipEvent_t> copied;
+  std::vector<std::vector<hipEvent_t>> users;  // events of the streams that consumed each buffer
+  int64_t next_ring = 0;
+  int64_t scan_pos = 0;
+  // queue and bookkeeping
+  std::mutex mu;
+  std::condition_variable cv_submit, cv_done;
+  std::deque<std::shared_ptr<pyst::Request>> pending;
+  std::unordered_map<uint64_t, std::shared_ptr<pyst::Request>> all;
+  std::vector<std::shared_ptr<pyst::Request>> active;
+  std::map<std::string, std::unique_ptr<pyst::DimEntry>> dim_cache;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread thr;
+  pyst_server_stats stats{};
+};
+
+namespace pyst {
+
+static double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// Aggregation-state bytes a request reserves while active (its admission cost).
+static size_t request_bytes(const pyst_server *sv, const Request &r) {
+  if (r.q.agg_mode == 0)
+    return table_capacity_host(r.pc.plan.joins[0].key.n, r.pc.plan.joins[0].max_load) * (sizeof(uint64_t) + 1) + 512;
+  const int64_t bound = std::min<int64_t>(r.pc.plan.max_groups, std::max<int64_t>(r.rows, 1));
+  (void)sv;
+  return group_bytes(table_capacity_host(bound, r.pc.plan.group_max_load)) + 256;
+}
+
+// Start a request: dimension tables (cached), own aggregation state, zeroed outputs.
+static bool admit(pyst_server *sv, const std::shared_ptr<Request> &r) {
+  const std::string sig = r->pc.dim_signature();
+  auto it = sv->dim_cache.find(sig);
+  hipStream_t st = sv->slots[r->slot];
+  if (it == sv->dim_cache.end()) {
+    auto e = std::make_unique<DimEntry>();
+    std::memset(&e->d, 0, sizeof(e->d));
+    pyst_status ps = fast_build_dimensions(sv->ctx, &r->pc.plan, r->q, &e->d, nullptr, nullptr, st);
+    if (ps != PYST_OK) {
+      free_dimensions(sv->ctx, &e->d, st);
+      if (ps == PYST_ERR_NOMEM) return false;  // retry once memory frees up
+      r->status = ps;
+      return true;
+    }
+    (void)hipEventCreateWithFlags(&e->ready, hipEventDisableTiming);
+    (void)hipEventRecord(e->ready, st);
+    it = sv->dim_cache.emplace(sig, std::move(e)).first;
+  }
+  r->dims = it->second.get();
+  (void)hipStreamWaitEvent(st, r->dims->ready, 0);
+  r->d = r->dims->d;
+  std::memset(&r->s, 0, sizeof(r->s));
+  if (r->q.agg_mode == 0) {
+    const int64_t cap = r->d.t[0].cap_alloc;
+    r->sums_mem = ctx_alloc(sv->ctx, static_cast<size_t>(cap) * (sizeof(uint64_t) + 1) + 256, st);
+    if (!r->sums_mem) return false;
+    r->d.t[0].sums = static_cast<uint64_t *>(r->sums_mem);
+    r->d.t[0].flags = reinterpret_cast<uint8_t *>(r->d.t[0].sums + cap);
+    k_req_init<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(cap, 256), 2048)), 256, 0, st>>>(r->d.t[0], r->d_ngroups);
+  } else {
+    const int64_t bound = std::min<int64_t>(r->pc.plan.max_groups, std::max<int64_t>(r->rows, 1));
+    const int64_t cap = table_capacity_host(bound, r->pc.plan.group_max_load);
+    r->s.mem = ctx_alloc(sv->ctx, group_bytes(cap), st);
+    if (!r->s.mem) return false;
+    r->s.g = group_view(r->s.mem, cap);
+    (void)group_init(r->s.g, nullptr, bound, 0, r->pc.plan.group_max_load, st);
+    TableDev t{};
+    t.hdr = r->d.t[0].hdr;
+    k_req_init<<<1, 64, 0, st>>>(t, r->d_ngroups);
+  }
+  r->nchunks = ceil_div(r->rows, sv->cfg.chunk_rows);
+  r->remaining = r->nchunks;
+  r->done.assign(static_cast<size_t>(r->nchunks), 0);
+  return true;
+}
+
+static void release(pyst_server *sv, Request &r) {
+  hipStream_t st = sv->slots[r.slot];
+  if (r.sums_mem) ctx_free(sv->ctx, r.sums_mem, st);
+  if (r.s.mem) ctx_free(sv->ctx, r.s.mem, st);
+  r.sums_mem = r.s.mem = nullptr;
+  sv->slot_free.push_back(r.slot);
+}
+
+// Copy chunk c once and run the fact pass of every active request needing it.
+static void serve_chunk(pyst_server *sv, int64_t c) {
+  const int b = static_cast<int>(sv->next_ring++ % sv->cfg.nbuf);
+  hipStream_t cs = ctx_copy_stream(sv->ctx);
+  for (hipEvent_t e : sv->users[b]) (void)hipStreamWaitEvent(cs, e, 0);
+  for (hipEvent_t e : sv->users[b]) (void)hipEventDestroy(e);
+  sv->users[b].clear();
+  const int64_t off = c * sv->cfg.chunk_rows;
+  int64_t need = 0;  // rows of this chunk that any active request reads
+  for (auto &r : sv->active)
+    if (c < r->nchunks && !r->done[c]) need = std::max(need, std::min(sv->cfg.chunk_rows, r->rows - off));
+  {
+    TimedRegion timed(sv->ctx, "h2d_chunk", cs);
+    for (size_t k = 0; k < sv->fact.size(); ++k) {
+      const size_t w = sv->fact[k].dtype == PYST_I64 ? 8 : 4;
+      (void)hipMemcpyAsync(sv->buf[b][k], static_cast<const char *>(sv->fact[k].data) + off * w,
+                           static_cast<size_t>(need) * w, hipMemcpyHostToDevice, cs);
+    }
+  }
+  (void)hipEventRecord(sv->copied[b], cs);
+  sv->stats.chunks_copied++;
+  sv->stats.bytes_copied += static_cast<double>(need) * sv->row_bytes;
+  std::vector<pyst_col> dev(sv->fact);
+  for (auto &r : sv->active) {
+    if (c >= r->nchunks || r->done[c] || r->status != PYST_OK) continue;
+    hipStream_t st = sv->slots[r->slot];
+    (void)hipStreamWaitEvent(st, sv->copied[b], 0);
+    const int64_t rows = std::min(sv->cfg.chunk_rows, r->rows - off);
+    for (size_t k = 0; k < dev.size(); ++k) {
+      dev[k].data = sv->buf[b][k];
+      dev[k].n = rows;
+    }
+    FastArgs fa;
+    fast_shape(&r->pc.plan, dev.data(), r->q, &fa);
+    pyst_status ps = fast_fact_pass(sv->ctx, r->pc.plan.njoins, r->q.agg_mode, fa, r->d, r->s.g, r->s.po, st);
+    if (ps != PYST_OK) r->status = ps;
+    hipEvent_t ev = nullptr;
+    (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    (void)hipEventRecord(ev, st);
+    sv->users[b].push_back(ev);
+    r->done[c] = 1;
+    r->remaining--;
+    sv->stats.fact_rows_processed += static_cast<double>(rows);
+  }
+}
+
+static void finish_ready(pyst_server *sv) {
+  for (auto &r : sv->active) {
+    if (r->finish || r->remaining > 0) continue;
+    hipStream_t st = sv->slots[r->slot];
+    if (r->status == PYST_OK)
+      r->status = fast_finish(sv->ctx, &r->pc.plan, r->q, r->d, &r->s, r->out_keys, r->out_sums, r->out_cap,
+                              r->d_ngroups, st);
+    (void)hipEventCreateWithFlags(&r->finish, hipEventDisableTiming);
+    (void)hipEventRecord(r->finish, st);
+  }
+}
+
+static void reap_done(pyst_server *sv) {
+  for (size_t i = 0; i < sv->active.size();) {
+    auto r = sv->active[i];
+    if (r->finish && hipEventQuery(r->finish) == hipSuccess) {
+      (void)hipEventDestroy(r->finish);
+      r->finish = nullptr;
+      r->t_done = std::chrono::steady_clock::now();
+      release(sv, *r);
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->completed = true;
+        sv->stats.completed++;
+      }
+      sv->cv_done.notify_all();
+      sv->active.erase(sv->active.begin() + static_cast<long>(i));
+    } else {
+      ++i;
+    }
+  }
+}
+
+static void scheduler(pyst_server *sv) {
+  (void)hipSetDevice(ctx_device(sv->ctx));
+  while (true) {
+    // admit while slots and memory allow (FIFO; the head blocks the rest)
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (sv->active.empty() && sv->pending.empty()) {
+        if (sv->stop) break;
+        sv->cv_submit.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+      while (!sv->pending.empty() && !sv->slot_free.empty()) {
+        auto r = sv->pending.front();
+        if (ctx_budget_free(sv->ctx) < request_bytes(sv, *r) && !sv->active.empty()) {
+          sv->stats.admission_waits++;
+          break;
+        }
+        r->slot = sv->slot_free.back();
+        sv->slot_free.pop_back();
+        lk.unlock();
+        const bool ok = admit(sv, r);
+        lk.lock();
+        if (!ok) {  // out of memory: wait for an active request to finish
+          sv->slot_free.push_back(r->slot);
+          r->slot = -1;
+          if (sv->active.empty()) {  // can never fit
+            sv->pending.pop_front();
+            r->status = PYST_ERR_NOMEM;
+            r->completed = true;
+            r->t_done = std::chrono::steady_clock::now();
+            sv->cv_done.notify_all();
+            continue;
+          }
+          sv->stats.admission_waits++;
+          break;
+        }
+        sv->pending.pop_front();
+        sv->active.push_back(r);
+        sv->stats.max_active_seen = std::max<int64_t>(sv->stats.max_active_seen, static_cast<int64_t>(sv->active.size()));
+      }
+    }
+    // next chunk of the circular scan that some active request still needs
+    int64_t maxc = 0;
+    for (auto &r : sv->active) maxc = std::max(maxc, r->nchunks);
+    int64_t pick = -1;
+    for (int64_t k = 0; k < maxc && pick < 0; ++k) {
+      const int64_t c = (sv->scan_pos + k) % maxc;
+      for (auto &r : sv->active)
+        if (c < r->nchunks && !r->done[c] && r->status == PYST_OK) {
+          pick = c;
+          break;
+        }
+    }
+    if (pick >= 0) {
+      serve_chunk(sv, pick);
+      sv->scan_pos = pick + 1;
+    }
+    finish_ready(sv);
+    reap_done(sv);
+    if (pick < 0 && !sv->active.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+}
+
+}  // namespace pyst
+
+using namespace pyst;
+
+extern "C" {
+
+pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pyst_col *host_fact, int nfact,
+                               pyst_server **out) {
+  if (!cfg || !host_fact || !out || nfact < 1 || nfact > PYST_MAX_COLS)
+    return set_error(PYST_ERR_ARG, "pyst_server_create: bad argument");
+  *out = nullptr;
+  if (cfg->max_active < 1 || cfg->max_active > 64 || cfg->nbuf < 2 || cfg->nbuf > 8 || cfg->chunk_rows < 4 ||
+      cfg->chunk_rows % 4 != 0 || cfg->chunk_rows >= (int64_t{1} << 31))
+    return set_error(PYST_ERR_ARG, "pyst_server_create: max_active 1..64, nbuf 2..8, chunk_rows a multiple of 4");
+  const int64_t n = host_fact[0].n;
+  for (int c = 0; c < nfact; ++c)
+    if (host_fact[c].n != n || !(host_fact[c].dtype == PYST_I32 || host_fact[c].dtype == PYST_I64) || !host_fact[c].data)
+      return set_error(PYST_ERR_ARG, "pyst_server_create: fact columns must be int32/int64 of equal length");
+  auto *sv = new pyst_server();
+  sv->cfg = *cfg;
+  sv->fact.assign(host_fact, host_fact + nfact);
+  sv->fact_rows = n;
+  for (int c = 0; c < nfact; ++c) sv->row_bytes += host_fact[c].dtype == PYST_I64 ? 8 : 4;
+  const size_t ring_bytes = static_cast<size_t>(cfg->nbuf) * cfg->chunk_rows * sv->row_bytes + 512 * nfact * cfg->nbuf;
+  pyst_status st = pyst_ctx_create(device, cfg->budget_bytes + ring_bytes, &sv->ctx);
+  if (st != PYST_OK) {
+    delete sv;
+    return st;
+  }
+  sv->ring = ctx_alloc(sv->ctx, ring_bytes, nullptr);
+  if (!sv->ring) {
+    pyst_ctx_destroy(sv->ctx);
+    delete sv;
+    return set_error(PYST_ERR_NOMEM, "pyst_server_create: chunk ring");
+  }
+  char *p = static_cast<char *>(sv->ring);
+  sv->buf.assign(cfg->nbuf, std::vector<char *>(nfact));
+  sv->copied.assign(cfg->nbuf, nullptr);
+  sv->users.assign(cfg->nbuf, {});
+  for (int b = 0; b < cfg->nbuf; ++b) {
+    (void)hipEventCreateWithFlags(&sv->copied[b], hipEventDisableTiming);
+    for (int c = 0; c < nfact; ++c) {
+      sv->buf[b][c] = p;
+      p += (static_cast<size_t>(cfg->chunk_rows) * (host_fact[c].dtype == PYST_I64 ? 8 : 4) + 255) / 256 * 256;
+    }
+  }
+  sv->slots.resize(cfg->max_active);
+  for (int i = 0; i < cfg->max_active; ++i) {
+    (void)hipStreamCreateWithFlags(&sv->slots[i], hipStreamNonBlocking);  // default priority
+    sv->slot_free.push_back(cfg->max_active - 1 - i);
+  }
+  sv->thr = std::thread(scheduler, sv);
+  *out = sv;
+  return PYST_OK;
+}
+
+pyst_status pyst_server_submit(pyst_server *sv, const pyst_request *req, uint64_t *ticket) {
+  if (!sv || !req || !req->plan || !ticket || !req->d_ngroups || req->rows < 0 || req->rows > sv->fact_rows ||
+      req->out_cap < 0 || (req->out_cap > 0 && (!req->out_keys || !req->out_sums)))
+    return set_error(PYST_ERR_ARG, "pyst_server_submit: bad request");
+  auto r = std::make_shared<Request>();
+  r->pc.take(*req->plan);
+  r->rows = req->rows;
+  r->out_keys = req->out_keys;
+  r->out_sums = req->out_sums;
+  r->out_cap = req->out_cap;
+  r->d_ngroups = req->d_ngroups;
+  std::vector<pyst_col> shape(sv->fact);
+  for (auto &c : shape) {
+    c.n = std::max<int64_t>(req->rows, 0);
+    c.data = reinterpret_cast<const void *>(uintptr_t{256});  // any aligned non-null address: shape checks only
+  }
+  pyst_status st = prepare_query(&r->pc.plan, shape.data(), static_cast<int>(shape.size()), &r->q);
+  if (st != PYST_OK) return st;
+  FastArgs fa;
+  if (!fast_shape(&r->pc.plan, shape.data(), r->q, &fa))
+    return set_error(PYST_ERR_UNSUPPORTED, "pyst_server_submit: plan shape cannot be served");
+  if (r->q.agg_mode == 2) return set_error(PYST_ERR_UNSUPPORTED, "pyst_server_submit: set plan->max_groups");
+  r->t_submit = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return set_error(PYST_ERR_ARG, "pyst_server_submit: server is stopping");
+    r->id = sv->next_id++;
+    sv->all[r->id] = r;
+    sv->pending.push_back(r);
+    sv->stats.submitted++;
+  }
+  sv->cv_submit.notify_one();
+  *ticket = r->id;
+  return PYST_OK;
+}
+
+pyst_status pyst_server_wait(pyst_server *sv, uint64_t ticket, double *latency_ms) {
+  if (!sv) return set_error(PYST_ERR_ARG, "pyst_server_wait: NULL server");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return set_error(PYST_ERR_ARG, "pyst_server_wait: unknown ticket");
+  auto r = it->second;
+  sv->cv_done.wait(lk, [&] { return r->completed; });
+  if (latency_ms) *latency_ms = ms_between(r->t_submit, r->t_done);
+  sv->all.erase(it);
+  if (r->status != PYST_OK) return set_error(r->status, "pyst_server_wait: request failed");
+  return PYST_OK;
+}
+
+pyst_status pyst_server_get_stats(pyst_server *sv, pyst_server_stats *out) {
+  if (!sv || !out) return set_error(PYST_ERR_ARG, "pyst_server_get_stats: NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  *out = sv->stats;
+  return PYST_OK;
+}
+
+pyst_status pyst_server_check(pyst_server *sv) {
+  if (!sv) return set_error(PYST_ERR_ARG, "pyst_server_check: NULL server");
+  (void)hipDeviceSynchronize();
+  return pyst_ctx_check(sv->ctx, nullptr);
+}
+
+void pyst_server_destroy(pyst_server *sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_submit.notify_all();
+  if (sv->thr.joinable()) sv->thr.join();
+  (void)hipDeviceSynchronize();
+  for (auto &kv : sv->dim_cache) {
+    free_dimensions(sv->ctx, &kv.second->d, nullptr);
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+  }
+  for (auto &u : sv->users)
+    for (hipEvent_t e : u) (void)hipEventDestroy(e);
+  for (hipEvent_t e : sv->copied) (void)hipEventDestroy(e);
+  for (hipStream_t s : sv->slots) (void)hipStreamDestroy(s);
+  pyst_ctx_destroy(sv->ctx);
+  delete sv;
+}
+
+}  // extern "C"

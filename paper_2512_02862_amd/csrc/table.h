@@ -25,6 +25,7 @@ struct TableDev {
   int64_t *hdr;    // [0] effective capacity, [1] rows offered for insertion
   uint64_t *sums;  // optional per-slot SUM (group by the join key), else null
   uint8_t *flags;  // optional per-slot "group exists" flags
+  uint32_t *bloom; // optional blocked Bloom filter over the inserted keys (fast path)
   int64_t cap_alloc;
   int32_t slot_bytes;
   int32_t reserved;

@@ -22,12 +22,15 @@ CMP = {"==": 0, "!=": 1, "<": 2, "<=": 3, ">": 4, ">=": 5}
 I32, I64 = 0, 1
 G_NONE, G_JOIN_KEY, G_JOIN_PAYLOAD, G_FACT_COL = 0, 1, 2, 3
 V_COL, V_COL_TIMES_C_MINUS = 0, 1
+OPT_GENERIC_ONLY = 1
 
 EXPORTS = [
     "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
     "pyst_last_error", "pyst_filter", "pyst_partition", "pyst_join_build", "pyst_join_probe",
     "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
-    "pyst_ctx_kernel_time",
+    "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
+    "pyst_server_create", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
+    "pyst_server_destroy",
 ]
 
 
@@ -60,6 +63,32 @@ class Plan(ctypes.Structure):
                 ("vconst", ctypes.c_int64), ("max_groups", ctypes.c_int64), ("group_max_load", ctypes.c_double)]
 
 
+class Fragment(ctypes.Structure):
+    _fields_ = [("plan", ctypes.POINTER(Plan)), ("fact", ctypes.POINTER(Col)), ("nfact", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("out_keys", ctypes.c_void_p), ("out_sums", ctypes.c_void_p),
+                ("out_cap", ctypes.c_int64), ("d_ngroups", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fanout", ctypes.c_int32), ("block", ctypes.c_int32), ("max_load", ctypes.c_double)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32), ("nbuf", ctypes.c_int32),
+                ("chunk_rows", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("plan", ctypes.POINTER(Plan)), ("rows", ctypes.c_int64), ("out_keys", ctypes.c_void_p),
+                ("out_sums", ctypes.c_void_p), ("out_cap", ctypes.c_int64), ("d_ngroups", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("chunks_copied", ctypes.c_int64),
+                ("admission_waits", ctypes.c_int64), ("max_active_seen", ctypes.c_int64),
+                ("bytes_copied", ctypes.c_double), ("fact_rows_processed", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -90,6 +119,16 @@ def load(path: str = LIB_PATH):
         "pyst_groupby_sum": ([p, P(Col), P(Col), p, p, i64, ctypes.c_double, p, p, p, i32, p], i32),
         "pyst_query": ([p, P(Plan), P(Col), i32, p, p, i64, p, p], i32),
         "pyst_ctx_timing": ([p, i32], i32),
+        "pyst_ctx_option": ([p, i32, i64], i32),
+        "pyst_query_streamed": ([p, P(Plan), P(Col), i32, i64, i32, p, p, i64, p, p], i32),
+        "pyst_query_batch": ([p, P(Fragment), i32, P(Tuning), p], i32),
+        "pyst_autotune": ([p, P(Fragment), i32, i32, P(Tuning), P(ctypes.c_double)], i32),
+        "pyst_server_create": ([i32, P(ServerCfg), P(Col), i32, P(p)], i32),
+        "pyst_server_submit": ([p, P(Request), P(ctypes.c_uint64)], i32),
+        "pyst_server_wait": ([p, ctypes.c_uint64, P(ctypes.c_double)], i32),
+        "pyst_server_get_stats": ([p, P(ServerStats)], i32),
+        "pyst_server_check": ([p], i32),
+        "pyst_server_destroy": ([p], None),
         "pyst_ctx_kernel_time": ([p, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
     }
     for name, (args, res) in sig.items():
@@ -157,6 +196,10 @@ class Ctx:
     def check(self, stream=None):
         """Synchronize the stream and raise on any error latched by a kernel."""
         _check(_lib.pyst_ctx_check(self.h, _stream(stream)))
+
+    def generic_only(self, enable: bool):
+        """Force pyst_query's generic fact pass (no plan-shape-specialized kernel)."""
+        _check(_lib.pyst_ctx_option(self.h, OPT_GENERIC_ONLY, int(bool(enable))))
 
     def timing(self, enable: bool):
         """Record HIP events around the library's timed kernels (see kernel_time)."""
@@ -345,6 +388,134 @@ def query(ctx: Ctx, plan: QueryPlan, fact, out_cap=None, stream=None):
     return ok, osum, ng
 
 
+def host_col(t: torch.Tensor) -> Col:
+    if t.is_cuda or not t.is_contiguous() or t.dtype not in (torch.int32, torch.int64):
+        raise ValueError("streamed fact columns are contiguous int32/int64 host tensors")
+    if not t.is_pinned():
+        raise ValueError("streamed fact columns must be in pinned host memory")
+    return Col(t.data_ptr(), t.numel(), I64 if t.dtype == torch.int64 else I32, 0)
+
+
+def query_streamed(ctx: Ctx, plan: QueryPlan, host_fact, chunk_rows: int, nbuf: int = 2, out_cap=None,
+                   stream=None):
+    """pyst_query over pinned host fact columns, streamed in chunks: (keys, sums, count int64[1])."""
+    host_fact = list(host_fact)
+    cp, keep = plan.to_c()
+    if out_cap is None:
+        out_cap = plan.joins[0]["key"].numel() if plan.hi is None and plan.lo == ("join_key", 0) \
+            and len(plan.joins) == 1 else max(plan.max_groups, 1)
+    ok = torch.empty(max(out_cap, 1), dtype=torch.int64, device=_dev(ctx))
+    osum = torch.empty(max(out_cap, 1), dtype=torch.int64, device=_dev(ctx))
+    ng = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+    farr = (Col * len(host_fact))(*[host_col(t) for t in host_fact])
+    _check(_lib.pyst_query_streamed(ctx.h, ctypes.byref(cp), farr, len(host_fact), int(chunk_rows), int(nbuf),
+                                    _ptr(ok), _ptr(osum), int(out_cap), _ptr(ng), _stream(stream)))
+    del keep
+    return ok, osum, ng
+
+
+class Batch:
+    """A batch of independent star fragments with preallocated outputs.
+
+    fragments: list of (plan, fact columns); outputs get the dimension's row
+    count as capacity.  run() enqueues pyst_query_batch; results() reads back.
+    """
+
+    def __init__(self, ctx: Ctx, fragments):
+        self.ctx = ctx
+        self._keep = []
+        n = len(fragments)
+        self.arr = (Fragment * max(n, 1))()
+        self.outs = []
+        for i, (plan, fact) in enumerate(fragments):
+            cp, keep = plan.to_c()
+            cp = ctypes.pointer(cp)
+            farr = (Col * len(fact))(*[col(t) for t in fact])
+            cap = plan.joins[0]["key"].numel()
+            ok = torch.empty(max(cap, 1), dtype=torch.int64, device=_dev(ctx))
+            osum = torch.empty(max(cap, 1), dtype=torch.int64, device=_dev(ctx))
+            ng = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+            self._keep += [cp, keep, farr, fact]
+            self.outs.append((ok, osum, ng))
+            self.arr[i] = Fragment(cp, ctypes.cast(farr, ctypes.POINTER(Col)), len(fact), 0, ok.data_ptr(),
+                                   osum.data_ptr(), cap, ng.data_ptr())
+        self.n = n
+
+    def run(self, tuning=None, stream=None):
+        t = ctypes.byref(Tuning(*tuning)) if tuning is not None else None
+        _check(_lib.pyst_query_batch(self.ctx.h, self.arr, self.n, t, _stream(stream)))
+
+    def autotune(self, reps=2):
+        t, ms = Tuning(), ctypes.c_double()
+        _check(_lib.pyst_autotune(self.ctx.h, self.arr, self.n, reps, ctypes.byref(t), ctypes.byref(ms)))
+        return (t.fanout, t.block, t.max_load), ms.value
+
+    def results(self):
+        out = []
+        for ok, osum, ng in self.outs:
+            m = int(ng.item())
+            out.append((ok[:m], osum[:m]))
+        return out
+
+
+class Server:
+    """pyst_server: continuous batching over a pinned host fact table.
+
+    submit(plan, rows, out_cap) -> ticket (outputs allocated here);
+    wait(ticket) -> (keys, sums, latency_ms).
+    """
+
+    def __init__(self, host_fact, budget=4 << 30, max_active=8, nbuf=3, chunk_rows=1 << 24, device=0):
+        load()
+        self.host_fact = list(host_fact)
+        self.device = device
+        self._cols = (Col * len(self.host_fact))(*[host_col(t) for t in self.host_fact])
+        cfg = ServerCfg(budget, max_active, nbuf, chunk_rows)
+        h = ctypes.c_void_p()
+        _check(_lib.pyst_server_create(device, ctypes.byref(cfg), self._cols, len(self.host_fact), ctypes.byref(h)))
+        self.h = h
+        self._live = {}
+
+    def submit(self, plan: QueryPlan, rows: int, out_cap: int):
+        cp, keep = plan.to_c()
+        d = torch.device("cuda", self.device)
+        ok = torch.empty(max(out_cap, 1), dtype=torch.int64, device=d)
+        osum = torch.empty(max(out_cap, 1), dtype=torch.int64, device=d)
+        ng = torch.empty(1, dtype=torch.int64, device=d)
+        req = Request(ctypes.pointer(cp), int(rows), ok.data_ptr(), osum.data_ptr(), int(out_cap), ng.data_ptr())
+        t = ctypes.c_uint64()
+        _check(_lib.pyst_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = (ok, osum, ng, plan)  # plan holds the dimension tensors alive
+        del keep
+        return t.value
+
+    def wait(self, ticket):
+        lat = ctypes.c_double()
+        _check(_lib.pyst_server_wait(self.h, ticket, ctypes.byref(lat)))
+        ok, osum, ng, _ = self._live.pop(ticket)
+        m = int(ng.item())
+        return ok[:m], osum[:m], lat.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(_lib.pyst_server_get_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def check(self):
+        _check(_lib.pyst_server_check(self.h))
+
+    def close(self):
+        if self.h:
+            _lib.pyst_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------------------ plans of the measured workloads
 
 def star_plan(build, seg_eq=1, date_lt=1200, max_load=0.5):
@@ -356,6 +527,15 @@ def star_plan(build, seg_eq=1, date_lt=1200, max_load=0.5):
         joins=[{"key": build["key"], "payload": None, "cols": [build["key"], build["segment"]],
                 "preds": [(1, "==", seg_eq)], "probe_col": 0, "max_load": max_load}],
         preds=[(1, "<", date_lt)], lo=("join_key", 0), value=("col", 2))
+
+
+def fact_star_plan(b, seg_eq=1, date_lt=1200, max_load=0.5):
+    """The star query over the chain's fact columns [a_fk, b_fk, date, price, discount]:
+    fact JOIN B ON b_fk = B.key WHERE B.segment == seg_eq AND date < date_lt GROUP BY B.key SUM(price)."""
+    return QueryPlan(
+        joins=[{"key": b["key"], "payload": None, "cols": [b["key"], b["segment"]], "preds": [(1, "==", seg_eq)],
+                "probe_col": 1, "max_load": max_load}],
+        preds=[(2, "<", date_lt)], lo=("join_key", 0), value=("col", 3))
 
 
 def chain_plan(a, b, seg_eq=1, date_lt=1200, max_load=0.5, group_max_load=0.5, max_groups=0):

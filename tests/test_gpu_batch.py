@@ -1,0 +1,89 @@
+"""GPU parity of batched fragment execution: every fragment of a batch gets
+exactly its one-at-a-time pyst_query result and the oracle's, under every
+tuning of the autotuner's grid."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = gpu.Ctx(0, 4 << 30)
+    yield c
+    c.close()
+
+
+def make_fragments(gpu, nfrag, lo=1e3, hi=2e5):
+    sizes, builds = gen.fragment_sizes(nfrag, lo=lo, hi=hi)
+    frags, host = [], []
+    for f, (p, b) in enumerate(zip(sizes, builds)):
+        bt, pt = gen.star_tables(max(int(b), 1), int(p), workload=3, fragment=f)
+        bd = {k: dev(v) for k, v in bt.items()}
+        fact = [dev(pt[c]) for c in ("fk", "date", "price")]
+        frags.append((gpu.star_plan(bd), fact))
+        host.append((bt, pt))
+    return frags, host
+
+
+def sorted_np(k, s):
+    k, s = k.cpu().numpy(), s.cpu().numpy()
+    o = np.argsort(k)
+    return k[o], s[o]
+
+
+@pytest.mark.parametrize("tuning", [None, (16, 256, 0.5), (256, 1024, 0.7), (64, 512, 0.5), (1, 256, 0.0)])
+def test_batch_matches_oracle(gpu, ctx, tuning):
+    frags, host = make_fragments(gpu, 40)
+    batch = gpu.Batch(ctx, frags)
+    batch.run(tuning)
+    ctx.check()
+    for (k, s), (bt, pt) in zip(batch.results(), host):
+        wk, ws = oracle.star_query(bt, pt)
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, wk)
+        np.testing.assert_array_equal(gs, ws)
+
+
+def test_batch_equals_one_at_a_time_and_autotune(gpu, ctx):
+    frags, host = make_fragments(gpu, 24, lo=1e4, hi=1e6)
+    batch = gpu.Batch(ctx, frags)
+    best, ms = batch.autotune(reps=1)
+    assert best[1] in (256, 512, 1024) and best[2] in (0.5, 0.7) and best[0] in (16, 32, 64, 128, 256)
+    assert ms > 0
+    batch.run(best)
+    ctx.check()
+    for (k, s), (plan, fact) in zip(batch.results(), frags):
+        r = gpu.query(ctx, plan, fact)
+        ctx.check()
+        m = int(r[2].item())
+        ak, asum = sorted_np(r[0][:m], r[1][:m])
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, ak)
+        np.testing.assert_array_equal(gs, asum)
+
+
+def test_batch_with_empty_fragments(gpu, ctx):
+    frags, host = make_fragments(gpu, 6)
+    bt, pt = gen.star_tables(1, 0, workload=3, fragment=99)  # empty fact table
+    import torch
+    frags.insert(2, (gpu.star_plan({k: dev(v) for k, v in bt.items()}),
+                     [torch.empty(0, dtype=torch.int32, device="cuda"), torch.empty(0, dtype=torch.int32, device="cuda"),
+                      torch.empty(0, dtype=torch.int64, device="cuda")]))
+    host.insert(2, (bt, pt))
+    batch = gpu.Batch(ctx, frags)
+    batch.run((32, 256, 0.5))
+    ctx.check()
+    for (k, s), (bt, pt) in zip(batch.results(), host):
+        wk, ws = oracle.star_query(bt, pt)
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, wk)
+        np.testing.assert_array_equal(gs, ws)

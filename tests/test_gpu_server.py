@@ -1,0 +1,117 @@
+"""GPU tests of the serving loop: every request's result equals the oracle's on
+its fact prefix, equals its result when served alone, and admission control
+keeps load beyond the memory budget waiting instead of failing."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+COLS = ("a_fk", "b_fk", "date", "price", "discount")
+NA, NB, NF = 30_000, 3_000, 3_000_000
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def db():
+    import torch
+    a, b = gen.chain_dims(NA, NB)
+    f = gen.chain_fact(NF, NA, NB, 0.0)
+    host = [torch.from_numpy(f[c]).pin_memory() for c in COLS]
+    return a, b, f, host, {k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()}
+
+
+def expected(kind, a, b, f, rows):
+    pref = {c: v[:rows] for c, v in f.items()}
+    if kind == "star":
+        return oracle.star_query(b, {"fk": pref["b_fk"], "date": pref["date"], "price": pref["price"]})
+    return oracle.chain_query(a, b, pref)
+
+
+def plan_for(gpu, kind, ad, bd):
+    if kind == "star":
+        return gpu.fact_star_plan(bd), NB
+    return gpu.chain_plan(ad, bd, max_groups=400_000), 400_000
+
+
+def sorted_np(k, s):
+    k, s = k.cpu().numpy(), s.cpu().numpy()
+    o = np.argsort(k)
+    return k[o], s[o]
+
+
+def test_server_mix_matches_oracle_and_alone(gpu, db):
+    a, b, f, host, ad, bd = db
+    rng = np.random.default_rng(5)
+    reqs = [("star" if i % 2 == 0 else "chain", int(rng.integers(1, NF + 1))) for i in range(12)]
+    reqs[3] = ("chain", NF)
+    srv = gpu.Server(host, budget=1 << 30, max_active=6, nbuf=3, chunk_rows=250_000)
+    tickets = []
+    for kind, rows in reqs:
+        plan, cap = plan_for(gpu, kind, ad, bd)
+        tickets.append(srv.submit(plan, rows, cap))
+    mixed = [srv.wait(t) for t in tickets]
+    srv.check()
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["max_active_seen"] > 1
+    # the shared scan copied fewer chunks than private scans would have
+    assert st["chunks_copied"] < sum(-(-r // 250_000) for _, r in reqs)
+    srv.close()
+    alone_srv = gpu.Server(host, budget=1 << 30, max_active=1, nbuf=2, chunk_rows=250_000)
+    for (kind, rows), (k, s, lat) in zip(reqs, mixed):
+        assert lat > 0
+        got = sorted_np(k, s)
+        wk, ws = expected(kind, a, b, f, rows)
+        np.testing.assert_array_equal(got[0], wk)
+        np.testing.assert_array_equal(got[1], ws)
+    for kind, rows in reqs[:4]:
+        plan, cap = plan_for(gpu, kind, ad, bd)
+        k, s, _ = alone_srv.wait(alone_srv.submit(plan, rows, cap))
+        got = sorted_np(k, s)
+        wk, ws = expected(kind, a, b, f, rows)
+        np.testing.assert_array_equal(got[0], wk)
+        np.testing.assert_array_equal(got[1], ws)
+    alone_srv.check()
+    alone_srv.close()
+
+
+def test_server_admission_waits_for_memory(gpu, db):
+    a, b, f, host, ad, bd = db
+    # each chain request reserves a 400k-group table (~16 MiB); a ~40 MiB budget admits two at a time
+    srv = gpu.Server(host, budget=40 << 20, max_active=8, nbuf=2, chunk_rows=500_000)
+    plan, cap = plan_for(gpu, "chain", ad, bd)
+    tickets = [srv.submit(plan, NF - 1000 * i, cap) for i in range(6)]
+    res = [srv.wait(t) for t in tickets]
+    srv.check()
+    st = srv.stats()
+    assert st["admission_waits"] > 0 and st["max_active_seen"] <= 3
+    for i, (k, s, _) in enumerate(res):
+        got = sorted_np(k, s)
+        wk, ws = expected("chain", a, b, f, NF - 1000 * i)
+        np.testing.assert_array_equal(got[0], wk)
+        np.testing.assert_array_equal(got[1], ws)
+    srv.close()
+
+
+def test_server_rejects_request_that_cannot_fit(gpu, db):
+    a, b, f, host, ad, bd = db
+    srv = gpu.Server(host, budget=8 << 20, max_active=2, nbuf=2, chunk_rows=500_000)
+    plan, cap = plan_for(gpu, "chain", ad, bd)
+    t = srv.submit(plan, NF, cap)
+    with pytest.raises(gpu.PystError) as e:
+        srv.wait(t)
+    assert e.value.status == gpu.ERR_NOMEM
+    # a request that fits is still served afterwards
+    plan, cap = plan_for(gpu, "star", ad, bd)
+    k, s, _ = srv.wait(srv.submit(plan, 100_000, cap))
+    got = sorted_np(k, s)
+    wk, ws = expected("star", a, b, f, 100_000)
+    np.testing.assert_array_equal(got[0], wk)
+    np.testing.assert_array_equal(got[1], ws)
+    srv.close()
