@@ -81,7 +81,23 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the partition and chain measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=30_000_000)
+    ap.add_argument("--stream-rows", type=int, default=240_000_000, help="chain fact rows streamed from pinned host")
+    ap.add_argument("--batch-fragments", type=int, default=512)
+    ap.add_argument("--batch-max-rows", type=float, default=2e7, help="largest fragment probe size")
+    ap.add_argument("--serve-rows", type=int, default=512_000_000, help="pinned host fact rows of the server")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 5}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the shuffle stops at the "
               "partitioned per-destination buffers); run with --gpus 1", file=sys.stderr)
@@ -102,7 +118,7 @@ def main():
     b = to_dev(b_host)
     p = to_dev(p_host)
     fact = [p["fk"], p["date"], p["price"]]
-    ctx = pyst.Ctx(0, 8 << 30)
+    ctx = pyst.Ctx(0, 16 << 30)
     plan = pyst.star_plan(b, max_load=args.max_load)
     out_cap = nb
     keys = torch.empty(out_cap, dtype=torch.int64, device="cuda")
@@ -168,6 +184,12 @@ def main():
         del b, p, fact
         torch.cuda.empty_cache()
         result["chain"] = bench_chain(ctx, pyst, gen, log)
+        torch.cuda.empty_cache()
+        result["stream"] = bench_stream(ctx, pyst, gen, log, args.stream_rows)
+        torch.cuda.empty_cache()
+        result["batch"] = bench_batch(ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
+        torch.cuda.empty_cache()
+        result["serve"] = bench_serve(pyst, gen, log, args.serve_rows, args.serve_requests)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(b_host, p_host, args.cpu_sample_rows, log)
@@ -239,6 +261,183 @@ def bench_chain(ctx, pyst, gen, log):
         del f, fact, k, s
         torch.cuda.empty_cache()
     return out
+
+
+def pinned_empty(n, dtype):
+    import torch
+    return torch.empty(n, dtype=dtype, pin_memory=True)
+
+
+def chain_fact_pinned(gen, n, na, nb, zs):
+    """Chain fact columns generated straight into pinned host tensors."""
+    import torch
+    cols = {"a_fk": torch.int32, "b_fk": torch.int32, "date": torch.int32, "price": torch.int64,
+            "discount": torch.int32}
+    t = {c: pinned_empty(n, d) for c, d in cols.items()}
+    gen.chain_fact(n, na, nb, zs, out={c: v.numpy() for c, v in t.items()})
+    return [t[c] for c in ("a_fk", "b_fk", "date", "price", "discount")]
+
+
+def h2d_peak(host_t, log):
+    """Plain pinned host-to-device copy rate of a large buffer (GB/s)."""
+    import torch
+    d = torch.empty(host_t.numel(), dtype=host_t.dtype, device="cuda")
+    d.copy_(host_t, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        d.copy_(host_t, non_blocking=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    gbs = host_t.numel() * host_t.element_size() / dt / 1e9
+    log("pinned H2D copy: %.1f GB/s" % gbs)
+    return gbs
+
+
+def bench_stream(ctx, pyst, gen, log, nrows):
+    """Chain query over a pinned host fact table streamed in 64M-row chunks, double-buffered."""
+    import torch
+    na, nbd = 3_000_000, 300_000
+    a_h, b_h = gen.chain_dims(na, nbd)
+    a, b = to_dev(a_h), to_dev(b_h)
+    log("stream: generating %d pinned fact rows" % nrows)
+    host = chain_fact_pinned(gen, nrows, na, nbd, 0.0)
+    peak = h2d_peak(host[3], log)
+    plan = pyst.chain_plan(a, b, max_groups=min(nrows // 8, 150_000_000))
+    chunk = 64_000_000
+    out = {}
+    for nbuf in (2, 3):
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        k, s, ng = pyst.query_streamed(ctx, plan, host, chunk_rows=chunk, nbuf=nbuf, out_cap=plan.max_groups)
+        ctx.check()
+        dt = time.perf_counter() - t0
+        ctx.timing(False)
+        copy_ms, copies = ctx.kernel_time("h2d_chunk")
+        fact_ms, _ = ctx.kernel_time("fact_pass")
+        gbs = nrows * 24 / dt / 1e9
+        out["nbuf%d" % nbuf] = {"seconds": dt, "fact_rows_per_s": nrows / dt, "h2d_gbs": gbs,
+                                "frac_of_pinned_h2d": gbs / peak, "copy_busy_ms": copy_ms,
+                                "compute_busy_ms": fact_ms, "chunks": copies, "groups": int(ng.item())}
+        del k, s
+    out.update({"rows": nrows, "chunk_rows": chunk, "pinned_h2d_peak_gbs": peak,
+                "workload": "chain query, fact %d rows (24 B/row) in pinned host memory" % nrows})
+    del host
+    return out
+
+
+def bench_batch(ctx, pyst, gen, log, nfrag, max_rows):
+    """512 star fragments in one batch vs one at a time (each read back, as a sizing caller must)."""
+    import torch
+    sizes, builds = gen.fragment_sizes(nfrag, hi=max_rows)
+    log("batch: generating %d fragments, %d probe rows" % (nfrag, int(sizes.sum())))
+    frags = []
+    for f, (p, b) in enumerate(zip(sizes, builds)):
+        bt, pt = gen.star_tables(max(int(b), 1), int(p), workload=3, fragment=f)
+        bd = to_dev(bt)
+        frags.append((pyst.star_plan(bd), [torch.from_numpy(pt[c]).cuda() for c in ("fk", "date", "price")]))
+    batch = pyst.Batch(ctx, frags)
+    best, best_ms = batch.autotune(reps=2)
+    log("autotune best %s: %.3f ms" % (best, best_ms))
+    batch.run(best)
+    ctx.check()
+    el = timed_loop(lambda: batch.run(best), 5, 0)
+    batched_s = el / 5
+
+    def one_at_a_time():
+        for plan, fact in frags:
+            k, s, ng = pyst.query(ctx, plan, fact)
+            int(ng.item())
+
+    one_at_a_time()
+    t0 = time.perf_counter()
+    one_at_a_time()
+    seq_s = time.perf_counter() - t0
+    # results of the two executions agree fragment by fragment
+    res = batch.results()
+    mismatches = 0
+    for (k, s), (plan, fact) in zip(res, frags):
+        r = pyst.query(ctx, plan, fact)
+        m = int(r[2].item())
+        if m != k.numel() or not torch.equal(torch.sort(k).values, torch.sort(r[0][:m]).values):
+            mismatches += 1
+    total_rows = int(sizes.sum())
+    return {"fragments": nfrag, "probe_rows": total_rows, "tuning": {"fanout": best[0], "block": best[1],
+            "max_load": best[2]}, "batched_ms": batched_s * 1e3, "sequential_ms": seq_s * 1e3,
+            "batched_fragments_per_s": nfrag / batched_s, "sequential_fragments_per_s": nfrag / seq_s,
+            "speedup": seq_s / batched_s, "batched_probe_rows_per_s": total_rows / batched_s,
+            "batched_gbs": total_rows * 16 / batched_s / 1e9, "result_mismatches": mismatches}
+
+
+def bench_serve(pyst, gen, log, nrows, nreq):
+    """Poisson stream of star/chain requests over a pinned host fact table: continuous batching
+    (shared scan, up to 8 active) vs one-at-a-time FIFO on the same trace."""
+    import threading
+
+    import numpy as np
+    import torch
+    na, nbd = 3_000_000, 300_000
+    a_h, b_h = gen.chain_dims(na, nbd)
+    a, b = to_dev(a_h), to_dev(b_h)
+    log("serve: generating %d pinned fact rows" % nrows)
+    host = chain_fact_pinned(gen, nrows, na, nbd, 0.0)
+    rows = np.minimum(gen.loguniform_i64(nreq, 1e6, nrows, gen.seed(4, 7, 0)), nrows)
+    kinds = ["star" if i % 2 == 0 else "chain" for i in range(nreq)]
+
+    def plan_for(kind, r):
+        if kind == "star":
+            return pyst.fact_star_plan(b), nbd
+        g = int(min(max(r // 8, 1024), 150_000_000))
+        return pyst.chain_plan(a, b, max_groups=g), g
+
+    def run(max_active, arrivals):
+        srv = pyst.Server(host, budget=48 << 30, max_active=max_active, nbuf=3, chunk_rows=32_000_000)
+        # warm the resident dimension tables outside the trace
+        for kind in ("star", "chain"):
+            p, c = plan_for(kind, 1_000_000)
+            srv.wait(srv.submit(p, 1_000_000, c))
+        t_start = time.perf_counter()
+        tickets = [None] * nreq
+
+        def producer():
+            for i in range(nreq):
+                delay = t_start + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                p, c = plan_for(kinds[i], int(rows[i]))
+                tickets[i] = srv.submit(p, int(rows[i]), c)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        lat = []
+        for i in range(nreq):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            lat.append(srv.wait(tickets[i])[2])
+        th.join()
+        makespan = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.check()
+        srv.close()
+        lat = np.array(lat)
+        return {"p50_ms": float(np.percentile(lat, 50, method="nearest")),
+                "p99_ms": float(np.percentile(lat, 99, method="nearest")),
+                "mean_ms": float(lat.mean()), "makespan_s": makespan,
+                "requests_per_s": nreq / makespan, "rows_per_s": float(rows.sum()) / makespan,
+                "chunks_copied": st["chunks_copied"], "h2d_gb": st["bytes_copied"] / 1e9,
+                "max_active_seen": st["max_active_seen"], "admission_waits": st["admission_waits"]}
+
+    # service rate of one-at-a-time execution, from a back-to-back burst
+    burst = run(1, np.zeros(nreq))
+    lam = 0.9 * burst["requests_per_s"]
+    arrivals = gen.poisson_arrivals(nreq, lam, gen.seed(4, 8, 0))
+    log("serve: Poisson rate %.2f req/s (0.9 x one-at-a-time capacity)" % lam)
+    fifo = run(1, arrivals)
+    cont = run(8, arrivals)
+    del host
+    return {"fact_rows": nrows, "requests": nreq, "arrival_rate_per_s": lam, "one_at_a_time": fifo,
+            "continuous_batching": cont, "burst_one_at_a_time": burst,
+            "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]" % nrows}
 
 
 def cpu_baseline(b_host, p_host, sample_rows, log):

@@ -348,11 +348,12 @@ pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, 
    multi-producer queue; one scheduler thread issues all GPU work.  It admits
    requests while stream slots and device memory allow (adaptive regulation:
    excess load waits in the queue), keeps built dimension tables resident
-   across requests, and runs every active request on one shared circular scan
-   of the fact table -- each chunk is copied to the device once and consumed
-   by every active request that still needs it (the reader combining of
-   Sec. 5.2).  Requests arriving while others run join the scan at its current
-   position (continuous batching).  max_active = 1 gives one-at-a-time FIFO
+   across requests, and runs every active request on one shared scan of the
+   fact table -- the next chunk is the lowest one the oldest active request
+   still needs; it is copied to the device once and consumed by every active
+   request that needs it (the reader combining of Sec. 5.2).  Requests
+   arriving while others run are admitted at once and ride along on the shared
+   chunks (continuous batching).  max_active = 1 gives one-at-a-time FIFO
    service over the same machinery. */
 typedef struct pyst_server pyst_server;
 

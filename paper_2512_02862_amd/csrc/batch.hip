@@ -66,12 +66,16 @@ __global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const 
   __shared__ int32_t s_cnt[NW];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = local * kDimTile + int64_t{w} * kWave * ITEMS;
+  int64_t rows[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
+  bool keep[ITEMS];
+  eval_preds_items<ITEMS>(fr.bpred, rows, fr.nb, keep);
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    const int64_t row = wbase + int64_t{j} * kWave + lane;
-    m[j] = __ballot(row < fr.nb && eval_preds(fr.bpred, row));
+    m[j] = __ballot(keep[j]);
     c += __popcll(m[j]);
   }
   if (lane == 0) s_cnt[w] = c;
@@ -132,14 +136,10 @@ __global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const i
     int64_t s = (table_hash32(k) & mask) & ~int64_t{3};
     bool done = false;
     for (int64_t step = 0; step <= mask; ++step) {
-      int32_t cur = keys[s];
+      const int32_t cur = atomicCAS(&keys[s], kEmpty32, k);  // fresh table: CAS first
       if (cur == kEmpty32) {
-        const int32_t old = atomicCAS(&keys[s], kEmpty32, k);
-        if (old == kEmpty32) {
-          done = true;
-          break;
-        }
-        cur = old;
+        done = true;
+        break;
       }
       if (cur == k) {
         latch(err, kErrDup);
@@ -163,27 +163,59 @@ __global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int
 
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
   PYST_BLOCK_FRAG(kPreCompact)
+  // whole tiles per block, one counter atomic per tile
+  constexpr int ITEMS = 8, NW = 256 / kWave;
+  constexpr int64_t TILE = 256 * ITEMS;
+  __shared__ int32_t s_cnt[NW];
+  __shared__ int64_t s_base;
   const TableDev &t = fr.t;
   const int64_t cap = t.hdr[0];
-  for (int64_t s0 = local * 256; s0 < cap; s0 += nloc * 256) {
-    const int64_t s = s0 + threadIdx.x;
-    const bool keep = s < cap && t.flags[s] != 0;
-    const uint64_t m = __ballot(keep);
-    if (!m) continue;
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    unsigned long long wb = 0;
-    if (lane_id() == leader)
-      wb = atomicAdd(reinterpret_cast<unsigned long long *>(fr.d_ngroups), static_cast<unsigned long long>(__popcll(m)));
-    wb = __shfl(wb, leader);
-    if (keep) {
-      const int64_t p = static_cast<int64_t>(wb) + mbcnt(m);
-      if (p < fr.out_cap) {
-        fr.out_keys[p] = static_cast<const int32_t *>(t.slots)[s];
-        fr.out_sums[p] = static_cast<int64_t>(t.sums[s]);
-      } else {
-        latch(err, kErrCapacity);
-      }
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int64_t tile = local; tile * TILE < cap; tile += nloc) {  // block-uniform
+    const int64_t wbase = tile * TILE + int64_t{w} * kWave * ITEMS;
+    bool keep[ITEMS];
+    int64_t key[ITEMS], sum[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int64_t s = wbase + int64_t{j} * kWave + lane;
+      const int64_t sc = s < cap ? s : cap - 1;
+      keep[j] = t.flags[sc] != 0 && s < cap;
+      key[j] = static_cast<const int32_t *>(t.slots)[sc];
+      sum[j] = static_cast<int64_t>(t.sums[sc]);
     }
+    uint64_t m[ITEMS];
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      m[j] = __ballot(keep[j]);
+      c += __popcll(m[j]);
+    }
+    if (lane == 0) s_cnt[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int k = 0; k < NW; ++k) tot += s_cnt[k];
+      s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(fr.d_ngroups),
+                                                    static_cast<unsigned long long>(tot)))
+                   : 0;
+    }
+    __syncthreads();
+    int64_t pos = s_base;
+    for (int k = 0; k < w; ++k) pos += s_cnt[k];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (keep[j]) {
+        const int64_t p = pos + mbcnt(m[j]);
+        if (p < fr.out_cap) {
+          fr.out_keys[p] = key[j];
+          fr.out_sums[p] = sum[j];
+        } else {
+          latch(err, kErrCapacity);
+        }
+      }
+      pos += __popcll(m[j]);
+    }
+    __syncthreads();
   }
 }
 
@@ -240,7 +272,7 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
     const int64_t blocks[kPreKinds] = {
         b.nblk,
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus)),
-        std::max<int64_t>(1, std::min<int64_t>(ceil_div(b.nb, 256 * 4), 4 * cus)),
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(b.nb, 256), 16 * cus)),
         ceil_div(std::max<int64_t>(fa.n, 1), b.rows_per_unit),
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus))};
     for (int k = 0; k < kPreKinds; ++k) bp->pre[k * (nfrag + 1) + f + 1] = bp->pre[k * (nfrag + 1) + f] + blocks[k];

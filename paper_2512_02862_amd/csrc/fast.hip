@@ -28,11 +28,12 @@ namespace pyst {
 
 #define PYST_GLOBAL __attribute__((address_space(1)))
 
-constexpr int kBloomLgw = 14;                       // 2^14 words = 64 KiB of LDS
+constexpr int kBloomLgw = 15;                       // 2^15 words = 128 KiB of LDS
+constexpr int64_t kPairRun = 2048;                  // pair slots a wave reserves at a time
 constexpr int kBloomWords = 1 << kBloomLgw;
 constexpr int64_t kBloomMaxKeys = (int64_t{32} << kBloomLgw) * 2 / 3;  // above this the filter passes almost all
 constexpr int kDimTile = 4096;                      // rows per block of the dimension filter
-constexpr int kFastBlock = 1024;                    // 2 blocks of 16 waves per CU with the 64 KiB filter
+constexpr int kFastBlock = 1024;                    // one block of 16 waves per CU next to the 128 KiB filter
 constexpr int kBufOob = 0x7ffffff0;                 // buffer offset beyond any table: load returns 0, no access
 constexpr int kBufferDword3 = 0x00020000;           // raw buffer resource word 3 on CDNA
 
@@ -51,12 +52,16 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
   __shared__ int32_t s_cnt[NW];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = int64_t{blockIdx.x} * kDimTile + int64_t{w} * kWave * ITEMS;
+  int64_t rows[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
+  bool keep[ITEMS];
+  eval_preds_items<ITEMS>(ps, rows, n, keep);
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    const int64_t row = wbase + int64_t{j} * kWave + lane;
-    m[j] = __ballot(row < n && eval_preds(ps, row));
+    m[j] = __ballot(keep[j]);
     c += __popcll(m[j]);
   }
   if (lane == 0) s_cnt[w] = c;
@@ -135,17 +140,14 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
     }
     bool done = false;
     if (SB == 4) {
+      // A fresh table is mostly empty: try the CAS first instead of reading the slot.
       int32_t *keys = static_cast<int32_t *>(t.slots);
       int64_t s = (table_hash32(k) & mask) & ~int64_t{3};
       for (int64_t step = 0; step <= mask; ++step) {
-        int32_t cur = keys[s];
+        const int32_t cur = atomicCAS(&keys[s], kEmpty32, k);
         if (cur == kEmpty32) {
-          const int32_t old = atomicCAS(&keys[s], kEmpty32, k);
-          if (old == kEmpty32) {
-            done = true;
-            break;
-          }
-          cur = old;
+          done = true;
+          break;
         }
         if (cur == k) {
           latch(err, kErrDup);
@@ -209,7 +211,12 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   const __amdgpu_buffer_rsrc_t r1 =
       __builtin_amdgcn_make_buffer_rsrc(NJ > 1 ? t1.slots : t0.slots, 0, static_cast<int>(cap1 * SB1), kBufferDword3);
   const int64_t n = end;
-  for (int64_t base = begin + int64_t{threadIdx.x} * 4; base < n; base += step) {
+  int64_t wpos = 0, wend = 0;  // the wave's pair run (AGG 2), wave-uniform
+  // The loop is wave-uniform (lanes past the end have no live rows), so the
+  // wave-level state above stays consistent across lanes.
+  const int64_t wofs = int64_t{threadIdx.x & ~(kWave - 1)} * 4, lofs = int64_t{threadIdx.x & (kWave - 1)} * 4;
+  for (int64_t wbase = begin + wofs; wbase < n; wbase += step) {
+    const int64_t base = wbase + lofs;
     const bool full = base + 4 <= n;
     v4i32 f0 = 0, f1 = 0, c0 = 0, c1 = 0, w1 = 0;
     int64_t x0[4] = {0, 0, 0, 0};
@@ -293,38 +300,44 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (slot0[r] < 0) continue;
         const int32_t k = f1[r];
-        int32_t s = s1[r];
-        v4i32 q = q1[r];
-        bool found = false;
-        for (int64_t step = 0; step <= mask1; step += GS) {
-          if (SB1 == 4) {
-            bool empty;
-            const int h = match4(q, k, &empty);
-            if (h >= 0) {
-              found = true;
-              break;
-            }
-            if (empty) break;
-          } else {
-            if (q.x == k) {
-              found = true;
-              pay1[r] = q.y;
-              break;
-            }
-            if (q.x == kEmpty32) break;
-            if (q.z == k) {
-              found = true;
-              pay1[r] = q.w;
-              break;
-            }
-            if (q.z == kEmpty32) break;
-          }
-          s = static_cast<int32_t>((s + GS) & mask1);
-          q = __builtin_amdgcn_raw_buffer_load_b128(r1, s * SB1, 0, 0);
+        // state of the probe after one 16-byte group: 1 found, 0 absent, -1 continue
+        int state;
+        int32_t pl = 0;
+        if (SB1 == 4) {
+          bool empty;
+          const int h = match4(q1[r], k, &empty);
+          state = h >= 0 ? 1 : (empty ? 0 : -1);
+        } else {
+          const v4i32 q = q1[r];
+          state = q.x == k ? 1 : q.x == kEmpty32 ? 0 : q.z == k ? 2 : q.z == kEmpty32 ? 0 : -1;
+          pl = state == 1 ? q.y : q.w;
+          state = state == 2 ? 1 : state;
         }
-        if (!found) slot0[r] = -1;
+        if (slot0[r] >= 0 && state < 0) {  // the run continues past the first group (rare)
+          int32_t s = s1[r];
+          state = 0;
+          for (int64_t step = GS; step <= mask1; step += GS) {
+            s = static_cast<int32_t>((s + GS) & mask1);
+            const v4i32 q = __builtin_amdgcn_raw_buffer_load_b128(r1, s * SB1, 0, 0);
+            int st;
+            if (SB1 == 4) {
+              bool empty;
+              const int h = match4(q, k, &empty);
+              st = h >= 0 ? 1 : (empty ? 0 : -1);
+            } else {
+              st = q.x == k ? 1 : q.x == kEmpty32 ? 0 : q.z == k ? 2 : q.z == kEmpty32 ? 0 : -1;
+              pl = st == 1 ? q.y : q.w;
+              st = st == 2 ? 1 : st;
+            }
+            if (st >= 0) {
+              state = st;
+              break;
+            }
+          }
+        }
+        if (state != 1) slot0[r] = -1;
+        pay1[r] = pl;
       }
     }
     int64_t val[4];
@@ -361,25 +374,37 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
           if (hit && gkey != kEmpty64 && !group_add(g.slots, gmask, gkey, static_cast<uint64_t>(val[r])))
             latch(err, kErrTableFull);
         } else {
+          // Pairs go to the wave's current run of kPairRun slots; a new run is
+          // reserved with one atomic when it fills (a counter bumped by every
+          // wave for every group of rows serializes the whole pass).
           const uint64_t m = __ballot(hit);
-          if (m) {
-            const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-            unsigned long long wb = 0;
-            if (lane_id() == leader)
-              wb = atomicAdd(reinterpret_cast<unsigned long long *>(po.count), static_cast<unsigned long long>(__popcll(m)));
-            wb = __shfl(wb, leader);
+          const int c = __popcll(m);
+          if (c) {
+            if (wpos + c > wend) {
+              for (int64_t p = wpos + lane_id(); p < wend; p += kWave) po.keys[p] = kEmpty64;
+              unsigned long long rb = 0;
+              if (lane_id() == 0)
+                rb = atomicAdd(reinterpret_cast<unsigned long long *>(po.count), static_cast<unsigned long long>(kPairRun));
+              rb = __shfl(rb, 0);
+              wpos = static_cast<int64_t>(rb);
+              wend = wpos + kPairRun;
+            }
             if (hit) {
-              const int64_t p = static_cast<int64_t>(wb) + mbcnt(m);
+              const int64_t p = wpos + mbcnt(m);
               if (p < po.cap) {
                 po.keys[p] = gkey;
                 po.vals[p] = val[r];
               }
             }
+            wpos += c;
           }
         }
       }
     }
   }
+  if (AGG == 2)
+    for (int64_t p = wpos + lane_id(); p < wend; p += kWave)
+      if (p < po.cap) po.keys[p] = kEmpty64;
 }
 
 template <int NJ, int SB1, int AGG, bool V64>
@@ -400,41 +425,65 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
 template <bool SLOTS>
 __global__ __launch_bounds__(256) void k_compact_unordered(TableDev t, GroupDev g, int64_t *out_keys, int64_t *out_sums,
                                                           int64_t out_cap, int64_t *d_ngroups, uint32_t *err) {
+  // Each block compacts whole tiles and takes ONE counter atomic per tile (a
+  // counter bumped by every wave serializes the kernel on a single address).
+  constexpr int ITEMS = 8, NW = 256 / kWave;
+  constexpr int64_t TILE = 256 * ITEMS;
+  __shared__ int32_t s_cnt[NW];
+  __shared__ int64_t s_base;
   const int64_t cap = SLOTS ? t.hdr[0] : g.hdr[0];
-  const int64_t stride = int64_t{gridDim.x} * blockDim.x;
-  for (int64_t s0 = int64_t{blockIdx.x} * blockDim.x; s0 < cap; s0 += stride) {
-    const int64_t s = s0 + threadIdx.x;
-    bool keep = false;
-    int64_t key = 0, sum = 0;
-    if (s < cap) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int64_t tile = blockIdx.x; tile * TILE < cap; tile += gridDim.x) {  // block-uniform
+    const int64_t wbase = tile * TILE + int64_t{w} * kWave * ITEMS;
+    int64_t key[ITEMS], sum[ITEMS];
+    bool keep[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {  // every load issued before any use
+      const int64_t s = wbase + int64_t{j} * kWave + lane;
+      const int64_t sc = s < cap ? s : cap - 1;
       if (SLOTS) {
-        keep = t.flags[s] != 0;
-        if (keep) {
-          key = static_cast<const int32_t *>(t.slots)[s];
-          sum = static_cast<int64_t>(t.sums[s]);
+        keep[j] = t.flags[sc] != 0 && s < cap;
+        key[j] = static_cast<const int32_t *>(t.slots)[sc];
+        sum[j] = static_cast<int64_t>(t.sums[sc]);
+      } else {
+        key[j] = static_cast<int64_t>(g.slots[2 * sc]);
+        sum[j] = static_cast<int64_t>(g.slots[2 * sc + 1]);
+        keep[j] = key[j] != kEmpty64 && s < cap;
+      }
+    }
+    uint64_t m[ITEMS];
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      m[j] = __ballot(keep[j]);
+      c += __popcll(m[j]);
+    }
+    if (lane == 0) s_cnt[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int k = 0; k < NW; ++k) tot += s_cnt[k];
+      s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
+                                                    static_cast<unsigned long long>(tot)))
+                   : 0;
+    }
+    __syncthreads();
+    int64_t pos = s_base;
+    for (int k = 0; k < w; ++k) pos += s_cnt[k];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (keep[j]) {
+        const int64_t p = pos + mbcnt(m[j]);
+        if (p < out_cap) {
+          out_keys[p] = key[j];
+          out_sums[p] = sum[j];
+        } else {
+          latch(err, kErrCapacity);
         }
-      } else {
-        key = static_cast<int64_t>(g.slots[2 * s]);
-        keep = key != kEmpty64;
-        if (keep) sum = static_cast<int64_t>(g.slots[2 * s + 1]);
       }
+      pos += __popcll(m[j]);
     }
-    const uint64_t m = __ballot(keep);
-    if (!m) continue;
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    unsigned long long wb = 0;
-    if (lane_id() == leader)
-      wb = atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups), static_cast<unsigned long long>(__popcll(m)));
-    wb = __shfl(wb, leader);
-    if (keep) {
-      const int64_t p = static_cast<int64_t>(wb) + mbcnt(m);
-      if (p < out_cap) {
-        out_keys[p] = key;
-        out_sums[p] = sum;
-      } else {
-        latch(err, kErrCapacity);
-      }
-    }
+    __syncthreads();  // s_cnt / s_base are reused by the next tile
   }
 }
 
@@ -504,7 +553,8 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     s.g = group_view(s.mem, cap);
     st = group_init(s.g, nullptr, bound, 0, plan->group_max_load, stream);
   } else if (q.agg_mode == 2) {
-    const int64_t cap = std::max<int64_t>(fa.n, 1);
+    // every wave may leave up to one partly used run of kPairRun slots
+    const int64_t cap = std::max<int64_t>(fa.n, 1) + int64_t{fast_grid(ctx, fa.n)} * (kFastBlock / kWave) * kPairRun;
     s.mem = ctx_alloc(ctx, 256 + static_cast<size_t>(cap) * 16, stream);
     if (!s.mem) return set_error(PYST_ERR_NOMEM, "pyst_query: arena exhausted (pair buffer)");
     s.po.count = static_cast<int64_t *>(s.mem);
@@ -564,7 +614,8 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
                                                    j == 0 ? zero1 : nullptr);
     PYST_LAUNCH_CHECK("k_fast_table_init");
     if (nb > 0) {
-      const int blocks = grid_for(ctx, nb, 256, 8);
+      // one row per thread: each insert is a chain of dependent memory operations
+      const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(nb, 256), int64_t{1} << 20));
       const int32_t *key = static_cast<const int32_t *>(js.key.data);
       const int32_t *pay = static_cast<const int32_t *>(js.payload.data);
       if (sb == 4) k_fast_build<4><<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
@@ -573,6 +624,11 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
     }
   }
   return PYST_OK;
+}
+
+// One 1024-thread block per CU (the 128 KiB Bloom filter takes most of the LDS).
+int fast_grid(pyst_ctx *ctx, int64_t n) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4 * kFastBlock), ctx_num_cus(ctx))));
 }
 
 template <int NJ, int SB1, int AGG, bool V64>
@@ -584,8 +640,7 @@ static void launch_fast(int grid, const FastArgs &a, const DimTables &d, const G
 pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastArgs &a, const DimTables &d,
                            const GroupDev &g, const PairsOut &po, hipStream_t stream) {
   if (a.n <= 0) return PYST_OK;
-  const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(a.n, 4 * kFastBlock),
-                                                                           int64_t{ctx_num_cus(ctx)} * 2)));
+  const int grid = fast_grid(ctx, a.n);
   uint32_t *err = ctx_err_word(ctx);
   const int sb1 = njoins > 1 ? d.t[1].slot_bytes : 4;
   const bool v64 = a.v0_64 != 0;
@@ -634,7 +689,7 @@ pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &
     }
     const int blocks = grid_for(ctx, s->po.cap, 256, 8);
     k_gb_insert<<<blocks, 256, 0, stream>>>(s->po.keys, 1, s->po.vals, 1, nullptr, s->po.count, s->po.cap, g,
-                                            ctx_err_word(ctx));
+                                            ctx_err_word(ctx), 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
       ctx_free(ctx, gm, stream);

@@ -104,13 +104,16 @@ __global__ __launch_bounds__(BLOCK) void k_filter(PredSet ps, int64_t n, int32_t
   const int64_t t = s_tile;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = t * TILE + int64_t{w} * kWave * ITEMS;
+  int64_t rows[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
+  bool keep[ITEMS];
+  eval_preds_items<ITEMS>(ps, rows, n, keep);
   uint64_t m[ITEMS];
   int cnt = 0;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    const int64_t row = wbase + int64_t{j} * kWave + lane;
-    const bool keep = row < n && eval_preds(ps, row);
-    m[j] = __ballot(keep);
+    m[j] = __ballot(keep[j]);
     cnt += __popcll(m[j]);
   }
   if (lane == 0) s_cnt[w] = cnt;
@@ -176,6 +179,37 @@ __device__ __forceinline__ uint32_t part_dest(const PartArgs &a, int64_t row) {
   return (a.fanout & (a.fanout - 1)) == 0 ? (h & (a.fanout - 1)) : (h % a.fanout);
 }
 
+__device__ __forceinline__ uint32_t part_dest_key(const PartArgs &a, int64_t k) {
+  if (a.radix_shift >= 0) return static_cast<uint32_t>(((static_cast<uint64_t>(k) ^ (1ull << 63)) >> a.radix_shift) & 0xffu);
+  const uint32_t h = a.key64 ? static_cast<uint32_t>(fmix64(static_cast<uint64_t>(k)))
+                             : fmix32(static_cast<uint32_t>(static_cast<int32_t>(k)));
+  return (a.fanout & (a.fanout - 1)) == 0 ? (h & (a.fanout - 1)) : (h % a.fanout);
+}
+
+// Row ids and keys of a wave's ITEMS items (all loads issued before any use).
+// Items at or past `cnt` get a valid clamped row; callers mask them.
+template <int ITEMS>
+__device__ __forceinline__ void part_load(const PartArgs &a, int64_t wbase, int64_t cnt, int64_t (&row)[ITEMS],
+                                          int64_t (&key)[ITEMS]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) row[j] = wbase + int64_t{j} * kWave + lane;
+  if (wbase >= cnt) {  // the whole wave is past the end (uniform)
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) key[j] = 0;
+    return;
+  }
+  if (a.sel) {
+    int64_t r[ITEMS];
+    load_items<ITEMS>(a.sel, 0, row, cnt, r);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) row[j] = r[j];
+    load_items<ITEMS>(a.key, a.key64, row, a.n, key);
+  } else {
+    load_items<ITEMS>(a.key, a.key64, row, cnt, key);
+  }
+}
+
 // Lanes of `valid` holding the same destination as the calling lane (AMD has no
 // match instruction: intersect one ballot per destination bit).
 __device__ __forceinline__ uint64_t match_peers(uint32_t d, uint64_t valid, int fbits) {
@@ -204,11 +238,13 @@ __global__ __launch_bounds__(BLOCK) void k_part_hist(PartArgs a, int32_t *hist, 
   const int64_t t = blockIdx.x;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = t * TILE + int64_t{w} * kWave * ITEMS;
-#pragma unroll 4
+  int64_t row[ITEMS], key[ITEMS];
+  part_load<ITEMS>(a, wbase, cnt, row, key);
+#pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const int64_t i = wbase + int64_t{j} * kWave + lane;
     const bool valid = i < cnt;
-    const uint32_t d = valid ? part_dest(a, row_of(a.sel, i)) : 0u;
+    const uint32_t d = valid ? part_dest_key(a, key[j]) : 0u;
     const uint64_t vm = __ballot(valid);
     const uint64_t peers = match_peers(d, vm, a.fbits);
     if (valid && lane == __ffsll(static_cast<unsigned long long>(peers)) - 1) atomicAdd(&s_h[d], __popcll(peers));
@@ -297,14 +333,17 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
   int32_t pos[ITEMS];
   uint16_t dst[ITEMS];
   int64_t keyv[ITEMS];
+  {
+    int64_t r64[ITEMS];
+    part_load<ITEMS>(a, wbase, cnt, r64, keyv);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) rowv[j] = static_cast<int32_t>(r64[j]);
+  }
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const int64_t i = wbase + int64_t{j} * kWave + lane;
     const bool valid = i < cnt;
-    const int64_t row = valid ? row_of(a.sel, i) : 0;
-    rowv[j] = static_cast<int32_t>(row);
-    keyv[j] = valid ? load_as_i64(a.key, a.key64, row) : 0;
-    const uint32_t d = valid ? part_dest(a, row) : 0u;
+    const uint32_t d = valid ? part_dest_key(a, keyv[j]) : 0u;
     dst[j] = static_cast<uint16_t>(d);
     const uint64_t vm = __ballot(valid);
     const uint64_t peers = match_peers(d, vm, a.fbits);
@@ -334,11 +373,19 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
   }
   const int tile_rows = static_cast<int>(std::min<int64_t>(TILE, std::max<int64_t>(0, cnt - t * TILE)));
   for (int c = 0; c <= a.npay; ++c) {
-    const void *src = c == 0 ? a.key : a.pay[c - 1];
     const int is64 = c == 0 ? a.key64 : a.pay64[c - 1];
+    if (c == 0) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (pos[j] >= 0) s_stage[pos[j]] = c == 0 ? keyv[j] : load_as_i64(src, is64, rowv[j]);
+      for (int j = 0; j < ITEMS; ++j)
+        if (pos[j] >= 0) s_stage[pos[j]] = keyv[j];
+    } else if (wbase < cnt) {
+      int64_t rr[ITEMS], x[ITEMS];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) rr[j] = rowv[j];
+      load_items<ITEMS>(a.pay[c - 1], is64, rr, a.n, x);
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (pos[j] >= 0) s_stage[pos[j]] = x[j];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < tile_rows; i += BLOCK) {
@@ -617,17 +664,19 @@ __global__ void k_gb_init(GroupDev g, const int64_t *d_nsel, int64_t n, int64_t 
 
 __global__ __launch_bounds__(256) void k_gb_insert(const void *key, int key64, const void *val, int val64,
                                                    const int32_t *sel, const int64_t *d_nsel, int64_t n, GroupDev g,
-                                                   uint32_t *err) {
-  const int64_t cnt = count_of(d_nsel, n);
+                                                   uint32_t *err, int skip_empty) {
+  // skip_empty: the input is a pair buffer whose unused slots hold the EMPTY key
+  int64_t cnt = count_of(d_nsel, n);
+  if (cnt > n) cnt = n;
   const int64_t mask = g.hdr[0] - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = row_of(sel, i);
     const int64_t k = load_as_i64(key, key64, row);
-    const int64_t v = load_as_i64(val, val64, row);
     if (k == kEmpty64) {
-      latch(err, kErrKey);
+      if (!skip_empty) latch(err, kErrKey);
       continue;
     }
+    const int64_t v = load_as_i64(val, val64, row);
     if (!group_add(g.slots, mask, k, static_cast<uint64_t>(v))) latch(err, kErrTableFull);
   }
 }
@@ -885,7 +934,7 @@ pyst_status pyst_groupby_sum(pyst_ctx *ctx, const pyst_col *key, const pyst_col 
   if (key->n > 0) {
     const int blocks = grid_for(ctx, key->n, 256, 8);
     k_gb_insert<<<blocks, 256, 0, stream>>>(key->data, key->dtype == PYST_I64, val->data, val->dtype == PYST_I64, sel,
-                                            d_nsel, key->n, g, ctx_err_word(ctx));
+                                            d_nsel, key->n, g, ctx_err_word(ctx), 0);
     PYST_LAUNCH_CHECK("k_gb_insert");
   }
   st = group_compact(ctx, g, out_keys, out_sums, out_cap, d_ngroups, stream);

@@ -79,6 +79,39 @@ __device__ __forceinline__ int64_t load_as_i64(const void *p, int is64, int64_t 
   return is64 ? static_cast<const int64_t *>(p)[i] : static_cast<int64_t>(static_cast<const int32_t *>(p)[i]);
 }
 
+// Load element rows[j] of a column for every item before any of them is used,
+// so the ITEMS loads of a wave are in flight together.  Rows are clamped to
+// [0, n) so every address is valid; callers mask the out-of-range items.
+template <int ITEMS>
+__device__ __forceinline__ void load_items(const void *col, int is64, const int64_t (&rows)[ITEMS], int64_t n,
+                                           int64_t (&x)[ITEMS]) {
+  const int64_t last = n > 0 ? n - 1 : 0;
+  if (is64) {
+    const int64_t *p = static_cast<const int64_t *>(col);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) x[j] = p[rows[j] < last ? rows[j] : last];
+  } else {
+    const int32_t *p = static_cast<const int32_t *>(col);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) x[j] = p[rows[j] < last ? rows[j] : last];
+  }
+}
+
+// keep[j] = rows[j] < n and every predicate holds for row rows[j].
+template <int ITEMS>
+__device__ __forceinline__ void eval_preds_items(const PredSet &ps, const int64_t (&rows)[ITEMS], int64_t n,
+                                                 bool (&keep)[ITEMS]) {
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) keep[j] = rows[j] < n;
+  if (n <= 0) return;
+  for (int k = 0; k < ps.n; ++k) {
+    int64_t x[ITEMS];
+    load_items<ITEMS>(ps.col[k], ps.is64[k], rows, n, x);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) keep[j] = keep[j] && compare_op(x[j], ps.op[k], ps.val[k]);
+  }
+}
+
 __device__ __forceinline__ bool eval_preds(const PredSet &ps, int64_t row) {
   bool keep = true;
   for (int k = 0; k < ps.n; ++k) keep = keep && compare_op(load_as_i64(ps.col[k], ps.is64[k], row), ps.op[k], ps.val[k]);

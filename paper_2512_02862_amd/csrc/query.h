@@ -83,6 +83,7 @@ pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &
                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                         hipStream_t stream);
 bool ctx_generic_only(const pyst_ctx *ctx);
+int fast_grid(pyst_ctx *ctx, int64_t n);
 hipStream_t ctx_copy_stream(pyst_ctx *ctx);
 char *ctx_pinned_staging(pyst_ctx *ctx, size_t bytes);
 size_t ctx_budget_free(const pyst_ctx *ctx);

@@ -523,7 +523,7 @@ pyst_status agg_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     if (st == PYST_OK) {
       const int blocks = grid_for(ctx, s->po.cap, 256, 8);
       k_gb_insert<<<blocks, 256, 0, stream>>>(s->po.keys, 1, s->po.vals, 1, nullptr, s->po.count, s->po.cap, g,
-                                              ctx_err_word(ctx));
+                                              ctx_err_word(ctx), 0);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) st = hip_error(e, "k_gb_insert");
     }

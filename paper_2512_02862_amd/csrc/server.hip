@@ -7,9 +7,10 @@
 // regulated by device memory (Sec. 5.4, "Adaptive Regulation"): a request
 // starts only when its aggregation state fits in the server's arena, so load
 // beyond the budget waits in the queue instead of failing.  All active
-// requests share one circular scan of the fact table -- each chunk is copied
-// once and consumed by every request that still needs it, the analog of one
-// I/O pool serving every scan of a plan (Sec. 5.2, "Reader Combining").
+// requests share one scan of the fact table, driven by the oldest request --
+// each chunk is copied once and consumed by every request that still needs
+// it, the analog of one I/O pool serving every scan of a plan (Sec. 5.2,
+// "Reader Combining").
 // Dimension tables are built once and stay resident for later requests.
 #include <algorithm>
 #include <chrono>
@@ -96,7 +97,7 @@ struct Request {
   DimTables d;      // the cached tables with this request's own sums
   AggState s;
   void *sums_mem = nullptr;
-  int64_t nchunks = 0, remaining = 0;
+  int64_t nchunks = 0, remaining = 0, cursor = 0;
   std::vector<char> done;
   hipEvent_t finish = nullptr;
   std::chrono::steady_clock::time_point t_submit, t_done;
@@ -324,22 +325,26 @@ static void scheduler(pyst_server *sv) {
         sv->stats.max_active_seen = std::max<int64_t>(sv->stats.max_active_seen, static_cast<int64_t>(sv->active.size()));
       }
     }
-    // next chunk of the circular scan that some active request still needs
-    int64_t maxc = 0;
-    for (auto &r : sv->active) maxc = std::max(maxc, r->nchunks);
-    int64_t pick = -1;
-    for (int64_t k = 0; k < maxc && pick < 0; ++k) {
-      const int64_t c = (sv->scan_pos + k) % maxc;
-      for (auto &r : sv->active)
-        if (c < r->nchunks && !r->done[c] && r->status == PYST_OK) {
-          pick = c;
-          break;
-        }
+    // Next chunk: among the next chunks of the active requests (each request
+    // reads its chunks in order), the one the most active requests still need;
+    // ties go to the oldest request.  Every request needing the chunk consumes
+    // the same copy, so requests waiting together share their common prefix,
+    // and a request alone proceeds as under one-at-a-time service.
+    int64_t pick = -1, best = 0;
+    for (auto &r : sv->active) {
+      if (r->status != PYST_OK) continue;
+      while (r->cursor < r->nchunks && r->done[r->cursor]) ++r->cursor;
+      if (r->cursor >= r->nchunks) continue;
+      const int64_t c = r->cursor;
+      int64_t users = 0;
+      for (auto &o : sv->active)
+        if (o->status == PYST_OK && c < o->nchunks && !o->done[c]) ++users;
+      if (users > best) {  // strict: earlier (older) requests win ties
+        best = users;
+        pick = c;
+      }
     }
-    if (pick >= 0) {
-      serve_chunk(sv, pick);
-      sv->scan_pos = pick + 1;
-    }
+    if (pick >= 0) serve_chunk(sv, pick);
     finish_ready(sv);
     reap_done(sv);
     if (pick < 0 && !sv->active.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
