@@ -32,11 +32,70 @@ BUILD_ROW_BYTES = 8    # key int32 + segment int32
 GROUP_OUT_BYTES = 16   # key int64 + sum int64
 
 
-def source_hash():
+KERNEL_SOURCES = {  # the files that define each profiled kernel
+    "k_fast_fact": ["fast.hip", "pyst_internal.h", "table.h", "query.h"],
+}
+
+
+def source_hash(kernel="k_fast_fact"):
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2512_02862_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2512_02862_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def _db_rows(db, sql):
+    import sqlite3
+    return list(sqlite3.connect(db).execute(sql))
+
+
+def summarize(args):
+    """Turn rocprofv3 result databases into the text summaries and traffic.json kept in profiles/.
+
+    --summarize trace DB OUT.txt CMD...          kernel-trace statistics (top kernels)
+    --summarize pmc FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB KERNEL WORKLOAD CMD...
+        per-dispatch FETCH_SIZE / WRITE_SIZE of KERNEL, scaled by the same counters of a plain
+        1 GiB copy (bench.py --calibrate-copy), into profiles/traffic.json and a text summary.
+    """
+    kind, rest = args[0], args[1:]
+    prof = os.path.join(ROOT, "profiles")
+    if kind == "trace":
+        db, out, cmd = rest[0], rest[1], " ".join(rest[2:])
+        rows = _db_rows(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
+        with open(os.path.join(prof, out), "w") as fh:
+            fh.write("# rocprofv3 --kernel-trace --stats\n# command: %s\n" % cmd)
+            fh.write("%-90s %6s %14s %12s %7s\n" % ("kernel", "calls", "total_us", "avg_us", "pct"))
+            for r in rows:
+                fh.write("%-90s %6d %14.1f %12.2f %7.2f\n" % (r[0][:90], r[1], r[2], r[3], r[4]))
+        return
+    fdb, wdb, cfdb, cwdb, kernel, workload = rest[:6]
+    cmd = " ".join(rest[6:])
+
+    def avg(db, counter, like):
+        r = _db_rows(db, "select avg(value), count(*) from counters_collection where counter_name='%s' "
+                         "and kernel_name like '%%%s%%'" % (counter, like))
+        return r[0]
+
+    fetch, nf = avg(fdb, "FETCH_SIZE", kernel)
+    write, nw = avg(wdb, "WRITE_SIZE", kernel)
+    copy_bytes = 1 << 30
+    cfetch, _ = avg(cfdb, "FETCH_SIZE", "copyBuffer")
+    cwrite, _ = avg(cwdb, "WRITE_SIZE", "copyBuffer")
+    ffac, wfac = copy_bytes / 1024 / cfetch, copy_bytes / 1024 / cwrite
+    traffic = fetch * ffac * 1024 + write * wfac * 1024
+    path = os.path.join(prof, "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec[kernel + "|" + workload] = {
+        "bytes_per_launch": traffic, "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+        "fetch_scale": ffac, "write_scale": wfac, "dispatches": [nf, nw], "source_hash": source_hash(kernel),
+        "command": cmd}
+    json.dump(rec, open(path, "w"), indent=1, sort_keys=True)
+    with open(os.path.join(prof, "%s_%s_traffic.txt" % (kernel, workload)), "w") as fh:
+        fh.write("# HBM traffic of %s on %s from rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE\n" % (kernel, workload))
+        fh.write("# command: %s\n" % cmd)
+        fh.write("FETCH_SIZE KiB/dispatch %.1f (x%.3f from a 1 GiB copy reading %.1f KiB)\n" % (fetch, ffac, cfetch))
+        fh.write("WRITE_SIZE KiB/dispatch %.1f (x%.3f from a 1 GiB copy writing %.1f KiB)\n" % (write, wfac, cwrite))
+        fh.write("HBM bytes per launch %.4g\n" % traffic)
 
 
 def counter_traffic(kernel, workload):
@@ -48,7 +107,7 @@ def counter_traffic(kernel, workload):
         rec = json.load(open(path)).get(kernel + "|" + workload)
     except ValueError:
         return None
-    if not rec or rec.get("source_hash") != source_hash():
+    if not rec or rec.get("source_hash") != source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -71,6 +130,9 @@ def timed_loop(fn, steps, warmup):
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize":
+        summarize(sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -78,7 +140,9 @@ def main():
     ap.add_argument("--build-rows", type=int, default=1_500_000)
     ap.add_argument("--probe-rows", type=int, default=60_000_000)
     ap.add_argument("--max-load", type=float, default=0.5)
-    ap.add_argument("--no-extras", action="store_true", help="skip the partition and chain measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip every measurement beside the headline")
+    ap.add_argument("--extras", default="partition,chain,stream,batch,serve",
+                    help="comma-separated extra measurements to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=30_000_000)
     ap.add_argument("--stream-rows", type=int, default=240_000_000, help="chain fact rows streamed from pinned host")
@@ -147,7 +211,7 @@ def main():
     achieved = fact_bytes / fact_mean_s / 1e9
     query_bytes = npr * PROBE_ROW_BYTES + nb * BUILD_ROW_BYTES + n_groups * GROUP_OUT_BYTES
     workload = "star_b%d_p%d" % (nb, npr)
-    traffic = counter_traffic("k_fact_pass", workload)
+    traffic = counter_traffic("k_fast_fact", workload)
 
     result = {
         "metric": "probe rows/s and % HBM peak for filter+join+agg; batched p50/p99 latency",
@@ -171,7 +235,7 @@ def main():
         "query_hbm": {"algorithmic_bytes": query_bytes, "gbs": query_bytes / (ms_per_step / 1e3) / 1e9,
                       "frac_of_peak": query_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {
-            "kernel": "k_fact_pass (fused filter + probe + SUM)",
+            "kernel": "k_fast_fact (fused filter + probe + SUM)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": fact_bytes, "mean_launch_us": fact_mean_s * 1e6,
@@ -179,16 +243,21 @@ def main():
         },
     }
 
-    if not args.no_extras:
+    extras = [] if args.no_extras else args.extras.split(",")
+    if "partition" in extras:
         result["partition"] = bench_partition(ctx, pyst, p, npr, log)
-        del b, p, fact
-        torch.cuda.empty_cache()
+    del b, p, fact
+    torch.cuda.empty_cache()
+    if "chain" in extras:
         result["chain"] = bench_chain(ctx, pyst, gen, log)
         torch.cuda.empty_cache()
+    if "stream" in extras:
         result["stream"] = bench_stream(ctx, pyst, gen, log, args.stream_rows)
         torch.cuda.empty_cache()
+    if "batch" in extras:
         result["batch"] = bench_batch(ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
         torch.cuda.empty_cache()
+    if "serve" in extras:
         result["serve"] = bench_serve(pyst, gen, log, args.serve_rows, args.serve_requests)
 
     if not args.no_cpu_baseline:
@@ -391,7 +460,7 @@ def bench_serve(pyst, gen, log, nrows, nreq):
         return pyst.chain_plan(a, b, max_groups=g), g
 
     def run(max_active, arrivals):
-        srv = pyst.Server(host, budget=48 << 30, max_active=max_active, nbuf=3, chunk_rows=32_000_000)
+        srv = pyst.Server(host, budget=48 << 30, max_active=max_active, nbuf=2, chunk_rows=16_000_000)
         # warm the resident dimension tables outside the trace
         for kind in ("star", "chain"):
             p, c = plan_for(kind, 1_000_000)

@@ -209,7 +209,11 @@ static void release(pyst_server *sv, Request &r) {
 static void serve_chunk(pyst_server *sv, int64_t c) {
   const int b = static_cast<int>(sv->next_ring++ % sv->cfg.nbuf);
   hipStream_t cs = ctx_copy_stream(sv->ctx);
-  for (hipEvent_t e : sv->users[b]) (void)hipStreamWaitEvent(cs, e, 0);
+  // Backpressure: wait on the host until the buffer's previous consumers are
+  // done, so the scheduler runs at most nbuf chunks ahead of the device and
+  // chooses each chunk when it is needed -- requests that arrive meanwhile can
+  // still share it.  (Enqueuing ahead would fix every choice at admission.)
+  for (hipEvent_t e : sv->users[b]) (void)hipEventSynchronize(e);
   for (hipEvent_t e : sv->users[b]) (void)hipEventDestroy(e);
   sv->users[b].clear();
   const int64_t off = c * sv->cfg.chunk_rows;
