@@ -37,6 +37,39 @@ constexpr int kFastBlock = 1024;                    // one block of 16 waves per
 constexpr int kBufOob = 0x7ffffff0;                 // buffer offset beyond any table: load returns 0, no access
 constexpr int kBufferDword3 = 0x00020000;           // raw buffer resource word 3 on CDNA
 
+// Bucketed slot sums (single-join queries grouped by the join key).  Random
+// 64-bit atomic adds on MI355X retire at about 23e9/s chip-wide whatever the
+// table size (one L2 atomic per cache line touched), so a fact pass that adds
+// every matching row into the join table is bound by them.  Instead the pass
+// stages (slot, value) pairs in LDS and moves them, bucket by bucket of
+// kBucketSlots slots, into chunks in HBM; a second kernel adds each bucket up
+// in LDS.  That costs 12 bytes written and read per matching row.
+constexpr int kBucketLg = 13;
+constexpr int64_t kBucketSlots = int64_t{1} << kBucketLg;  // 64 KiB of LDS sums in the second kernel
+constexpr int kMaxBuckets = 128;                            // staged join tables: up to 2^20 slots
+constexpr int kMaxSumBuckets = 512;                         // second-kernel blocks: tables up to 2^22 slots
+constexpr uint32_t kStageCap = 2048;                        // staged pairs per block (24 KiB of LDS)
+constexpr uint32_t kFlushAt = 1024;                         // staged pairs that trigger a move to HBM
+constexpr int kFlushEvery = 2;                              // steps between the block's staging checks
+constexpr uint32_t kChunk = 512;                            // pairs per chunk
+constexpr uint32_t kNoChunk = 0xffffffffu;
+
+struct BucketPool {
+  uint32_t *slot;    // pair e of chunk c at [c * kChunk + e]
+  uint64_t *val;
+  uint32_t *bucket;  // bucket of each chunk
+  uint32_t *fill;    // pairs in each chunk
+  uint32_t *next;    // chunks handed out beyond the blocks' first ones (zeroed with the table)
+  uint32_t nchunks;  // chunks in the pool
+  uint32_t blocks;   // fact-pass blocks; block k starts with chunks [k * stride, k * stride + nb)
+  uint32_t stride;   // buckets a block's first chunks are reserved for; a table with more
+                     // buckets than this (its size is only known on the device) is not staged
+};
+
+__host__ __device__ inline uint32_t bucket_count(int64_t cap) {
+  return cap > kBucketSlots ? static_cast<uint32_t>(cap >> kBucketLg) : 1u;
+}
+
 __device__ __forceinline__ uint32_t bloom_hash(int32_t k) { return fmix32(static_cast<uint32_t>(k) ^ 0x9e3779b9u); }
 __device__ __forceinline__ uint32_t bloom_word(uint32_t h) { return h & (kBloomWords - 1); }
 __device__ __forceinline__ uint32_t bloom_bits(uint32_t h) { return (1u << ((h >> 17) & 31)) | (1u << ((h >> 22) & 31)); }
@@ -185,8 +218,87 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
 }
 
 // ------------------------------------------------------------------ the fact pass
-__device__ __forceinline__ v4i32 ld4(const int32_t *p, int64_t base) {
-  return __builtin_nontemporal_load(reinterpret_cast<const PYST_GLOBAL v4i32 *>(gmem(p) + base));
+// Every memory access of the pass is a raw buffer access.  An offset at or past
+// a resource's byte count reads zeros and writes nothing, without touching
+// memory, so a dead row is an offset rather than a branch and all lanes of a
+// wave issue the same instructions.  That keeps the compiler's count of
+// outstanding memory operations exact around the loop: a store or atomic that
+// some path skips would make every later wait for an older load (the next
+// rows, loaded one iteration ahead) wait for the stores as well.
+extern "C" __device__ long long pyst_buffer_atomic_add_i64(long long v, __amdgpu_buffer_rsrc_t r, int off, int soff,
+                                                           int aux) __asm("llvm.amdgcn.raw.ptr.buffer.atomic.add.i64");
+
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
+
+constexpr int64_t kWaveRows = 4 * kWave;  // rows of one wave step: 4 consecutive rows per lane
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, static_cast<int>(bytes), kBufferDword3);
+}
+
+// Rows [wbase, min(wbase + kWaveRows, end)) of a column as a buffer; empty for a null column.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t window(const void *col, int esz, int64_t wbase, int64_t end) {
+  int64_t rows = end - wbase;
+  rows = rows < 0 ? 0 : rows > kWaveRows ? kWaveRows : rows;
+  const char *p = col ? static_cast<const char *>(col) + wbase * esz : nullptr;
+  return rsrc(p, col ? rows * esz : 0);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(x) >> 32));
+  return static_cast<int64_t>((uint64_t{hi} << 32) | lo);
+}
+
+__device__ __forceinline__ v2u32 split64(int64_t x) {
+  return v2u32{static_cast<uint32_t>(x), static_cast<uint32_t>(static_cast<uint64_t>(x) >> 32)};
+}
+
+// x in [lo, lo + span] as 32-bit integers, negated when neg (the host turns every comparison into this form).
+__device__ __forceinline__ bool in_range(int32_t x, int32_t lo, uint32_t span, int32_t neg) {
+  return (static_cast<uint32_t>(x) - static_cast<uint32_t>(lo) <= span) != (neg != 0);
+}
+
+// The columns read before the probes, for a lane's 4 consecutive rows.
+struct FactRows {
+  v4i32 f0, f1, c0, c1;
+};
+
+// The lane whose 4 rows run past the end of the range (1-3 live rows) reads
+// them one by one: a 16-byte load that is only partly in range is not used.
+__device__ __forceinline__ void fix_tail(v4i32 &x, __amdgpu_buffer_rsrc_t r, int lane, int left) {
+  const bool mine = lane == (left >> 2);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int row = lane * 4 + k;
+    const int32_t v =
+        static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(r, mine && row < left ? row * 4 : kBufOob, 0, 0));
+    if (mine) x[k] = v;
+  }
+}
+
+template <int NJ>
+__device__ __forceinline__ FactRows load_rows(const FastArgs &a, int64_t wbase, int64_t end, int lane) {
+  const __amdgpu_buffer_rsrc_t rf0 = window(a.fk[0], 4, wbase, end);
+  const __amdgpu_buffer_rsrc_t rf1 = window(NJ > 1 ? a.fk[1] : nullptr, 4, wbase, end);
+  const __amdgpu_buffer_rsrc_t rc0 = window(a.pcol[0], 4, wbase, end);
+  const __amdgpu_buffer_rsrc_t rc1 = window(a.pcol[1], 4, wbase, end);
+  const int off = lane * 16;
+  FactRows x;
+  x.f0 = __builtin_amdgcn_raw_buffer_load_b128(rf0, off, 0, 0);
+  x.f1 = NJ > 1 ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rf1, off, 0, 0)) : v4i32{0, 0, 0, 0};
+  x.c0 = __builtin_amdgcn_raw_buffer_load_b128(rc0, off, 0, 0);
+  // (a uniform branch: a plan without a second predicate issues no load for it)
+  x.c1 = a.pcol[1] ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rc1, off, 0, 0)) : v4i32{0, 0, 0, 0};
+  const int64_t left = end - wbase;
+  if (left > 0 && left < kWaveRows && (left & 3)) {  // wave-uniform; once per range
+    const int l = static_cast<int>(left);
+    fix_tail(x.f0, rf0, lane, l);
+    if (NJ > 1) fix_tail(x.f1, rf1, lane, l);
+    fix_tail(x.c0, rc0, lane, l);
+    if (a.pcol[1]) fix_tail(x.c1, rc1, lane, l);
+  }
+  return x;
 }
 
 // First match of k in a 16-byte group of 4 keys: index, or -1 (none), and whether it holds EMPTY.
@@ -197,89 +309,175 @@ __device__ __forceinline__ int match4(v4i32 q, int32_t k, bool *empty) {
 
 #define PYST_LDS __attribute__((address_space(3)))
 
-// The fact pass over rows [begin + 4*threadIdx.x, end) in steps of `step` rows;
-// s_bloom is the block's LDS copy of join 0's filter (used when use_bloom).
-template <int NJ, int SB1, int AGG, bool V64>
+__device__ __forceinline__ uint32_t lds_add(PYST_LDS uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// A block's LDS staging area of (slot, value) pairs and its current chunk per bucket.
+struct StageLds {
+  PYST_LDS uint32_t *slot;
+  PYST_LDS uint64_t *val;
+  PYST_LDS uint32_t *cnt;      // staged pairs (may exceed kStageCap: the excess was added directly)
+  PYST_LDS uint32_t *chunk;    // [kMaxBuckets] current chunk
+  PYST_LDS uint32_t *fill;     // [kMaxBuckets] pairs in it
+  PYST_LDS uint32_t *hist;     // [kMaxBuckets] staged pairs per bucket
+  PYST_LDS uint32_t *rank;     // [kMaxBuckets] pairs placed so far in this move
+  PYST_LDS uint32_t *newbase;  // [kMaxBuckets] first chunk added in this move
+};
+
+// Moves the staged pairs into the block's chunks, bucket by bucket.  Every
+// thread of the block calls it; it leaves the staging area empty.
+__device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool &bp, uint32_t nb, uint32_t *err) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = *sl.cnt < kStageCap ? *sl.cnt : kStageCap;
+  for (uint32_t i = tid; i < n; i += kFastBlock) lds_add(&sl.hist[sl.slot[i] >> kBucketLg], 1u);
+  __syncthreads();
+  if (tid < nb) {
+    const uint32_t t = sl.fill[tid] + sl.hist[tid];
+    const uint32_t k = t > kChunk ? (t - 1) / kChunk : 0;  // chunks to add once the current one is full
+    uint32_t first = 0;
+    if (k) {
+      first = bp.blocks * bp.stride + atomicAdd(bp.next, k);
+      if (first + k > bp.nchunks) {
+        latch(err, kErrTableFull);
+        first = kNoChunk;
+      } else {
+        bp.fill[sl.chunk[tid]] = kChunk;
+        for (uint32_t j = 0; j < k; ++j) {
+          bp.bucket[first + j] = tid;
+          if (j + 1 < k) bp.fill[first + j] = kChunk;
+        }
+      }
+    }
+    sl.newbase[tid] = first;
+    sl.rank[tid] = 0;
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += kFastBlock) {
+    const uint32_t s = sl.slot[i], b = s >> kBucketLg;
+    const uint32_t pos = sl.fill[b] + lds_add(&sl.rank[b], 1u);
+    if (pos >= kChunk && sl.newbase[b] == kNoChunk) continue;  // pool exhausted (error latched)
+    const uint32_t c = pos < kChunk ? sl.chunk[b] : sl.newbase[b] + pos / kChunk - 1;
+    const size_t e = size_t{c} * kChunk + pos % kChunk;
+    bp.slot[e] = s;
+    bp.val[e] = sl.val[i];
+  }
+  __syncthreads();
+  if (tid < nb) {
+    const uint32_t t = sl.fill[tid] + sl.hist[tid];
+    if (t > kChunk && sl.newbase[tid] != kNoChunk) {
+      const uint32_t k = (t - 1) / kChunk;
+      sl.chunk[tid] = sl.newbase[tid] + k - 1;
+      sl.fill[tid] = t - k * kChunk;
+    } else {
+      sl.fill[tid] = t < kChunk ? t : kChunk;
+    }
+    sl.hist[tid] = 0;
+  }
+  if (tid == 0) *sl.cnt = 0;
+  __syncthreads();
+}
+
+// The fact pass over rows [begin, end): wave w of the block takes the 256 rows
+// at begin + 256*w, then steps by `step` rows.  The next step's columns are
+// loaded while the current step's probes are in flight.  s_bloom is the
+// block's LDS copy of join 0's filter (used when use_bloom).
+// VX: the value may be v0 * (c - v1) (the plan says which at run time); without
+// it the value is the column v0 and the v1 column is never read.
+template <int NJ, int SB1, int AGG, bool V64, bool VX>
 __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0, const TableDev &t1, const GroupDev &g,
                                            const PairsOut &po, uint32_t *err, const PYST_LDS uint32_t *s_bloom,
-                                           bool use_bloom, int64_t begin, int64_t step, int64_t end) {
+                                           bool use_bloom, int64_t begin, int64_t step, int64_t end,
+                                           const BucketPool *bp = nullptr, const StageLds *sl = nullptr) {
   const int64_t cap0 = t0.hdr[0], mask0 = cap0 - 1;
   const int64_t cap1 = NJ > 1 ? t1.hdr[0] : 4, mask1 = cap1 - 1;
   const int64_t gmask = AGG == 1 ? g.hdr[0] - 1 : 0;
-  const __amdgpu_buffer_rsrc_t r0 =
-      __builtin_amdgcn_make_buffer_rsrc(t0.slots, 0, static_cast<int>(cap0 * 4), kBufferDword3);
-  const __amdgpu_buffer_rsrc_t r1 =
-      __builtin_amdgcn_make_buffer_rsrc(NJ > 1 ? t1.slots : t0.slots, 0, static_cast<int>(cap1 * SB1), kBufferDword3);
-  const int64_t n = end;
+  const __amdgpu_buffer_rsrc_t r0 = rsrc(t0.slots, cap0 * 4);
+  const __amdgpu_buffer_rsrc_t r1 = rsrc(NJ > 1 ? t1.slots : t0.slots, cap1 * SB1);
+  const __amdgpu_buffer_rsrc_t rsum = rsrc(AGG == 0 ? t0.sums : nullptr, AGG == 0 ? cap0 * 8 : 0);
+  const __amdgpu_buffer_rsrc_t rflag = rsrc(AGG == 0 ? t0.flags : nullptr, AGG == 0 ? cap0 : 0);
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   int64_t wpos = 0, wend = 0;  // the wave's pair run (AGG 2), wave-uniform
-  // The loop is wave-uniform (lanes past the end have no live rows), so the
-  // wave-level state above stays consistent across lanes.
-  const int64_t wofs = int64_t{threadIdx.x & ~(kWave - 1)} * 4, lofs = int64_t{threadIdx.x & (kWave - 1)} * 4;
-  for (int64_t wbase = begin + wofs; wbase < n; wbase += step) {
-    const int64_t base = wbase + lofs;
-    const bool full = base + 4 <= n;
-    v4i32 f0 = 0, f1 = 0, c0 = 0, c1 = 0, w1 = 0;
-    int64_t x0[4] = {0, 0, 0, 0};
-    if (full) {
-      f0 = ld4(a.fk[0], base);
-      if (NJ > 1) f1 = ld4(a.fk[1], base);
-      if (a.npred > 0 && a.psrc[0] == 0) c0 = ld4(a.pcol[0], base);
-      if (a.npred > 1 && a.psrc[1] == 0) c1 = ld4(a.pcol[1], base);
-      if (V64) {
-        const v2i64 lo = __builtin_nontemporal_load(reinterpret_cast<const PYST_GLOBAL v2i64 *>(gmem(static_cast<const int64_t *>(a.v0)) + base));
-        const v2i64 hi = __builtin_nontemporal_load(reinterpret_cast<const PYST_GLOBAL v2i64 *>(gmem(static_cast<const int64_t *>(a.v0)) + base + 2));
-        x0[0] = lo.x; x0[1] = lo.y; x0[2] = hi.x; x0[3] = hi.y;
-      } else {
-        const v4i32 v = ld4(static_cast<const int32_t *>(a.v0), base);
-        x0[0] = v.x; x0[1] = v.y; x0[2] = v.z; x0[3] = v.w;
-      }
-      if (a.vexpr == PYST_V_COL_TIMES_C_MINUS) w1 = ld4(a.v1, base);
-    } else {
+  int64_t wbase = begin + int64_t{wv} * kWaveRows;
+  FactRows cur = load_rows<NJ>(a, wbase, end, lane);
+  // Stand-ins for the stores that end every step, into an empty buffer (no
+  // memory access), so that the loop is entered with as many operations younger
+  // than `cur` as it repeats with.  Distinct per-lane offsets keep the compiler
+  // from merging them or turning them into one lane's atomic.
+  {
+    const __amdgpu_buffer_rsrc_t none = rsrc(nullptr, 0);
+    if (AGG == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (base + r >= n) continue;
-        f0[r] = a.fk[0][base + r];
-        if (NJ > 1) f1[r] = a.fk[1][base + r];
-        if (a.npred > 0 && a.psrc[0] == 0) c0[r] = a.pcol[0][base + r];
-        if (a.npred > 1 && a.psrc[1] == 0) c1[r] = a.pcol[1][base + r];
-        x0[r] = V64 ? static_cast<const int64_t *>(a.v0)[base + r] : static_cast<const int32_t *>(a.v0)[base + r];
-        if (a.vexpr == PYST_V_COL_TIMES_C_MINUS) w1[r] = a.v1[base + r];
-      }
+      for (int r = 0; r < 4; ++r) pyst_buffer_atomic_add_i64(0, none, lane * 64 + r * 8, 0, 0);
+    } else if (AGG == 2) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 64 + r * 8, 0, 0);
     }
+  }
+  const uint32_t nb = AGG == 3 ? bucket_count(cap0) : 0;
+  const uint32_t stage_cap = AGG == 3 && nb <= bp->stride ? kStageCap : 0;  // 0: every pair is added directly
+  uint32_t steps = 0;
+  // AGG 3 steps the whole block together (it meets at a barrier every step);
+  // otherwise each wave runs on its own.
+  for (; (AGG == 3 ? wbase - int64_t{wv} * kWaveRows : wbase) < end; wbase += step) {
+    const int64_t left64 = end - wbase;
+    const int left = static_cast<int>(left64 < kWaveRows ? left64 : kWaveRows);
     bool live[4];
     int32_t s0[4];
     v4i32 q0[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      bool l = base + r < n;
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        if (k < a.npred) {
-          const int32_t x = a.psrc[k] == 0 ? (k == 0 ? c0[r] : c1[r])
-                            : a.psrc[k] == 1 ? f0[r] : a.psrc[k] == 2 ? f1[r] : w1[r];
-          l = l && compare_op(x, a.pop[k], a.pval[k]);
-        }
-      }
+      bool l = lane * 4 + r < left && in_range(cur.c0[r], a.plo[0], a.pspan[0], a.pneg[0]) &&
+               in_range(cur.c1[r], a.plo[1], a.pspan[1], a.pneg[1]);
       if (use_bloom) {
-        const uint32_t h = bloom_hash(f0[r]);
+        const uint32_t h = bloom_hash(cur.f0[r]);
         const uint32_t m = bloom_bits(h);
         l = l && (s_bloom[bloom_word(h)] & m) == m;
       }
       live[r] = l;
-      s0[r] = static_cast<int32_t>((table_hash32(f0[r]) & mask0) & ~int64_t{3});
+      s0[r] = static_cast<int32_t>((table_hash32(cur.f0[r]) & mask0) & ~int64_t{3});
       q0[r] = __builtin_amdgcn_raw_buffer_load_b128(r0, l ? s0[r] * 4 : kBufOob, 0, 0);
     }
+    // AGG 0: the group-exists flags of the 4 slots each probe reads first, so
+    // that only a hit on a slot not yet flagged writes its flag
+    uint32_t fl[4] = {0, 0, 0, 0};
+    if (AGG == 0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fl[r] = __builtin_amdgcn_raw_buffer_load_b32(rflag, live[r] ? s0[r] : kBufOob, 0, 0);
+    // the value columns of live rows only
+    const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end);
+    const __amdgpu_buffer_rsrc_t rw = window(a.v1, 4, wbase, end);
+    int64_t x0[4];
+    int32_t w1[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = lane * 4 + r;
+      if (V64) {
+        const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, live[r] ? row * 8 : kBufOob, 0, 0);
+        x0[r] = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
+      } else {
+        x0[r] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rv, live[r] ? row * 4 : kBufOob, 0, 0));
+      }
+    }
+    if (VX)  // an empty resource when the plan's value is a plain column
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        w1[r] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, live[r] ? (lane * 4 + r) * 4 : kBufOob, 0, 0));
+    const FactRows nxt = load_rows<NJ>(a, wbase + step, end, lane);
     int32_t slot0[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       bool empty;
-      const int hit = match4(q0[r], f0[r], &empty);
+      const int32_t k = cur.f0[r];
+      const int hit = match4(q0[r], k, &empty);
       slot0[r] = live[r] && hit >= 0 ? s0[r] + hit : -1;
+      if (AGG == 0) fl[r] = hit >= 0 ? (fl[r] >> (8 * hit)) & 0xffu : 0u;
       if (live[r] && hit < 0 && !empty) {  // the run continues past the first group (rare)
         int32_t s = s0[r];
-        for (int64_t step = 4; step <= mask0; step += 4) {
+        for (int64_t st = 4; st <= mask0; st += 4) {
           s = static_cast<int32_t>((s + 4) & mask0);
-          const int h2 = match4(__builtin_amdgcn_raw_buffer_load_b128(r0, s * 4, 0, 0), f0[r], &empty);
+          const int h2 = match4(__builtin_amdgcn_raw_buffer_load_b128(r0, s * 4, 0, 0), k, &empty);
           if (h2 >= 0) {
             slot0[r] = s + h2;
             break;
@@ -295,12 +493,12 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       constexpr int GS = 16 / SB1;  // slots per 16-byte load
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        s1[r] = static_cast<int32_t>((table_hash32(f1[r]) & mask1) & ~int64_t{GS - 1});
+        s1[r] = static_cast<int32_t>((table_hash32(cur.f1[r]) & mask1) & ~int64_t{GS - 1});
         q1[r] = __builtin_amdgcn_raw_buffer_load_b128(r1, slot0[r] >= 0 ? s1[r] * SB1 : kBufOob, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int32_t k = f1[r];
+        const int32_t k = cur.f1[r];
         // state of the probe after one 16-byte group: 1 found, 0 absent, -1 continue
         int state;
         int32_t pl = 0;
@@ -317,21 +515,21 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
         if (slot0[r] >= 0 && state < 0) {  // the run continues past the first group (rare)
           int32_t s = s1[r];
           state = 0;
-          for (int64_t step = GS; step <= mask1; step += GS) {
+          for (int64_t st = GS; st <= mask1; st += GS) {
             s = static_cast<int32_t>((s + GS) & mask1);
             const v4i32 q = __builtin_amdgcn_raw_buffer_load_b128(r1, s * SB1, 0, 0);
-            int st;
+            int sx;
             if (SB1 == 4) {
               bool empty;
               const int h = match4(q, k, &empty);
-              st = h >= 0 ? 1 : (empty ? 0 : -1);
+              sx = h >= 0 ? 1 : (empty ? 0 : -1);
             } else {
-              st = q.x == k ? 1 : q.x == kEmpty32 ? 0 : q.z == k ? 2 : q.z == kEmpty32 ? 0 : -1;
-              pl = st == 1 ? q.y : q.w;
-              st = st == 2 ? 1 : st;
+              sx = q.x == k ? 1 : q.x == kEmpty32 ? 0 : q.z == k ? 2 : q.z == kEmpty32 ? 0 : -1;
+              pl = sx == 1 ? q.y : q.w;
+              sx = sx == 2 ? 1 : sx;
             }
-            if (st >= 0) {
-              state = st;
+            if (sx >= 0) {
+              state = sx;
               break;
             }
           }
@@ -343,33 +541,62 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
     int64_t val[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      val[r] = a.vexpr == PYST_V_COL ? x0[r]
+      val[r] = !VX || a.vexpr == PYST_V_COL ? x0[r]
                                      : static_cast<int64_t>(static_cast<uint64_t>(x0[r]) *
                                                             static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w1[r])));
     if (AGG == 0) {
-      uint64_t old[4] = {1, 1, 1, 1};
+      // Sums in the join table's slots (adds that return nothing); the flag
+      // read with the probe may be stale, which costs a repeated store only.
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (slot0[r] >= 0) old[r] = atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[slot0[r]]),
-                                              static_cast<unsigned long long>(val[r]));
+        pyst_buffer_atomic_add_i64(val[r], rsum, slot0[r] >= 0 ? slot0[r] * 8 : kBufOob, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (slot0[r] >= 0 && old[r] == 0) t0.flags[slot0[r]] = 1;
+        if (slot0[r] >= 0 && fl[r] == 0) t0.flags[slot0[r]] = 1;
+    } else if (AGG == 3) {
+      uint64_t m[4];
+      uint32_t cw = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        m[r] = __ballot(slot0[r] >= 0);
+        cw += static_cast<uint32_t>(__popcll(m[r]));
+      }
+      uint32_t off = 0;
+      if (cw) {  // wave-uniform
+        if (lane == 0) off = lds_add(sl->cnt, cw);
+        off = __builtin_amdgcn_readfirstlane(off);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (slot0[r] >= 0) {
+          const uint32_t p = off + mbcnt(m[r]);
+          if (p < stage_cap) {
+            sl->slot[p] = static_cast<uint32_t>(slot0[r]);
+            sl->val[p] = static_cast<uint64_t>(val[r]);
+          } else {  // staging full: add directly (the second kernel adds these in)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[slot0[r]]), static_cast<unsigned long long>(val[r]));
+            t0.flags[slot0[r]] = 1;
+          }
+        }
+        off += static_cast<uint32_t>(__popcll(m[r]));
+      }
+      // Every kFlushEvery steps the block meets and moves its staged pairs to
+      // HBM once there are kFlushAt of them (pairs past kStageCap in between
+      // were added directly).
+      if (stage_cap > 0 && ++steps % kFlushEvery == 0) {  // block-uniform
+        __syncthreads();
+        if (*sl->cnt >= kFlushAt) stage_flush(*sl, *bp, nb, err);
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const bool hit = slot0[r] >= 0;
-        int64_t gkey = 0;
-        if (hit) {
-          const int64_t lo = a.lo_src == PYST_G_JOIN_KEY ? (a.lo_idx == 0 ? f0[r] : f1[r]) : pay1[r];
-          if (a.hi_src == PYST_G_NONE) {
-            gkey = lo;
-          } else {
-            const int64_t hi = a.hi_src == PYST_G_JOIN_KEY ? (a.hi_idx == 0 ? f0[r] : f1[r]) : pay1[r];
-            gkey = static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(lo));
-          }
-          if (gkey == kEmpty64) latch(err, kErrKey);
-        }
+        const int64_t lo = a.lo_src == PYST_G_JOIN_KEY ? (a.lo_idx == 0 ? cur.f0[r] : cur.f1[r]) : pay1[r];
+        const int64_t hi = a.hi_src == PYST_G_JOIN_KEY ? (a.hi_idx == 0 ? cur.f0[r] : cur.f1[r]) : pay1[r];
+        const int64_t gkey = a.hi_src == PYST_G_NONE
+                                 ? lo
+                                 : static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+        if (hit && gkey == kEmpty64) latch(err, kErrKey);
         if (AGG == 1) {
           if (hit && gkey != kEmpty64 && !group_add(g.slots, gmask, gkey, static_cast<uint64_t>(val[r])))
             latch(err, kErrTableFull);
@@ -379,47 +606,187 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
           // wave for every group of rows serializes the whole pass).
           const uint64_t m = __ballot(hit);
           const int c = __popcll(m);
-          if (c) {
-            if (wpos + c > wend) {
-              for (int64_t p = wpos + lane_id(); p < wend; p += kWave) po.keys[p] = kEmpty64;
-              unsigned long long rb = 0;
-              if (lane_id() == 0)
-                rb = atomicAdd(reinterpret_cast<unsigned long long *>(po.count), static_cast<unsigned long long>(kPairRun));
-              rb = __shfl(rb, 0);
-              wpos = static_cast<int64_t>(rb);
-              wend = wpos + kPairRun;
-            }
-            if (hit) {
-              const int64_t p = wpos + mbcnt(m);
-              if (p < po.cap) {
-                po.keys[p] = gkey;
-                po.vals[p] = val[r];
-              }
-            }
-            wpos += c;
+          if (c > 0 && wpos + c > wend) {  // wave-uniform, once per kPairRun pairs
+            for (int64_t p = wpos + lane; p < wend; p += kWave)
+              if (p < po.cap) po.keys[p] = kEmpty64;
+            unsigned long long rb = 0;
+            if (lane == 0)
+              rb = atomicAdd(reinterpret_cast<unsigned long long *>(po.count), static_cast<unsigned long long>(kPairRun));
+            wpos = uniform64(static_cast<int64_t>(__shfl(rb, 0)));
+            wend = wpos + kPairRun;
           }
+          // the 64 pair slots from wpos, clipped to the buffer
+          int64_t room = po.cap - wpos;
+          room = room < 0 ? 0 : room > kWave ? kWave : room;
+          const __amdgpu_buffer_rsrc_t rk = rsrc(po.keys + wpos, room * 8);
+          const __amdgpu_buffer_rsrc_t rvv = rsrc(po.vals + wpos, room * 8);
+          const int off = hit ? static_cast<int>(mbcnt(m)) * 8 : kBufOob;
+          __builtin_amdgcn_raw_buffer_store_b64(split64(gkey), rk, off, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(split64(val[r]), rvv, off, 0, 0);
+          wpos += c;
         }
       }
     }
+    cur = nxt;
   }
   if (AGG == 2)
-    for (int64_t p = wpos + lane_id(); p < wend; p += kWave)
+    for (int64_t p = wpos + lane; p < wend; p += kWave)
       if (p < po.cap) po.keys[p] = kEmpty64;
-}
-
-template <int NJ, int SB1, int AGG, bool V64>
-__global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t0, TableDev t1, GroupDev g, PairsOut po,
-                                                         uint32_t *err) {
-  __shared__ uint32_t s_bloom[kBloomWords];
-  const bool use_bloom = t0.bloom != nullptr && t0.hdr[1] <= kBloomMaxKeys;
-  if (use_bloom) {
-    for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];
+  if (AGG == 3 && stage_cap > 0) {
     __syncthreads();
+    if (*sl->cnt > 0) stage_flush(*sl, *bp, nb, err);  // block-uniform
+    if (threadIdx.x < nb) bp->fill[sl->chunk[threadIdx.x]] = sl->fill[threadIdx.x];
   }
-  fact_range<NJ, SB1, AGG, V64>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom,
-                                int64_t{blockIdx.x} * kFastBlock * 4, int64_t{gridDim.x} * kFastBlock * 4, a.n);
 }
 
+template <int NJ, int SB1, int AGG, bool V64, bool VX>
+__global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t0, TableDev t1, GroupDev g, PairsOut po,
+                                                         BucketPool bp, uint32_t *err) {
+  __shared__ uint32_t s_bloom[kBloomWords];
+  __shared__ uint32_t s_slot[AGG == 3 ? kStageCap : 1];
+  __shared__ uint64_t s_val[AGG == 3 ? kStageCap : 1];
+  __shared__ uint32_t s_bk[AGG == 3 ? 5 * kMaxBuckets + 1 : 1];
+  StageLds sl;
+  sl.slot = (PYST_LDS uint32_t *)s_slot;
+  sl.val = (PYST_LDS uint64_t *)s_val;
+  sl.chunk = (PYST_LDS uint32_t *)s_bk;
+  sl.fill = sl.chunk + kMaxBuckets;
+  sl.hist = sl.fill + kMaxBuckets;
+  sl.rank = sl.hist + kMaxBuckets;
+  sl.newbase = sl.rank + kMaxBuckets;
+  sl.cnt = sl.newbase + kMaxBuckets;
+  if (AGG == 3) {
+    const uint32_t nb = bucket_count(t0.hdr[0]);
+    if (nb <= bp.stride && threadIdx.x < bp.stride) {  // the block's first chunks, one per bucket
+      const uint32_t c = blockIdx.x * bp.stride + threadIdx.x;
+      bp.bucket[c] = threadIdx.x < nb ? threadIdx.x : kNoChunk;
+      bp.fill[c] = 0;
+      if (threadIdx.x < nb) {
+        sl.chunk[threadIdx.x] = c;
+        sl.fill[threadIdx.x] = 0;
+        sl.hist[threadIdx.x] = 0;
+      }
+    }
+    if (threadIdx.x == 0) *sl.cnt = 0;
+  }
+  const bool use_bloom = t0.bloom != nullptr && t0.hdr[1] <= kBloomMaxKeys;
+  if (use_bloom)
+    for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];
+  if (use_bloom || AGG == 3) __syncthreads();
+  fact_range<NJ, SB1, AGG, V64, VX>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom,
+                                int64_t{blockIdx.x} * kFastBlock * 4, int64_t{gridDim.x} * kFastBlock * 4, a.n, &bp, &sl);
+}
+
+// Adds the pairs of chunks ca and cb (kNoChunk: none) into the LDS sums of
+// their bucket (one wave; every lane loads its pairs of both chunks before any
+// add, so two chunks cost one memory round trip per 512 pairs each).
+__device__ __forceinline__ void add_chunks(const BucketPool &bp, uint32_t ca, uint32_t cb, int64_t lo, uint64_t *s_sum,
+                                           uint32_t *s_bits) {
+  constexpr int U = 8;
+  const uint32_t fa = ca != kNoChunk ? bp.fill[ca] : 0, fb = cb != kNoChunk ? bp.fill[cb] : 0;
+  const size_t ba = size_t{ca != kNoChunk ? ca : 0} * kChunk, bb = size_t{cb != kNoChunk ? cb : 0} * kChunk;
+  const uint32_t f = fa > fb ? fa : fb;
+  for (uint32_t e0 = 0; e0 < f; e0 += U * kWave) {  // wave-uniform
+    uint32_t sl[2 * U];
+    uint64_t v[2 * U];
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      const uint32_t e = e0 + (u % U) * kWave + lane_id();
+      const uint32_t n = u < U ? fa : fb;
+      const size_t at = (u < U ? ba : bb) + (e < n ? e : 0);
+      sl[u] = e < n ? bp.slot[at] : 0xffffffffu;
+      v[u] = e < n ? bp.val[at] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      const uint32_t s = static_cast<uint32_t>(static_cast<int64_t>(sl[u]) - lo);
+      if (sl[u] != 0xffffffffu && s < kBucketSlots) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(v[u]));
+        atomicOr(&s_bits[s >> 5], 1u << (s & 31));
+      }
+    }
+  }
+}
+
+// Second kernel of the bucketed slot sums: block b adds up the pairs of bucket
+// b in LDS, adds the sums the fact pass made directly, and writes the groups
+// present with one counter atomic.  *d_ngroups must be zero on entry.
+__global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPool bp, int64_t *out_keys,
+                                                           int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                                                           uint32_t *err) {
+  __shared__ uint64_t s_sum[kBucketSlots];
+  __shared__ uint32_t s_bits[kBucketSlots / 32];
+  __shared__ uint32_t s_wsum[kFastBlock / kWave];
+  __shared__ int64_t s_base;
+  const int64_t cap = t.hdr[0];
+  const uint32_t nb = bucket_count(cap);
+  const uint32_t b = blockIdx.x;
+  if (b >= nb) return;  // block-uniform
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  const int64_t lo = int64_t{b} << kBucketLg;
+  const uint32_t span = static_cast<uint32_t>(cap - lo < kBucketSlots ? cap - lo : kBucketSlots);
+  for (uint32_t i = tid; i < kBucketSlots; i += kFastBlock) s_sum[i] = 0;
+  for (uint32_t i = tid; i < kBucketSlots / 32; i += kFastBlock) s_bits[i] = 0;
+  __syncthreads();
+  if (nb <= bp.stride) {  // pairs were staged
+    uint32_t total = bp.blocks * bp.stride + *bp.next;
+    total = total < bp.nchunks ? total : bp.nchunks;
+    // the blocks' first chunks of bucket b, then the chunks added later (found by their tags)
+    constexpr uint32_t NW = kFastBlock / kWave;
+    for (uint32_t k = wv; k < bp.blocks; k += 2 * NW)
+      add_chunks(bp, k * bp.stride + b, k + NW < bp.blocks ? (k + NW) * bp.stride + b : kNoChunk, lo, s_sum, s_bits);
+    for (uint32_t c0 = bp.blocks * bp.stride + wv * kWave; c0 < total; c0 += kFastBlock) {
+      const uint32_t c = c0 + lane;
+      uint64_t m = __ballot(c < total && bp.bucket[c < total ? c : c0] == b);
+      while (m) {  // wave-uniform
+        const uint32_t j = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
+        m &= m - 1;
+        uint32_t j2 = kNoChunk;
+        if (m) {
+          j2 = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
+          m &= m - 1;
+        }
+        add_chunks(bp, c0 + j, j2 != kNoChunk ? c0 + j2 : kNoChunk, lo, s_sum, s_bits);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t s = tid; s < span; s += kFastBlock)
+    if (t.flags[lo + s]) {
+      s_sum[s] += t.sums[lo + s];
+      atomicOr(&s_bits[s >> 5], 1u << (s & 31));
+    }
+  __syncthreads();
+  constexpr uint32_t kPer = kBucketSlots / kFastBlock;  // each thread writes out kPer consecutive slots
+  const uint32_t s0 = tid * kPer;
+  uint32_t m = (s_bits[s0 >> 5] >> (s0 & 31)) & ((1u << kPer) - 1);
+  const uint32_t c = static_cast<uint32_t>(__popc(m));
+  const uint32_t incl = wave_inclusive_scan(c);
+  if (lane == kWave - 1) s_wsum[wv] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t tot = 0;
+    for (int k = 0; k < kFastBlock / kWave; ++k) tot += s_wsum[k];
+    s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
+                                                  static_cast<unsigned long long>(tot)))
+                 : 0;
+  }
+  __syncthreads();
+  int64_t pos = s_base + incl - c;
+  for (uint32_t k = 0; k < wv; ++k) pos += s_wsum[k];
+  const int32_t *keys = static_cast<const int32_t *>(t.slots);
+  while (m) {
+    const uint32_t j = static_cast<uint32_t>(__ffs(m) - 1);
+    m &= m - 1;
+    if (pos < out_cap) {
+      out_keys[pos] = keys[lo + s0 + j];
+      out_sums[pos] = static_cast<int64_t>(s_sum[s0 + j]);
+    } else {
+      latch(err, kErrCapacity);
+    }
+    ++pos;
+  }
+}
 // Unordered compaction of groups (slot sums or a group table): one counter
 // atomic per wave; *d_ngroups must be zero on entry.
 template <bool SLOTS>
@@ -490,6 +857,34 @@ __global__ __launch_bounds__(256) void k_compact_unordered(TableDev t, GroupDev 
 __global__ void k_zero_i64(int64_t *p) { *p = 0; }
 
 // ------------------------------------------------------------------ host side
+// A comparison "x OP c" of an int32 column with an int64 constant as the
+// range form the fact pass evaluates: x in [lo, lo + span] XOR neg.
+static void pred_range(int op, int64_t c, int32_t *lo, uint32_t *span, int32_t *neg) {
+  // past the int32 range by one, the constant compares with every x as c does
+  c = std::min<int64_t>(std::max<int64_t>(c, int64_t{INT32_MIN} - 1), int64_t{INT32_MAX} + 1);
+  int64_t l = INT32_MIN, h = INT32_MAX;
+  bool n = false;
+  switch (op) {
+    case PYST_EQ: l = h = c; break;
+    case PYST_NE: l = h = c; n = true; break;
+    case PYST_LT: h = c - 1; break;
+    case PYST_LE: h = c; break;
+    case PYST_GT: l = c + 1; break;
+    default: l = c; break;  // PYST_GE
+  }
+  l = std::max<int64_t>(l, INT32_MIN);
+  h = std::min<int64_t>(h, INT32_MAX);
+  if (l > h) {  // no int32 value is in the range: the result is the constant n
+    *lo = INT32_MIN;
+    *span = 0xffffffffu;
+    *neg = n ? 0 : 1;
+    return;
+  }
+  *lo = static_cast<int32_t>(l);
+  *span = static_cast<uint32_t>(h - l);
+  *neg = n ? 1 : 0;
+}
+
 // Can this plan take the fast path?  Fills the kernel arguments if so.
 bool fast_shape(const pyst_plan *plan, const pyst_col *fact, const QueryShape &q, FastArgs *fa) {
   std::memset(fa, 0, sizeof(*fa));
@@ -514,27 +909,45 @@ bool fast_shape(const pyst_plan *plan, const pyst_col *fact, const QueryShape &q
     if (fact[plan->v1].dtype != PYST_I32) return false;
     fa->v1 = static_cast<const int32_t *>(fact[plan->v1].data);
   }
-  fa->npred = plan->npreds;
+  for (int k = 0; k < 2; ++k) {
+    fa->plo[k] = INT32_MIN;
+    fa->pspan[k] = 0xffffffffu;
+  }
   for (int k = 0; k < plan->npreds; ++k) {
     const int c = plan->preds[k].col;
     if (fact[c].dtype != PYST_I32) return false;
-    fa->pop[k] = plan->preds[k].cmp;
-    fa->pval[k] = plan->preds[k].value;
-    if (c == plan->joins[0].probe_col) fa->psrc[k] = 1;
-    else if (plan->njoins > 1 && c == plan->joins[1].probe_col) fa->psrc[k] = 2;
-    else if (plan->vexpr == PYST_V_COL_TIMES_C_MINUS && c == plan->v1) fa->psrc[k] = 3;
-    else {
-      fa->psrc[k] = 0;
-      fa->pcol[k] = static_cast<const int32_t *>(fact[c].data);
-    }
+    fa->pcol[k] = static_cast<const int32_t *>(fact[c].data);
+    pred_range(plan->preds[k].cmp, plan->preds[k].value, &fa->plo[k], &fa->pspan[k], &fa->pneg[k]);
   }
   fa->n = fact[0].n;
-  // buffer resources address at most 2^31 bytes of a table
+  // buffer resources address less than kBufOob bytes of a table
   for (int j = 0; j < plan->njoins; ++j) {
-    const int sb = (j == 1 && q.need_payload[1]) ? 8 : 4;
-    if (table_capacity_host(plan->joins[j].key.n, plan->joins[j].max_load) * sb >= (int64_t{1} << 31)) return false;
+    const int sb = (j == 0 && q.slot_agg) ? 8 : (j == 1 && q.need_payload[1]) ? 8 : 4;
+    if (table_capacity_host(plan->joins[j].key.n, plan->joins[j].max_load) * sb >= kBufOob) return false;
   }
   return true;
+}
+
+// Fact pass with staged (slot, value) pairs, then the per-bucket sums and the
+// output (single join, sums grouped by the join key).
+static pyst_status bucketed_sums(pyst_ctx *ctx, const FastArgs &a, const DimTables &d, const BucketPool &bp,
+                                 int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                                 hipStream_t stream) {
+  uint32_t *err = ctx_err_word(ctx);
+  {
+    TimedRegion timed(ctx, "fact_pass", stream);
+    const dim3 grid(bp.blocks), block(kFastBlock);
+    const bool vx = a.vexpr != PYST_V_COL;
+    if (a.v0_64 && vx) k_fast_fact<1, 4, 3, true, true><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    else if (a.v0_64) k_fast_fact<1, 4, 3, true, false><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    else if (vx) k_fast_fact<1, 4, 3, false, true><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    else k_fast_fact<1, 4, 3, false, false><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    PYST_LAUNCH_CHECK("k_fast_fact");
+  }
+  k_bucket_sums<<<bucket_count(d.t[0].cap_alloc), kFastBlock, 0, stream>>>(d.t[0], bp, out_keys, out_sums, out_cap,
+                                                                           d_ngroups, err);
+  PYST_LAUNCH_CHECK("k_bucket_sums");
+  return PYST_OK;
 }
 
 pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const FastArgs &fa,
@@ -562,9 +975,41 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     s.po.vals = s.po.keys + cap;
     s.po.cap = cap;
   }
-  if (st == PYST_OK) st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, s.po.count, stream);
-  if (st == PYST_OK) st = fast_fact_pass(ctx, plan->njoins, q.agg_mode, fa, d, s.g, s.po, stream);
-  if (st == PYST_OK) st = fast_finish(ctx, plan, q, d, &s, out_keys, out_sums, out_cap, d_ngroups, stream);
+  // Sums kept in join-table slots go through bucketed pairs when the arena
+  // holds the pair pool and the table has at most kMaxSumBuckets buckets; the
+  // fact pass stages pairs when the table it sized on the device has at most
+  // kMaxBuckets buckets, and otherwise adds into the slots directly.
+  BucketPool bp;
+  std::memset(&bp, 0, sizeof(bp));
+  void *pool = nullptr;
+  if (st == PYST_OK && q.agg_mode == 0 && plan->njoins == 1 && fa.n > 0) {
+    const int64_t cap_alloc = table_capacity_host(plan->joins[0].key.n, plan->joins[0].max_load);
+    const int64_t grid = fast_grid(ctx, fa.n);
+    const int64_t stride = std::min<int64_t>(kMaxBuckets, bucket_count(cap_alloc));
+    const int64_t nchunks = grid * stride + ceil_div(fa.n, int64_t{kChunk}) + 1;
+    if (cap_alloc <= kBucketSlots * kMaxSumBuckets && nchunks < (int64_t{1} << 31))
+      pool = ctx_alloc(ctx, 256 + static_cast<size_t>(nchunks) * (size_t{kChunk} * 12 + 8), stream);
+    if (pool) {
+      char *p = static_cast<char *>(pool);
+      bp.next = reinterpret_cast<uint32_t *>(p);  // zeroed by the table initializer
+      bp.val = reinterpret_cast<uint64_t *>(p + 256);
+      bp.slot = reinterpret_cast<uint32_t *>(bp.val + static_cast<size_t>(nchunks) * kChunk);
+      bp.bucket = bp.slot + static_cast<size_t>(nchunks) * kChunk;
+      bp.fill = bp.bucket + nchunks;
+      bp.nchunks = static_cast<uint32_t>(nchunks);
+      bp.blocks = static_cast<uint32_t>(grid);
+      bp.stride = static_cast<uint32_t>(stride);
+    }
+  }
+  int64_t *zero1 = pool ? reinterpret_cast<int64_t *>(bp.next) : s.po.count;
+  if (st == PYST_OK) st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, zero1, stream);
+  if (pool) {
+    if (st == PYST_OK) st = bucketed_sums(ctx, fa, d, bp, out_keys, out_sums, out_cap, d_ngroups, stream);
+    ctx_free(ctx, pool, stream);
+  } else {
+    if (st == PYST_OK) st = fast_fact_pass(ctx, plan->njoins, q.agg_mode, fa, d, s.g, s.po, stream);
+    if (st == PYST_OK) st = fast_finish(ctx, plan, q, d, &s, out_keys, out_sums, out_cap, d_ngroups, stream);
+  }
   ctx_free(ctx, s.mem, stream);
   free_dimensions(ctx, &d, stream);
   return st;
@@ -631,10 +1076,10 @@ int fast_grid(pyst_ctx *ctx, int64_t n) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4 * kFastBlock), ctx_num_cus(ctx))));
 }
 
-template <int NJ, int SB1, int AGG, bool V64>
+template <int NJ, int SB1, int AGG, bool V64, bool VX>
 static void launch_fast(int grid, const FastArgs &a, const DimTables &d, const GroupDev &g, const PairsOut &po,
                         uint32_t *err, hipStream_t stream) {
-  k_fast_fact<NJ, SB1, AGG, V64><<<grid, kFastBlock, 0, stream>>>(a, d.t[0], d.t[1], g, po, err);
+  k_fast_fact<NJ, SB1, AGG, V64, VX><<<grid, kFastBlock, 0, stream>>>(a, d.t[0], d.t[1], g, po, BucketPool{}, err);
 }
 
 pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastArgs &a, const DimTables &d,
@@ -647,10 +1092,16 @@ pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastAr
   TimedRegion timed(ctx, "fact_pass", stream);
 #define PYST_FAST_CASE(NJ_, S1_, AG_)                                                    \
   if (njoins == NJ_ && sb1 == S1_ && agg_mode == AG_) {                                 \
-    if (v64) launch_fast<NJ_, S1_, AG_, true>(grid, a, d, g, po, err, stream);           \
-    else launch_fast<NJ_, S1_, AG_, false>(grid, a, d, g, po, err, stream);              \
+    if (v64) launch_fast<NJ_, S1_, AG_, true, true>(grid, a, d, g, po, err, stream);     \
+    else launch_fast<NJ_, S1_, AG_, false, true>(grid, a, d, g, po, err, stream);        \
     PYST_LAUNCH_CHECK("k_fast_fact");                                                   \
     return PYST_OK;                                                                     \
+  }
+  if (njoins == 1 && agg_mode == 0 && a.vexpr == PYST_V_COL) {  // sums of a plain column in the join slots
+    if (v64) launch_fast<1, 4, 0, true, false>(grid, a, d, g, po, err, stream);
+    else launch_fast<1, 4, 0, false, false>(grid, a, d, g, po, err, stream);
+    PYST_LAUNCH_CHECK("k_fast_fact");
+    return PYST_OK;
   }
   PYST_FAST_CASE(1, 4, 0)
   PYST_FAST_CASE(1, 4, 1)

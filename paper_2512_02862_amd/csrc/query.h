@@ -61,11 +61,13 @@ struct FastArgs {
   int32_t v0_64;
   int32_t vexpr;
   int64_t vconst;
-  int32_t npred;
-  int32_t psrc[2];  // 0: own column pcol, 1: fk[0], 2: fk[1], 3: v1
+  // Up to two predicates on int32 fact columns, each as "x in [plo, plo + pspan]"
+  // (32-bit wrap-around arithmetic) XOR pneg; an unused one has a null column
+  // and the full range.
   const int32_t *pcol[2];
-  int32_t pop[2];
-  int64_t pval[2];
+  int32_t plo[2];
+  uint32_t pspan[2];
+  int32_t pneg[2];
   int32_t hi_src, hi_idx, lo_src, lo_idx;
   int64_t n;
 };

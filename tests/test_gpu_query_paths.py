@@ -83,6 +83,81 @@ def test_star_int32_value_column(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
+@pytest.mark.parametrize("path", ["fast", "generic"])
+def test_star_every_comparison_at_its_boundaries(gpu, ctx, path):
+    # date is U[0, 2406]; constants at, inside and outside the int32 range
+    b, p = gen.star_tables(5_000, 60_001)
+    bd = {k: dev(v) for k, v in b.items()}
+    fact = [dev(p[c]) for c in FACT_STAR]
+    plan = gpu.star_plan(bd)
+    consts = [-(2 ** 40), -(2 ** 31) - 1, -(2 ** 31), -1, 0, 1200, 2406, 2407, 2 ** 31 - 1, 2 ** 31, 2 ** 40]
+    for op in ("==", "!=", "<", "<=", ">", ">="):
+        for c in consts:
+            plan.preds = [(1, op, c)]
+            k, s = run(gpu, ctx, plan, fact, path)
+            wk, ws = oracle.star_query(b, p, probe_preds=(("date", op, c),))
+            np.testing.assert_array_equal(k, wk, err_msg="%s %d" % (op, c))
+            np.testing.assert_array_equal(s, ws, err_msg="%s %d" % (op, c))
+
+
+@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("np_", [1, 4, 255, 256, 257, 258, 259, 4095, 4097, 262_143, 262_145])
+def test_star_ragged_fact_lengths(gpu, ctx, path, np_):
+    # wave steps of 256 rows, 4 rows per lane: every remainder of the last step
+    b, p = gen.star_tables(3_000, np_)
+    bd = {k: dev(v) for k, v in b.items()}
+    k, s = run(gpu, ctx, gpu.star_plan(bd), [dev(p[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, p)
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "generic"])
+def test_star_every_row_matches(gpu, ctx, path):
+    # no predicate on either side: every fact row joins, so the fast path's LDS
+    # staging overflows every step and the excess is added directly
+    b, p = gen.star_tables(100_000, 3_000_001)
+    bd = {k: dev(v) for k, v in b.items()}
+    plan = gpu.star_plan(bd)
+    plan.joins[0]["preds"] = []
+    plan.preds = []
+    k, s = run(gpu, ctx, plan, [dev(p[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, p, build_preds=(), probe_preds=())
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "generic"])
+def test_star_groups_whose_sum_is_zero(gpu, ctx, path):
+    # each fact row is followed by a copy with the negated price: every group
+    # that exists sums to 0 and must still be reported
+    b, p = gen.star_tables(20_000, 200_000)
+    q = {"fk": np.repeat(p["fk"], 2), "date": np.repeat(p["date"], 2),
+         "price": np.stack([p["price"], -p["price"]], axis=1).ravel()}
+    bd = {k: dev(v) for k, v in b.items()}
+    k, s = run(gpu, ctx, gpu.star_plan(bd), [dev(q[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, q)
+    assert len(wk) > 1000 and not ws.any()
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("nb", [600_000, 2_200_000])
+def test_star_tables_too_large_to_stage(gpu, ctx, path, nb):
+    # no dimension predicate: 600k keys make a 2^21-slot table (sized on the
+    # device, too many buckets to stage: the pairs are added directly), 2.2M
+    # keys a 2^23-slot one (the host does not set up bucketed sums at all)
+    b, p = gen.star_tables(nb, 2_000_003)
+    bd = {k: dev(v) for k, v in b.items()}
+    plan = gpu.star_plan(bd)
+    plan.joins[0]["preds"] = []
+    k, s = run(gpu, ctx, plan, [dev(p[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, p, build_preds=())
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
 def _chain(n=1_000_003, na=40_000, nb=4_000, zs=0.0):
     a, b = gen.chain_dims(na, nb)
     f = gen.chain_fact(n, na, nb, zs)
