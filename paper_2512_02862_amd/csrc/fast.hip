@@ -43,7 +43,7 @@ constexpr int kBufferDword3 = 0x00020000;           // raw buffer resource word 
 // every matching row into the join table is bound by them.  Instead the pass
 // stages (slot, value) pairs in LDS and moves them, bucket by bucket of
 // kBucketSlots slots, into chunks in HBM; a second kernel adds each bucket up
-// in LDS.  That costs 12 bytes written and read per matching row.
+// in LDS.  That costs 16 bytes written and read per matching row.
 constexpr int kBucketLg = 13;
 constexpr int64_t kBucketSlots = int64_t{1} << kBucketLg;  // 64 KiB of LDS sums in the second kernel
 constexpr int kMaxBuckets = 128;                            // staged join tables: up to 2^20 slots
@@ -55,8 +55,7 @@ constexpr uint32_t kChunk = 512;                            // pairs per chunk
 constexpr uint32_t kNoChunk = 0xffffffffu;
 
 struct BucketPool {
-  uint32_t *slot;    // pair e of chunk c at [c * kChunk + e]
-  uint64_t *val;
+  v2i64 *pair;       // pair e of chunk c at [c * kChunk + e]: {value, slot} (one 16-byte store)
   uint32_t *bucket;  // bucket of each chunk
   uint32_t *fill;    // pairs in each chunk
   uint32_t *next;    // chunks handed out beyond the blocks' first ones (zeroed with the table)
@@ -70,9 +69,10 @@ __host__ __device__ inline uint32_t bucket_count(int64_t cap) {
   return cap > kBucketSlots ? static_cast<uint32_t>(cap >> kBucketLg) : 1u;
 }
 
-__device__ __forceinline__ uint32_t bloom_hash(int32_t k) { return fmix32(static_cast<uint32_t>(k) ^ 0x9e3779b9u); }
-__device__ __forceinline__ uint32_t bloom_word(uint32_t h) { return h & (kBloomWords - 1); }
-__device__ __forceinline__ uint32_t bloom_bits(uint32_t h) { return (1u << ((h >> 17) & 31)) | (1u << ((h >> 22) & 31)); }
+// The Bloom filter reuses the join table's key hash h: the word from bits
+// 17..31, the two bits from bits 7..16 (the slot takes the low bits).
+__device__ __forceinline__ uint32_t bloom_word(uint32_t h) { return h >> (32 - kBloomLgw); }
+__device__ __forceinline__ uint32_t bloom_bits(uint32_t h) { return (1u << ((h >> 7) & 31)) | (1u << ((h >> 12) & 31)); }
 
 template <typename T>
 __device__ __forceinline__ const PYST_GLOBAL T *gmem(const T *p) { return (const PYST_GLOBAL T *)p; }
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
       continue;
     }
     if (t.bloom) {
-      const uint32_t h = bloom_hash(k);
+      const uint32_t h = table_hash32(k);
       atomicOr(&t.bloom[bloom_word(h)], bloom_bits(h));
     }
     bool done = false;
@@ -359,8 +359,7 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
     if (pos >= kChunk && sl.newbase[b] == kNoChunk) continue;  // pool exhausted (error latched)
     const uint32_t c = pos < kChunk ? sl.chunk[b] : sl.newbase[b] + pos / kChunk - 1;
     const size_t e = size_t{c} * kChunk + pos % kChunk;
-    bp.slot[e] = s;
-    bp.val[e] = sl.val[i];
+    bp.pair[e] = v2i64{static_cast<int64_t>(sl.val[i]), static_cast<int64_t>(s)};
   }
   __syncthreads();
   if (tid < nb) {
@@ -430,13 +429,13 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
     for (int r = 0; r < 4; ++r) {
       bool l = lane * 4 + r < left && in_range(cur.c0[r], a.plo[0], a.pspan[0], a.pneg[0]) &&
                in_range(cur.c1[r], a.plo[1], a.pspan[1], a.pneg[1]);
+      const uint32_t h = table_hash32(cur.f0[r]);
       if (use_bloom) {
-        const uint32_t h = bloom_hash(cur.f0[r]);
         const uint32_t m = bloom_bits(h);
         l = l && (s_bloom[bloom_word(h)] & m) == m;
       }
       live[r] = l;
-      s0[r] = static_cast<int32_t>((table_hash32(cur.f0[r]) & mask0) & ~int64_t{3});
+      s0[r] = static_cast<int32_t>((h & mask0) & ~int64_t{3});
       q0[r] = __builtin_amdgcn_raw_buffer_load_b128(r0, l ? s0[r] * 4 : kBufOob, 0, 0);
     }
     // AGG 0: the group-exists flags of the 4 slots each probe reads first, so
@@ -677,31 +676,32 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
                                 int64_t{blockIdx.x} * kFastBlock * 4, int64_t{gridDim.x} * kFastBlock * 4, a.n, &bp, &sl);
 }
 
-// Adds the pairs of chunks ca and cb (kNoChunk: none) into the LDS sums of
-// their bucket (one wave; every lane loads its pairs of both chunks before any
-// add, so two chunks cost one memory round trip per 512 pairs each).
-__device__ __forceinline__ void add_chunks(const BucketPool &bp, uint32_t ca, uint32_t cb, int64_t lo, uint64_t *s_sum,
+// Adds the pairs of up to 4 chunks (kNoChunk: none) into the LDS sums of their
+// bucket.  One wave; every lane loads its pairs of all 4 chunks before any add,
+// so 4 chunks cost one memory round trip per 256 pairs each.
+__device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t (&c)[4], int64_t lo, uint64_t *s_sum,
                                            uint32_t *s_bits) {
-  constexpr int U = 8;
-  const uint32_t fa = ca != kNoChunk ? bp.fill[ca] : 0, fb = cb != kNoChunk ? bp.fill[cb] : 0;
-  const size_t ba = size_t{ca != kNoChunk ? ca : 0} * kChunk, bb = size_t{cb != kNoChunk ? cb : 0} * kChunk;
-  const uint32_t f = fa > fb ? fa : fb;
-  for (uint32_t e0 = 0; e0 < f; e0 += U * kWave) {  // wave-uniform
-    uint32_t sl[2 * U];
-    uint64_t v[2 * U];
+  constexpr int U = 4;
+  uint32_t f[4], fmax = 0;
+  size_t base[4];
 #pragma unroll
-    for (int u = 0; u < 2 * U; ++u) {
+  for (int i = 0; i < 4; ++i) {
+    f[i] = c[i] != kNoChunk ? bp.fill[c[i]] : 0;
+    base[i] = size_t{c[i] != kNoChunk ? c[i] : 0} * kChunk;
+    fmax = f[i] > fmax ? f[i] : fmax;
+  }
+  for (uint32_t e0 = 0; e0 < fmax; e0 += U * kWave) {  // wave-uniform
+    v2i64 q[4 * U];
+#pragma unroll
+    for (int u = 0; u < 4 * U; ++u) {
       const uint32_t e = e0 + (u % U) * kWave + lane_id();
-      const uint32_t n = u < U ? fa : fb;
-      const size_t at = (u < U ? ba : bb) + (e < n ? e : 0);
-      sl[u] = e < n ? bp.slot[at] : 0xffffffffu;
-      v[u] = e < n ? bp.val[at] : 0;
+      q[u] = e < f[u / U] ? bp.pair[base[u / U] + e] : v2i64{0, -1};
     }
 #pragma unroll
-    for (int u = 0; u < 2 * U; ++u) {
-      const uint32_t s = static_cast<uint32_t>(static_cast<int64_t>(sl[u]) - lo);
-      if (sl[u] != 0xffffffffu && s < kBucketSlots) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(v[u]));
+    for (int u = 0; u < 4 * U; ++u) {
+      const uint32_t s = static_cast<uint32_t>(q[u].y - lo);
+      if (q[u].y >= 0 && s < kBucketSlots) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(q[u].x));
         atomicOr(&s_bits[s >> 5], 1u << (s & 31));
       }
     }
@@ -733,20 +733,26 @@ __global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPo
     total = total < bp.nchunks ? total : bp.nchunks;
     // the blocks' first chunks of bucket b, then the chunks added later (found by their tags)
     constexpr uint32_t NW = kFastBlock / kWave;
-    for (uint32_t k = wv; k < bp.blocks; k += 2 * NW)
-      add_chunks(bp, k * bp.stride + b, k + NW < bp.blocks ? (k + NW) * bp.stride + b : kNoChunk, lo, s_sum, s_bits);
+    for (uint32_t k = wv; k < bp.blocks; k += 4 * NW) {
+      uint32_t cs[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cs[i] = k + i * NW < bp.blocks ? (k + i * NW) * bp.stride + b : kNoChunk;
+      add_chunks(bp, cs, lo, s_sum, s_bits);
+    }
     for (uint32_t c0 = bp.blocks * bp.stride + wv * kWave; c0 < total; c0 += kFastBlock) {
       const uint32_t c = c0 + lane;
       uint64_t m = __ballot(c < total && bp.bucket[c < total ? c : c0] == b);
       while (m) {  // wave-uniform
-        const uint32_t j = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
-        m &= m - 1;
-        uint32_t j2 = kNoChunk;
-        if (m) {
-          j2 = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
-          m &= m - 1;
+        uint32_t cs[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          cs[i] = kNoChunk;
+          if (m) {
+            cs[i] = c0 + static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
+            m &= m - 1;
+          }
         }
-        add_chunks(bp, c0 + j, j2 != kNoChunk ? c0 + j2 : kNoChunk, lo, s_sum, s_bits);
+        add_chunks(bp, cs, lo, s_sum, s_bits);
       }
     }
   }
@@ -988,13 +994,12 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     const int64_t stride = std::min<int64_t>(kMaxBuckets, bucket_count(cap_alloc));
     const int64_t nchunks = grid * stride + ceil_div(fa.n, int64_t{kChunk}) + 1;
     if (cap_alloc <= kBucketSlots * kMaxSumBuckets && nchunks < (int64_t{1} << 31))
-      pool = ctx_alloc(ctx, 256 + static_cast<size_t>(nchunks) * (size_t{kChunk} * 12 + 8), stream);
+      pool = ctx_alloc(ctx, 256 + static_cast<size_t>(nchunks) * (size_t{kChunk} * 16 + 8), stream);
     if (pool) {
       char *p = static_cast<char *>(pool);
       bp.next = reinterpret_cast<uint32_t *>(p);  // zeroed by the table initializer
-      bp.val = reinterpret_cast<uint64_t *>(p + 256);
-      bp.slot = reinterpret_cast<uint32_t *>(bp.val + static_cast<size_t>(nchunks) * kChunk);
-      bp.bucket = bp.slot + static_cast<size_t>(nchunks) * kChunk;
+      bp.pair = reinterpret_cast<v2i64 *>(p + 256);
+      bp.bucket = reinterpret_cast<uint32_t *>(bp.pair + static_cast<size_t>(nchunks) * kChunk);
       bp.fill = bp.bucket + nchunks;
       bp.nchunks = static_cast<uint32_t>(nchunks);
       bp.blocks = static_cast<uint32_t>(grid);
