@@ -1,0 +1,210 @@
+// Group-by SUM over materialized (key, value) pairs by hash partitioning and
+// LDS aggregation.
+//
+// A hash table in HBM takes two L2 atomics per pair (claim the key, add the
+// value), and random atomics on MI355X retire at about 23e9/s chip-wide, so 12M
+// pairs cost a millisecond however the table is laid out.  Here the pairs are
+// moved twice, 64 ways each time, by 6 bits of a hash of the key (per-block
+// counts, one exclusive scan, a scatter): the first move splits all pairs, the
+// second splits each of the 64 parts in place of the first, so that pairs end
+// in 4096 contiguous buckets.  One block per bucket then adds its pairs up in
+// an LDS hash table (indexed by low bits of the same hash) and writes out the
+// groups.  64 ways keep every block's writes to a bucket in a few active lines
+// that the L2 combines; one 4096-way move would write 8-byte fragments.
+#include "pyst_internal.h"
+#include "table.h"
+
+namespace pyst {
+
+constexpr int kAggBlock = 1024;
+constexpr int kRadixLg = 6;
+constexpr int kRadix = 1 << kRadixLg;
+constexpr int kAggBuckets = kRadix * kRadix;   // 4096 buckets after two moves
+constexpr int kAggSlotsLg = 13;
+constexpr int kAggSlots = 1 << kAggSlotsLg;    // LDS table: 8192 x 16 bytes = 128 KiB per bucket
+constexpr int kAggBlocks1 = 512;               // blocks of the first move
+constexpr int kAggBlocks2 = 8;                 // blocks per part in the second move
+constexpr uint64_t kAggSeed = 0xd6e8feb86659fd93ull;
+
+__device__ __forceinline__ uint64_t agg_hash(int64_t key) { return fmix64(static_cast<uint64_t>(key) ^ kAggSeed); }
+
+// The rows a block of a move reads: segment blockIdx.x / bps of the input
+// (segment s is [seg_off[s * seg_stride], seg_off[(s + 1) * seg_stride]), or the
+// whole input [0, min(*count, cap)) without seg_off), split evenly into bps parts.
+struct MoveArgs {
+  const int64_t *keys;
+  const int64_t *vals;
+  const int64_t *count;
+  int64_t cap;
+  const int32_t *seg_off;
+  int seg_stride;
+  int bps;
+  int shift;  // bucket = (hash >> shift) & (kRadix - 1)
+};
+
+__device__ __forceinline__ void move_range(const MoveArgs &m, int *seg, int *part, int64_t *lo, int64_t *hi) {
+  *seg = blockIdx.x / m.bps;
+  *part = blockIdx.x % m.bps;
+  int64_t a, b;
+  if (m.seg_off) {
+    a = m.seg_off[int64_t{*seg} * m.seg_stride];
+    b = m.seg_off[int64_t{*seg + 1} * m.seg_stride];
+  } else {
+    a = 0;
+    b = *m.count < m.cap ? *m.count : m.cap;
+  }
+  const int64_t per = (b - a + m.bps - 1) / m.bps;
+  *lo = a + per * *part;
+  *hi = *lo + per < b ? *lo + per : b;
+  if (*lo > b) *lo = b;
+}
+
+// Counts per (segment, bucket, part), in that order: the exclusive scan of the
+// array is then where each block writes each bucket.  kEmpty64 keys are skipped.
+__global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hist) {
+  __shared__ int32_t s_h[kRadix];
+  if (threadIdx.x < kRadix) s_h[threadIdx.x] = 0;
+  __syncthreads();
+  int seg, part;
+  int64_t lo, hi;
+  move_range(m, &seg, &part, &lo, &hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kAggBlock) {
+    const int64_t k = m.keys[i];
+    if (k != kEmpty64) atomicAdd(&s_h[(agg_hash(k) >> m.shift) & (kRadix - 1)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kRadix) hist[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kAggBlock) void k_move_scatter(MoveArgs m, const int32_t *pos, int64_t *okeys,
+                                                           int64_t *ovals) {
+  __shared__ int32_t s_p[kRadix];
+  int seg, part;
+  int64_t lo, hi;
+  move_range(m, &seg, &part, &lo, &hi);
+  if (threadIdx.x < kRadix) s_p[threadIdx.x] = pos[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part];
+  __syncthreads();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kAggBlock) {
+    const int64_t k = m.keys[i];
+    if (k == kEmpty64) continue;
+    const int32_t p = atomicAdd(&s_p[(agg_hash(k) >> m.shift) & (kRadix - 1)], 1);
+    okeys[p] = k;
+    ovals[p] = m.vals[i];
+  }
+}
+
+// Block b adds up bucket b, [pos[b * bps], pos[(b + 1) * bps]), in an LDS hash
+// table and appends its groups to the output with one counter atomic.
+// *d_ngroups must be zero on entry.
+__global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys, const int64_t *vals,
+                                                            const int32_t *pos, int bps, int64_t *out_keys,
+                                                            int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                                                            uint32_t *err) {
+  __shared__ uint64_t s_key[kAggSlots];
+  __shared__ uint64_t s_sum[kAggSlots];
+  __shared__ int32_t s_w[kAggBlock / kWave];
+  __shared__ int64_t s_base;
+  for (int s = threadIdx.x; s < kAggSlots; s += kAggBlock) {
+    s_key[s] = static_cast<uint64_t>(kEmpty64);
+    s_sum[s] = 0;
+  }
+  __syncthreads();
+  const int64_t lo = pos[int64_t{blockIdx.x} * bps], hi = pos[int64_t{blockIdx.x + 1} * bps];
+  bool full = false;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kAggBlock) {
+    const int64_t k = keys[i];
+    const uint64_t v = static_cast<uint64_t>(vals[i]);
+    uint32_t s = static_cast<uint32_t>(agg_hash(k)) & (kAggSlots - 1);
+    for (int probes = 0;; ++probes) {
+      if (probes == kAggSlots) {
+        full = true;
+        break;
+      }
+      const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[s]),
+                                     static_cast<unsigned long long>(kEmpty64), static_cast<unsigned long long>(k));
+      if (old == static_cast<uint64_t>(kEmpty64) || old == static_cast<uint64_t>(k)) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(v));
+        break;
+      }
+      s = (s + 1) & (kAggSlots - 1);
+    }
+  }
+  if (full) latch(err, kErrTableFull);
+  __syncthreads();
+  constexpr int PER = kAggSlots / kAggBlock;  // each thread writes out PER consecutive slots
+  const int s0 = threadIdx.x * PER;
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) c += s_key[s0 + j] != static_cast<uint64_t>(kEmpty64);
+  const int incl = wave_inclusive_scan(c);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) s_w[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t tot = 0;
+    for (int k = 0; k < kAggBlock / kWave; ++k) tot += s_w[k];
+    s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
+                                                  static_cast<unsigned long long>(tot)))
+                 : 0;
+  }
+  __syncthreads();
+  int64_t p = s_base + incl - c;
+  for (int k = 0; k < w; ++k) p += s_w[k];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const uint64_t k = s_key[s0 + j];
+    if (k == static_cast<uint64_t>(kEmpty64)) continue;
+    if (p < out_cap) {
+      out_keys[p] = static_cast<int64_t>(k);
+      out_sums[p] = static_cast<int64_t>(s_sum[s0 + j]);
+    } else {
+      latch(err, kErrCapacity);
+    }
+    ++p;
+  }
+}
+
+// Groups of the pairs [0, min(*count, cap)) of keys/vals (kEmpty64 keys are
+// skipped) into out_keys/out_sums, their number into *d_ngroups (which must be
+// zero on entry).  keys/vals are overwritten (they hold the second move).
+// Fewer than 2^31 pairs; a bucket may hold at most kAggSlots distinct keys
+// (about 8192 x 4096 keys in all for keys that hash evenly), else the table-full
+// error is latched.
+pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *count, int64_t cap,
+                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                         hipStream_t stream) {
+  if (cap >= (int64_t{1} << 31)) return set_error(PYST_ERR_ARG, "group-by: too many pairs");
+  const int64_t n1 = int64_t{kRadix} * kAggBlocks1, n2 = int64_t{kAggBuckets} * kAggBlocks2;
+  const size_t counts = static_cast<size_t>(n1 + 1 + n2 + 1) * 2 * sizeof(int32_t);
+  Scratch sc(ctx, (counts + 255) / 256 * 256 + static_cast<size_t>(cap) * 16, stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "group-by: arena exhausted");
+  int32_t *h1 = sc.as<int32_t>(), *p1 = h1 + n1 + 1, *h2 = p1 + n1 + 1, *p2 = h2 + n2 + 1;
+  int64_t *tk = reinterpret_cast<int64_t *>(static_cast<char *>(sc.p) + (counts + 255) / 256 * 256);
+  int64_t *tv = tk + cap;
+  // First move: all pairs, by hash bits 58..63.  The scans run over one more
+  // entry than the counts, so that the last offset is the total.
+  MoveArgs m1{keys, vals, count, cap, nullptr, 0, kAggBlocks1, 64 - kRadixLg};
+  pyst_status st = fill_u32(reinterpret_cast<uint32_t *>(h1 + n1), 1, 0, stream);
+  if (st == PYST_OK) st = fill_u32(reinterpret_cast<uint32_t *>(h2 + n2), 1, 0, stream);
+  if (st != PYST_OK) return st;
+  k_move_hist<<<kAggBlocks1, kAggBlock, 0, stream>>>(m1, h1);
+  PYST_LAUNCH_CHECK("k_move_hist");
+  st = scan_excl_i32(ctx, h1, p1, n1 + 1, nullptr, stream);
+  if (st != PYST_OK) return st;
+  k_move_scatter<<<kAggBlocks1, kAggBlock, 0, stream>>>(m1, p1, tk, tv);
+  PYST_LAUNCH_CHECK("k_move_scatter");
+  // Second move: each of the 64 parts of the first, by hash bits 52..57, back into keys/vals.
+  MoveArgs m2{tk, tv, count, cap, p1, kAggBlocks1, kAggBlocks2, 64 - 2 * kRadixLg};
+  k_move_hist<<<kRadix * kAggBlocks2, kAggBlock, 0, stream>>>(m2, h2);
+  PYST_LAUNCH_CHECK("k_move_hist");
+  st = scan_excl_i32(ctx, h2, p2, n2 + 1, nullptr, stream);
+  if (st != PYST_OK) return st;
+  k_move_scatter<<<kRadix * kAggBlocks2, kAggBlock, 0, stream>>>(m2, p2, keys, vals);
+  PYST_LAUNCH_CHECK("k_move_scatter");
+  k_bucket_groups<<<kAggBuckets, kAggBlock, 0, stream>>>(keys, vals, p2, kAggBlocks2, out_keys, out_sums, out_cap,
+                                                         d_ngroups, ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_bucket_groups");
+  return PYST_OK;
+}
+
+}  // namespace pyst

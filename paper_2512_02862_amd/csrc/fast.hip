@@ -1119,8 +1119,9 @@ pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastAr
   return set_error(PYST_ERR_UNSUPPORTED, "pyst_query: no fast kernel for this shape");
 }
 
-// Group-by over materialized pairs, then unordered compaction.  *d_ngroups is
-// cleared here, on the stream, before the compaction adds to it.
+// The groups of the fact pass: slot sums or a group table are compacted
+// (unordered); materialized pairs are grouped by pair_groupby.  *d_ngroups must
+// be zero on entry (the table initializer clears it).
 pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const DimTables &d, AggState *s,
                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                         hipStream_t stream) {
@@ -1131,32 +1132,12 @@ pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &
     PYST_LAUNCH_CHECK("k_compact_unordered");
     return PYST_OK;
   }
-  GroupDev g = s->g;
-  void *gm = nullptr;
-  if (q.agg_mode == 2) {
-    const int64_t cap = table_capacity_host(s->po.cap, plan->group_max_load);
-    gm = ctx_alloc(ctx, group_bytes(cap), stream);
-    if (!gm) return set_error(PYST_ERR_NOMEM, "pyst_query: arena exhausted (group table)");
-    g = group_view(gm, cap);
-    pyst_status st = group_init(g, s->po.count, s->po.cap, 0, plan->group_max_load, stream);
-    if (st != PYST_OK) {
-      ctx_free(ctx, gm, stream);
-      return st;
-    }
-    const int blocks = grid_for(ctx, s->po.cap, 256, 8);
-    k_gb_insert<<<blocks, 256, 0, stream>>>(s->po.keys, 1, s->po.vals, 1, nullptr, s->po.count, s->po.cap, g,
-                                            ctx_err_word(ctx), 1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-      ctx_free(ctx, gm, stream);
-      return hip_error(e, "k_gb_insert");
-    }
-  }
-  k_compact_unordered<false><<<cgrid, 256, 0, stream>>>(TableDev{}, g, out_keys, out_sums, out_cap, d_ngroups,
+  if (q.agg_mode == 2)  // pairs: hash-partitioned LDS aggregation
+    return pair_groupby(ctx, s->po.keys, s->po.vals, s->po.count, s->po.cap, out_keys, out_sums, out_cap, d_ngroups,
+                        stream);
+  k_compact_unordered<false><<<cgrid, 256, 0, stream>>>(TableDev{}, s->g, out_keys, out_sums, out_cap, d_ngroups,
                                                        ctx_err_word(ctx));
-  hipError_t e = hipGetLastError();
-  if (gm) ctx_free(ctx, gm, stream);
-  if (e != hipSuccess) return hip_error(e, "k_compact_unordered");
+  PYST_LAUNCH_CHECK("k_compact_unordered");
   return PYST_OK;
 }
 

@@ -2,6 +2,7 @@
 // unit keeps kernel launches and their definitions together).
 #include "ctx.hip"
 #include "ops.hip"
+#include "agg.hip"
 #include "query.hip"
 #include "fast.hip"
 #include "stream.hip"

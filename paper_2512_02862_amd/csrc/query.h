@@ -84,6 +84,9 @@ pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastAr
 pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const DimTables &d, AggState *s,
                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                         hipStream_t stream);
+pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *count, int64_t cap,
+                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                         hipStream_t stream);
 bool ctx_generic_only(const pyst_ctx *ctx);
 int fast_grid(pyst_ctx *ctx, int64_t n);
 hipStream_t ctx_copy_stream(pyst_ctx *ctx);
