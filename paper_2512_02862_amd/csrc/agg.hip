@@ -61,6 +61,10 @@ __device__ __forceinline__ void move_range(const MoveArgs &m, int *seg, int *par
 
 // Counts per (segment, bucket, part), in that order: the exclusive scan of the
 // array is then where each block writes each bucket.  kEmpty64 keys are skipped.
+// Each thread handles kMoveItems consecutive-by-stride pairs per round, all
+// loads first.
+constexpr int kMoveItems = 8;
+
 __global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hist) {
   __shared__ int32_t s_h[kRadix];
   if (threadIdx.x < kRadix) s_h[threadIdx.x] = 0;
@@ -68,9 +72,16 @@ __global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hi
   int seg, part;
   int64_t lo, hi;
   move_range(m, &seg, &part, &lo, &hi);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kAggBlock) {
-    const int64_t k = m.keys[i];
-    if (k != kEmpty64) atomicAdd(&s_h[(agg_hash(k) >> m.shift) & (kRadix - 1)], 1);
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * kMoveItems) {
+    int64_t k[kMoveItems];
+#pragma unroll
+    for (int u = 0; u < kMoveItems; ++u) {
+      const int64_t i = i0 + int64_t{u} * kAggBlock;
+      k[u] = i < hi ? m.keys[i] : kEmpty64;
+    }
+#pragma unroll
+    for (int u = 0; u < kMoveItems; ++u)
+      if (k[u] != kEmpty64) atomicAdd(&s_h[(agg_hash(k[u]) >> m.shift) & (kRadix - 1)], 1);
   }
   __syncthreads();
   if (threadIdx.x < kRadix) hist[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part] = s_h[threadIdx.x];
@@ -84,12 +95,21 @@ __global__ __launch_bounds__(kAggBlock) void k_move_scatter(MoveArgs m, const in
   move_range(m, &seg, &part, &lo, &hi);
   if (threadIdx.x < kRadix) s_p[threadIdx.x] = pos[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part];
   __syncthreads();
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kAggBlock) {
-    const int64_t k = m.keys[i];
-    if (k == kEmpty64) continue;
-    const int32_t p = atomicAdd(&s_p[(agg_hash(k) >> m.shift) & (kRadix - 1)], 1);
-    okeys[p] = k;
-    ovals[p] = m.vals[i];
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * kMoveItems) {
+    int64_t k[kMoveItems], v[kMoveItems];
+#pragma unroll
+    for (int u = 0; u < kMoveItems; ++u) {
+      const int64_t i = i0 + int64_t{u} * kAggBlock;
+      k[u] = i < hi ? m.keys[i] : kEmpty64;
+      v[u] = i < hi ? m.vals[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kMoveItems; ++u) {
+      if (k[u] == kEmpty64) continue;
+      const int32_t p = atomicAdd(&s_p[(agg_hash(k[u]) >> m.shift) & (kRadix - 1)], 1);
+      okeys[p] = k[u];
+      ovals[p] = v[u];
+    }
   }
 }
 
@@ -111,22 +131,32 @@ __global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys
   __syncthreads();
   const int64_t lo = pos[int64_t{blockIdx.x} * bps], hi = pos[int64_t{blockIdx.x + 1} * bps];
   bool full = false;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kAggBlock) {
-    const int64_t k = keys[i];
-    const uint64_t v = static_cast<uint64_t>(vals[i]);
-    uint32_t s = static_cast<uint32_t>(agg_hash(k)) & (kAggSlots - 1);
-    for (int probes = 0;; ++probes) {
-      if (probes == kAggSlots) {
-        full = true;
-        break;
+  constexpr int U = 4;  // pairs per thread per round, loaded before any insert
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * U) {
+    int64_t kk[U], vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + int64_t{u} * kAggBlock;
+      kk[u] = i < hi ? keys[i] : kEmpty64;
+      vv[u] = i < hi ? vals[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (kk[u] == kEmpty64) continue;
+      uint32_t s = static_cast<uint32_t>(agg_hash(kk[u])) & (kAggSlots - 1);
+      for (int probes = 0;; ++probes) {
+        if (probes == kAggSlots) {
+          full = true;
+          break;
+        }
+        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[s]),
+                                       static_cast<unsigned long long>(kEmpty64), static_cast<unsigned long long>(kk[u]));
+        if (old == static_cast<uint64_t>(kEmpty64) || old == static_cast<uint64_t>(kk[u])) {
+          atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(vv[u]));
+          break;
+        }
+        s = (s + 1) & (kAggSlots - 1);
       }
-      const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[s]),
-                                     static_cast<unsigned long long>(kEmpty64), static_cast<unsigned long long>(k));
-      if (old == static_cast<uint64_t>(kEmpty64) || old == static_cast<uint64_t>(k)) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(v));
-        break;
-      }
-      s = (s + 1) & (kAggSlots - 1);
     }
   }
   if (full) latch(err, kErrTableFull);

@@ -43,7 +43,8 @@ constexpr int kBufferDword3 = 0x00020000;           // raw buffer resource word 
 // every matching row into the join table is bound by them.  Instead the pass
 // stages (slot, value) pairs in LDS and moves them, bucket by bucket of
 // kBucketSlots slots, into chunks in HBM; a second kernel adds each bucket up
-// in LDS.  That costs 16 bytes written and read per matching row.
+// in LDS.  That costs 8 bytes written and read per matching row (a value that
+// does not fit in 51 bits is added directly).
 constexpr int kBucketLg = 13;
 constexpr int64_t kBucketSlots = int64_t{1} << kBucketLg;  // 64 KiB of LDS sums in the second kernel
 constexpr int kMaxBuckets = 128;                            // staged join tables: up to 2^20 slots
@@ -54,8 +55,15 @@ constexpr int kFlushEvery = 2;                              // steps between the
 constexpr uint32_t kChunk = 512;                            // pairs per chunk
 constexpr uint32_t kNoChunk = 0xffffffffu;
 
+// A staged value must fit in 64 - kBucketLg bits (two's complement); others
+// are added directly.
+__device__ __forceinline__ bool fits_rec(int64_t v) {
+  const int64_t t = v >> (63 - kBucketLg);
+  return t == 0 || t == -1;
+}
+
 struct BucketPool {
-  v2i64 *pair;       // pair e of chunk c at [c * kChunk + e]: {value, slot} (one 16-byte store)
+  uint64_t *rec;     // pair e of chunk c at [c * kChunk + e]: value << kBucketLg | slot within the bucket
   uint32_t *bucket;  // bucket of each chunk
   uint32_t *fill;    // pairs in each chunk
   uint32_t *next;    // chunks handed out beyond the blocks' first ones (zeroed with the table)
@@ -359,7 +367,7 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
     if (pos >= kChunk && sl.newbase[b] == kNoChunk) continue;  // pool exhausted (error latched)
     const uint32_t c = pos < kChunk ? sl.chunk[b] : sl.newbase[b] + pos / kChunk - 1;
     const size_t e = size_t{c} * kChunk + pos % kChunk;
-    bp.pair[e] = v2i64{static_cast<int64_t>(sl.val[i]), static_cast<int64_t>(s)};
+    bp.rec[e] = (sl.val[i] << kBucketLg) | (s & (kBucketSlots - 1));
   }
   __syncthreads();
   if (tid < nb) {
@@ -555,9 +563,11 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
     } else if (AGG == 3) {
       uint64_t m[4];
       uint32_t cw = 0;
+      bool st[4];  // staged, else added directly
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        m[r] = __ballot(slot0[r] >= 0);
+        st[r] = slot0[r] >= 0 && fits_rec(val[r]);
+        m[r] = __ballot(st[r]);
         cw += static_cast<uint32_t>(__popcll(m[r]));
       }
       uint32_t off = 0;
@@ -568,7 +578,7 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (slot0[r] >= 0) {
-          const uint32_t p = off + mbcnt(m[r]);
+          const uint32_t p = st[r] ? off + mbcnt(m[r]) : stage_cap;
           if (p < stage_cap) {
             sl->slot[p] = static_cast<uint32_t>(slot0[r]);
             sl->val[p] = static_cast<uint64_t>(val[r]);
@@ -691,19 +701,21 @@ __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t 
     fmax = f[i] > fmax ? f[i] : fmax;
   }
   for (uint32_t e0 = 0; e0 < fmax; e0 += U * kWave) {  // wave-uniform
-    v2i64 q[4 * U];
+    uint64_t q[4 * U];
+    bool ok[4 * U];
 #pragma unroll
     for (int u = 0; u < 4 * U; ++u) {
       const uint32_t e = e0 + (u % U) * kWave + lane_id();
-      q[u] = e < f[u / U] ? bp.pair[base[u / U] + e] : v2i64{0, -1};
+      ok[u] = e < f[u / U];
+      q[u] = ok[u] ? bp.rec[base[u / U] + e] : 0;
     }
 #pragma unroll
     for (int u = 0; u < 4 * U; ++u) {
-      const uint32_t s = static_cast<uint32_t>(q[u].y - lo);
-      if (q[u].y >= 0 && s < kBucketSlots) {
-        atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(q[u].x));
-        atomicOr(&s_bits[s >> 5], 1u << (s & 31));
-      }
+      if (!ok[u]) continue;
+      const uint32_t s = static_cast<uint32_t>(q[u]) & (kBucketSlots - 1);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]),
+                static_cast<unsigned long long>(static_cast<int64_t>(q[u]) >> kBucketLg));
+      atomicOr(&s_bits[s >> 5], 1u << (s & 31));
     }
   }
 }
@@ -994,12 +1006,12 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     const int64_t stride = std::min<int64_t>(kMaxBuckets, bucket_count(cap_alloc));
     const int64_t nchunks = grid * stride + ceil_div(fa.n, int64_t{kChunk}) + 1;
     if (cap_alloc <= kBucketSlots * kMaxSumBuckets && nchunks < (int64_t{1} << 31))
-      pool = ctx_alloc(ctx, 256 + static_cast<size_t>(nchunks) * (size_t{kChunk} * 16 + 8), stream);
+      pool = ctx_alloc(ctx, 256 + static_cast<size_t>(nchunks) * (size_t{kChunk} * 8 + 8), stream);
     if (pool) {
       char *p = static_cast<char *>(pool);
       bp.next = reinterpret_cast<uint32_t *>(p);  // zeroed by the table initializer
-      bp.pair = reinterpret_cast<v2i64 *>(p + 256);
-      bp.bucket = reinterpret_cast<uint32_t *>(bp.pair + static_cast<size_t>(nchunks) * kChunk);
+      bp.rec = reinterpret_cast<uint64_t *>(p + 256);
+      bp.bucket = reinterpret_cast<uint32_t *>(bp.rec + static_cast<size_t>(nchunks) * kChunk);
       bp.fill = bp.bucket + nchunks;
       bp.nchunks = static_cast<uint32_t>(nchunks);
       bp.blocks = static_cast<uint32_t>(grid);

@@ -143,6 +143,21 @@ def test_star_groups_whose_sum_is_zero(gpu, ctx, path):
 
 
 @pytest.mark.parametrize("path", ["fast", "generic"])
+def test_star_values_of_every_width(gpu, ctx, path):
+    # values shifted left by 0..62 bits (wrapping): the fast path stages the
+    # ones that fit in 51 bits and adds the others directly; sums wrap mod 2^64
+    b, p = gen.star_tables(20_000, 400_003)
+    shift = (np.arange(len(p["price"])) % 63).astype(np.uint64)
+    q = dict(p)
+    q["price"] = (p["price"].astype(np.uint64) << shift).view(np.int64)
+    bd = {k: dev(v) for k, v in b.items()}
+    k, s = run(gpu, ctx, gpu.star_plan(bd), [dev(q[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, q)
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "generic"])
 @pytest.mark.parametrize("nb", [600_000, 2_200_000])
 def test_star_tables_too_large_to_stage(gpu, ctx, path, nb):
     # no dimension predicate: 600k keys make a 2^21-slot table (sized on the
