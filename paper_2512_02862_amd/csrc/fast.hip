@@ -77,10 +77,23 @@ __host__ __device__ inline uint32_t bucket_count(int64_t cap) {
   return cap > kBucketSlots ? static_cast<uint32_t>(cap >> kBucketLg) : 1u;
 }
 
-// The Bloom filter reuses the join table's key hash h: the word from bits
-// 17..31, the two bits from bits 7..16 (the slot takes the low bits).
-__device__ __forceinline__ uint32_t bloom_word(uint32_t h) { return h >> (32 - kBloomLgw); }
-__device__ __forceinline__ uint32_t bloom_bits(uint32_t h) { return (1u << ((h >> 7) & 31)) | (1u << ((h >> 12) & 31)); }
+// The Bloom filter reuses the join table's key hash h.  The word is the top
+// kBloomLgw bits of the key's home slot (h & mask), so that the keys of word w
+// sit, up to probe displacement, in one run of table slots and the filter can
+// be built from the table without a global atomic per key; the two bits come
+// from a multiplicative remix of h.
+__device__ __forceinline__ int bloom_shift(int64_t cap) {
+  int lg = 0;
+  while ((int64_t{1} << lg) < cap) ++lg;
+  return lg > kBloomLgw ? lg - kBloomLgw : 0;
+}
+__device__ __forceinline__ uint32_t bloom_word(uint32_t h, int64_t mask, int shift) {
+  return static_cast<uint32_t>((h & mask) >> shift);
+}
+__device__ __forceinline__ uint32_t bloom_bits(uint32_t h) {
+  const uint32_t p = h * 0x9e3779b1u;
+  return (1u << (p >> 27)) | (1u << ((p >> 22) & 31));
+}
 
 template <typename T>
 __device__ __forceinline__ const PYST_GLOBAL T *gmem(const T *p) { return (const PYST_GLOBAL T *)p; }
@@ -175,10 +188,6 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
       latch(err, kErrKey);
       continue;
     }
-    if (t.bloom) {
-      const uint32_t h = table_hash32(k);
-      atomicOr(&t.bloom[bloom_word(h)], bloom_bits(h));
-    }
     bool done = false;
     if (SB == 4) {
       // A fresh table is mostly empty: try the CAS first instead of reading the slot.
@@ -223,6 +232,45 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
     }
     if (!done) latch(err, kErrTableFull);
   }
+}
+
+// Bloom filter of a built keys-only table: thread w reads the slots whose home
+// word is w and ORs their keys' bits into word w with one atomic; a key that
+// probing moved into another word's slots ORs into its own word.
+__global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
+  const int64_t cap = t.hdr[0], mask = cap - 1;
+  if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter
+  const int shift = bloom_shift(cap);
+  const int64_t w = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
+  const int64_t lo = w << shift, hi = (w + 1) << shift;
+  if (lo >= cap) return;
+  const int32_t *keys = static_cast<const int32_t *>(t.slots);
+  uint32_t acc = 0;
+  for (int64_t s0 = lo; s0 < hi; s0 += 32) {  // up to 32 slots (8 16-byte loads) per round, loads first
+    int32_t k[32];
+    if (hi - s0 >= 32) {  // runs of 32 and more are 16-byte aligned (powers of two)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const v4i32 v = reinterpret_cast<const v4i32 *>(keys + s0)[q];
+        k[4 * q] = v.x;
+        k[4 * q + 1] = v.y;
+        k[4 * q + 2] = v.z;
+        k[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 32; ++q) k[q] = s0 + q < hi ? keys[s0 + q] : kEmpty32;
+    }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      if (k[q] == kEmpty32) continue;
+      const uint32_t h = table_hash32(k[q]);
+      const uint32_t ww = bloom_word(h, mask, shift);
+      if (ww == static_cast<uint32_t>(w)) acc |= bloom_bits(h);
+      else atomicOr(&t.bloom[ww], bloom_bits(h));
+    }
+  }
+  if (acc) atomicOr(&t.bloom[w], acc);
 }
 
 // ------------------------------------------------------------------ the fact pass
@@ -397,6 +445,7 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
                                            bool use_bloom, int64_t begin, int64_t step, int64_t end,
                                            const BucketPool *bp = nullptr, const StageLds *sl = nullptr) {
   const int64_t cap0 = t0.hdr[0], mask0 = cap0 - 1;
+  const int bshift = bloom_shift(cap0);
   const int64_t cap1 = NJ > 1 ? t1.hdr[0] : 4, mask1 = cap1 - 1;
   const int64_t gmask = AGG == 1 ? g.hdr[0] - 1 : 0;
   const __amdgpu_buffer_rsrc_t r0 = rsrc(t0.slots, cap0 * 4);
@@ -440,7 +489,7 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       const uint32_t h = table_hash32(cur.f0[r]);
       if (use_bloom) {
         const uint32_t m = bloom_bits(h);
-        l = l && (s_bloom[bloom_word(h)] & m) == m;
+        l = l && (s_bloom[bloom_word(h, mask0, bshift)] & m) == m;
       }
       live[r] = l;
       s0[r] = static_cast<int32_t>((h & mask0) & ~int64_t{3});
@@ -1083,6 +1132,10 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
       if (sb == 4) k_fast_build<4><<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
       else k_fast_build<8><<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
       PYST_LAUNCH_CHECK("k_fast_build");
+      if (d->t[j].bloom) {  // keys-only (join 0)
+        k_fast_bloom<<<kBloomWords / 256, 256, 0, stream>>>(d->t[j]);
+        PYST_LAUNCH_CHECK("k_fast_bloom");
+      }
     }
   }
   return PYST_OK;

@@ -210,6 +210,23 @@ def test_chain_group_by_two_join_keys(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
+@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("n", [1, 5, 4097])
+def test_chain_small_and_empty(gpu, ctx, path, n):
+    # a handful of fact rows (few or no pairs reach the group-by), and a
+    # predicate no row passes (no pairs at all)
+    a, b, f = _chain(n=n, na=1_000, nb=100)
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()})
+    fact = [dev(f[c]) for c in FACT_CHAIN]
+    k, s = run(gpu, ctx, plan, fact, path)
+    wk, ws = oracle.chain_query(a, b, f)
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+    plan.preds = [(2, "<", -5)]
+    k, s = run(gpu, ctx, plan, fact, path)
+    assert len(k) == 0 and len(oracle.chain_query(a, b, f, fact_preds=(("date", "<", -5),))[0]) == 0
+
+
 def test_fast_query_capacity_error(gpu, ctx):
     b, p = gen.star_tables(10_000, 100_000)
     bd = {k: dev(v) for k, v in b.items()}
