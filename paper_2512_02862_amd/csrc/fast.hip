@@ -466,6 +466,9 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
     if (AGG == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) pyst_buffer_atomic_add_i64(0, none, lane * 64 + r * 8, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), none, lane * 64 + 32 + r, 0, 0);
     } else if (AGG == 2) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 64 + r * 8, 0, 0);
@@ -495,12 +498,6 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       s0[r] = static_cast<int32_t>((h & mask0) & ~int64_t{3});
       q0[r] = __builtin_amdgcn_raw_buffer_load_b128(r0, l ? s0[r] * 4 : kBufOob, 0, 0);
     }
-    // AGG 0: the group-exists flags of the 4 slots each probe reads first, so
-    // that only a hit on a slot not yet flagged writes its flag
-    uint32_t fl[4] = {0, 0, 0, 0};
-    if (AGG == 0)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) fl[r] = __builtin_amdgcn_raw_buffer_load_b32(rflag, live[r] ? s0[r] : kBufOob, 0, 0);
     // the value columns of live rows only
     const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end);
     const __amdgpu_buffer_rsrc_t rw = window(a.v1, 4, wbase, end);
@@ -528,7 +525,6 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       const int32_t k = cur.f0[r];
       const int hit = match4(q0[r], k, &empty);
       slot0[r] = live[r] && hit >= 0 ? s0[r] + hit : -1;
-      if (AGG == 0) fl[r] = hit >= 0 ? (fl[r] >> (8 * hit)) & 0xffu : 0u;
       if (live[r] && hit < 0 && !empty) {  // the run continues past the first group (rare)
         int32_t s = s0[r];
         for (int64_t st = 4; st <= mask0; st += 4) {
@@ -601,14 +597,14 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
                                      : static_cast<int64_t>(static_cast<uint64_t>(x0[r]) *
                                                             static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w1[r])));
     if (AGG == 0) {
-      // Sums in the join table's slots (adds that return nothing); the flag
-      // read with the probe may be stale, which costs a repeated store only.
+      // Sums in the join table's slots (adds that return nothing) and the
+      // group-exists flag of every hit (a sum alone cannot tell: it may be 0).
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         pyst_buffer_atomic_add_i64(val[r], rsum, slot0[r] >= 0 ? slot0[r] * 8 : kBufOob, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (slot0[r] >= 0 && fl[r] == 0) t0.flags[slot0[r]] = 1;
+        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), rflag, slot0[r] >= 0 ? slot0[r] : kBufOob, 0, 0);
     } else if (AGG == 3) {
       uint64_t m[4];
       uint32_t cw = 0;
