@@ -348,13 +348,16 @@ pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, 
    multi-producer queue; one scheduler thread issues all GPU work.  It admits
    requests while stream slots and device memory allow (adaptive regulation:
    excess load waits in the queue), keeps built dimension tables resident
-   across requests, and runs every active request on one shared scan of the
-   fact table -- the next chunk is the lowest one the oldest active request
-   still needs; it is copied to the device once and consumed by every active
-   request that needs it (the reader combining of Sec. 5.2).  Requests
-   arriving while others run are admitted at once and ride along on the shared
-   chunks (continuous batching).  max_active = 1 gives one-at-a-time FIFO
-   service over the same machinery. */
+   across requests, and runs the active requests on shared chunks of the fact
+   table -- the next chunk copied is, among the next chunks of the active
+   requests (each reads its chunks in order), the one the most of them still
+   need (ties to the oldest request); it is copied to the device once and
+   consumed by every active request that needs it (the reader combining of
+   Sec. 5.2).  The scheduler reuses a ring buffer only after that buffer's
+   previous readers have finished, so it decides each chunk just in time.
+   Requests arriving while others run are admitted at once and ride along on
+   the shared chunks (continuous batching).  max_active = 1 gives
+   one-at-a-time FIFO service over the same machinery. */
 typedef struct pyst_server pyst_server;
 
 typedef struct pyst_server_cfg {

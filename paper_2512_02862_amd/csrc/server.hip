@@ -121,7 +121,6 @@ struct pyst_server {
   std::vector<hipEvent_t> copied;
   std::vector<std::vector<hipEvent_t>> users;  // events of the streams that consumed each buffer
   int64_t next_ring = 0;
-  int64_t scan_pos = 0;
   // queue and bookkeeping
   std::mutex mu;
   std::condition_variable cv_submit, cv_done;
