@@ -51,7 +51,8 @@ constexpr int kMaxBuckets = 128;                            // staged join table
 constexpr int kMaxSumBuckets = 512;                         // second-kernel blocks: tables up to 2^22 slots
 constexpr uint32_t kStageCap = 2048;                        // staged pairs per block (24 KiB of LDS)
 constexpr uint32_t kFlushAt = 1024;                         // staged pairs that trigger a move to HBM
-constexpr int kFlushEvery = 2;                              // steps between the block's staging checks
+constexpr int kFlushEvery = 2;                              // steps between the block's staging checks (4 rows per lane)
+constexpr int kStarRows = 4;                                // rows per lane and step of the staged fact pass
 constexpr uint32_t kChunk = 512;                            // pairs per chunk
 constexpr uint32_t kNoChunk = 0xffffffffu;
 
@@ -286,16 +287,16 @@ extern "C" __device__ long long pyst_buffer_atomic_add_i64(long long v, __amdgpu
 
 typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
 
-constexpr int64_t kWaveRows = 4 * kWave;  // rows of one wave step: 4 consecutive rows per lane
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int64_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, static_cast<int>(bytes), kBufferDword3);
 }
 
-// Rows [wbase, min(wbase + kWaveRows, end)) of a column as a buffer; empty for a null column.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t window(const void *col, int esz, int64_t wbase, int64_t end) {
+// Rows [wbase, min(wbase + wr, end)) of a column as a buffer; empty for a null column.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t window(const void *col, int esz, int64_t wbase, int64_t end,
+                                                         int64_t wr) {
   int64_t rows = end - wbase;
-  rows = rows < 0 ? 0 : rows > kWaveRows ? kWaveRows : rows;
+  rows = rows < 0 ? 0 : rows > wr ? wr : rows;
   const char *p = col ? static_cast<const char *>(col) + wbase * esz : nullptr;
   return rsrc(p, col ? rows * esz : 0);
 }
@@ -315,44 +316,58 @@ __device__ __forceinline__ bool in_range(int32_t x, int32_t lo, uint32_t span, i
   return (static_cast<uint32_t>(x) - static_cast<uint32_t>(lo) <= span) != (neg != 0);
 }
 
-// The columns read before the probes, for a lane's 4 consecutive rows.
+// The columns read before the probes, for a lane's R consecutive rows (R / 4
+// 16-byte loads per column).
+template <int R>
 struct FactRows {
-  v4i32 f0, f1, c0, c1;
+  v4i32 f0[R / 4], f1[R / 4], c0[R / 4], c1[R / 4];
 };
 
-// The lane whose 4 rows run past the end of the range (1-3 live rows) reads
-// them one by one: a 16-byte load that is only partly in range is not used.
-__device__ __forceinline__ void fix_tail(v4i32 &x, __amdgpu_buffer_rsrc_t r, int lane, int left) {
-  const bool mine = lane == (left >> 2);
+template <int N>
+__device__ __forceinline__ int32_t row_of(const v4i32 (&x)[N], int r) {
+  return x[r >> 2][r & 3];
+}
+
+// The lane whose R rows run past the end of the range reads its live rows one
+// by one: a 16-byte load that is only partly in range is not used.
+template <int R>
+__device__ __forceinline__ void fix_tail(v4i32 (&x)[R / 4], __amdgpu_buffer_rsrc_t r, int lane, int left) {
+  const bool mine = lane == left / R;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int row = lane * 4 + k;
+  for (int k = 0; k < R; ++k) {
+    const int row = lane * R + k;
     const int32_t v =
         static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(r, mine && row < left ? row * 4 : kBufOob, 0, 0));
-    if (mine) x[k] = v;
+    if (mine) x[k >> 2][k & 3] = v;
   }
 }
 
-template <int NJ>
-__device__ __forceinline__ FactRows load_rows(const FastArgs &a, int64_t wbase, int64_t end, int lane) {
-  const __amdgpu_buffer_rsrc_t rf0 = window(a.fk[0], 4, wbase, end);
-  const __amdgpu_buffer_rsrc_t rf1 = window(NJ > 1 ? a.fk[1] : nullptr, 4, wbase, end);
-  const __amdgpu_buffer_rsrc_t rc0 = window(a.pcol[0], 4, wbase, end);
-  const __amdgpu_buffer_rsrc_t rc1 = window(a.pcol[1], 4, wbase, end);
-  const int off = lane * 16;
-  FactRows x;
-  x.f0 = __builtin_amdgcn_raw_buffer_load_b128(rf0, off, 0, 0);
-  x.f1 = NJ > 1 ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rf1, off, 0, 0)) : v4i32{0, 0, 0, 0};
-  x.c0 = __builtin_amdgcn_raw_buffer_load_b128(rc0, off, 0, 0);
+template <int NJ, int R>
+__device__ __forceinline__ FactRows<R> load_rows(const FastArgs &a, int64_t wbase, int64_t end, int lane) {
+  constexpr int64_t WR = int64_t{kWave} * R;
+  const __amdgpu_buffer_rsrc_t rf0 = window(a.fk[0], 4, wbase, end, WR);
+  const __amdgpu_buffer_rsrc_t rf1 = window(NJ > 1 ? a.fk[1] : nullptr, 4, wbase, end, WR);
+  const __amdgpu_buffer_rsrc_t rc0 = window(a.pcol[0], 4, wbase, end, WR);
+  const __amdgpu_buffer_rsrc_t rc1 = window(a.pcol[1], 4, wbase, end, WR);
+  const int off = lane * 4 * R;
+  FactRows<R> x;
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    x.f0[q] = __builtin_amdgcn_raw_buffer_load_b128(rf0, off + 16 * q, 0, 0);
+    x.f1[q] = NJ > 1 ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rf1, off + 16 * q, 0, 0)) : v4i32{0, 0, 0, 0};
+    x.c0[q] = __builtin_amdgcn_raw_buffer_load_b128(rc0, off + 16 * q, 0, 0);
+  }
   // (a uniform branch: a plan without a second predicate issues no load for it)
-  x.c1 = a.pcol[1] ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rc1, off, 0, 0)) : v4i32{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q)
+    x.c1[q] = a.pcol[1] ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rc1, off + 16 * q, 0, 0)) : v4i32{0, 0, 0, 0};
   const int64_t left = end - wbase;
-  if (left > 0 && left < kWaveRows && (left & 3)) {  // wave-uniform; once per range
+  if (left > 0 && left < WR && (left & 3)) {  // wave-uniform; once per range
     const int l = static_cast<int>(left);
-    fix_tail(x.f0, rf0, lane, l);
-    if (NJ > 1) fix_tail(x.f1, rf1, lane, l);
-    fix_tail(x.c0, rc0, lane, l);
-    if (a.pcol[1]) fix_tail(x.c1, rc1, lane, l);
+    fix_tail<R>(x.f0, rf0, lane, l);
+    if (NJ > 1) fix_tail<R>(x.f1, rf1, lane, l);
+    fix_tail<R>(x.c0, rc0, lane, l);
+    if (a.pcol[1]) fix_tail<R>(x.c1, rc1, lane, l);
   }
   return x;
 }
@@ -439,11 +454,12 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
 // block's LDS copy of join 0's filter (used when use_bloom).
 // VX: the value may be v0 * (c - v1) (the plan says which at run time); without
 // it the value is the column v0 and the v1 column is never read.
-template <int NJ, int SB1, int AGG, bool V64, bool VX>
+template <int NJ, int SB1, int AGG, bool V64, bool VX, int R = 4>
 __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0, const TableDev &t1, const GroupDev &g,
                                            const PairsOut &po, uint32_t *err, const PYST_LDS uint32_t *s_bloom,
                                            bool use_bloom, int64_t begin, int64_t step, int64_t end,
                                            const BucketPool *bp = nullptr, const StageLds *sl = nullptr) {
+  constexpr int64_t WR = int64_t{kWave} * R;  // rows of one wave step: R consecutive rows per lane
   const int64_t cap0 = t0.hdr[0], mask0 = cap0 - 1;
   const int bshift = bloom_shift(cap0);
   const int64_t cap1 = NJ > 1 ? t1.hdr[0] : 4, mask1 = cap1 - 1;
@@ -455,8 +471,8 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   int64_t wpos = 0, wend = 0;  // the wave's pair run (AGG 2), wave-uniform
-  int64_t wbase = begin + int64_t{wv} * kWaveRows;
-  FactRows cur = load_rows<NJ>(a, wbase, end, lane);
+  int64_t wbase = begin + int64_t{wv} * WR;
+  FactRows<R> cur = load_rows<NJ, R>(a, wbase, end, lane);
   // Stand-ins for the stores that end every step, into an empty buffer (no
   // memory access), so that the loop is entered with as many operations younger
   // than `cur` as it repeats with.  Distinct per-lane offsets keep the compiler
@@ -465,13 +481,13 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
     const __amdgpu_buffer_rsrc_t none = rsrc(nullptr, 0);
     if (AGG == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) pyst_buffer_atomic_add_i64(0, none, lane * 64 + r * 8, 0, 0);
+      for (int r = 0; r < R; ++r) pyst_buffer_atomic_add_i64(0, none, lane * 128 + r * 8, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), none, lane * 64 + 32 + r, 0, 0);
+      for (int r = 0; r < R; ++r)
+        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), none, lane * 128 + 64 + r, 0, 0);
     } else if (AGG == 2) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 64 + r * 8, 0, 0);
+      for (int r = 0; r < 2 * R; ++r) __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 128 + r * 8, 0, 0);
     }
   }
   const uint32_t nb = AGG == 3 ? bucket_count(cap0) : 0;
@@ -479,17 +495,17 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   uint32_t steps = 0;
   // AGG 3 steps the whole block together (it meets at a barrier every step);
   // otherwise each wave runs on its own.
-  for (; (AGG == 3 ? wbase - int64_t{wv} * kWaveRows : wbase) < end; wbase += step) {
+  for (; (AGG == 3 ? wbase - int64_t{wv} * WR : wbase) < end; wbase += step) {
     const int64_t left64 = end - wbase;
-    const int left = static_cast<int>(left64 < kWaveRows ? left64 : kWaveRows);
-    bool live[4];
-    int32_t s0[4];
-    v4i32 q0[4];
+    const int left = static_cast<int>(left64 < WR ? left64 : WR);
+    bool live[R];
+    int32_t s0[R];
+    v4i32 q0[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bool l = lane * 4 + r < left && in_range(cur.c0[r], a.plo[0], a.pspan[0], a.pneg[0]) &&
-               in_range(cur.c1[r], a.plo[1], a.pspan[1], a.pneg[1]);
-      const uint32_t h = table_hash32(cur.f0[r]);
+    for (int r = 0; r < R; ++r) {
+      bool l = lane * R + r < left && in_range(row_of(cur.c0, r), a.plo[0], a.pspan[0], a.pneg[0]) &&
+               in_range(row_of(cur.c1, r), a.plo[1], a.pspan[1], a.pneg[1]);
+      const uint32_t h = table_hash32(row_of(cur.f0, r));
       if (use_bloom) {
         const uint32_t m = bloom_bits(h);
         l = l && (s_bloom[bloom_word(h, mask0, bshift)] & m) == m;
@@ -499,13 +515,13 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       q0[r] = __builtin_amdgcn_raw_buffer_load_b128(r0, l ? s0[r] * 4 : kBufOob, 0, 0);
     }
     // the value columns of live rows only
-    const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end);
-    const __amdgpu_buffer_rsrc_t rw = window(a.v1, 4, wbase, end);
-    int64_t x0[4];
-    int32_t w1[4] = {0, 0, 0, 0};
+    const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end, WR);
+    const __amdgpu_buffer_rsrc_t rw = window(a.v1, 4, wbase, end, WR);
+    int64_t x0[R];
+    int32_t w1[R] = {};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = lane * 4 + r;
+    for (int r = 0; r < R; ++r) {
+      const int row = lane * R + r;
       if (V64) {
         const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, live[r] ? row * 8 : kBufOob, 0, 0);
         x0[r] = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
@@ -515,14 +531,14 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
     }
     if (VX)  // an empty resource when the plan's value is a plain column
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        w1[r] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, live[r] ? (lane * 4 + r) * 4 : kBufOob, 0, 0));
-    const FactRows nxt = load_rows<NJ>(a, wbase + step, end, lane);
-    int32_t slot0[4];
+      for (int r = 0; r < R; ++r)
+        w1[r] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, live[r] ? (lane * R + r) * 4 : kBufOob, 0, 0));
+    const FactRows<R> nxt = load_rows<NJ, R>(a, wbase + step, end, lane);
+    int32_t slot0[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
       bool empty;
-      const int32_t k = cur.f0[r];
+      const int32_t k = row_of(cur.f0, r);
       const int hit = match4(q0[r], k, &empty);
       slot0[r] = live[r] && hit >= 0 ? s0[r] + hit : -1;
       if (live[r] && hit < 0 && !empty) {  // the run continues past the first group (rare)
@@ -538,19 +554,19 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
         }
       }
     }
-    int32_t pay1[4] = {0, 0, 0, 0};
+    int32_t pay1[R] = {};
     if (NJ > 1) {
-      int32_t s1[4];
-      v4i32 q1[4];
+      int32_t s1[R];
+      v4i32 q1[R];
       constexpr int GS = 16 / SB1;  // slots per 16-byte load
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        s1[r] = static_cast<int32_t>((table_hash32(cur.f1[r]) & mask1) & ~int64_t{GS - 1});
+      for (int r = 0; r < R; ++r) {
+        s1[r] = static_cast<int32_t>((table_hash32(row_of(cur.f1, r)) & mask1) & ~int64_t{GS - 1});
         q1[r] = __builtin_amdgcn_raw_buffer_load_b128(r1, slot0[r] >= 0 ? s1[r] * SB1 : kBufOob, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int32_t k = cur.f1[r];
+      for (int r = 0; r < R; ++r) {
+        const int32_t k = row_of(cur.f1, r);
         // state of the probe after one 16-byte group: 1 found, 0 absent, -1 continue
         int state;
         int32_t pl = 0;
@@ -590,9 +606,9 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
         pay1[r] = pl;
       }
     }
-    int64_t val[4];
+    int64_t val[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < R; ++r)
       val[r] = !VX || a.vexpr == PYST_V_COL ? x0[r]
                                      : static_cast<int64_t>(static_cast<uint64_t>(x0[r]) *
                                                             static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w1[r])));
@@ -600,17 +616,17 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       // Sums in the join table's slots (adds that return nothing) and the
       // group-exists flag of every hit (a sum alone cannot tell: it may be 0).
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < R; ++r)
         pyst_buffer_atomic_add_i64(val[r], rsum, slot0[r] >= 0 ? slot0[r] * 8 : kBufOob, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < R; ++r)
         __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), rflag, slot0[r] >= 0 ? slot0[r] : kBufOob, 0, 0);
     } else if (AGG == 3) {
-      uint64_t m[4];
+      uint64_t m[R];
       uint32_t cw = 0;
-      bool st[4];  // staged, else added directly
+      bool st[R];  // staged, else added directly
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < R; ++r) {
         st[r] = slot0[r] >= 0 && fits_rec(val[r]);
         m[r] = __ballot(st[r]);
         cw += static_cast<uint32_t>(__popcll(m[r]));
@@ -621,7 +637,7 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
         off = __builtin_amdgcn_readfirstlane(off);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < R; ++r) {
         if (slot0[r] >= 0) {
           const uint32_t p = st[r] ? off + mbcnt(m[r]) : stage_cap;
           if (p < stage_cap) {
@@ -637,16 +653,16 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       // Every kFlushEvery steps the block meets and moves its staged pairs to
       // HBM once there are kFlushAt of them (pairs past kStageCap in between
       // were added directly).
-      if (stage_cap > 0 && ++steps % kFlushEvery == 0) {  // block-uniform
+      if (stage_cap > 0 && ++steps % (R >= 8 ? 1 : kFlushEvery) == 0) {  // block-uniform
         __syncthreads();
         if (*sl->cnt >= kFlushAt) stage_flush(*sl, *bp, nb, err);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < R; ++r) {
         const bool hit = slot0[r] >= 0;
-        const int64_t lo = a.lo_src == PYST_G_JOIN_KEY ? (a.lo_idx == 0 ? cur.f0[r] : cur.f1[r]) : pay1[r];
-        const int64_t hi = a.hi_src == PYST_G_JOIN_KEY ? (a.hi_idx == 0 ? cur.f0[r] : cur.f1[r]) : pay1[r];
+        const int64_t lo = a.lo_src == PYST_G_JOIN_KEY ? (a.lo_idx == 0 ? row_of(cur.f0, r) : row_of(cur.f1, r)) : pay1[r];
+        const int64_t hi = a.hi_src == PYST_G_JOIN_KEY ? (a.hi_idx == 0 ? row_of(cur.f0, r) : row_of(cur.f1, r)) : pay1[r];
         const int64_t gkey = a.hi_src == PYST_G_NONE
                                  ? lo
                                  : static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(lo));
@@ -693,7 +709,7 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   }
 }
 
-template <int NJ, int SB1, int AGG, bool V64, bool VX>
+template <int NJ, int SB1, int AGG, bool V64, bool VX, int R = 4>
 __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t0, TableDev t1, GroupDev g, PairsOut po,
                                                          BucketPool bp, uint32_t *err) {
   __shared__ uint32_t s_bloom[kBloomWords];
@@ -727,8 +743,9 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
   if (use_bloom)
     for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];
   if (use_bloom || AGG == 3) __syncthreads();
-  fact_range<NJ, SB1, AGG, V64, VX>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom,
-                                int64_t{blockIdx.x} * kFastBlock * 4, int64_t{gridDim.x} * kFastBlock * 4, a.n, &bp, &sl);
+  fact_range<NJ, SB1, AGG, V64, VX, R>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom,
+                                   int64_t{blockIdx.x} * kFastBlock * R, int64_t{gridDim.x} * kFastBlock * R, a.n, &bp,
+                                   &sl);
 }
 
 // Adds the pairs of up to 4 chunks (kNoChunk: none) into the LDS sums of their
@@ -1001,10 +1018,11 @@ static pyst_status bucketed_sums(pyst_ctx *ctx, const FastArgs &a, const DimTabl
     TimedRegion timed(ctx, "fact_pass", stream);
     const dim3 grid(bp.blocks), block(kFastBlock);
     const bool vx = a.vexpr != PYST_V_COL;
-    if (a.v0_64 && vx) k_fast_fact<1, 4, 3, true, true><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
-    else if (a.v0_64) k_fast_fact<1, 4, 3, true, false><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
-    else if (vx) k_fast_fact<1, 4, 3, false, true><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
-    else k_fast_fact<1, 4, 3, false, false><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    constexpr int R = kStarRows;
+    if (a.v0_64 && vx) k_fast_fact<1, 4, 3, true, true, R><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    else if (a.v0_64) k_fast_fact<1, 4, 3, true, false, R><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    else if (vx) k_fast_fact<1, 4, 3, false, true, R><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
+    else k_fast_fact<1, 4, 3, false, false, R><<<grid, block, 0, stream>>>(a, d.t[0], d.t[1], GroupDev{}, PairsOut{}, bp, err);
     PYST_LAUNCH_CHECK("k_fast_fact");
   }
   k_bucket_sums<<<bucket_count(d.t[0].cap_alloc), kFastBlock, 0, stream>>>(d.t[0], bp, out_keys, out_sums, out_cap,
