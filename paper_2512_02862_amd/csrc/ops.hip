@@ -307,6 +307,70 @@ __global__ void k_part_offsets(const int32_t *scan, uint32_t fanout, int64_t nti
 // ballots; the block lays the tile out destination-major in LDS, then writes
 // every destination's run with consecutive threads on consecutive addresses
 // (software write combining: whole lines per destination, not scattered words).
+// Histogram of one 4096-row tile for the common case: int32 keys read in
+// place (no selection), hash destinations, F <= 64.  Each thread reads its 16
+// rows as four 16-byte loads.  Up to 8 destinations are counted in registers
+// and summed across the wave; more go to per-wave LDS counters.
+template <int FMAX>
+__global__ __launch_bounds__(256) void k_part_hist_i32(PartArgs a, int32_t *hist, int64_t ntiles) {
+  constexpr int BLOCK = 256, NW = BLOCK / kWave;
+  constexpr int64_t TILE = 4096;
+  __shared__ int32_t s_h[NW][FMAX];
+  const int F = static_cast<int>(a.fanout);
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int p = lane; p < F; p += kWave) s_h[w][p] = 0;
+  const int64_t t = blockIdx.x;
+  const int64_t n = a.n;
+  const int32_t *key = static_cast<const int32_t *>(a.key);
+  int32_t k[16];
+  bool ok[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r0 = t * TILE + int64_t{q} * 1024 + int64_t{threadIdx.x} * 4;
+    if (r0 + 4 <= n) {
+      const v4i32 v = *reinterpret_cast<const v4i32 *>(key + r0);
+      k[4 * q] = v.x;
+      k[4 * q + 1] = v.y;
+      k[4 * q + 2] = v.z;
+      k[4 * q + 3] = v.w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ok[4 * q + j] = true;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ok[4 * q + j] = r0 + j < n;
+        k[4 * q + j] = ok[4 * q + j] ? key[r0 + j] : 0;
+      }
+    }
+  }
+  __syncthreads();
+  if (F <= 8) {  // uniform
+    int32_t c[8] = {};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t d = part_dest_key(a, k[j]);
+#pragma unroll
+      for (int f = 0; f < 8; ++f) c[f] += (ok[j] && d == static_cast<uint32_t>(f)) ? 1 : 0;
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const int32_t tot = wave_sum(c[f]);
+      if (lane == 0 && f < F) s_h[w][f] = tot;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (ok[j]) atomicAdd(&s_h[w][part_dest_key(a, k[j])], 1);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < F; p += BLOCK) {
+    int32_t tot = 0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) tot += s_h[v][p];
+    hist[int64_t{p} * ntiles + t] = tot;
+  }
+}
+
 template <int BLOCK, int ITEMS, int FMAX>
 __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_t *scan, int64_t ntiles) {
   constexpr int NW = BLOCK / kWave;
@@ -401,7 +465,10 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
 template <int FMAX>
 static void launch_partition(const PartArgs &a, int32_t *hist, int32_t *scan, int64_t ntiles, hipStream_t stream,
                              bool hist_phase) {
-  if (hist_phase)
+  if (hist_phase && FMAX <= 64 && !a.sel && !a.key64 && a.radix_shift < 0 && !a.d_nsel && kPartTile == 4096 &&
+      (reinterpret_cast<uintptr_t>(a.key) & 15) == 0)
+    k_part_hist_i32<64><<<static_cast<unsigned>(ntiles), 256, 0, stream>>>(a, hist, ntiles);
+  else if (hist_phase)
     k_part_hist<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, hist, ntiles);
   else
     k_part_scatter<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, scan, ntiles);
