@@ -397,9 +397,16 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
   int32_t pos[ITEMS];
   uint16_t dst[ITEMS];
   int64_t keyv[ITEMS];
+  // The first two payload columns are loaded with the keys (one memory round
+  // trip per tile instead of one per column); later ones in the column loop.
+  constexpr int PRE = 2;
+  int64_t pre[PRE][ITEMS];
   {
     int64_t r64[ITEMS];
     part_load<ITEMS>(a, wbase, cnt, r64, keyv);
+#pragma unroll
+    for (int c = 0; c < PRE; ++c)
+      if (c < a.npay && wbase < cnt) load_items<ITEMS>(a.pay[c], a.pay64[c], r64, a.n, pre[c]);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) rowv[j] = static_cast<int32_t>(r64[j]);
   }
@@ -442,6 +449,13 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j)
         if (pos[j] >= 0) s_stage[pos[j]] = keyv[j];
+    } else if (c <= PRE && wbase < cnt) {
+#pragma unroll
+      for (int q = 0; q < PRE; ++q)
+        if (q == c - 1)
+#pragma unroll
+          for (int j = 0; j < ITEMS; ++j)
+            if (pos[j] >= 0) s_stage[pos[j]] = pre[q][j];
     } else if (wbase < cnt) {
       int64_t rr[ITEMS], x[ITEMS];
 #pragma unroll
@@ -471,7 +485,10 @@ static void launch_partition(const PartArgs &a, int32_t *hist, int32_t *scan, in
   else if (hist_phase)
     k_part_hist<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, hist, ntiles);
   else
-    k_part_scatter<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, scan, ntiles);
+    // the same 4096-row tiles as the histogram, as 512 threads x 8 rows (fewer
+    // registers per thread with the payloads loaded up front)
+    k_part_scatter<2 * kPartBlock, kPartItems / 2, FMAX><<<static_cast<unsigned>(ntiles), 2 * kPartBlock, 0, stream>>>(
+        a, scan, ntiles);
 }
 
 pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_t len, int64_t *d_total,
