@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int
   (void)nloc;
   const int64_t begin = local * fr.rows_per_unit;
   const int64_t end = begin + fr.rows_per_unit < fr.fa.n ? begin + fr.rows_per_unit : fr.fa.n;
-  fact_range<1, 4, 0, V64, true>(fr.fa, fr.t, fr.t, GroupDev{}, PairsOut{}, err, nullptr, false, begin, int64_t{BS} * 4, end);
+  star_range<0, V64, true, 4>(fr.fa, fr.t, err, nullptr, false, begin, int64_t{BS} * 4, end, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {

@@ -35,6 +35,7 @@ constexpr int64_t kBloomMaxKeys = (int64_t{32} << kBloomLgw) * 2 / 3;  // above 
 constexpr int kDimTile = 4096;                      // rows per block of the dimension filter
 constexpr int kFastBlock = 1024;                    // one block of 16 waves per CU next to the 128 KiB filter
 constexpr int kBufOob = 0x7ffffff0;                 // buffer offset beyond any table: load returns 0, no access
+constexpr int kNonTemporal = 2;                     // cache policy of streamed columns: keep the table in the L2
 constexpr int kBufferDword3 = 0x00020000;           // raw buffer resource word 3 on CDNA
 
 // Bucketed slot sums (single-join queries grouped by the join key).  Random
@@ -353,14 +354,16 @@ __device__ __forceinline__ FactRows<R> load_rows(const FastArgs &a, int64_t wbas
   FactRows<R> x;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    x.f0[q] = __builtin_amdgcn_raw_buffer_load_b128(rf0, off + 16 * q, 0, 0);
-    x.f1[q] = NJ > 1 ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rf1, off + 16 * q, 0, 0)) : v4i32{0, 0, 0, 0};
-    x.c0[q] = __builtin_amdgcn_raw_buffer_load_b128(rc0, off + 16 * q, 0, 0);
+    x.f0[q] = __builtin_amdgcn_raw_buffer_load_b128(rf0, off + 16 * q, 0, kNonTemporal);
+    x.f1[q] = NJ > 1 ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rf1, off + 16 * q, 0, kNonTemporal))
+                     : v4i32{0, 0, 0, 0};
+    x.c0[q] = __builtin_amdgcn_raw_buffer_load_b128(rc0, off + 16 * q, 0, kNonTemporal);
   }
   // (a uniform branch: a plan without a second predicate issues no load for it)
 #pragma unroll
   for (int q = 0; q < R / 4; ++q)
-    x.c1[q] = a.pcol[1] ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rc1, off + 16 * q, 0, 0)) : v4i32{0, 0, 0, 0};
+    x.c1[q] = a.pcol[1] ? v4i32(__builtin_amdgcn_raw_buffer_load_b128(rc1, off + 16 * q, 0, kNonTemporal))
+                        : v4i32{0, 0, 0, 0};
   const int64_t left = end - wbase;
   if (left > 0 && left < WR && (left & 3)) {  // wave-uniform; once per range
     const int l = static_cast<int>(left);
@@ -709,6 +712,276 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   }
 }
 
+// Pushes the live rows of a wave step to consecutive lanes: the row with
+// compact index j (rows taken r-major: every lane's row 0, then row 1, ...)
+// lands in lane j - w0.  m[r]: the lanes whose row r is live; b[r]: the compact
+// index of the first of them.  The other lanes are pushed to the remaining
+// lanes, so each push is a permutation.  Returns the key and the row within
+// the step (lane * R + r) of this lane's compact row.
+template <int R>
+__device__ __forceinline__ void compact_rows(const uint64_t (&m)[R], const uint32_t (&b)[R], const int32_t (&key)[R],
+                                             int lane, uint32_t w0, int32_t *ck, int32_t *crow) {
+  int32_t kv[R], lv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t below = mbcnt(m[r]);
+    const uint32_t c = static_cast<uint32_t>(__popcll(m[r]));
+    const uint32_t pos = (m[r] >> lane) & 1 ? below : c + (static_cast<uint32_t>(lane) - below);
+    const int dst = static_cast<int>((pos + b[r] - w0) & (kWave - 1));
+    kv[r] = __builtin_amdgcn_ds_permute(dst << 2, key[r]);
+    lv[r] = __builtin_amdgcn_ds_permute(dst << 2, lane);
+  }
+  const uint32_t j = w0 + static_cast<uint32_t>(lane);
+  int32_t k = kv[0], src = lv[0], rr = 0;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const bool mine = j >= b[r];
+    k = mine ? kv[r] : k;
+    src = mine ? lv[r] : src;
+    rr = mine ? r : rr;
+  }
+  *ck = k;
+  *crow = src * R + rr;
+}
+
+// Walks the run of full groups after group `s` for key k, reading at most
+// `groups` more groups; the slot of k, or -1.
+__device__ __forceinline__ int32_t walk_run(__amdgpu_buffer_rsrc_t r0, int32_t mask, int32_t s, int32_t groups,
+                                            int32_t k) {
+  for (; groups > 0; --groups) {
+    s = (s + 4) & mask;
+    bool empty;
+    const int h = match4(__builtin_amdgcn_raw_buffer_load_b128(r0, s * 4, 0, 0), k, &empty);
+    if (h >= 0) return s + h;
+    if (empty) return -1;
+  }
+  return -1;
+}
+
+// The one-join fact pass (star query) over rows [begin, end), summing into the
+// join table's slots: AGG 0 adds with buffer atomics plus a group-exists flag,
+// AGG 3 stages (slot, value) pairs in LDS and moves them to the bucket pool.
+//
+// Each wave takes R rows per lane per step.  After the predicates and the
+// Bloom filter only a fifth of the rows are live, so they are first pushed
+// together (compact_rows): one 16-byte probe and one value load per lane then
+// serve 64 live rows, where per-row loads would issue R instructions each,
+// mostly for dead lanes (every issued lane costs address-unit time even when
+// it touches no memory).  A key not settled by its first 16-byte group is
+// carried to the next step, whose probes load its next group (no round trip of
+// its own); one carried key per lane, another one walks its run at once.
+template <int AGG, bool V64, bool VX, int R>
+__device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0, uint32_t *err,
+                                           const PYST_LDS uint32_t *s_bloom, bool use_bloom, int64_t begin,
+                                           int64_t step, int64_t end, const BucketPool *bp, const StageLds *sl) {
+  static_assert(AGG == 0 || AGG == 3, "star_range sums into the join table");
+  constexpr int64_t WR = int64_t{kWave} * R;
+  const int64_t cap0 = t0.hdr[0];
+  const int32_t mask0 = static_cast<int32_t>(cap0 - 1);
+  const int32_t groups0 = static_cast<int32_t>(cap0 >> 2);  // 16-byte groups in the table
+  const int bshift = bloom_shift(cap0);
+  const __amdgpu_buffer_rsrc_t r0 = rsrc(t0.slots, cap0 * 4);
+  const __amdgpu_buffer_rsrc_t rsum = rsrc(AGG == 0 ? t0.sums : nullptr, AGG == 0 ? cap0 * 8 : 0);
+  const __amdgpu_buffer_rsrc_t rflag = rsrc(AGG == 0 ? t0.flags : nullptr, AGG == 0 ? cap0 : 0);
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  int64_t wbase = begin + int64_t{wv} * WR;
+  bool pend = false;  // the carried key of this lane
+  int32_t pkey = 0, ppos = 0, pleft = 0;  // key, its next group, groups it may still read
+  int64_t pval = 0;
+  FactRows<R> cur = load_rows<1, R>(a, wbase, end, lane);
+  if (AGG == 0) {
+    // Stand-ins for the adds that end every step, into an empty buffer (no
+    // memory access), so that the loop is entered with as many operations
+    // younger than `cur` as it repeats with.  Distinct per-lane offsets keep
+    // the compiler from merging them.
+    const __amdgpu_buffer_rsrc_t none = rsrc(nullptr, 0);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) pyst_buffer_atomic_add_i64(0, none, lane * 128 + e * 8, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), none, lane * 128 + 64 + e, 0, 0);
+  }
+  const uint32_t nb = AGG == 3 ? bucket_count(cap0) : 0;
+  const uint32_t stage_cap = AGG == 3 && nb <= bp->stride ? kStageCap : 0;  // 0: every pair is added directly
+  // Adds this lane's entries (slot -1: none): AGG 0 adds in place, AGG 3 stages.
+  auto add = [&](const int32_t (&es)[2], const int64_t (&ev)[2]) {
+    if (AGG == 0) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) pyst_buffer_atomic_add_i64(ev[e], rsum, es[e] >= 0 ? es[e] * 8 : kBufOob, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), rflag, es[e] >= 0 ? es[e] : kBufOob, 0, 0);
+    } else {
+      uint64_t m[2];
+      bool st[2];  // staged, else added directly
+      uint32_t cw = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        st[e] = es[e] >= 0 && fits_rec(ev[e]);
+        m[e] = __ballot(st[e]);
+        cw += static_cast<uint32_t>(__popcll(m[e]));
+      }
+      uint32_t off = 0;
+      if (cw) {  // wave-uniform
+        if (lane == 0) off = lds_add(sl->cnt, cw);
+        off = __builtin_amdgcn_readfirstlane(off);
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (es[e] >= 0) {
+          const uint32_t p = st[e] ? off + mbcnt(m[e]) : stage_cap;
+          if (p < stage_cap) {
+            sl->slot[p] = static_cast<uint32_t>(es[e]);
+            sl->val[p] = static_cast<uint64_t>(ev[e]);
+          } else {  // staging full: add directly (the second kernel adds these in)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[es[e]]), static_cast<unsigned long long>(ev[e]));
+            t0.flags[es[e]] = 1;
+          }
+        }
+        off += static_cast<uint32_t>(__popcll(m[e]));
+      }
+    }
+  };
+  auto value = [&](int64_t x, int32_t w) -> int64_t {
+    return !VX || a.vexpr == PYST_V_COL
+               ? x
+               : static_cast<int64_t>(static_cast<uint64_t>(x) * static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w)));
+  };
+  uint32_t steps = 0;
+  // AGG 3 steps the whole block together (it meets at a barrier every
+  // kFlushEvery steps); otherwise each wave runs on its own.
+  for (; (AGG == 3 ? wbase - int64_t{wv} * WR : wbase) < end; wbase += step) {
+    const int64_t left64 = end - wbase;
+    const int left = static_cast<int>(left64 < WR ? left64 : WR);
+    uint64_t m[R];
+    uint32_t b[R], n = 0;
+    int32_t key[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      bool l = lane * R + r < left && in_range(row_of(cur.c0, r), a.plo[0], a.pspan[0], a.pneg[0]) &&
+               in_range(row_of(cur.c1, r), a.plo[1], a.pspan[1], a.pneg[1]);
+      key[r] = row_of(cur.f0, r);
+      if (use_bloom) {
+        const uint32_t h = table_hash32(key[r]);
+        const uint32_t bits = bloom_bits(h);
+        l = l && (s_bloom[bloom_word(h, cap0 - 1, bshift)] & bits) == bits;
+      }
+      m[r] = __ballot(l);
+      b[r] = n;
+      n += static_cast<uint32_t>(__popcll(m[r]));
+    }
+    n = __builtin_amdgcn_readfirstlane(n);
+    const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end, WR);
+    const __amdgpu_buffer_rsrc_t rw = window(VX ? a.v1 : nullptr, 4, wbase, end, WR);
+    // the first 64 live rows, the carried keys, then the next step's columns
+    int32_t ck, crow;
+    compact_rows<R>(m, b, key, lane, 0, &ck, &crow);
+    bool ok = static_cast<uint32_t>(lane) < n;
+    int32_t cs = static_cast<int32_t>(table_hash32(ck)) & mask0 & ~3;
+    const v4i32 q = __builtin_amdgcn_raw_buffer_load_b128(r0, ok ? cs * 4 : kBufOob, 0, 0);
+    const v4i32 qp = __builtin_amdgcn_raw_buffer_load_b128(r0, pend ? ppos * 4 : kBufOob, 0, 0);
+    int64_t x;
+    if (V64) {
+      const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, ok ? crow * 8 : kBufOob, 0, kNonTemporal);
+      x = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
+    } else {
+      x = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rv, ok ? crow * 4 : kBufOob, 0, 0));
+    }
+    const int32_t w = VX ? static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, ok ? crow * 4 : kBufOob, 0, 0)) : 0;
+    const FactRows<R> nxt = load_rows<1, R>(a, wbase + step, end, lane);
+    bool npend = false, nold = false;  // a key carried to the next step; it is the carried key again
+    int32_t nkey = 0, npos = 0, nleft = 0;
+    int32_t es[2] = {-1, -1};
+    {
+      bool empty;
+      const int h = match4(q, ck, &empty);
+      es[0] = ok && h >= 0 ? cs + h : -1;
+      if (ok && h < 0 && !empty && groups0 > 1) {
+        npend = true;
+        nkey = ck;
+        npos = (cs + 4) & mask0;
+        nleft = groups0 - 1;
+      }
+    }
+    if (pend) {
+      bool empty;
+      const int h = match4(qp, pkey, &empty);
+      if (h >= 0) {
+        es[1] = ppos + h;
+      } else if (!empty && pleft > 1) {
+        if (!npend) {
+          npend = nold = true;
+          nkey = pkey;
+          npos = (ppos + 4) & mask0;
+          nleft = pleft - 1;
+        } else {
+          es[1] = walk_run(r0, mask0, ppos, pleft - 1, pkey);
+        }
+      }
+    }
+    const int64_t v0 = value(x, w);
+    add(es, {v0, pval});
+    pval = nold ? pval : v0;
+    pend = npend;
+    pkey = nkey;
+    ppos = npos;
+    pleft = nleft;
+    // more than 64 live rows (rare at R = 4)
+    for (uint32_t w0 = kWave; w0 < n; w0 += kWave) {  // wave-uniform
+      compact_rows<R>(m, b, key, lane, w0, &ck, &crow);
+      ok = w0 + static_cast<uint32_t>(lane) < n;
+      cs = static_cast<int32_t>(table_hash32(ck)) & mask0 & ~3;
+      const v4i32 q2 = __builtin_amdgcn_raw_buffer_load_b128(r0, ok ? cs * 4 : kBufOob, 0, 0);
+      int64_t x2;
+      if (V64) {
+        const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, ok ? crow * 8 : kBufOob, 0, 0);
+        x2 = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
+      } else {
+        x2 = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rv, ok ? crow * 4 : kBufOob, 0, 0));
+      }
+      const int32_t w2 =
+          VX ? static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, ok ? crow * 4 : kBufOob, 0, 0)) : 0;
+      bool empty;
+      const int h = match4(q2, ck, &empty);
+      int32_t s2[2] = {ok && h >= 0 ? cs + h : -1, -1};
+      const int64_t v2 = value(x2, w2);
+      if (ok && h < 0 && !empty && groups0 > 1) {
+        if (!pend) {
+          pend = true;
+          pkey = ck;
+          ppos = (cs + 4) & mask0;
+          pleft = groups0 - 1;
+          pval = v2;
+        } else {
+          s2[0] = walk_run(r0, mask0, cs, groups0 - 1, ck);
+        }
+      }
+      add(s2, {v2, 0});
+    }
+    // Every kFlushEvery steps the block meets and moves its staged pairs to
+    // HBM once there are kFlushAt of them (pairs past kStageCap in between
+    // were added directly).
+    if (AGG == 3 && stage_cap > 0 && ++steps % kFlushEvery == 0) {  // block-uniform
+      __syncthreads();
+      if (*sl->cnt >= kFlushAt) stage_flush(*sl, *bp, nb, err);
+    }
+    cur = nxt;
+  }
+  if (pend) {  // the key still carried walks the rest of its run and is added directly
+    const int32_t s = walk_run(r0, mask0, (ppos - 4) & mask0, pleft, pkey);
+    if (s >= 0) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[s]), static_cast<unsigned long long>(pval));
+      t0.flags[s] = 1;
+    }
+  }
+  if (AGG == 3 && stage_cap > 0) {
+    __syncthreads();
+    if (*sl->cnt > 0) stage_flush(*sl, *bp, nb, err);  // block-uniform
+    if (threadIdx.x < nb) bp->fill[sl->chunk[threadIdx.x]] = sl->fill[threadIdx.x];
+  }
+}
+
 template <int NJ, int SB1, int AGG, bool V64, bool VX, int R = 4>
 __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t0, TableDev t1, GroupDev g, PairsOut po,
                                                          BucketPool bp, uint32_t *err) {
@@ -743,9 +1016,12 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
   if (use_bloom)
     for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];
   if (use_bloom || AGG == 3) __syncthreads();
-  fact_range<NJ, SB1, AGG, V64, VX, R>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom,
-                                   int64_t{blockIdx.x} * kFastBlock * R, int64_t{gridDim.x} * kFastBlock * R, a.n, &bp,
-                                   &sl);
+  const int64_t begin = int64_t{blockIdx.x} * kFastBlock * R, step = int64_t{gridDim.x} * kFastBlock * R;
+  if constexpr (NJ == 1 && (AGG == 0 || AGG == 3))
+    star_range<AGG, V64, VX, R>(a, t0, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n, &bp, &sl);
+  else
+    fact_range<NJ, SB1, AGG, V64, VX, R>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
+                                         step, a.n, &bp, &sl);
 }
 
 // Adds the pairs of up to 4 chunks (kNoChunk: none) into the LDS sums of their
