@@ -716,31 +716,35 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
 // compact index j (rows taken r-major: every lane's row 0, then row 1, ...)
 // lands in lane j - w0.  m[r]: the lanes whose row r is live; b[r]: the compact
 // index of the first of them.  The other lanes are pushed to the remaining
-// lanes, so each push is a permutation.  Returns the key and the row within
-// the step (lane * R + r) of this lane's compact row.
-template <int R>
-__device__ __forceinline__ void compact_rows(const uint64_t (&m)[R], const uint32_t (&b)[R], const int32_t (&key)[R],
-                                             int lane, uint32_t w0, int32_t *ck, int32_t *crow) {
-  int32_t kv[R], lv[R];
+// lanes, so each push is a permutation.  Gives this lane's compact row: its NV
+// values v[.][r] and its row within the step (lane * R + r).
+template <int R, int NV>
+__device__ __forceinline__ void compact_rows(const uint64_t (&m)[R], const uint32_t (&b)[R],
+                                             const int32_t (&v)[NV][R], int lane, uint32_t w0, int32_t (&out)[NV],
+                                             int32_t *crow) {
+  int32_t pv[NV][R], lv[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t below = mbcnt(m[r]);
     const uint32_t c = static_cast<uint32_t>(__popcll(m[r]));
     const uint32_t pos = (m[r] >> lane) & 1 ? below : c + (static_cast<uint32_t>(lane) - below);
     const int dst = static_cast<int>((pos + b[r] - w0) & (kWave - 1));
-    kv[r] = __builtin_amdgcn_ds_permute(dst << 2, key[r]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pv[i][r] = __builtin_amdgcn_ds_permute(dst << 2, v[i][r]);
     lv[r] = __builtin_amdgcn_ds_permute(dst << 2, lane);
   }
   const uint32_t j = w0 + static_cast<uint32_t>(lane);
-  int32_t k = kv[0], src = lv[0], rr = 0;
+  int32_t src = lv[0], rr = 0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = pv[i][0];
 #pragma unroll
   for (int r = 1; r < R; ++r) {
     const bool mine = j >= b[r];
-    k = mine ? kv[r] : k;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = mine ? pv[i][r] : out[i];
     src = mine ? lv[r] : src;
     rr = mine ? r : rr;
   }
-  *ck = k;
   *crow = src * R + rr;
 }
 
@@ -856,14 +860,14 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
     const int left = static_cast<int>(left64 < WR ? left64 : WR);
     uint64_t m[R];
     uint32_t b[R], n = 0;
-    int32_t key[R];
+    int32_t key[1][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       bool l = lane * R + r < left && in_range(row_of(cur.c0, r), a.plo[0], a.pspan[0], a.pneg[0]) &&
                in_range(row_of(cur.c1, r), a.plo[1], a.pspan[1], a.pneg[1]);
-      key[r] = row_of(cur.f0, r);
+      key[0][r] = row_of(cur.f0, r);
       if (use_bloom) {
-        const uint32_t h = table_hash32(key[r]);
+        const uint32_t h = table_hash32(key[0][r]);
         const uint32_t bits = bloom_bits(h);
         l = l && (s_bloom[bloom_word(h, cap0 - 1, bshift)] & bits) == bits;
       }
@@ -876,7 +880,11 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
     const __amdgpu_buffer_rsrc_t rw = window(VX ? a.v1 : nullptr, 4, wbase, end, WR);
     // the first 64 live rows, the carried keys, then the next step's columns
     int32_t ck, crow;
-    compact_rows<R>(m, b, key, lane, 0, &ck, &crow);
+    {
+      int32_t o[1];
+      compact_rows<R, 1>(m, b, key, lane, 0, o, &crow);
+      ck = o[0];
+    }
     bool ok = static_cast<uint32_t>(lane) < n;
     int32_t cs = static_cast<int32_t>(table_hash32(ck)) & mask0 & ~3;
     const v4i32 q = __builtin_amdgcn_raw_buffer_load_b128(r0, ok ? cs * 4 : kBufOob, 0, 0);
@@ -929,7 +937,11 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
     pleft = nleft;
     // more than 64 live rows (rare at R = 4)
     for (uint32_t w0 = kWave; w0 < n; w0 += kWave) {  // wave-uniform
-      compact_rows<R>(m, b, key, lane, w0, &ck, &crow);
+      {
+        int32_t o[1];
+        compact_rows<R, 1>(m, b, key, lane, w0, o, &crow);
+        ck = o[0];
+      }
       ok = w0 + static_cast<uint32_t>(lane) < n;
       cs = static_cast<int32_t>(table_hash32(ck)) & mask0 & ~3;
       const v4i32 q2 = __builtin_amdgcn_raw_buffer_load_b128(r0, ok ? cs * 4 : kBufOob, 0, 0);
@@ -982,6 +994,233 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
   }
 }
 
+// The two-join fact pass writing (group key, value) pairs (the chain query).
+// Rows that pass the predicates and join 0's Bloom filter are pushed to
+// consecutive lanes (compact_rows), probe join 0 and, when found there, join 1.
+// A probe not settled by its first 16-byte group reads the next group of every
+// such lane of the wave at once: one round trip per group for the whole wave,
+// where per-row probes would wait once per row.  Pairs go to the wave's current
+// run of kPairRun slots; a new run is reserved with one atomic when it fills
+// (a counter bumped by every wave for every group of rows serializes the pass).
+template <int SB1, bool V64, bool VX, int R>
+__device__ __forceinline__ void chain_range(const FastArgs &a, const TableDev &t0, const TableDev &t1,
+                                            const PairsOut &po, uint32_t *err, const PYST_LDS uint32_t *s_bloom,
+                                            bool use_bloom, int64_t begin, int64_t step, int64_t end) {
+  constexpr int64_t WR = int64_t{kWave} * R;
+  constexpr int GS = 16 / SB1;  // join 1 slots per 16-byte load
+  constexpr int NW = R / 4;     // windows of 64 live rows a step provides for (about a fifth of its rows live)
+  const int64_t cap0 = t0.hdr[0], cap1 = t1.hdr[0];
+  const int32_t mask0 = static_cast<int32_t>(cap0 - 1), mask1 = static_cast<int32_t>(cap1 - 1);
+  const int32_t groups0 = static_cast<int32_t>(cap0 / 4), groups1 = static_cast<int32_t>(cap1 / GS);
+  const int bshift = bloom_shift(cap0);
+  const __amdgpu_buffer_rsrc_t r0 = rsrc(t0.slots, cap0 * 4);
+  const __amdgpu_buffer_rsrc_t r1 = rsrc(t1.slots, cap1 * SB1);
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  int64_t wpos = 0, wend = 0;  // the wave's pair run, wave-uniform
+  int64_t wbase = begin + int64_t{wv} * WR;
+  FactRows<R> cur = load_rows<2, R>(a, wbase, end, lane);
+  v4i32 stand_in[NW];
+  {
+    // Stand-ins for join 1's probe and the two pair stores that end every
+    // step, on an empty buffer (no memory access), so that the loop is entered
+    // with as many operations younger than `cur` as it repeats with.
+    const __amdgpu_buffer_rsrc_t none = rsrc(nullptr, 0);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) stand_in[k] = __builtin_amdgcn_raw_buffer_load_b128(none, lane * 128 + 64 + 16 * k, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 2 * NW; ++e)
+      __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 128 + e * 8, 0, 0);
+  }
+  // join 1 after one 16-byte group: 1 found (payload in *pl), 0 absent, -1 the run goes on
+  auto probe1 = [&](v4i32 q, int32_t k, int32_t *pl) -> int {
+    if (SB1 == 4) {
+      bool empty;
+      const int h = match4(q, k, &empty);
+      *pl = 0;
+      return h >= 0 ? 1 : empty ? 0 : -1;
+    }
+    const int st = q.x == k ? 1 : q.x == kEmpty32 ? 0 : q.z == k ? 2 : q.z == kEmpty32 ? 0 : -1;
+    *pl = st == 1 ? q.y : q.w;
+    return st == 2 ? 1 : st;
+  };
+  struct Win {
+    int32_t k0, k1, crow, s0;
+    bool ok;
+    v4i32 q0;
+    int64_t x;
+    int32_t w;
+  };
+  // compact window w0 of the live rows and load its first group of join 0 and its values
+  auto issue = [&](const uint64_t (&m)[R], const uint32_t (&b)[R], const int32_t (&kv)[2][R], uint32_t w0,
+                   uint32_t n, __amdgpu_buffer_rsrc_t rv, __amdgpu_buffer_rsrc_t rw) -> Win {
+    Win W;
+    int32_t o[2];
+    compact_rows<R, 2>(m, b, kv, lane, w0, o, &W.crow);
+    W.k0 = o[0];
+    W.k1 = o[1];
+    W.ok = w0 + static_cast<uint32_t>(lane) < n;
+    W.s0 = static_cast<int32_t>(table_hash32(W.k0)) & mask0 & ~3;
+    W.q0 = __builtin_amdgcn_raw_buffer_load_b128(r0, W.ok ? W.s0 * 4 : kBufOob, 0, 0);
+    if (V64) {
+      const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, W.ok ? W.crow * 8 : kBufOob, 0, kNonTemporal);
+      W.x = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
+    } else {
+      W.x = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rv, W.ok ? W.crow * 4 : kBufOob, 0, kNonTemporal));
+    }
+    W.w = VX ? static_cast<int32_t>(
+                   __builtin_amdgcn_raw_buffer_load_b32(rw, W.ok ? W.crow * 4 : kBufOob, 0, kNonTemporal))
+             : 0;
+    return W;
+  };
+  // The pairs of one window: hit, the payload of join 1 in pl.
+  auto emit = [&](const Win &W, bool hit, int32_t pl) {
+    const int64_t lo = a.lo_src == PYST_G_JOIN_KEY ? (a.lo_idx == 0 ? W.k0 : W.k1) : pl;
+    const int64_t hi = a.hi_src == PYST_G_JOIN_KEY ? (a.hi_idx == 0 ? W.k0 : W.k1) : pl;
+    const int64_t gkey = a.hi_src == PYST_G_NONE
+                             ? lo
+                             : static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+    if (hit && gkey == kEmpty64) latch(err, kErrKey);
+    const int64_t val = !VX || a.vexpr == PYST_V_COL
+                            ? W.x
+                            : static_cast<int64_t>(static_cast<uint64_t>(W.x) *
+                                                   static_cast<uint64_t>(a.vconst - static_cast<int64_t>(W.w)));
+    const uint64_t mm = __ballot(hit);
+    const int c = __popcll(mm);
+    if (c > 0 && wpos + c > wend) {  // wave-uniform, once per kPairRun pairs
+      for (int64_t p = wpos + lane; p < wend; p += kWave)
+        if (p < po.cap) po.keys[p] = kEmpty64;
+      unsigned long long rb = 0;
+      if (lane == 0)
+        rb = atomicAdd(reinterpret_cast<unsigned long long *>(po.count), static_cast<unsigned long long>(kPairRun));
+      wpos = uniform64(static_cast<int64_t>(__shfl(rb, 0)));
+      wend = wpos + kPairRun;
+    }
+    // the 64 pair slots from wpos, clipped to the buffer
+    int64_t room = po.cap - wpos;
+    room = room < 0 ? 0 : room > kWave ? kWave : room;
+    const __amdgpu_buffer_rsrc_t rk = rsrc(po.keys + wpos, room * 8);
+    const __amdgpu_buffer_rsrc_t rvv = rsrc(po.vals + wpos, room * 8);
+    const int off = hit ? static_cast<int>(mbcnt(mm)) * 8 : kBufOob;
+    __builtin_amdgcn_raw_buffer_store_b64(split64(gkey), rk, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(split64(val), rvv, off, 0, 0);
+    wpos += c;
+  };
+  // Both probes of the windows W[0..K).  Each table is read for all K windows
+  // before any wait, and runs that go on past their first 16-byte group read
+  // their next group in one round trip for all lanes and windows that need it.
+  auto both_probes = [&](const auto &W) {
+    constexpr int K = sizeof(W) / sizeof(W[0]);
+    int32_t slot0[K], s[K];
+    bool need[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      bool empty;
+      const int h = match4(W[k].q0, W[k].k0, &empty);
+      slot0[k] = W[k].ok && h >= 0 ? W[k].s0 + h : -1;
+      need[k] = W[k].ok && h < 0 && !empty && groups0 > 1;
+      s[k] = W[k].s0;
+    }
+    for (int32_t g = groups0 - 1;; --g) {
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) any = any || need[k];
+      if (__ballot(any) == 0) break;  // wave-uniform
+      v4i32 q[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        s[k] = (s[k] + 4) & mask0;
+        q[k] = __builtin_amdgcn_raw_buffer_load_b128(r0, need[k] ? s[k] * 4 : kBufOob, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        bool empty;
+        const int h = match4(q[k], W[k].k0, &empty);
+        if (need[k] && h >= 0) slot0[k] = s[k] + h;
+        need[k] = need[k] && h < 0 && !empty && g > 1;
+      }
+    }
+    v4i32 q1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      s[k] = static_cast<int32_t>(table_hash32(W[k].k1)) & mask1 & ~(GS - 1);
+      q1[k] = __builtin_amdgcn_raw_buffer_load_b128(r1, slot0[k] >= 0 ? s[k] * SB1 : kBufOob, 0, 0);
+    }
+    int state[K];
+    int32_t pl[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      state[k] = probe1(q1[k], W[k].k1, &pl[k]);
+      need[k] = slot0[k] >= 0 && state[k] < 0 && groups1 > 1;
+    }
+    for (int32_t g = groups1 - 1;; --g) {
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) any = any || need[k];
+      if (__ballot(any) == 0) break;  // wave-uniform
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        s[k] = (s[k] + GS) & mask1;
+        q1[k] = __builtin_amdgcn_raw_buffer_load_b128(r1, need[k] ? s[k] * SB1 : kBufOob, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        int32_t pl2;
+        const int st2 = probe1(q1[k], W[k].k1, &pl2);
+        if (need[k] && st2 >= 0) {
+          state[k] = st2;
+          pl[k] = pl2;
+        }
+        need[k] = need[k] && st2 < 0 && g > 1;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) emit(W[k], slot0[k] >= 0 && state[k] == 1, pl[k]);
+  };
+  for (; wbase < end; wbase += step) {
+    const int64_t left64 = end - wbase;
+    const int left = static_cast<int>(left64 < WR ? left64 : WR);
+    uint64_t m[R];
+    uint32_t b[R], n = 0;
+    int32_t kv[2][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      bool l = lane * R + r < left && in_range(row_of(cur.c0, r), a.plo[0], a.pspan[0], a.pneg[0]) &&
+               in_range(row_of(cur.c1, r), a.plo[1], a.pspan[1], a.pneg[1]);
+      kv[0][r] = row_of(cur.f0, r);
+      kv[1][r] = row_of(cur.f1, r);
+      if (use_bloom) {
+        const uint32_t h = table_hash32(kv[0][r]);
+        const uint32_t bits = bloom_bits(h);
+        l = l && (s_bloom[bloom_word(h, cap0 - 1, bshift)] & bits) == bits;
+      }
+      m[r] = __ballot(l);
+      b[r] = n;
+      n += static_cast<uint32_t>(__popcll(m[r]));
+    }
+    n = __builtin_amdgcn_readfirstlane(n);
+    const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end, WR);
+    const __amdgpu_buffer_rsrc_t rw = window(VX ? a.v1 : nullptr, 4, wbase, end, WR);
+    // NW windows go through each probe together, so that a step waits for
+    // each table once; windows past them (rare) go one at a time.
+    Win W[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) W[k] = issue(m, b, kv, k * kWave, n, rv, rw);
+    const FactRows<R> nxt = load_rows<2, R>(a, wbase + step, end, lane);
+    both_probes(W);
+    for (uint32_t w0 = NW * kWave; w0 < n; w0 += kWave) {  // wave-uniform; rare
+      Win W2[1] = {issue(m, b, kv, w0, n, rv, rw)};
+      both_probes(W2);
+    }
+    cur = nxt;
+  }
+  for (int64_t p = wpos + lane; p < wend; p += kWave)
+    if (p < po.cap) po.keys[p] = kEmpty64;
+#pragma unroll
+  for (int k = 0; k < NW; ++k)
+    if (stand_in[k].x != 0) latch(err, kErrKey);  // never: an empty buffer reads 0
+}
+
 template <int NJ, int SB1, int AGG, bool V64, bool VX, int R = 4>
 __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t0, TableDev t1, GroupDev g, PairsOut po,
                                                          BucketPool bp, uint32_t *err) {
@@ -1019,6 +1258,8 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
   const int64_t begin = int64_t{blockIdx.x} * kFastBlock * R, step = int64_t{gridDim.x} * kFastBlock * R;
   if constexpr (NJ == 1 && (AGG == 0 || AGG == 3))
     star_range<AGG, V64, VX, R>(a, t0, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n, &bp, &sl);
+  else if constexpr (NJ == 2 && AGG == 2)
+    chain_range<SB1, V64, VX, R>(a, t0, t1, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n);
   else
     fact_range<NJ, SB1, AGG, V64, VX, R>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
                                          step, a.n, &bp, &sl);
