@@ -50,17 +50,22 @@ constexpr int kBucketLg = 13;
 constexpr int64_t kBucketSlots = int64_t{1} << kBucketLg;  // 64 KiB of LDS sums in the second kernel
 constexpr int kMaxBuckets = 128;                            // staged join tables: up to 2^20 slots
 constexpr int kMaxSumBuckets = 512;                         // second-kernel blocks: tables up to 2^22 slots
-constexpr uint32_t kStageCap = 2048;                        // staged pairs per block (24 KiB of LDS)
+constexpr uint32_t kStageCap = 3712;                        // staged pairs per block (29 KiB: the LDS the filter leaves)
 constexpr uint32_t kFlushAt = 1024;                         // staged pairs that trigger a move to HBM
-constexpr int kFlushEvery = 2;                              // steps between the block's staging checks (4 rows per lane)
+constexpr uint32_t kCheckMax = 8;                           // most steps between the block's staging checks
+constexpr int kStageSlotBits = 20;                          // slot bits of a staged pair: kMaxBuckets buckets
 constexpr int kStarRows = 4;                                // rows per lane and step of the staged fact pass
 constexpr uint32_t kChunk = 512;                            // pairs per chunk
 constexpr uint32_t kNoChunk = 0xffffffffu;
 
-// A staged value must fit in 64 - kBucketLg bits (two's complement); others
-// are added directly.
-__device__ __forceinline__ bool fits_rec(int64_t v) {
-  const int64_t t = v >> (63 - kBucketLg);
+static_assert((int64_t{kMaxBuckets} << kBucketLg) == (int64_t{1} << kStageSlotBits), "staged slot bits");
+
+// A staged pair is one 8-byte word, value << kStageSlotBits | slot, so the
+// value must fit in 64 - kStageSlotBits bits (two's complement); others are
+// added directly.  (Its chunk record, value << kBucketLg | slot within the
+// bucket, then fits too.)
+__device__ __forceinline__ bool fits_stage(int64_t v) {
+  const int64_t t = v >> (63 - kStageSlotBits);
   return t == 0 || t == -1;
 }
 
@@ -389,8 +394,7 @@ __device__ __forceinline__ uint32_t lds_add(PYST_LDS uint32_t *p, uint32_t v) {
 
 // A block's LDS staging area of (slot, value) pairs and its current chunk per bucket.
 struct StageLds {
-  PYST_LDS uint32_t *slot;
-  PYST_LDS uint64_t *val;
+  PYST_LDS uint64_t *ent;      // staged pairs: value << kStageSlotBits | slot
   PYST_LDS uint32_t *cnt;      // staged pairs (may exceed kStageCap: the excess was added directly)
   PYST_LDS uint32_t *chunk;    // [kMaxBuckets] current chunk
   PYST_LDS uint32_t *fill;     // [kMaxBuckets] pairs in it
@@ -404,7 +408,9 @@ struct StageLds {
 __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool &bp, uint32_t nb, uint32_t *err) {
   const uint32_t tid = threadIdx.x;
   const uint32_t n = *sl.cnt < kStageCap ? *sl.cnt : kStageCap;
-  for (uint32_t i = tid; i < n; i += kFastBlock) lds_add(&sl.hist[sl.slot[i] >> kBucketLg], 1u);
+  constexpr uint64_t slot_mask = (uint64_t{1} << kStageSlotBits) - 1;
+  for (uint32_t i = tid; i < n; i += kFastBlock)
+    lds_add(&sl.hist[static_cast<uint32_t>(sl.ent[i] & slot_mask) >> kBucketLg], 1u);
   __syncthreads();
   if (tid < nb) {
     const uint32_t t = sl.fill[tid] + sl.hist[tid];
@@ -428,12 +434,14 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
   }
   __syncthreads();
   for (uint32_t i = tid; i < n; i += kFastBlock) {
-    const uint32_t s = sl.slot[i], b = s >> kBucketLg;
+    const uint64_t en = sl.ent[i];
+    const uint32_t s = static_cast<uint32_t>(en & slot_mask), b = s >> kBucketLg;
     const uint32_t pos = sl.fill[b] + lds_add(&sl.rank[b], 1u);
     if (pos >= kChunk && sl.newbase[b] == kNoChunk) continue;  // pool exhausted (error latched)
     const uint32_t c = pos < kChunk ? sl.chunk[b] : sl.newbase[b] + pos / kChunk - 1;
     const size_t e = size_t{c} * kChunk + pos % kChunk;
-    bp.rec[e] = (sl.val[i] << kBucketLg) | (s & (kBucketSlots - 1));
+    bp.rec[e] = static_cast<uint64_t>((static_cast<int64_t>(en) >> kStageSlotBits) << kBucketLg) |
+                (s & (kBucketSlots - 1));
   }
   __syncthreads();
   if (tid < nb) {
@@ -451,17 +459,20 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
   __syncthreads();
 }
 
-// The fact pass over rows [begin, end): wave w of the block takes the 256 rows
-// at begin + 256*w, then steps by `step` rows.  The next step's columns are
-// loaded while the current step's probes are in flight.  s_bloom is the
+// The general fact pass over rows [begin, end), adding into a group table
+// (AGG 1) or writing (group key, value) pairs (AGG 2), one or two joins, rows
+// probed where they are (the one-join slot sums and the two-join pairs have
+// the faster star_range and chain_range).  Wave w of the block takes the 256
+// rows at begin + 256*w, then steps by `step` rows.  The next step's columns
+// are loaded while the current step's probes are in flight.  s_bloom is the
 // block's LDS copy of join 0's filter (used when use_bloom).
 // VX: the value may be v0 * (c - v1) (the plan says which at run time); without
 // it the value is the column v0 and the v1 column is never read.
 template <int NJ, int SB1, int AGG, bool V64, bool VX, int R = 4>
 __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0, const TableDev &t1, const GroupDev &g,
                                            const PairsOut &po, uint32_t *err, const PYST_LDS uint32_t *s_bloom,
-                                           bool use_bloom, int64_t begin, int64_t step, int64_t end,
-                                           const BucketPool *bp = nullptr, const StageLds *sl = nullptr) {
+                                           bool use_bloom, int64_t begin, int64_t step, int64_t end) {
+  static_assert(AGG == 1 || AGG == 2, "sums into the join table go through star_range");
   constexpr int64_t WR = int64_t{kWave} * R;  // rows of one wave step: R consecutive rows per lane
   const int64_t cap0 = t0.hdr[0], mask0 = cap0 - 1;
   const int bshift = bloom_shift(cap0);
@@ -469,8 +480,6 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   const int64_t gmask = AGG == 1 ? g.hdr[0] - 1 : 0;
   const __amdgpu_buffer_rsrc_t r0 = rsrc(t0.slots, cap0 * 4);
   const __amdgpu_buffer_rsrc_t r1 = rsrc(NJ > 1 ? t1.slots : t0.slots, cap1 * SB1);
-  const __amdgpu_buffer_rsrc_t rsum = rsrc(AGG == 0 ? t0.sums : nullptr, AGG == 0 ? cap0 * 8 : 0);
-  const __amdgpu_buffer_rsrc_t rflag = rsrc(AGG == 0 ? t0.flags : nullptr, AGG == 0 ? cap0 : 0);
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   int64_t wpos = 0, wend = 0;  // the wave's pair run (AGG 2), wave-uniform
@@ -479,26 +488,13 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   // Stand-ins for the stores that end every step, into an empty buffer (no
   // memory access), so that the loop is entered with as many operations younger
   // than `cur` as it repeats with.  Distinct per-lane offsets keep the compiler
-  // from merging them or turning them into one lane's atomic.
-  {
+  // from merging them.
+  if (AGG == 2) {
     const __amdgpu_buffer_rsrc_t none = rsrc(nullptr, 0);
-    if (AGG == 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) pyst_buffer_atomic_add_i64(0, none, lane * 128 + r * 8, 0, 0);
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), none, lane * 128 + 64 + r, 0, 0);
-    } else if (AGG == 2) {
-#pragma unroll
-      for (int r = 0; r < 2 * R; ++r) __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 128 + r * 8, 0, 0);
-    }
+    for (int r = 0; r < 2 * R; ++r) __builtin_amdgcn_raw_buffer_store_b64(v2u32{0, 0}, none, lane * 128 + r * 8, 0, 0);
   }
-  const uint32_t nb = AGG == 3 ? bucket_count(cap0) : 0;
-  const uint32_t stage_cap = AGG == 3 && nb <= bp->stride ? kStageCap : 0;  // 0: every pair is added directly
-  uint32_t steps = 0;
-  // AGG 3 steps the whole block together (it meets at a barrier every step);
-  // otherwise each wave runs on its own.
-  for (; (AGG == 3 ? wbase - int64_t{wv} * WR : wbase) < end; wbase += step) {
+  for (; wbase < end; wbase += step) {
     const int64_t left64 = end - wbase;
     const int left = static_cast<int>(left64 < WR ? left64 : WR);
     bool live[R];
@@ -615,52 +611,7 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
       val[r] = !VX || a.vexpr == PYST_V_COL ? x0[r]
                                      : static_cast<int64_t>(static_cast<uint64_t>(x0[r]) *
                                                             static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w1[r])));
-    if (AGG == 0) {
-      // Sums in the join table's slots (adds that return nothing) and the
-      // group-exists flag of every hit (a sum alone cannot tell: it may be 0).
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        pyst_buffer_atomic_add_i64(val[r], rsum, slot0[r] >= 0 ? slot0[r] * 8 : kBufOob, 0, 0);
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        __builtin_amdgcn_raw_buffer_store_b8(static_cast<uint8_t>(1), rflag, slot0[r] >= 0 ? slot0[r] : kBufOob, 0, 0);
-    } else if (AGG == 3) {
-      uint64_t m[R];
-      uint32_t cw = 0;
-      bool st[R];  // staged, else added directly
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        st[r] = slot0[r] >= 0 && fits_rec(val[r]);
-        m[r] = __ballot(st[r]);
-        cw += static_cast<uint32_t>(__popcll(m[r]));
-      }
-      uint32_t off = 0;
-      if (cw) {  // wave-uniform
-        if (lane == 0) off = lds_add(sl->cnt, cw);
-        off = __builtin_amdgcn_readfirstlane(off);
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (slot0[r] >= 0) {
-          const uint32_t p = st[r] ? off + mbcnt(m[r]) : stage_cap;
-          if (p < stage_cap) {
-            sl->slot[p] = static_cast<uint32_t>(slot0[r]);
-            sl->val[p] = static_cast<uint64_t>(val[r]);
-          } else {  // staging full: add directly (the second kernel adds these in)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[slot0[r]]), static_cast<unsigned long long>(val[r]));
-            t0.flags[slot0[r]] = 1;
-          }
-        }
-        off += static_cast<uint32_t>(__popcll(m[r]));
-      }
-      // Every kFlushEvery steps the block meets and moves its staged pairs to
-      // HBM once there are kFlushAt of them (pairs past kStageCap in between
-      // were added directly).
-      if (stage_cap > 0 && ++steps % (R >= 8 ? 1 : kFlushEvery) == 0) {  // block-uniform
-        __syncthreads();
-        if (*sl->cnt >= kFlushAt) stage_flush(*sl, *bp, nb, err);
-      }
-    } else {
+    {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const bool hit = slot0[r] >= 0;
@@ -705,11 +656,6 @@ __device__ __forceinline__ void fact_range(const FastArgs &a, const TableDev &t0
   if (AGG == 2)
     for (int64_t p = wpos + lane; p < wend; p += kWave)
       if (p < po.cap) po.keys[p] = kEmpty64;
-  if (AGG == 3 && stage_cap > 0) {
-    __syncthreads();
-    if (*sl->cnt > 0) stage_flush(*sl, *bp, nb, err);  // block-uniform
-    if (threadIdx.x < nb) bp->fill[sl->chunk[threadIdx.x]] = sl->fill[threadIdx.x];
-  }
 }
 
 // Pushes the live rows of a wave step to consecutive lanes: the row with
@@ -822,7 +768,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
       uint32_t cw = 0;
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        st[e] = es[e] >= 0 && fits_rec(ev[e]);
+        st[e] = es[e] >= 0 && fits_stage(ev[e]);
         m[e] = __ballot(st[e]);
         cw += static_cast<uint32_t>(__popcll(m[e]));
       }
@@ -836,8 +782,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
         if (es[e] >= 0) {
           const uint32_t p = st[e] ? off + mbcnt(m[e]) : stage_cap;
           if (p < stage_cap) {
-            sl->slot[p] = static_cast<uint32_t>(es[e]);
-            sl->val[p] = static_cast<uint64_t>(ev[e]);
+            sl->ent[p] = (static_cast<uint64_t>(ev[e]) << kStageSlotBits) | static_cast<uint32_t>(es[e]);
           } else {  // staging full: add directly (the second kernel adds these in)
             atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[es[e]]), static_cast<unsigned long long>(ev[e]));
             t0.flags[es[e]] = 1;
@@ -852,9 +797,9 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
                ? x
                : static_cast<int64_t>(static_cast<uint64_t>(x) * static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w)));
   };
-  uint32_t steps = 0;
+  uint32_t since = 0, every = 2;  // steps since the last staging check; steps between checks
   // AGG 3 steps the whole block together (it meets at a barrier every
-  // kFlushEvery steps); otherwise each wave runs on its own.
+  // `every` steps); otherwise each wave runs on its own.
   for (; (AGG == 3 ? wbase - int64_t{wv} * WR : wbase) < end; wbase += step) {
     const int64_t left64 = end - wbase;
     const int left = static_cast<int>(left64 < WR ? left64 : WR);
@@ -971,12 +916,18 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
       }
       add(s2, {v2, 0});
     }
-    // Every kFlushEvery steps the block meets and moves its staged pairs to
-    // HBM once there are kFlushAt of them (pairs past kStageCap in between
-    // were added directly).
-    if (AGG == 3 && stage_cap > 0 && ++steps % kFlushEvery == 0) {  // block-uniform
+    // Every `every` steps the block meets and moves its staged pairs to HBM
+    // once there are kFlushAt of them (pairs past kStageCap in between were
+    // added directly).  The next interval is the number of steps whose pairs
+    // fill the staging area at the rate seen so far (all threads read the
+    // same count after the barrier, so it stays block-uniform).
+    if (AGG == 3 && stage_cap > 0 && ++since == every) {  // block-uniform
       __syncthreads();
-      if (*sl->cnt >= kFlushAt) stage_flush(*sl, *bp, nb, err);
+      const uint32_t c = *sl->cnt;
+      const uint32_t fit = kStageCap / (c / since + 1);
+      every = fit < 1 ? 1 : fit > kCheckMax ? kCheckMax : fit;
+      since = 0;
+      if (c >= kFlushAt) stage_flush(*sl, *bp, nb, err);
     }
     cur = nxt;
   }
@@ -1225,12 +1176,10 @@ template <int NJ, int SB1, int AGG, bool V64, bool VX, int R = 4>
 __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t0, TableDev t1, GroupDev g, PairsOut po,
                                                          BucketPool bp, uint32_t *err) {
   __shared__ uint32_t s_bloom[kBloomWords];
-  __shared__ uint32_t s_slot[AGG == 3 ? kStageCap : 1];
-  __shared__ uint64_t s_val[AGG == 3 ? kStageCap : 1];
+  __shared__ uint64_t s_ent[AGG == 3 ? kStageCap : 1];
   __shared__ uint32_t s_bk[AGG == 3 ? 5 * kMaxBuckets + 1 : 1];
   StageLds sl;
-  sl.slot = (PYST_LDS uint32_t *)s_slot;
-  sl.val = (PYST_LDS uint64_t *)s_val;
+  sl.ent = (PYST_LDS uint64_t *)s_ent;
   sl.chunk = (PYST_LDS uint32_t *)s_bk;
   sl.fill = sl.chunk + kMaxBuckets;
   sl.hist = sl.fill + kMaxBuckets;
@@ -1262,7 +1211,7 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
     chain_range<SB1, V64, VX, R>(a, t0, t1, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n);
   else
     fact_range<NJ, SB1, AGG, V64, VX, R>(a, t0, t1, g, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
-                                         step, a.n, &bp, &sl);
+                                         step, a.n);
 }
 
 // Adds the pairs of up to 4 chunks (kNoChunk: none) into the LDS sums of their
