@@ -173,6 +173,28 @@ def test_star_tables_too_large_to_stage(gpu, ctx, path, nb):
     np.testing.assert_array_equal(s, ws)
 
 
+@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("preds", [True, False])
+def test_star_nearly_full_table(gpu, ctx, path, preds):
+    # the join table at load ~0.92: many probes run past their first 16-byte
+    # group (carried into the next step, carried again, walked at once when the
+    # lane already carries one, or walked after the last step); without
+    # predicates every row is live, so every wave step has more than 64 live
+    # rows and the staging area fills within a step
+    nb = 150_000 if preds else 240_000  # 30k or 240k keys in a 32k- or 256k-slot table
+    b, p = gen.star_tables(nb, 2_000_003)
+    bd = {k: dev(v) for k, v in b.items()}
+    plan = gpu.star_plan(bd, max_load=0.95)
+    if not preds:
+        plan.joins[0]["preds"] = []
+        plan.preds = []
+    k, s = run(gpu, ctx, plan, [dev(p[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, p) if preds else oracle.star_query(b, p, build_preds=(), probe_preds=())
+    assert len(wk) > 0
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
 def _chain(n=1_000_003, na=40_000, nb=4_000, zs=0.0):
     a, b = gen.chain_dims(na, nb)
     f = gen.chain_fact(n, na, nb, zs)
@@ -188,6 +210,26 @@ def test_chain_both_paths(gpu, ctx, path, zs, max_groups):
                           max_groups=max_groups)
     k, s = run(gpu, ctx, plan, [dev(f[c]) for c in FACT_CHAIN], path)
     wk, ws = oracle.chain_query(a, b, f)
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("preds", [True, False])
+def test_chain_nearly_full_tables(gpu, ctx, path, preds):
+    # both join tables near load 0.92 (B keys-only, A key + payload, two slots
+    # per 16-byte group): runs past the first group in both probes, read for all
+    # lanes of a wave together; without predicates every row is live, so a
+    # wave step has several windows of 64 live rows
+    nb = 18_840 if preds else 3_768  # 3768 selected B keys in a 4096-slot table
+    a, b, f = _chain(n=1_000_003, na=30_000, nb=nb)
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()}, max_load=0.95)
+    if not preds:
+        plan.joins[0]["preds"] = []
+        plan.preds = []
+    k, s = run(gpu, ctx, plan, [dev(f[c]) for c in FACT_CHAIN], path)
+    wk, ws = oracle.chain_query(a, b, f) if preds else oracle.chain_query(a, b, f, b_preds=(), fact_preds=())
+    assert len(wk) > 0
     np.testing.assert_array_equal(k, wk)
     np.testing.assert_array_equal(s, ws)
 
