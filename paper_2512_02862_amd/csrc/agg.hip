@@ -87,29 +87,68 @@ __global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hi
   if (threadIdx.x < kRadix) hist[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part] = s_h[threadIdx.x];
 }
 
+// Writes each block's pairs to its positions (pos: the exclusive scan of
+// k_move_hist's counts).  A tile of kMoveTile pairs is ranked by bucket in LDS
+// (per-bucket counts with LDS atomics, one scan over kRadix buckets), laid out
+// bucket-major in LDS, and written so that consecutive threads write
+// consecutive slots of each bucket's run: every bucket's pairs of a tile leave
+// in one contiguous piece (about 512 bytes) instead of as 8-byte fragments.
+constexpr int kMoveTileItems = 4;
+static_assert(kRadix == kWave, "one wave scans the bucket counts");
+constexpr int kMoveTile = kAggBlock * kMoveTileItems;
 __global__ __launch_bounds__(kAggBlock) void k_move_scatter(MoveArgs m, const int32_t *pos, int64_t *okeys,
                                                            int64_t *ovals) {
-  __shared__ int32_t s_p[kRadix];
+  __shared__ int64_t s_k[kMoveTile];
+  __shared__ int64_t s_v[kMoveTile];
+  __shared__ uint8_t s_b[kMoveTile];
+  __shared__ int32_t s_base[kRadix], s_cnt[kRadix], s_off[kRadix + 1];
   int seg, part;
   int64_t lo, hi;
   move_range(m, &seg, &part, &lo, &hi);
-  if (threadIdx.x < kRadix) s_p[threadIdx.x] = pos[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part];
-  __syncthreads();
-  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * kMoveItems) {
-    int64_t k[kMoveItems], v[kMoveItems];
+  const int tid = static_cast<int>(threadIdx.x);
+  if (tid < kRadix) s_base[tid] = pos[(int64_t{seg} * kRadix + tid) * m.bps + part];
+  for (int64_t t0 = lo; t0 < hi; t0 += kMoveTile) {  // block-uniform
+    if (tid < kRadix) s_cnt[tid] = 0;
+    __syncthreads();
+    int64_t k[kMoveTileItems], v[kMoveTileItems];
+    int bk[kMoveTileItems], rk[kMoveTileItems];
 #pragma unroll
-    for (int u = 0; u < kMoveItems; ++u) {
-      const int64_t i = i0 + int64_t{u} * kAggBlock;
+    for (int u = 0; u < kMoveTileItems; ++u) {
+      const int64_t i = t0 + int64_t{u} * kAggBlock + tid;
       k[u] = i < hi ? m.keys[i] : kEmpty64;
       v[u] = i < hi ? m.vals[i] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kMoveItems; ++u) {
-      if (k[u] == kEmpty64) continue;
-      const int32_t p = atomicAdd(&s_p[(agg_hash(k[u]) >> m.shift) & (kRadix - 1)], 1);
-      okeys[p] = k[u];
-      ovals[p] = v[u];
+    for (int u = 0; u < kMoveTileItems; ++u) {
+      bk[u] = k[u] != kEmpty64 ? static_cast<int>((agg_hash(k[u]) >> m.shift) & (kRadix - 1)) : -1;
+      rk[u] = bk[u] >= 0 ? atomicAdd(&s_cnt[bk[u]], 1) : 0;
     }
+    __syncthreads();
+    if (tid < kWave) {  // one wave: exclusive scan of the kRadix (= 64) counts
+      const int c = s_cnt[tid];
+      const int incl = wave_inclusive_scan(c);
+      s_off[tid] = incl - c;
+      if (tid == kWave - 1) s_off[kRadix] = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMoveTileItems; ++u)
+      if (bk[u] >= 0) {
+        const int p = s_off[bk[u]] + rk[u];
+        s_k[p] = k[u];
+        s_v[p] = v[u];
+        s_b[p] = static_cast<uint8_t>(bk[u]);
+      }
+    __syncthreads();
+    const int n = s_off[kRadix];
+    for (int t = tid; t < n; t += kAggBlock) {
+      const int b = s_b[t];
+      const int64_t o = int64_t{s_base[b]} + (t - s_off[b]);
+      okeys[o] = s_k[t];
+      ovals[o] = s_v[t];
+    }
+    __syncthreads();
+    if (tid < kRadix) s_base[tid] += s_cnt[tid];
   }
 }
 
