@@ -152,9 +152,12 @@ __global__ __launch_bounds__(kAggBlock) void k_move_scatter(MoveArgs m, const in
   }
 }
 
-// Block b adds up bucket b, [pos[b * bps], pos[(b + 1) * bps]), in an LDS hash
-// table and appends its groups to the output with one counter atomic.
-// *d_ngroups must be zero on entry.
+// Adds up the pairs of each final bucket in an LDS hash table (indexed by low
+// bits of the key hash) and writes out its groups.  One block per CU walks its
+// buckets (blockIdx.x, + gridDim.x, ...): the table is cleared as it is written
+// out, and the next bucket's first pairs are loaded before the block waits for
+// the output position of the current one (one counter atomic per bucket), so a
+// bucket costs about one memory round trip.  *d_ngroups must be zero on entry.
 __global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys, const int64_t *vals,
                                                             const int32_t *pos, int bps, int64_t *out_keys,
                                                             int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
@@ -163,22 +166,24 @@ __global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys
   __shared__ uint64_t s_sum[kAggSlots];
   __shared__ int32_t s_w[kAggBlock / kWave];
   __shared__ int64_t s_base;
-  for (int s = threadIdx.x; s < kAggSlots; s += kAggBlock) {
+  constexpr int U = 4;  // pairs per thread per round, loaded before any insert
+  constexpr int PER = kAggSlots / kAggBlock;  // each thread counts, writes out and clears PER consecutive slots
+  const int tid = static_cast<int>(threadIdx.x);
+  for (int s = tid; s < kAggSlots; s += kAggBlock) {
     s_key[s] = static_cast<uint64_t>(kEmpty64);
     s_sum[s] = 0;
   }
-  __syncthreads();
-  const int64_t lo = pos[int64_t{blockIdx.x} * bps], hi = pos[int64_t{blockIdx.x + 1} * bps];
   bool full = false;
-  constexpr int U = 4;  // pairs per thread per round, loaded before any insert
-  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * U) {
-    int64_t kk[U], vv[U];
+  int64_t kk[U], vv[U];  // the first round of the bucket about to be added up
+  auto load_round = [&](int64_t i0, int64_t hi) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + int64_t{u} * kAggBlock;
       kk[u] = i < hi ? keys[i] : kEmpty64;
       vv[u] = i < hi ? vals[i] : 0;
     }
+  };
+  auto insert_round = [&]() {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (kk[u] == kEmpty64) continue;
@@ -197,40 +202,56 @@ __global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys
         s = (s + 1) & (kAggSlots - 1);
       }
     }
+  };
+  int b = static_cast<int>(blockIdx.x);
+  if (b < kAggBuckets) load_round(pos[int64_t{b} * bps] + tid, pos[int64_t{b + 1} * bps]);
+  __syncthreads();  // the cleared table
+  for (; b < kAggBuckets; b += static_cast<int>(gridDim.x)) {  // block-uniform
+    const int64_t lo = pos[int64_t{b} * bps], hi = pos[int64_t{b + 1} * bps];
+    insert_round();
+    for (int64_t i0 = lo + tid + int64_t{kAggBlock} * U; i0 < hi; i0 += int64_t{kAggBlock} * U) {  // large buckets
+      load_round(i0, hi);
+      insert_round();
+    }
+    __syncthreads();
+    const int s0 = tid * PER;
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c += s_key[s0 + j] != static_cast<uint64_t>(kEmpty64);
+    const int incl = wave_inclusive_scan(c);
+    const int w = tid / kWave;
+    if (lane_id() == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    // the next bucket's first round goes out before the wait for this one's position
+    const int nb = b + static_cast<int>(gridDim.x);
+    if (nb < kAggBuckets) load_round(pos[int64_t{nb} * bps] + tid, pos[int64_t{nb + 1} * bps]);
+    if (tid == 0) {
+      int64_t tot = 0;
+      for (int k = 0; k < kAggBlock / kWave; ++k) tot += s_w[k];
+      s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
+                                                    static_cast<unsigned long long>(tot)))
+                   : 0;
+    }
+    __syncthreads();
+    int64_t p = s_base + incl - c;
+    for (int k = 0; k < w; ++k) p += s_w[k];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint64_t k = s_key[s0 + j];
+      if (k == static_cast<uint64_t>(kEmpty64)) continue;
+      if (p < out_cap) {
+        out_keys[p] = static_cast<int64_t>(k);
+        out_sums[p] = static_cast<int64_t>(s_sum[s0 + j]);
+      } else {
+        latch(err, kErrCapacity);
+      }
+      ++p;
+      s_key[s0 + j] = static_cast<uint64_t>(kEmpty64);
+      s_sum[s0 + j] = 0;
+    }
+    __syncthreads();  // the table is clear (and s_base read) before the next bucket
   }
   if (full) latch(err, kErrTableFull);
-  __syncthreads();
-  constexpr int PER = kAggSlots / kAggBlock;  // each thread writes out PER consecutive slots
-  const int s0 = threadIdx.x * PER;
-  int c = 0;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) c += s_key[s0 + j] != static_cast<uint64_t>(kEmpty64);
-  const int incl = wave_inclusive_scan(c);
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == kWave - 1) s_w[w] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t tot = 0;
-    for (int k = 0; k < kAggBlock / kWave; ++k) tot += s_w[k];
-    s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
-                                                  static_cast<unsigned long long>(tot)))
-                 : 0;
-  }
-  __syncthreads();
-  int64_t p = s_base + incl - c;
-  for (int k = 0; k < w; ++k) p += s_w[k];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const uint64_t k = s_key[s0 + j];
-    if (k == static_cast<uint64_t>(kEmpty64)) continue;
-    if (p < out_cap) {
-      out_keys[p] = static_cast<int64_t>(k);
-      out_sums[p] = static_cast<int64_t>(s_sum[s0 + j]);
-    } else {
-      latch(err, kErrCapacity);
-    }
-    ++p;
-  }
 }
 
 // Groups of the pairs [0, min(*count, cap)) of keys/vals (kEmpty64 keys are
@@ -270,8 +291,9 @@ pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int6
   if (st != PYST_OK) return st;
   k_move_scatter<<<kRadix * kAggBlocks2, kAggBlock, 0, stream>>>(m2, p2, keys, vals);
   PYST_LAUNCH_CHECK("k_move_scatter");
-  k_bucket_groups<<<kAggBuckets, kAggBlock, 0, stream>>>(keys, vals, p2, kAggBlocks2, out_keys, out_sums, out_cap,
-                                                         d_ngroups, ctx_err_word(ctx));
+  const int gblocks = static_cast<int>(std::min<int64_t>(kAggBuckets, std::max(1, ctx_num_cus(ctx))));
+  k_bucket_groups<<<gblocks, kAggBlock, 0, stream>>>(keys, vals, p2, kAggBlocks2, out_keys, out_sums, out_cap,
+                                                     d_ngroups, ctx_err_word(ctx));
   PYST_LAUNCH_CHECK("k_bucket_groups");
   return PYST_OK;
 }
