@@ -3,9 +3,9 @@
 // Small inputs lose efficiency when each is processed by its own sequence of
 // launches and host round trips; the paper accumulates small chunks before
 // size-sensitive operators for the same reason (Sec. 5.3, "Dynamic
-// Buffering").  Here all fragments of a batch run through five launches in
-// total -- dimension filter, table init, build, fact pass, compaction -- each
-// launch covering every fragment.  A block finds its fragment by binary search
+// Buffering").  Here all fragments of a batch run through six launches in
+// total -- dimension filter, table init, build, Bloom filter, fact pass,
+// compaction -- each launch covering every fragment.  A block finds its fragment by binary search
 // over per-kernel block prefixes held in device memory.
 //
 // The batch path serves star-shaped fragments (one join, group by the join
@@ -38,7 +38,7 @@ struct BatFrag {
 };
 
 // Per-kernel block prefixes: blocks of fragment f are [pre[f], pre[f+1]).
-enum { kPreFilter = 0, kPreInit = 1, kPreBuild = 2, kPreFact = 3, kPreCompact = 4, kPreKinds = 5 };
+enum { kPreFilter = 0, kPreInit = 1, kPreBuild = 2, kPreBloom = 3, kPreFact = 4, kPreCompact = 5, kPreKinds = 6 };
 
 __device__ __forceinline__ int frag_of(const int64_t *pre, int nfrag, int64_t b) {
   int lo = 0, hi = nfrag - 1;  // largest f with pre[f] <= b
@@ -114,10 +114,12 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
     *fr.d_ngroups = 0;
   }
   int32_t *keys = static_cast<int32_t *>(t.slots);
+  const int64_t words = bloom_words(cap);
   for (int64_t i = tid; i < cap; i += nthr) {
     keys[i] = kEmpty32;
     t.sums[i] = 0;
     t.flags[i] = 0;
+    if (i < words) t.bloom[i] = 0;
   }
 }
 
@@ -152,13 +154,33 @@ __global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const i
   }
 }
 
+// Each fragment's Bloom filter, from its finished table (words past the ones
+// its capacity uses stay clear and are never read).
+__global__ __launch_bounds__(256) void k_bat_bloom(const BatFrag *frags, const int64_t *pre, int nfrag) {
+  PYST_BLOCK_FRAG(kPreBloom)
+  if (fr.t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use it
+  const int64_t words = bloom_words(fr.t.hdr[0]);
+  for (int64_t w = local * 256 + threadIdx.x; w < words; w += nloc * 256) bloom_build_word(fr.t, w);
+}
+
+// A work unit of a fragment's fact rows.  The block first copies the words of
+// the fragment's filter its table uses into LDS (a small table uses one word
+// per slot, so a small fragment copies little).
 template <int BS, bool V64>
 __global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
   PYST_BLOCK_FRAG(kPreFact)
   (void)nloc;
+  __shared__ uint32_t s_bloom[kBloomWords];
+  const bool use_bloom = fr.t.hdr[1] <= kBloomMaxKeys;
+  if (use_bloom) {
+    const int64_t words = bloom_words(fr.t.hdr[0]);
+    for (int64_t i = threadIdx.x; i < words; i += BS) s_bloom[i] = gmem(fr.t.bloom)[i];
+  }
+  __syncthreads();
   const int64_t begin = local * fr.rows_per_unit;
   const int64_t end = begin + fr.rows_per_unit < fr.fa.n ? begin + fr.rows_per_unit : fr.fa.n;
-  star_range<0, V64, true, 4>(fr.fa, fr.t, err, nullptr, false, begin, int64_t{BS} * 4, end, nullptr, nullptr);
+  star_range<0, V64, true, 4>(fr.fa, fr.t, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
+                              int64_t{BS} * 4, end, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
@@ -267,12 +289,14 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
     const int64_t cap_alloc = table_capacity_host(b.nb, b.max_load);
     b.t.cap_alloc = cap_alloc;
     b.t.slot_bytes = 4;
-    bp->table_bytes_total += (table_bytes(cap_alloc, 4, true) + 255) / 256 * 256;
+    bp->table_bytes_total += (table_bytes(cap_alloc, 4, true) + 255) / 256 * 256 +
+                             (static_cast<size_t>(bloom_words(cap_alloc)) * 4 + 255) / 256 * 256;
     bp->sel_bytes_total += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
     const int64_t blocks[kPreKinds] = {
         b.nblk,
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus)),
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(b.nb, 256), 16 * cus)),
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(bloom_words(cap_alloc), 256), 4 * cus)),
         ceil_div(std::max<int64_t>(fa.n, 1), b.rows_per_unit),
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus))};
     for (int k = 0; k < kPreKinds; ++k) bp->pre[k * (nfrag + 1) + f + 1] = bp->pre[k * (nfrag + 1) + f] + blocks[k];
@@ -295,6 +319,8 @@ static pyst_status batch_run(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, 
     BatFrag &b = bp.frags[f];
     b.t = table_view(p, b.t.cap_alloc, 4, true);
     p += (table_bytes(b.t.cap_alloc, 4, true) + 255) / 256 * 256;
+    b.t.bloom = reinterpret_cast<uint32_t *>(p);
+    p += (static_cast<size_t>(bloom_words(b.t.cap_alloc)) * 4 + 255) / 256 * 256;
   }
   for (int f = 0; f < nfrag; ++f) {
     BatFrag &b = bp.frags[f];
@@ -325,6 +351,7 @@ static pyst_status batch_run(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, 
     k_bat_filter<<<total(kPreFilter), 256, 0, stream>>>(d_frags, d_pre, nfrag);
     k_bat_init<<<total(kPreInit), 256, 0, stream>>>(d_frags, d_pre, nfrag);
     k_bat_build<<<total(kPreBuild), 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
+    k_bat_bloom<<<total(kPreBloom), 256, 0, stream>>>(d_frags, d_pre, nfrag);
     const bool v64 = bp.frags[0].fa.v0_64 != 0;
     for (int f = 1; f < nfrag; ++f)
       if ((bp.frags[f].fa.v0_64 != 0) != v64) {

@@ -244,11 +244,12 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
 // Bloom filter of a built keys-only table: thread w reads the slots whose home
 // word is w and ORs their keys' bits into word w with one atomic; a key that
 // probing moved into another word's slots ORs into its own word.
-__global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
+// Sets the filter bits of the keys whose home slots map to word w (words are
+// 1 << shift consecutive slots; a key displaced past its word's slots is
+// added to its own word with an atomic).  The filter must be clear first.
+__device__ __forceinline__ void bloom_build_word(const TableDev &t, int64_t w) {
   const int64_t cap = t.hdr[0], mask = cap - 1;
-  if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter
   const int shift = bloom_shift(cap);
-  const int64_t w = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
   const int64_t lo = w << shift, hi = (w + 1) << shift;
   if (lo >= cap) return;
   const int32_t *keys = static_cast<const int32_t *>(t.slots);
@@ -278,6 +279,17 @@ __global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
     }
   }
   if (acc) atomicOr(&t.bloom[w], acc);
+}
+
+// Words of the filter a table of capacity cap uses: a word covers 1 << shift
+// slots, so a table of fewer than kBloomWords slots uses one word per slot.
+__host__ __device__ __forceinline__ int64_t bloom_words(int64_t cap) {
+  return cap < kBloomWords ? cap : kBloomWords;
+}
+
+__global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
+  if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter
+  bloom_build_word(t, blockIdx.x * int64_t{blockDim.x} + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ the fact pass
