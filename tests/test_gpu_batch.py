@@ -87,3 +87,24 @@ def test_batch_with_empty_fragments(gpu, ctx):
         gk, gs = sorted_np(k, s)
         np.testing.assert_array_equal(gk, wk)
         np.testing.assert_array_equal(gs, ws)
+
+
+def test_batch_large_and_small_fragments(gpu, ctx):
+    # filters of every shape in one batch: tables of fewer than 32768 slots use
+    # one filter word per slot, larger ones several slots per word, and a
+    # fragment of a few rows copies a few words
+    spec = [(3_000_001, 1_000_000), (2_000, 200), (500_000, 400_000), (17, 5), (1_200_000, 40_000)]
+    frags, host = [], []
+    for f, (p, b) in enumerate(spec):
+        bt, pt = gen.star_tables(b, p, workload=3, fragment=100 + f)
+        bd = {k: dev(v) for k, v in bt.items()}
+        frags.append((gpu.star_plan(bd), [dev(pt[c]) for c in ("fk", "date", "price")]))
+        host.append((bt, pt))
+    batch = gpu.Batch(ctx, frags)
+    batch.run((64, 1024, 0.5))
+    ctx.check()
+    for (k, s), (bt, pt) in zip(batch.results(), host):
+        wk, ws = oracle.star_query(bt, pt)
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, wk)
+        np.testing.assert_array_equal(gs, ws)
