@@ -726,10 +726,10 @@ __device__ __forceinline__ int32_t walk_run(__amdgpu_buffer_rsrc_t r0, int32_t m
 //
 // Each wave takes R rows per lane per step.  After the predicates and the
 // Bloom filter only a fifth of the rows are live, so they are first pushed
-// together (compact_rows): one 16-byte probe and one value load per lane then
-// serve 64 live rows, where per-row loads would issue R instructions each,
-// mostly for dead lanes (every issued lane costs address-unit time even when
-// it touches no memory).  A key not settled by its first 16-byte group is
+// together (compact_rows): one 16-byte probe, one value load, one match and
+// one staging step per lane then serve 64 live rows, where per-row probing
+// repeats each of them R times, mostly for dead lanes.  A key not settled by
+// its first 16-byte group is
 // carried to the next step, whose probes load its next group (no round trip of
 // its own); one carried key per lane, another one walks its run at once.
 template <int AGG, bool V64, bool VX, int R>
