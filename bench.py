@@ -32,9 +32,11 @@ BUILD_ROW_BYTES = 8    # key int32 + segment int32
 GROUP_OUT_BYTES = 16   # key int64 + sum int64
 
 
-KERNEL_SOURCES = {  # the files that define each profiled kernel
+KERNEL_SOURCES = {  # the files that define each profiled kernel (name patterns as rocprofv3 prints them)
     "k_fast_fact": ["fast.hip", "pyst_internal.h", "table.h", "query.h"],
+    "k_fast_fact<2, 8, 2": ["fast.hip", "pyst_internal.h", "table.h", "query.h"],
 }
+CHAIN_WORKLOAD = "chain_a3000000_b300000_f120000000"  # fact-pass counters averaged over s = 0 and 1
 
 
 def source_hash(kernel="k_fast_fact"):
@@ -90,7 +92,9 @@ def summarize(args):
         "fetch_scale": ffac, "write_scale": wfac, "dispatches": [nf, nw], "source_hash": source_hash(kernel),
         "command": cmd}
     json.dump(rec, open(path, "w"), indent=1, sort_keys=True)
-    with open(os.path.join(prof, "%s_%s_traffic.txt" % (kernel, workload)), "w") as fh:
+    fname = "".join(ch if ch.isalnum() else "_" for ch in kernel).strip("_")
+    fname = "_".join(x for x in fname.split("_") if x)  # k_fast_fact<2, 8, 2 -> k_fast_fact_2_8_2
+    with open(os.path.join(prof, "%s_%s_traffic.txt" % (fname, workload)), "w") as fh:
         fh.write("# HBM traffic of %s on %s from rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE\n" % (kernel, workload))
         fh.write("# command: %s\n" % cmd)
         fh.write("FETCH_SIZE KiB/dispatch %.1f (x%.3f from a 1 GiB copy reading %.1f KiB)\n" % (fetch, ffac, cfetch))
@@ -329,6 +333,10 @@ def bench_chain(ctx, pyst, gen, log):
                            "fact_pass_us": fms / max(fn, 1) * 1e3}
         del f, fact, k, s
         torch.cuda.empty_cache()
+    # HBM bytes per launch of the chain's fact pass from committed counters (null
+    # when the kernel's source has changed since they were taken)
+    out["fact_pass_traffic"] = counter_traffic("k_fast_fact<2, 8, 2", CHAIN_WORKLOAD)
+    out["fact_pass_algorithmic_bytes"] = nf * 24
     return out
 
 
