@@ -420,6 +420,12 @@ def bench_batch(ctx, pyst, gen, log, nfrag, max_rows):
     ctx.check()
     el = timed_loop(lambda: batch.run(best), 5, 0)
     batched_s = el / 5
+    # the same batch captured once as a HIP graph and replayed
+    graph = batch.graph(best)
+    graph.launch()
+    ctx.check()
+    graph_s = timed_loop(graph.launch, 5, 0) / 5
+    graph.close()
 
     def one_at_a_time():
         for plan, fact in frags:
@@ -442,7 +448,8 @@ def bench_batch(ctx, pyst, gen, log, nfrag, max_rows):
     return {"fragments": nfrag, "probe_rows": total_rows, "tuning": {"fanout": best[0], "block": best[1],
             "max_load": best[2]}, "batched_ms": batched_s * 1e3, "sequential_ms": seq_s * 1e3,
             "batched_fragments_per_s": nfrag / batched_s, "sequential_fragments_per_s": nfrag / seq_s,
-            "speedup": seq_s / batched_s, "batched_probe_rows_per_s": total_rows / batched_s,
+            "speedup": seq_s / batched_s, "graph_ms": graph_s * 1e3, "graph_speedup": seq_s / graph_s,
+            "batched_probe_rows_per_s": total_rows / batched_s,
             "batched_gbs": total_rows * 16 / batched_s / 1e9, "result_mismatches": mismatches}
 
 

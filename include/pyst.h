@@ -321,8 +321,8 @@ typedef struct pyst_tuning {
   double max_load;
 } pyst_tuning;
 
-/* Run nfrag fragments as one batch: five launches in total (dimension filter,
-   table init, build, fact pass, compaction), each covering every fragment, in
+/* Run nfrag fragments as one batch: six launches in total (dimension filter,
+   table init, build, Bloom filter, fact pass, compaction), each covering every fragment, in
    place of a launch sequence and a host round trip per fragment -- the
    small-work inefficiency the paper counters by buffering small chunks into
    larger units (Sec. 5.3, "Dynamic Buffering").  Every fragment must be a
@@ -340,6 +340,27 @@ pyst_status pyst_query_batch(pyst_ctx *ctx, const pyst_fragment *frags, int nfra
    (may be NULL).  Errors: as pyst_query_batch. */
 pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, int reps, pyst_tuning *out,
                           double *best_ms);
+
+/* A batch captured once as a HIP graph of its six launches and replayed with
+   one hipGraphLaunch: the whole batch of uneven fragments becomes one unit of
+   work for the stream, with no host-side layout, upload or launch sequence per
+   run (the buffering of small work into large units, Sec. 5.3, carried down to
+   the launch itself).  pyst_batch_graph_create lays the batch out, allocates its
+   device memory from the context arena (held until destroy), uploads the
+   descriptors on `stream` and waits for them, then captures the launches on a
+   private stream.  Every replay recomputes every fragment from the current
+   contents of the inputs named at creation and overwrites the fragments'
+   outputs; the graph holds no memset node (tables are cleared by kernels).
+   Replays on one stream are ordered; replays that overlap on different streams
+   race on the batch's tables.  Errors: as pyst_query_batch. */
+typedef struct pyst_batch_graph pyst_batch_graph;
+pyst_status pyst_batch_graph_create(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, const pyst_tuning *tuning,
+                                    hipStream_t stream, pyst_batch_graph **out);
+/* Enqueue one replay on `stream`.  Errors: PYST_ERR_ARG, PYST_ERR_HIP. */
+pyst_status pyst_batch_graph_launch(pyst_batch_graph *g, hipStream_t stream);
+/* Wait for the device to be idle, then free the graph and its arena memory
+   (NULL: no-op).  Errors: PYST_ERR_HIP. */
+pyst_status pyst_batch_graph_destroy(pyst_batch_graph *g);
 
 /* ---------------------------------------------------------------- serving */
 

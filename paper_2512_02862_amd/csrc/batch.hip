@@ -11,6 +11,7 @@
 // The batch path serves star-shaped fragments (one join, group by the join
 // key, slot sums); every fragment has its own dimension, fact and outputs.
 #include <algorithm>
+#include <new>
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -304,11 +305,28 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
   return PYST_OK;
 }
 
-static pyst_status batch_run(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu,
-                             hipStream_t stream) {
+// A laid-out batch in device memory: descriptors, block prefixes, tables and
+// selections in one arena allocation, and the grid of each of its launches.
+struct BatchRun {
+  char *mem = nullptr;
+  const BatFrag *d_frags = nullptr;
+  const int64_t *d_pre = nullptr;
+  unsigned grid[kPreKinds] = {};
+  int nfrag = 0, block = 0;
+  bool v64 = false;
+};
+
+// Lays the fragments out, allocates their device memory and uploads the
+// descriptors on `stream`.
+static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu,
+                                 hipStream_t stream, BatchRun *run) {
   BatchPlan bp;
   pyst_status st = batch_layout(ctx, fr, nfrag, tu, &bp);
   if (st != PYST_OK) return st;
+  const bool v64 = bp.frags[0].fa.v0_64 != 0;
+  for (int f = 1; f < nfrag; ++f)
+    if ((bp.frags[f].fa.v0_64 != 0) != v64)
+      return set_error(PYST_ERR_UNSUPPORTED, "pyst_query_batch: value columns must share one dtype");
   const size_t desc_bytes = sizeof(BatFrag) * nfrag;
   const size_t pre_bytes = sizeof(int64_t) * bp.pre.size();
   const size_t meta = (desc_bytes + 255) / 256 * 256 + (pre_bytes + 255) / 256 * 256;
@@ -342,36 +360,69 @@ static pyst_status batch_run(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, 
     ctx_free(ctx, mem, stream);
     return hip_error(e, "pyst_query_batch: descriptor upload");
   }
-  const BatFrag *d_frags = reinterpret_cast<const BatFrag *>(mem);
-  const int64_t *d_pre = reinterpret_cast<const int64_t *>(mem + (desc_bytes + 255) / 256 * 256);
-  auto total = [&](int k) { return static_cast<unsigned>(bp.pre[k * (nfrag + 1) + nfrag]); };
-  uint32_t *err = ctx_err_word(ctx);
+  run->mem = mem;
+  run->d_frags = reinterpret_cast<const BatFrag *>(mem);
+  run->d_pre = reinterpret_cast<const int64_t *>(mem + (desc_bytes + 255) / 256 * 256);
+  for (int k = 0; k < kPreKinds; ++k) run->grid[k] = static_cast<unsigned>(bp.pre[k * (nfrag + 1) + nfrag]);
+  run->nfrag = nfrag;
+  run->block = tu.block;
+  run->v64 = v64;
+  return PYST_OK;
+}
+
+// The batch's six launches (also what a captured batch graph holds).
+static hipError_t batch_enqueue(const BatchRun &r, uint32_t *err, hipStream_t stream) {
+  const BatFrag *d_frags = r.d_frags;
+  const int64_t *d_pre = r.d_pre;
+  const int nfrag = r.nfrag;
+  k_bat_filter<<<r.grid[kPreFilter], 256, 0, stream>>>(d_frags, d_pre, nfrag);
+  k_bat_init<<<r.grid[kPreInit], 256, 0, stream>>>(d_frags, d_pre, nfrag);
+  k_bat_build<<<r.grid[kPreBuild], 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
+  k_bat_bloom<<<r.grid[kPreBloom], 256, 0, stream>>>(d_frags, d_pre, nfrag);
+#define PYST_BAT_FACT(BS_)                                                                                      \
+  if (r.block == BS_) {                                                                                       \
+    if (r.v64) k_bat_fact<BS_, true><<<r.grid[kPreFact], BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);        \
+    else k_bat_fact<BS_, false><<<r.grid[kPreFact], BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);             \
+  }
+  PYST_BAT_FACT(256)
+  PYST_BAT_FACT(512)
+  PYST_BAT_FACT(1024)
+#undef PYST_BAT_FACT
+  k_bat_compact<<<r.grid[kPreCompact], 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
+  return hipGetLastError();
+}
+
+static pyst_status batch_run(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu,
+                             hipStream_t stream) {
+  BatchRun r;
+  pyst_status st = batch_prepare(ctx, fr, nfrag, tu, stream, &r);
+  if (st != PYST_OK) return st;
+  hipError_t e;
   {
     TimedRegion timed(ctx, "batch", stream);
-    k_bat_filter<<<total(kPreFilter), 256, 0, stream>>>(d_frags, d_pre, nfrag);
-    k_bat_init<<<total(kPreInit), 256, 0, stream>>>(d_frags, d_pre, nfrag);
-    k_bat_build<<<total(kPreBuild), 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
-    k_bat_bloom<<<total(kPreBloom), 256, 0, stream>>>(d_frags, d_pre, nfrag);
-    const bool v64 = bp.frags[0].fa.v0_64 != 0;
-    for (int f = 1; f < nfrag; ++f)
-      if ((bp.frags[f].fa.v0_64 != 0) != v64) {
-        ctx_free(ctx, mem, stream);
-        return set_error(PYST_ERR_UNSUPPORTED, "pyst_query_batch: value columns must share one dtype");
-      }
-#define PYST_BAT_FACT(BS_)                                                                                      \
-  if (tu.block == BS_) {                                                                                      \
-    if (v64) k_bat_fact<BS_, true><<<total(kPreFact), BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);           \
-    else k_bat_fact<BS_, false><<<total(kPreFact), BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);              \
+    e = batch_enqueue(r, ctx_err_word(ctx), stream);
   }
-    PYST_BAT_FACT(256)
-    PYST_BAT_FACT(512)
-    PYST_BAT_FACT(1024)
-#undef PYST_BAT_FACT
-    k_bat_compact<<<total(kPreCompact), 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
-    e = hipGetLastError();
-  }
-  ctx_free(ctx, mem, stream);
+  ctx_free(ctx, r.mem, stream);
   if (e != hipSuccess) return hip_error(e, "pyst_query_batch: launch");
+  return PYST_OK;
+}
+
+}  // namespace pyst
+
+struct pyst_batch_graph {
+  pyst_ctx *ctx = nullptr;
+  char *mem = nullptr;  // the batch's arena memory, held while the graph exists
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace pyst {
+
+static pyst_status check_fragments(const pyst_fragment *frags, int nfrag, const char *who) {
+  for (int f = 0; f < nfrag; ++f)
+    if (!frags[f].plan || !frags[f].fact || !frags[f].d_ngroups || frags[f].out_cap < 0 ||
+        (frags[f].out_cap > 0 && (!frags[f].out_keys || !frags[f].out_sums)))
+      return set_error(PYST_ERR_ARG, who);
   return PYST_OK;
 }
 
@@ -392,11 +443,75 @@ pyst_status pyst_query_batch(pyst_ctx *ctx, const pyst_fragment *frags, int nfra
   if (nfrag == 0) return PYST_OK;
   pyst_tuning tu = tuning ? *tuning : pyst_tuning{64, 512, 0.0};
   if (!tuning_ok(tu)) return set_error(PYST_ERR_ARG, "pyst_query_batch: tuning fanout 1..65536, block 256/512/1024, max_load 0 or (0, 0.95]");
-  for (int f = 0; f < nfrag; ++f)
-    if (!frags[f].plan || !frags[f].fact || !frags[f].d_ngroups || frags[f].out_cap < 0 ||
-        (frags[f].out_cap > 0 && (!frags[f].out_keys || !frags[f].out_sums)))
-      return set_error(PYST_ERR_ARG, "pyst_query_batch: bad fragment");
+  const pyst_status st = check_fragments(frags, nfrag, "pyst_query_batch: bad fragment");
+  if (st != PYST_OK) return st;
   return batch_run(ctx, frags, nfrag, tu, stream);
+}
+
+pyst_status pyst_batch_graph_create(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, const pyst_tuning *tuning,
+                                    hipStream_t stream, pyst_batch_graph **out) {
+  if (!ctx || !frags || nfrag <= 0 || !out) return set_error(PYST_ERR_ARG, "pyst_batch_graph_create: NULL argument");
+  *out = nullptr;
+  pyst_tuning tu = tuning ? *tuning : pyst_tuning{64, 512, 0.0};
+  if (!tuning_ok(tu)) return set_error(PYST_ERR_ARG, "pyst_batch_graph_create: bad tuning");
+  pyst_status st = check_fragments(frags, nfrag, "pyst_batch_graph_create: bad fragment");
+  if (st != PYST_OK) return st;
+  BatchRun r;
+  st = batch_prepare(ctx, frags, nfrag, tu, stream, &r);
+  if (st != PYST_OK) return st;
+  auto fail = [&](hipError_t e, const char *what, hipStream_t cs, hipGraph_t g) {
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+    (void)hipStreamSynchronize(stream);
+    ctx_free(ctx, r.mem, stream);
+    return hip_error(e, what);
+  };
+  // the descriptors must be on the device before the graph may run
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(e, "pyst_batch_graph_create: descriptor upload", nullptr, nullptr);
+  hipStream_t cs = nullptr;
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+    return fail(e, "pyst_batch_graph_create: stream", nullptr, nullptr);
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return fail(e, "pyst_batch_graph_create: begin capture", cs, nullptr);
+  const hipError_t le = batch_enqueue(r, ctx_err_word(ctx), cs);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(cs, &g);
+  if (le != hipSuccess) return fail(le, "pyst_batch_graph_create: launch", cs, g);
+  if (e != hipSuccess) return fail(e, "pyst_batch_graph_create: end capture", cs, g);
+  hipGraphExec_t x = nullptr;
+  if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess)
+    return fail(e, "pyst_batch_graph_create: instantiate", cs, g);
+  (void)hipStreamDestroy(cs);
+  auto *bg = new (std::nothrow) pyst_batch_graph;
+  if (!bg) {
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    ctx_free(ctx, r.mem, stream);
+    return set_error(PYST_ERR_NOMEM, "pyst_batch_graph_create: host memory");
+  }
+  bg->ctx = ctx;
+  bg->mem = r.mem;
+  bg->graph = g;
+  bg->exec = x;
+  *out = bg;
+  return PYST_OK;
+}
+
+pyst_status pyst_batch_graph_launch(pyst_batch_graph *g, hipStream_t stream) {
+  if (!g) return set_error(PYST_ERR_ARG, "pyst_batch_graph_launch: NULL graph");
+  const hipError_t e = hipGraphLaunch(g->exec, stream);
+  return e == hipSuccess ? PYST_OK : hip_error(e, "pyst_batch_graph_launch");
+}
+
+pyst_status pyst_batch_graph_destroy(pyst_batch_graph *g) {
+  if (!g) return PYST_OK;
+  const hipError_t e = hipDeviceSynchronize();  // no launch of the graph may still run
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  ctx_free(g->ctx, g->mem, nullptr);
+  delete g;
+  return e == hipSuccess ? PYST_OK : hip_error(e, "pyst_batch_graph_destroy");
 }
 
 pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, int reps, pyst_tuning *out,

@@ -29,6 +29,7 @@ EXPORTS = [
     "pyst_last_error", "pyst_filter", "pyst_partition", "pyst_join_build", "pyst_join_probe",
     "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
+    "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
     "pyst_server_create", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
     "pyst_server_destroy",
 ]
@@ -123,6 +124,9 @@ def load(path: str = LIB_PATH):
         "pyst_query_streamed": ([p, P(Plan), P(Col), i32, i64, i32, p, p, i64, p, p], i32),
         "pyst_query_batch": ([p, P(Fragment), i32, P(Tuning), p], i32),
         "pyst_autotune": ([p, P(Fragment), i32, i32, P(Tuning), P(ctypes.c_double)], i32),
+        "pyst_batch_graph_create": ([p, P(Fragment), i32, P(Tuning), p, P(ctypes.c_void_p)], i32),
+        "pyst_batch_graph_launch": ([p, p], i32),
+        "pyst_batch_graph_destroy": ([p], i32),
         "pyst_server_create": ([i32, P(ServerCfg), P(Col), i32, P(p)], i32),
         "pyst_server_submit": ([p, P(Request), P(ctypes.c_uint64)], i32),
         "pyst_server_wait": ([p, ctypes.c_uint64, P(ctypes.c_double)], i32),
@@ -450,12 +454,35 @@ class Batch:
         _check(_lib.pyst_autotune(self.ctx.h, self.arr, self.n, reps, ctypes.byref(t), ctypes.byref(ms)))
         return (t.fanout, t.block, t.max_load), ms.value
 
+    def graph(self, tuning=None, stream=None):
+        """Capture this batch as a HIP graph (BatchGraph); results() reads its replays."""
+        return BatchGraph(self, tuning, stream)
+
     def results(self):
         out = []
         for ok, osum, ng in self.outs:
             m = int(ng.item())
             out.append((ok[:m], osum[:m]))
         return out
+
+
+class BatchGraph:
+    """pyst_batch_graph_*: a Batch captured once, replayed with launch()."""
+
+    def __init__(self, batch: Batch, tuning=None, stream=None):
+        self.batch = batch
+        t = ctypes.byref(Tuning(*tuning)) if tuning is not None else None
+        h = ctypes.c_void_p()
+        _check(_lib.pyst_batch_graph_create(batch.ctx.h, batch.arr, batch.n, t, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(_lib.pyst_batch_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _check(_lib.pyst_batch_graph_destroy(self.h))
+            self.h = None
 
 
 class Server:

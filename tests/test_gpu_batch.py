@@ -108,3 +108,33 @@ def test_batch_large_and_small_fragments(gpu, ctx):
         gk, gs = sorted_np(k, s)
         np.testing.assert_array_equal(gk, wk)
         np.testing.assert_array_equal(gs, ws)
+
+
+def test_batch_graph_replays_match(gpu, ctx):
+    # the batch captured once as a graph and replayed three times, with eager
+    # work (a batch run under another tuning) and synchronizations between
+    # replays; every output is overwritten before each replay, so each replay
+    # must write all of them again
+    import torch
+    frags, host = make_fragments(gpu, 24, lo=1e3, hi=4e5)
+    batch = gpu.Batch(ctx, frags)
+    g = batch.graph((64, 1024, 0.5))
+    try:
+        for rep in range(3):
+            if rep == 1:
+                batch.run((16, 256, 0.7))
+                ctx.check()
+            for ok, osum, ng in batch.outs:
+                ok.fill_(-7)
+                osum.fill_(-7)
+                ng.fill_(12345)
+            torch.cuda.synchronize()
+            g.launch()
+            ctx.check()
+            for (k, s), (bt, pt) in zip(batch.results(), host):
+                wk, ws = oracle.star_query(bt, pt)
+                gk, gs = sorted_np(k, s)
+                np.testing.assert_array_equal(gk, wk)
+                np.testing.assert_array_equal(gs, ws)
+    finally:
+        g.close()
