@@ -1,0 +1,88 @@
+"""GPU parity at the measured sizes, in the configuration bench.py times: the
+star query at 1.5M build / 60M probe rows (the headline workload), the hash
+partition of its probe table at F = 2, 8 and 64, and the two-join chain at
+3M / 300k / 120M rows with Zipf s = 0 and 1 -- every output element against
+the oracle run on the whole tables.  These take tens of seconds each, most of
+it the oracle on the host."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+NB, NP = 1_500_000, 60_000_000
+NA, NBD, NF = 3_000_000, 300_000, 120_000_000
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t, n=None):
+    a = t.cpu().numpy()
+    return a if n is None else a[:n]
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = gpu.Ctx(0, 16 << 30)  # the budget bench.py gives its context
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def star(gpu):
+    import torch
+    b, p = gen.star_tables(NB, NP, workload=1)  # the tables bench.py measures
+    yield b, p, {k: dev(v) for k, v in b.items()}, {k: dev(v) for k, v in p.items()}
+    torch.cuda.empty_cache()
+
+
+def test_star_query_full_size(gpu, ctx, star):
+    b, p, bd, pd = star
+    plan = gpu.star_plan(bd, max_load=0.5)
+    k, s, ng = gpu.query(ctx, plan, [pd["fk"], pd["date"], pd["price"]], out_cap=NB)
+    ctx.check()
+    m = int(ng.item())
+    gk, gs = host(k, m), host(s, m)
+    o = np.argsort(gk, kind="stable")
+    wk, ws = oracle.star_query(b, p)
+    assert m == len(wk) == 299_604
+    np.testing.assert_array_equal(gk[o], wk)
+    np.testing.assert_array_equal(gs[o], ws)
+
+
+@pytest.mark.parametrize("fanout", [2, 8, 64])
+def test_partition_full_size(gpu, ctx, star, fanout):
+    b, p, bd, pd = star
+    ok, (od, op), off = gpu.partition(ctx, pd["fk"], [pd["date"], pd["price"]], fanout)
+    ctx.check()
+    wk, (wd, wp), woff = oracle.partition(p["fk"], [p["date"], p["price"]], fanout)
+    np.testing.assert_array_equal(host(off), woff)
+    assert woff[-1] == NP
+    np.testing.assert_array_equal(host(ok), wk)
+    np.testing.assert_array_equal(host(od), wd)
+    np.testing.assert_array_equal(host(op), wp)
+
+
+@pytest.mark.parametrize("zs", [0.0, 1.0])
+def test_chain_query_full_size(gpu, ctx, zs):
+    import torch
+    a, b = gen.chain_dims(NA, NBD)
+    f = gen.chain_fact(NF, NA, NBD, zs)
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()})
+    fact = [dev(f[c]) for c in ("a_fk", "b_fk", "date", "price", "discount")]
+    k, s, ng = gpu.query(ctx, plan, fact, out_cap=16_000_000)  # bench.py's capacity
+    ctx.check()
+    m = int(ng.item())
+    gk, gs = host(k, m), host(s, m)
+    del fact, k, s
+    torch.cuda.empty_cache()
+    o = np.argsort(gk, kind="stable")
+    wk, ws = oracle.chain_query(a, b, f)
+    assert m == len(wk)
+    np.testing.assert_array_equal(gk[o], wk)
+    np.testing.assert_array_equal(gs[o], ws)
