@@ -1,9 +1,10 @@
 """GPU parity at the measured sizes, in the configuration bench.py times: the
 star query at 1.5M build / 60M probe rows (the headline workload), the hash
-partition of its probe table at F = 2, 8 and 64, and the two-join chain at
-3M / 300k / 120M rows with Zipf s = 0 and 1 -- every output element against
-the oracle run on the whole tables.  These take tens of seconds each, most of
-it the oracle on the host."""
+partition of its probe table at F = 2, 8 and 64, the two-join chain at
+3M / 300k / 120M rows with Zipf s = 0 and 1, and the batch of 512 fragments
+(1.19e9 probe rows) run as a captured graph -- every output element against
+the oracle run on the whole tables.  These take seconds to tens of seconds
+each, most of it generating the tables and running the oracle on the host."""
 import numpy as np
 import pytest
 
@@ -86,3 +87,33 @@ def test_chain_query_full_size(gpu, ctx, zs):
     assert m == len(wk)
     np.testing.assert_array_equal(gk[o], wk)
     np.testing.assert_array_equal(gs[o], ws)
+
+
+def test_batch_full_size(gpu, ctx):
+    # the 512 fragments bench.py batches (1.19e9 probe rows), run as the
+    # captured graph with the tuning its autotuner picks on the box; every
+    # fragment against the oracle
+    import torch
+    sizes, builds = gen.fragment_sizes(512)
+    frags, want = [], []
+    for f, (p, b) in enumerate(zip(sizes, builds)):
+        bt, pt = gen.star_tables(max(int(b), 1), int(p), workload=3, fragment=f)
+        frags.append((gpu.star_plan({k: dev(v) for k, v in bt.items()}),
+                      [dev(pt[c]) for c in ("fk", "date", "price")]))
+        want.append(oracle.star_query(bt, pt))
+        del bt, pt
+    batch = gpu.Batch(ctx, frags)
+    g = batch.graph((64, 1024, 0.5))
+    try:
+        g.launch()
+        ctx.check()
+        for f, ((k, s), (wk, ws)) in enumerate(zip(batch.results(), want)):
+            gk, gs = host(k), host(s)
+            o = np.argsort(gk, kind="stable")
+            assert len(gk) == len(wk), f
+            np.testing.assert_array_equal(gk[o], wk)
+            np.testing.assert_array_equal(gs[o], ws)
+    finally:
+        g.close()
+        del frags, batch
+        torch.cuda.empty_cache()
