@@ -14,6 +14,9 @@ Beside the headline line it reports, measured outside the timed region:
   cpu_baseline  : the CPU oracle (single thread) on a bounded sample
   partition     : hash partition of the probe table, fanout 2 / 8 / 64
   chain         : the two-join chain query (fact 120M, Zipf s = 0 and 1)
+  join          : the materializing join of the join microbenchmark at one GPU's
+                  share (build 60M / probe 160M, hit ratio 0.5, k = 1, 4, 8
+                  8-byte columns a side)
 """
 import argparse
 import glob
@@ -35,8 +38,13 @@ GROUP_OUT_BYTES = 16   # key int64 + sum int64
 KERNEL_SOURCES = {  # the files that define each profiled kernel (name patterns as rocprofv3 prints them)
     "k_fast_fact": ["fast.hip", "pyst_internal.h", "table.h", "query.h"],
     "k_fast_fact<2, 8, 2": ["fast.hip", "pyst_internal.h", "table.h", "query.h"],
+    "k_join_probe": ["ops.hip", "pyst_internal.h", "table.h"],
+    "k_join_build": ["ops.hip", "pyst_internal.h", "table.h"],
+    "k_gather_rows<4": ["ops.hip", "pyst_internal.h"],
+    "k_gather<": ["ops.hip", "pyst_internal.h"],
 }
 CHAIN_WORKLOAD = "chain_a3000000_b300000_f120000000"  # fact-pass counters averaged over s = 0 and 1
+JOIN_WORKLOAD = "join_b60000000_p160000000_k4"  # counters of the k = 4 materializing join
 
 
 def source_hash(kernel="k_fast_fact"):
@@ -145,11 +153,12 @@ def main():
     ap.add_argument("--probe-rows", type=int, default=60_000_000)
     ap.add_argument("--max-load", type=float, default=0.5)
     ap.add_argument("--no-extras", action="store_true", help="skip every measurement beside the headline")
-    ap.add_argument("--extras", default="partition,chain,stream,batch,serve",
+    ap.add_argument("--extras", default="partition,chain,join,stream,batch,serve",
                     help="comma-separated extra measurements to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=30_000_000)
     ap.add_argument("--stream-rows", type=int, default=240_000_000, help="chain fact rows streamed from pinned host")
+    ap.add_argument("--join-k", default="1,4,8", help="8-byte columns a side of the join microbenchmark")
     ap.add_argument("--batch-fragments", type=int, default=512)
     ap.add_argument("--batch-max-rows", type=float, default=2e7, help="largest fragment probe size")
     ap.add_argument("--serve-rows", type=int, default=512_000_000, help="pinned host fact rows of the server")
@@ -255,6 +264,9 @@ def main():
     if "chain" in extras:
         result["chain"] = bench_chain(ctx, pyst, gen, log)
         torch.cuda.empty_cache()
+    if "join" in extras:
+        result["join"] = bench_join(ctx, pyst, gen, log, ks=[int(x) for x in args.join_k.split(",")])
+        torch.cuda.empty_cache()
     if "stream" in extras:
         result["stream"] = bench_stream(ctx, pyst, gen, log, args.stream_rows)
         torch.cuda.empty_cache()
@@ -337,6 +349,60 @@ def bench_chain(ctx, pyst, gen, log):
     # when the kernel's source has changed since they were taken)
     out["fact_pass_traffic"] = counter_traffic("k_fast_fact<2, 8, 2", CHAIN_WORKLOAD)
     out["fact_pass_algorithmic_bytes"] = nf * 24
+    return out
+
+
+def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8)):
+    """Build + probe + materialize of k 8-byte columns per side (one pyst_join_materialize call)."""
+    import torch
+    out = {"build_rows": nb, "probe_rows": npr, "hit_ratio": 0.5}
+    for k in ks:
+        log("join microbenchmark: build %d, probe %d, k = %d" % (nb, npr, k))
+        b_h, p_h = gen.join_tables(nb, npr, k)
+        bk, pk = torch.from_numpy(b_h["key"]).cuda(), torch.from_numpy(p_h["key"]).cuda()
+        bc = [torch.from_numpy(b_h["c%d" % c]).cuda() for c in range(k)]
+        pc = [torch.from_numpy(p_h["c%d" % c]).cuda() for c in range(k)]
+        del b_h, p_h
+
+        def step():
+            return pyst.join_materialize(ctx, bk, bc, pk, pc)
+
+        r = step()
+        ctx.check()
+        m = int(r[3].item())
+        del r
+        ctx.timing(True)
+        el = timed_loop(step, 5, 0)
+        ctx.timing(False)
+        b_ms, b_n = ctx.kernel_time("join_build")
+        p_ms, p_n = ctx.kernel_time("join_probe")
+        g_ms, g_n = ctx.kernel_time("gather")
+        r_ms, r_n = ctx.kernel_time("gather_rows")
+        k_ms, k_n = ctx.kernel_time("pack_rows")
+        ctx.check()
+        ms = el / 5 * 1e3
+        cap = 1 << (int(nb / 0.5)).bit_length()
+        # algorithmic bytes: keys read once, one table slot written per build row and
+        # read per probe row, the table cleared, (probe row, build row) pairs written
+        # and read back, k values read and written per match and side
+        gather_bytes = m * (4 + 16 * k)  # per gather launch
+        alg = nb * (4 + 8) + cap * 8 + npr * (4 + 8) + m * 8 + 2 * gather_bytes
+        g_us = g_ms / max(g_n, 1) * 1e3
+        out["k%d" % k] = {
+            "ms": ms, "matches": m, "probe_rows_per_s": npr / (ms / 1e3), "output_tuples_per_s": m / (ms / 1e3),
+            "algorithmic_bytes": alg, "gbs": alg / (ms / 1e3) / 1e9,
+            "frac_of_peak": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "build_us": b_ms / max(b_n, 1) * 1e3, "probe_us": p_ms / max(p_n, 1) * 1e3,
+            # column gathers: the probe side (and the build side at k = 1); packed-row
+            # gathers: the build side at k > 1, after packing its columns row-major
+            "gather_us": g_us, "gather_gbs": gather_bytes / (g_us / 1e6) / 1e9 if g_us > 0 else None,
+            "gather_rows_us": r_ms / r_n * 1e3 if r_n else None, "pack_rows_us": k_ms / k_n * 1e3 if k_n else None}
+        del bk, pk, bc, pc
+        torch.cuda.empty_cache()
+    # HBM bytes per launch from committed counters of the k = 4 run (null once the kernels changed)
+    out["k4_counter_traffic"] = {"k_join_probe": counter_traffic("k_join_probe", JOIN_WORKLOAD),
+                                 "k_gather_rows": counter_traffic("k_gather_rows<4", JOIN_WORKLOAD),
+                                 "k_gather": counter_traffic("k_gather<", JOIN_WORKLOAD)}
     return out
 
 

@@ -10,6 +10,9 @@ with a ~2407-day date, a scaled-cents price and a 0..10 discount):
 
 * star  : build {key = shuffled 1..Nb, segment U[0,4]},
           probe {fk U[1,Nb], date U[0,2406], price int64 U[90000,10500000]}
+* join  : build {key = shuffled 1..Nb, c0..c(k-1) int64 U[-2^62, 2^62]},
+          probe {key U[1, 2 Nb] (half the probe keys find a build key),
+                 c0..c(k-1) int64 U[-2^62, 2^62]}
 * chain : A {key = shuffled 1..Na, date U[0,2406]},
           B {key = shuffled 1..Nb, segment U[0,4]},
           fact {a_fk U[1,Na], b_fk Zipf_s over 1..Nb, date U[0,2406],
@@ -178,6 +181,21 @@ def chain_fact(n_fact: int, n_a: int, n_b: int, zipf_s: float, workload: int = 2
         "discount": uniform_i32(n_fact, 0, DISCOUNT_MAX, seed(workload, 2, 4), offset,
                                 out.get("discount")),
     }
+
+
+JOIN_WORKLOAD = 6
+PAYLOAD_BOUND = 1 << 62
+
+
+def join_tables(n_build: int, n_probe: int, k: int, workload: int = JOIN_WORKLOAD):
+    """Tables of the join microbenchmark: unique build keys 1..Nb (shuffled), probe keys
+    uniform over 1..2Nb (hit ratio 0.5), and k 8-byte payload columns on each side."""
+    b = {"key": perm_i32(n_build, 1, seed(workload, 0, 0))}
+    p = {"key": uniform_i32(n_probe, 1, 2 * max(n_build, 1), seed(workload, 1, 0))}
+    for c in range(k):
+        b["c%d" % c] = uniform_i64(n_build, -PAYLOAD_BOUND, PAYLOAD_BOUND, seed(workload, 0, 1 + c))
+        p["c%d" % c] = uniform_i64(n_probe, -PAYLOAD_BOUND, PAYLOAD_BOUND, seed(workload, 1, 1 + c))
+    return b, p
 
 
 def fragment_sizes(n_frag: int, lo: float = 1e4, hi: float = 2e7, workload: int = 3):

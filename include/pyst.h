@@ -59,7 +59,8 @@ typedef enum pyst_status {
   PYST_ERR_KEY = 5,         /* a key equal to the EMPTY sentinel was seen              */
   PYST_ERR_TABLE_FULL = 6,  /* a hash table had no free slot                          */
   PYST_ERR_UNSUPPORTED = 7, /* a valid but unsupported combination                    */
-  PYST_ERR_DUP_KEY = 8      /* duplicate build key although unique_keys was promised  */
+  PYST_ERR_DUP_KEY = 8,     /* duplicate build key although unique_keys was promised  */
+  PYST_ERR_INDEX = 9        /* a gather index outside [0, rows of its columns)        */
 } pyst_status;
 
 typedef enum pyst_dtype { PYST_I32 = 0, PYST_I64 = 1 } pyst_dtype;
@@ -186,6 +187,39 @@ pyst_status pyst_join_probe(pyst_ctx *ctx, const pyst_table *table, const pyst_c
                             const int32_t *sel, const int64_t *d_nsel, int32_t *out_probe_row,
                             int32_t *out_payload, int64_t out_cap, int64_t *d_nout,
                             hipStream_t stream);
+
+/* Materialize join results (Sec. 3.1 "Anatomy...": the probe emits matching
+   tuples; the microbenchmarks of Sec. 3 carry 1..8 8-byte columns per tuple).
+   For every i < min(*d_n, cap): out_cols[c][i] = cols[c].data[idx[i]], for
+   c < ncols.  idx: device int32[cap], e.g. the probe rows or the stored row
+   ids that pyst_join_probe emits.  d_n: device int64 count of valid entries
+   of idx, or NULL for all cap entries.  cols: 1..8 int32 or int64 columns of
+   one common length; out_cols[c]: device buffers of cols[c]'s dtype with room
+   for cap values, owned by the caller.  An index outside [0, cols[0].n)
+   latches PYST_ERR_INDEX and leaves its output row unwritten.
+   Errors: PYST_ERR_ARG (NULL pointers, 0 or more than 8 columns, length
+   mismatch, cap outside [0, 2^31)). */
+pyst_status pyst_gather(pyst_ctx *ctx, const int32_t *idx, const int64_t *d_n, int64_t cap, const pyst_col *cols,
+                        int ncols, void *const *out_cols, hipStream_t stream);
+
+/* One-call materializing equi-join, the receive-side work of one GPU in the
+   join microbenchmark of Sec. 3 (build + probe + materialize; the send side is
+   pyst_partition): builds a table over the unique int32 build_key (a duplicate
+   latches PYST_ERR_DUP_KEY), probes it with every row of probe_key, and for
+   each match, in ascending probe row, writes the probe row, the build row and
+   the tuple npcols probe columns then nbcols build columns (each 0..8, int32
+   or int64, of their key's length): out_cols[c] for c < npcols holds
+   probe_cols[c] at the probe row, out_cols[npcols + c] build_cols[c] at the
+   build row.  out_probe_row / out_build_row: device int32[out_cap]; out_cols:
+   device buffers of their source's dtype with room for out_cap values, all
+   owned by the caller.  d_nout: device int64, receives the number of matches;
+   above out_cap only the first out_cap are written and PYST_ERR_CAPACITY is
+   latched.  The table lives in the context's arena for the call only.
+   Errors: PYST_ERR_ARG, PYST_ERR_NOMEM. */
+pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, const pyst_col *build_cols, int nbcols,
+                                  const pyst_col *probe_key, const pyst_col *probe_cols, int npcols, double max_load,
+                                  void *const *out_cols, int32_t *out_probe_row, int32_t *out_build_row,
+                                  int64_t out_cap, int64_t *d_nout, hipStream_t stream);
 
 /* Enqueue a copy of the table's header into d_out (device int64[2]):
    [0] the effective capacity chosen on the device, [1] the number of rows

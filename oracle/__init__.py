@@ -149,6 +149,17 @@ def join(build_key, probe_key, build_sel=None, probe_sel=None):
     return op[:m].copy(), ob[:m].copy()
 
 
+def join_materialize(build_key, build_cols, probe_key, probe_cols):
+    """Inner equi-join with materialized result tuples (Sec. 3.1, "Anatomy of a
+    Distributed Hash Join": the probe emits every matching (probe tuple, build
+    tuple) pair).  Returns (probe_row, build_row, columns): the match pairs in
+    the canonical order of join() and, per match, the probe columns at its probe
+    row followed by the build columns at its build row."""
+    pr, br = join(build_key, probe_key)
+    cols = [np.asarray(c)[pr] for c in probe_cols] + [np.asarray(c)[br] for c in build_cols]
+    return pr, br, cols
+
+
 def groupby_sum(key, val, sel=None):
     """GROUP BY key SUM(val): (keys int64 ascending, sums int64)."""
     k, v = _col(key), _col(val)

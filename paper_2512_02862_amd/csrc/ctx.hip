@@ -328,6 +328,7 @@ pyst_status pyst_ctx_check(pyst_ctx *c, hipStream_t stream) {
   if (bits & kErrKey) return set_error(PYST_ERR_KEY, "a key equal to the reserved EMPTY sentinel was seen");
   if (bits & kErrDup) return set_error(PYST_ERR_DUP_KEY, "duplicate build key under a unique-key promise");
   if (bits & kErrTableFull) return set_error(PYST_ERR_TABLE_FULL, "hash table full");
+  if (bits & kErrIndex) return set_error(PYST_ERR_INDEX, "a gather index outside its columns");
   return set_error(PYST_ERR_CAPACITY, "output capacity exceeded");
 }
 

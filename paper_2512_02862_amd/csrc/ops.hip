@@ -590,41 +590,68 @@ __global__ void k_table_init(TableDev t, const int64_t *d_nsel, int64_t n, doubl
     }
 }
 
-__global__ __launch_bounds__(256) void k_join_build(const int32_t *key, const int32_t *payload, const int32_t *sel,
-                                                    const int64_t *d_nsel, int64_t n, TableDev t, int unique,
-                                                    uint32_t *err) {
+// Each lane inserts ITEMS rows, one wave64 row apart: the ITEMS home slots are
+// read together, then CAS'd together where empty (the read brings the line
+// into the L2, where the atomic then runs; a CAS straight to a cold line
+// measured slower), and only rows whose home slot was taken walk on.
+constexpr int kBuildItems = 4;
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_join_build(const int32_t *key, const int32_t *payload, const int32_t *sel,
+                                                      const int64_t *d_nsel, int64_t n, TableDev t, int unique,
+                                                      uint32_t *err) {
   const int64_t cnt = count_of(d_nsel, n);
   const int64_t mask = t.hdr[0] - 1;
-  uint64_t *slots = static_cast<uint64_t *>(t.slots);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = row_of(sel, i);
-    const int32_t k = key[row];
-    if (k == kEmpty32) {
-      latch(err, kErrKey);
-      continue;
+  auto *slots = reinterpret_cast<unsigned long long *>(t.slots);
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  for (int64_t base = int64_t{blockIdx.x} * TILE + threadIdx.x; base < cnt; base += int64_t{gridDim.x} * TILE) {
+    int32_t k[ITEMS];
+    uint64_t packed[ITEMS], old[ITEMS];
+    int64_t s[ITEMS];
+    bool live[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int64_t i = base + int64_t{j} * BLOCK;
+      live[j] = i < cnt;
+      const int64_t row = live[j] ? row_of(sel, i) : 0;
+      k[j] = live[j] ? key[row] : kEmpty32;
+      const uint32_t pl = payload ? static_cast<uint32_t>(live[j] ? payload[row] : 0) : static_cast<uint32_t>(row);
+      packed[j] = uint64_t{static_cast<uint32_t>(k[j])} | (uint64_t{pl} << 32);
+      if (live[j] && k[j] == kEmpty32) {
+        latch(err, kErrKey);
+        live[j] = false;
+      }
+      s[j] = (table_hash32(k[j]) & mask) & ~int64_t{1};
     }
-    const uint32_t pl = payload ? static_cast<uint32_t>(payload[row]) : static_cast<uint32_t>(row);
-    const uint64_t packed = uint64_t{static_cast<uint32_t>(k)} | (uint64_t{pl} << 32);
-    int64_t s = (table_hash32(k) & mask) & ~int64_t{1};
-    bool done = false;
-    for (int64_t step = 0; step <= mask; ++step) {
-      uint64_t cur = slots[s];
-      if (static_cast<int32_t>(cur) == kEmpty32) {
-        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&slots[s]), kEmptySlot, packed);
-        if (old == kEmptySlot) {
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) old[j] = live[j] ? slots[s[j]] : kEmptySlot;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (live[j] && static_cast<int32_t>(old[j]) == kEmpty32) old[j] = atomicCAS(&slots[s[j]], kEmptySlot, packed[j]);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (!live[j] || old[j] == kEmptySlot) continue;
+      bool done = false;
+      uint64_t cur = old[j];
+      int64_t p = s[j];
+      for (int64_t step = 0; step <= mask; ++step) {
+        if (unique && static_cast<int32_t>(cur) == k[j]) {
+          latch(err, kErrDup);
           done = true;
           break;
         }
-        cur = old;
+        p = (p + 1) & mask;
+        cur = slots[p];
+        if (static_cast<int32_t>(cur) == kEmpty32) {
+          cur = atomicCAS(&slots[p], kEmptySlot, packed[j]);
+          if (cur == kEmptySlot) {
+            done = true;
+            break;
+          }
+        }
       }
-      if (unique && static_cast<int32_t>(cur) == k) {
-        latch(err, kErrDup);
-        done = true;
-        break;
-      }
-      s = (s + 1) & mask;
+      if (!done) latch(err, kErrTableFull);
     }
-    if (!done) latch(err, kErrTableFull);
   }
 }
 
@@ -650,6 +677,28 @@ __device__ __forceinline__ void probe_kp(const uint64_t *slots, int64_t mask, in
   }
 }
 
+// Visits the two slots of one 16-byte group in table order: counts matches of
+// k (remembering the first payload) and returns false once the run ends (an
+// EMPTY slot, or the first match under unique keys).
+__device__ __forceinline__ bool visit_pair(ulonglong2 pair, int32_t k, int unique, int32_t &c, int32_t &first) {
+  const uint64_t sl[2] = {pair.x, pair.y};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int32_t key = static_cast<int32_t>(sl[h]);
+    if (key == k) {
+      if (c == 0) first = static_cast<int32_t>(sl[h] >> 32);
+      ++c;
+      if (unique) return false;
+    } else if (key == kEmpty32) {
+      return false;
+    }
+  }
+  return true;
+}
+
+// Each lane probes ITEMS rows, one wave64 row apart: the keys, then the ITEMS
+// home groups are loaded together, and only rows whose run goes on past their
+// home group walk on.  A probe key equal to EMPTY matches nothing.
 template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_join_probe(const int32_t *key, const int32_t *sel, const int64_t *d_nsel,
                                                      int64_t n, TableDev t, int unique, int32_t *out_row,
@@ -668,25 +717,33 @@ __global__ __launch_bounds__(BLOCK) void k_join_probe(const int32_t *key, const 
   const uint64_t *slots = static_cast<const uint64_t *>(t.slots);
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = tile * TILE + int64_t{w} * kWave * ITEMS;
-  int32_t c[ITEMS];
-  int32_t first_pay[ITEMS];
+  int32_t kk[ITEMS], c[ITEMS], first_pay[ITEMS];
+  int64_t s[ITEMS];
+  ulonglong2 g[ITEMS];
+  bool live[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t i = wbase + int64_t{j} * kWave + lane;
+    kk[j] = i < cnt ? key[row_of(sel, i)] : kEmpty32;
+    live[j] = kk[j] != kEmpty32;
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    s[j] = (table_hash32(kk[j]) & mask) & ~int64_t{1};
+    g[j] = live[j] ? *reinterpret_cast<const ulonglong2 *>(&slots[s[j]]) : ulonglong2{kEmptySlot, kEmptySlot};
+  }
   int64_t wave_total = 0;
   int64_t lane_off[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    const int64_t i = wbase + int64_t{j} * kWave + lane;
     c[j] = 0;
     first_pay[j] = 0;
-    if (i < cnt) {
-      const int32_t k = key[row_of(sel, i)];
-      int32_t m = 0, fp = 0;
-      probe_kp(slots, mask, k, [&](int32_t pl) {
-        if (m == 0) fp = pl;
-        ++m;
-        return !unique;
-      });
-      c[j] = m;
-      first_pay[j] = fp;
+    if (live[j] && visit_pair(g[j], kk[j], unique, c[j], first_pay[j])) {
+      int64_t p = s[j];
+      for (int64_t step = 2; step <= mask; step += 2) {
+        p = (p + 2) & mask;
+        if (!visit_pair(*reinterpret_cast<const ulonglong2 *>(&slots[p]), kk[j], unique, c[j], first_pay[j])) break;
+      }
     }
     const int64_t incl = wave_inclusive_scan<int64_t>(c[j]);
     lane_off[j] = wave_total + incl - c[j];
@@ -843,6 +900,139 @@ pyst_status group_init(const GroupDev &g, const int64_t *d_nsel, int64_t n, int6
   return PYST_OK;
 }
 
+// ============================================================== gather (materialize)
+// Row-wise materialization of join results: dst[c][i] = src[c][idx[i]].  Each
+// lane owns ITEMS output rows, one wave64 row apart, so the index loads and
+// the stores of a wave are coalesced and the ITEMS value loads of a lane (one
+// per row, random for a hash join's build side, ascending for its probe side)
+// are in flight together.  An index outside [0, nsrc) is latched and its row
+// left unwritten; no load is made for it.
+struct GatherArgs {
+  const void *src[PYST_MAX_COLS];
+  void *dst[PYST_MAX_COLS];
+  int32_t w64[PYST_MAX_COLS];
+  int32_t ncols;
+  int64_t nsrc;
+};
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_gather(GatherArgs a, const int32_t *idx, const int64_t *d_n, int64_t cap,
+                                                  uint32_t *err) {
+  int64_t n = d_n ? *d_n : cap;
+  if (n > cap) n = cap;
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  for (int64_t base = int64_t{blockIdx.x} * TILE + threadIdx.x; base < n; base += int64_t{gridDim.x} * TILE) {
+    int64_t r[ITEMS];
+    bool ok[ITEMS];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int64_t i = base + int64_t{j} * BLOCK;
+      r[j] = i < n ? static_cast<int64_t>(__builtin_nontemporal_load(&idx[i])) : -1;
+      ok[j] = r[j] >= 0 && r[j] < a.nsrc;
+      bad |= i < n && !ok[j];
+    }
+    if (bad) latch(err, kErrIndex);
+    for (int c = 0; c < a.ncols; ++c) {
+      if (a.w64[c]) {
+        const int64_t *s = static_cast<const int64_t *>(a.src[c]);
+        int64_t *d = static_cast<int64_t *>(a.dst[c]);
+        int64_t v[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) v[j] = ok[j] ? s[r[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+          if (ok[j]) __builtin_nontemporal_store(v[j], &d[base + int64_t{j} * BLOCK]);
+      } else {
+        const int32_t *s = static_cast<const int32_t *>(a.src[c]);
+        int32_t *d = static_cast<int32_t *>(a.dst[c]);
+        int32_t v[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) v[j] = ok[j] ? s[r[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+          if (ok[j]) __builtin_nontemporal_store(v[j], &d[base + int64_t{j} * BLOCK]);
+      }
+    }
+  }
+}
+
+// Row-major copy of a side's columns for random gathers: row r holds the
+// ncols values (sign-extended to int64) at words [r*RS, r*RS + ncols), RS a
+// power of two >= ncols, so one row is one aligned RS*8-byte block (at most a
+// 64-byte line) and a gather reads it with RS/2 16-byte loads instead of
+// ncols separate random 8-byte loads.
+template <int RS>
+__global__ __launch_bounds__(256) void k_pack_rows(GatherArgs a, int64_t *rows) {
+  for (int64_t r = int64_t{blockIdx.x} * blockDim.x + threadIdx.x; r < a.nsrc; r += int64_t{gridDim.x} * blockDim.x) {
+    int64_t v[RS];
+#pragma unroll
+    for (int c = 0; c < RS; ++c) {
+      v[c] = 0;
+      if (c < a.ncols)
+        v[c] = a.w64[c] ? __builtin_nontemporal_load(&static_cast<const int64_t *>(a.src[c])[r])
+                        : static_cast<int64_t>(__builtin_nontemporal_load(&static_cast<const int32_t *>(a.src[c])[r]));
+    }
+    if constexpr (RS == 1) {
+      rows[r] = v[0];
+    } else {
+#pragma unroll
+      for (int c = 0; c < RS; c += 2)
+        *reinterpret_cast<longlong2 *>(&rows[r * RS + c]) = longlong2{v[c], v[c + 1]};
+    }
+  }
+}
+
+// dst[c][i] = column c of packed row idx[i], narrowed to the column's dtype;
+// ITEMS rows per lane, one wave64 row apart, as k_gather.
+template <int RS, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_gather_rows(const int64_t *rows, GatherArgs a, const int32_t *idx,
+                                                       const int64_t *d_n, int64_t cap, uint32_t *err) {
+  int64_t n = d_n ? *d_n : cap;
+  if (n > cap) n = cap;
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  for (int64_t base = int64_t{blockIdx.x} * TILE + threadIdx.x; base < n; base += int64_t{gridDim.x} * TILE) {
+    int64_t r[ITEMS];
+    bool ok[ITEMS];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int64_t i = base + int64_t{j} * BLOCK;
+      r[j] = i < n ? static_cast<int64_t>(__builtin_nontemporal_load(&idx[i])) : -1;
+      ok[j] = r[j] >= 0 && r[j] < a.nsrc;
+      bad |= i < n && !ok[j];
+    }
+    if (bad) latch(err, kErrIndex);
+    int64_t v[ITEMS][RS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if constexpr (RS == 1) {
+        v[j][0] = ok[j] ? rows[r[j]] : 0;
+      } else {
+#pragma unroll
+        for (int c = 0; c < RS; c += 2) {
+          const longlong2 x = ok[j] ? *reinterpret_cast<const longlong2 *>(&rows[r[j] * RS + c]) : longlong2{0, 0};
+          v[j][c] = x.x;
+          v[j][c + 1] = x.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RS; ++c) {
+      if (c >= a.ncols) break;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        if (!ok[j]) continue;
+        const int64_t i = base + int64_t{j} * BLOCK;
+        if (a.w64[c])
+          __builtin_nontemporal_store(v[j][c], &static_cast<int64_t *>(a.dst[c])[i]);
+        else
+          __builtin_nontemporal_store(static_cast<int32_t>(v[j][c]), &static_cast<int32_t *>(a.dst[c])[i]);
+      }
+    }
+  }
+}
+
 int grid_for(pyst_ctx *ctx, int64_t work, int block, int per_cu) {
   const int64_t want = ceil_div(std::max<int64_t>(work, 1), block);
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, int64_t{ctx_num_cus(ctx)} * per_cu)));
@@ -853,6 +1043,102 @@ pyst_status table_init(const TableDev &t, const int64_t *d_nsel, int64_t n, doub
   k_table_init<<<blocks, 256, 0, stream>>>(t, d_nsel, n, max_load);
   PYST_LAUNCH_CHECK("k_table_init");
   return PYST_OK;
+}
+
+// Table init + insertion of the selected rows of an int32 key column.
+pyst_status launch_join_build(pyst_ctx *ctx, const TableDev &t, const pyst_col *key, const int32_t *payload,
+                              const int32_t *sel, const int64_t *d_nsel, double max_load, int unique,
+                              hipStream_t stream) {
+  pyst_status st = table_init(t, d_nsel, key->n, max_load, stream);
+  if (st != PYST_OK || key->n == 0) return st;
+  const int blocks = grid_for(ctx, ceil_div(key->n, int64_t{kBuildItems}), 256, 8);
+  k_join_build<256, kBuildItems><<<blocks, 256, 0, stream>>>(static_cast<const int32_t *>(key->data), payload, sel,
+                                                             d_nsel, key->n, t, unique, ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_join_build");
+  return PYST_OK;
+}
+
+pyst_status launch_join_probe(pyst_ctx *ctx, const TableDev &t, int unique, const pyst_col *key, const int32_t *sel,
+                              const int64_t *d_nsel, int32_t *out_row, int32_t *out_pay, int64_t out_cap,
+                              int64_t *d_nout, hipStream_t stream) {
+  constexpr int BLOCK = 256, ITEMS = 8;
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(key->n, int64_t{BLOCK} * ITEMS));
+  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "join probe: arena exhausted");
+  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+  if (st != PYST_OK) return st;
+  uint64_t *status = sc.as<uint64_t>();
+  k_join_probe<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
+      static_cast<const int32_t *>(key->data), sel, d_nsel, key->n, t, unique, out_row, out_pay, out_cap, d_nout,
+      status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles, ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_join_probe");
+  return PYST_OK;
+}
+
+// Validates the columns of one gather call into `a`.
+pyst_status gather_args(const pyst_col *cols, int ncols, void *const *out_cols, int64_t cap, GatherArgs *a,
+                        const char *who) {
+  if (ncols < 1 || ncols > PYST_MAX_COLS) return set_error(PYST_ERR_ARG, std::string(who) + ": 1..8 columns");
+  if (!cols || !out_cols) return set_error(PYST_ERR_ARG, std::string(who) + ": NULL columns");
+  std::memset(a, 0, sizeof(*a));
+  a->ncols = ncols;
+  a->nsrc = cols[0].n;
+  for (int c = 0; c < ncols; ++c) {
+    if (!col_ok(&cols[c]) || cols[c].n != a->nsrc)
+      return set_error(PYST_ERR_ARG, std::string(who) + ": bad column or length mismatch");
+    if (cap > 0 && !out_cols[c]) return set_error(PYST_ERR_ARG, std::string(who) + ": NULL output column");
+    a->src[c] = cols[c].data;
+    a->dst[c] = out_cols[c];
+    a->w64[c] = cols[c].dtype == PYST_I64;
+  }
+  return PYST_OK;
+}
+
+pyst_status launch_gather(pyst_ctx *ctx, const GatherArgs &a, const int32_t *idx, const int64_t *d_n, int64_t cap,
+                          hipStream_t stream) {
+  if (cap == 0) return PYST_OK;
+  TimedRegion timed(ctx, "gather", stream);
+  constexpr int BLOCK = 256, ITEMS = 8;
+  const int blocks = grid_for(ctx, ceil_div(cap, int64_t{ITEMS}), BLOCK, 8);
+  k_gather<BLOCK, ITEMS><<<blocks, BLOCK, 0, stream>>>(a, idx, d_n, cap, ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_gather");
+  return PYST_OK;
+}
+
+int row_words(int ncols) {
+  int rs = 1;
+  while (rs < ncols) rs *= 2;
+  return rs;
+}
+
+template <int RS>
+pyst_status launch_rows(pyst_ctx *ctx, const GatherArgs &a, int64_t *rows, const int32_t *idx, const int64_t *d_n,
+                        int64_t cap, hipStream_t stream) {
+  {
+    TimedRegion timed(ctx, "pack_rows", stream);
+    const int blocks = grid_for(ctx, a.nsrc, 256, 8);
+    k_pack_rows<RS><<<blocks, 256, 0, stream>>>(a, rows);
+    PYST_LAUNCH_CHECK("k_pack_rows");
+  }
+  if (cap == 0) return PYST_OK;
+  TimedRegion timed(ctx, "gather_rows", stream);
+  constexpr int BLOCK = 256, ITEMS = RS >= 8 ? 4 : 8;
+  const int blocks = grid_for(ctx, ceil_div(cap, int64_t{ITEMS}), BLOCK, 8);
+  k_gather_rows<RS, BLOCK, ITEMS><<<blocks, BLOCK, 0, stream>>>(rows, a, idx, d_n, cap, ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_gather_rows");
+  return PYST_OK;
+}
+
+// Gather through a row-major copy of the source columns (`rows`: nsrc * row_words(ncols) int64).
+pyst_status launch_gather_rows(pyst_ctx *ctx, const GatherArgs &a, int64_t *rows, const int32_t *idx,
+                               const int64_t *d_n, int64_t cap, hipStream_t stream) {
+  if (a.nsrc == 0) return launch_gather(ctx, a, idx, d_n, cap, stream);
+  switch (row_words(a.ncols)) {
+    case 1: return launch_rows<1>(ctx, a, rows, idx, d_n, cap, stream);
+    case 2: return launch_rows<2>(ctx, a, rows, idx, d_n, cap, stream);
+    case 4: return launch_rows<4>(ctx, a, rows, idx, d_n, cap, stream);
+    default: return launch_rows<8>(ctx, a, rows, idx, d_n, cap, stream);
+  }
 }
 
 }  // namespace pyst
@@ -931,6 +1217,7 @@ pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *
     return set_error(PYST_ERR_ARG, "pyst_join_build: payload must be int32 with the key's length");
   if (!(max_load > 0.0 && max_load <= 0.95)) return set_error(PYST_ERR_ARG, "pyst_join_build: max_load in (0, 0.95]");
   if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_join_build: sel and d_nsel go together");
+  TimedRegion timed(ctx, "join_build", stream);
   const int64_t cap_alloc = table_capacity_host(key->n, max_load);
   const size_t bytes = table_bytes(cap_alloc, 8, false);
   void *mem = ctx_alloc(ctx, bytes, stream);
@@ -941,15 +1228,8 @@ pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *
   t->dev = table_view(mem, cap_alloc, 8, false);
   t->unique = unique_keys != 0;
   t->stream = stream;
-  pyst_status st = table_init(t->dev, d_nsel, key->n, max_load, stream);
-  if (st == PYST_OK && key->n > 0) {
-    const int blocks = grid_for(ctx, key->n, 256, 8);
-    k_join_build<<<blocks, 256, 0, stream>>>(static_cast<const int32_t *>(key->data),
-                                             payload ? static_cast<const int32_t *>(payload->data) : nullptr, sel,
-                                             d_nsel, key->n, t->dev, t->unique, ctx_err_word(ctx));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) st = hip_error(e, "k_join_build");
-  }
+  pyst_status st = launch_join_build(ctx, t->dev, key, payload ? static_cast<const int32_t *>(payload->data) : nullptr,
+                                     sel, d_nsel, max_load, t->unique, stream);
   if (st != PYST_OK) {
     pyst_table_destroy(t, stream);
     return st;
@@ -967,19 +1247,74 @@ pyst_status pyst_join_probe(pyst_ctx *ctx, const pyst_table *table, const pyst_c
   if (out_cap < 0 || (out_cap > 0 && (!out_probe_row || !out_payload)))
     return set_error(PYST_ERR_ARG, "pyst_join_probe: bad output");
   if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_join_probe: sel and d_nsel go together");
-  constexpr int BLOCK = 256, ITEMS = 8;
-  const int64_t ntiles = std::max<int64_t>(1, ceil_div(key->n, int64_t{BLOCK} * ITEMS));
-  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
-  if (!sc.p) return set_error(PYST_ERR_NOMEM, "pyst_join_probe: arena exhausted");
-  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+  TimedRegion timed(ctx, "join_probe", stream);
+  pyst_status st = launch_join_probe(ctx, table->dev, table->unique, key, sel, d_nsel, out_probe_row, out_payload,
+                                     out_cap, d_nout, stream);
   if (st != PYST_OK) return st;
-  uint64_t *status = sc.as<uint64_t>();
-  k_join_probe<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
-      static_cast<const int32_t *>(key->data), sel, d_nsel, key->n, table->dev, table->unique, out_probe_row,
-      out_payload, out_cap, d_nout, status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles,
-      ctx_err_word(ctx));
-  PYST_LAUNCH_CHECK("k_join_probe");
   const_cast<pyst_table *>(table)->stream = stream;
+  return PYST_OK;
+}
+
+pyst_status pyst_gather(pyst_ctx *ctx, const int32_t *idx, const int64_t *d_n, int64_t cap, const pyst_col *cols,
+                        int ncols, void *const *out_cols, hipStream_t stream) {
+  if (!ctx) return set_error(PYST_ERR_ARG, "pyst_gather: ctx is NULL");
+  if (cap < 0 || cap > INT32_MAX) return set_error(PYST_ERR_ARG, "pyst_gather: cap in [0, 2^31)");
+  if (cap > 0 && !idx) return set_error(PYST_ERR_ARG, "pyst_gather: idx is NULL");
+  GatherArgs a;
+  pyst_status st = gather_args(cols, ncols, out_cols, cap, &a, "pyst_gather");
+  if (st != PYST_OK) return st;
+  return launch_gather(ctx, a, idx, d_n, cap, stream);
+}
+
+pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, const pyst_col *build_cols, int nbcols,
+                                  const pyst_col *probe_key, const pyst_col *probe_cols, int npcols, double max_load,
+                                  void *const *out_cols, int32_t *out_probe_row, int32_t *out_build_row,
+                                  int64_t out_cap, int64_t *d_nout, hipStream_t stream) {
+  if (!ctx || !build_key || !probe_key || !d_nout) return set_error(PYST_ERR_ARG, "pyst_join_materialize: NULL argument");
+  if (!col_ok(build_key) || !col_ok(probe_key) || build_key->dtype != PYST_I32 || probe_key->dtype != PYST_I32)
+    return set_error(PYST_ERR_ARG, "pyst_join_materialize: keys are int32 columns");
+  if (!(max_load > 0.0 && max_load <= 0.95)) return set_error(PYST_ERR_ARG, "pyst_join_materialize: max_load in (0, 0.95]");
+  if (out_cap < 0 || out_cap > INT32_MAX || (out_cap > 0 && (!out_probe_row || !out_build_row)))
+    return set_error(PYST_ERR_ARG, "pyst_join_materialize: bad output");
+  if (npcols > 0 && !out_cols) return set_error(PYST_ERR_ARG, "pyst_join_materialize: NULL output columns");
+  if (nbcols > 0 && !out_cols) return set_error(PYST_ERR_ARG, "pyst_join_materialize: NULL output columns");
+  GatherArgs ga[2];
+  const pyst_col *keys[2] = {probe_key, build_key};
+  const pyst_col *cols[2] = {probe_cols, build_cols};
+  const int nc[2] = {npcols, nbcols};
+  for (int side = 0; side < 2; ++side) {
+    if (nc[side] < 0 || nc[side] > PYST_MAX_COLS) return set_error(PYST_ERR_ARG, "pyst_join_materialize: 0..8 columns a side");
+    if (nc[side] == 0) continue;
+    pyst_status st = gather_args(cols[side], nc[side], out_cols + (side ? npcols : 0), out_cap, &ga[side],
+                                 "pyst_join_materialize");
+    if (st != PYST_OK) return st;
+    if (ga[side].nsrc != keys[side]->n) return set_error(PYST_ERR_ARG, "pyst_join_materialize: column length differs from its key");
+  }
+  const int64_t cap_alloc = table_capacity_host(build_key->n, max_load);
+  Scratch mem(ctx, table_bytes(cap_alloc, 8, false), stream);
+  if (!mem.p) return set_error(PYST_ERR_NOMEM, "pyst_join_materialize: arena exhausted");
+  const TableDev t = table_view(mem.p, cap_alloc, 8, false);
+  pyst_status st;
+  {
+    TimedRegion timed(ctx, "join_build", stream);
+    st = launch_join_build(ctx, t, build_key, nullptr, nullptr, nullptr, max_load, 1, stream);
+  }
+  if (st != PYST_OK) return st;
+  {
+    TimedRegion timed(ctx, "join_probe", stream);
+    st = launch_join_probe(ctx, t, 1, probe_key, nullptr, nullptr, out_probe_row, out_build_row, out_cap, d_nout,
+                           stream);
+  }
+  if (st != PYST_OK) return st;
+  if (npcols > 0 && (st = launch_gather(ctx, ga[0], out_probe_row, d_nout, out_cap, stream)) != PYST_OK) return st;
+  if (nbcols == 1 && (st = launch_gather(ctx, ga[1], out_build_row, d_nout, out_cap, stream)) != PYST_OK) return st;
+  if (nbcols > 1) {
+    // several build columns: one random read of a packed row per match instead of one per column
+    Scratch rows(ctx, static_cast<size_t>(build_key->n) * row_words(nbcols) * sizeof(int64_t), stream);
+    if (!rows.p && build_key->n > 0) return set_error(PYST_ERR_NOMEM, "pyst_join_materialize: arena exhausted");
+    if ((st = launch_gather_rows(ctx, ga[1], rows.as<int64_t>(), out_build_row, d_nout, out_cap, stream)) != PYST_OK)
+      return st;
+  }
   return PYST_OK;
 }
 

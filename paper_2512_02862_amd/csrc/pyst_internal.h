@@ -20,7 +20,7 @@ typedef int64_t v2i64 __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ error latch
 // Bits set by kernels in the context's device error word (see pyst_ctx_check).
-enum : uint32_t { kErrKey = 1u, kErrTableFull = 2u, kErrCapacity = 4u, kErrDup = 8u };
+enum : uint32_t { kErrKey = 1u, kErrTableFull = 2u, kErrCapacity = 4u, kErrDup = 8u, kErrIndex = 16u };
 
 __device__ inline void latch(uint32_t *err, uint32_t bit) { atomicOr(err, bit); }
 

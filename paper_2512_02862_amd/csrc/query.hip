@@ -402,12 +402,13 @@ pyst_status build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QuerySh
     if (st != PYST_OK) return st;
     if (nb > 0) {
       const int blocks = grid_for(ctx, nb, 256, 8);
+      const int bblocks = grid_for(ctx, ceil_div(nb, int64_t{kBuildItems}), 256, 8);
       if (sb == 4) {
         k_build_keys<<<blocks, 256, 0, stream>>>(static_cast<const int32_t *>(js.key.data), sel, d_nsel, nb, d->t[j],
                                                  ctx_err_word(ctx));
         PYST_LAUNCH_CHECK("k_build_keys");
       } else {
-        k_join_build<<<blocks, 256, 0, stream>>>(static_cast<const int32_t *>(js.key.data),
+        k_join_build<256, kBuildItems><<<bblocks, 256, 0, stream>>>(static_cast<const int32_t *>(js.key.data),
                                                  static_cast<const int32_t *>(js.payload.data), sel, d_nsel, nb,
                                                  d->t[j], 1, ctx_err_word(ctx));
         PYST_LAUNCH_CHECK("k_join_build");

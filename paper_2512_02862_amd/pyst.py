@@ -15,9 +15,9 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpyst.so")
 
-OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_CAPACITY, ERR_KEY, ERR_TABLE_FULL, ERR_UNSUPPORTED, ERR_DUP_KEY = range(9)
+OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_CAPACITY, ERR_KEY, ERR_TABLE_FULL, ERR_UNSUPPORTED, ERR_DUP_KEY, ERR_INDEX = range(10)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_CAPACITY", 5: "ERR_KEY",
-                6: "ERR_TABLE_FULL", 7: "ERR_UNSUPPORTED", 8: "ERR_DUP_KEY"}
+                6: "ERR_TABLE_FULL", 7: "ERR_UNSUPPORTED", 8: "ERR_DUP_KEY", 9: "ERR_INDEX"}
 CMP = {"==": 0, "!=": 1, "<": 2, "<=": 3, ">": 4, ">=": 5}
 I32, I64 = 0, 1
 G_NONE, G_JOIN_KEY, G_JOIN_PAYLOAD, G_FACT_COL = 0, 1, 2, 3
@@ -27,7 +27,7 @@ OPT_GENERIC_ONLY = 1
 EXPORTS = [
     "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
     "pyst_last_error", "pyst_filter", "pyst_partition", "pyst_join_build", "pyst_join_probe",
-    "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
+    "pyst_gather", "pyst_join_materialize", "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
     "pyst_server_create", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
@@ -115,6 +115,9 @@ def load(path: str = LIB_PATH):
         "pyst_partition": ([p, P(Col), P(Col), i32, p, p, u32, P(p), p, p], i32),
         "pyst_join_build": ([p, P(Col), P(Col), p, p, ctypes.c_double, i32, P(p), p], i32),
         "pyst_join_probe": ([p, p, P(Col), p, p, p, p, i64, p, p], i32),
+        "pyst_gather": ([p, p, p, i64, P(Col), i32, P(p), p], i32),
+        "pyst_join_materialize": ([p, P(Col), P(Col), i32, P(Col), P(Col), i32, ctypes.c_double, P(p), p, p, i64, p,
+                                   p], i32),
         "pyst_table_info": ([p, p, p], i32),
         "pyst_table_destroy": ([p, p], None),
         "pyst_groupby_sum": ([p, P(Col), P(Col), p, p, i64, ctypes.c_double, p, p, p, i32, p], i32),
@@ -308,6 +311,40 @@ def join_probe(ctx: Ctx, table: Table, key, sel=None, nsel=None, out_cap=None, s
     _check(_lib.pyst_join_probe(ctx.h, table.h, ctypes.byref(kc), _sel_ptr(sel), _ptr(nsel), _ptr(rows), _ptr(pays),
                                 cap, _ptr(nout), _stream(stream)))
     return rows, pays, nout
+
+
+def gather(ctx: Ctx, idx, cols, n=None, stream=None):
+    """[col[idx[i]] for i < min(n, len(idx))] for each column: outputs of len(idx) entries.
+    n: device int64[1] count of valid entries of idx, or None for all of them."""
+    cols = list(cols)
+    cap = idx.numel()
+    outs = [torch.empty(max(cap, 1), dtype=c.dtype, device=_dev(ctx)) for c in cols]
+    carr = (Col * len(cols))(*[col(c) for c in cols])
+    oarr = (ctypes.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    _check(_lib.pyst_gather(ctx.h, _ptr(idx) if cap > 0 else None, _ptr(n), cap, carr, len(cols), oarr,
+                            _stream(stream)))
+    return [o[:cap] for o in outs]
+
+
+def join_materialize(ctx: Ctx, build_key, build_cols, probe_key, probe_cols, max_load=0.5, out_cap=None,
+                     stream=None):
+    """(probe rows int32, build rows int32, [probe columns..., build columns...], count int64[1]) of the
+    unique-key equi-join, in ascending probe row; outputs have out_cap (default: probe rows) entries."""
+    build_cols, probe_cols = list(build_cols), list(probe_cols)
+    cap = probe_key.numel() if out_cap is None else out_cap
+    d = _dev(ctx)
+    prow = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
+    brow = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
+    outs = [torch.empty(max(cap, 1), dtype=c.dtype, device=d) for c in probe_cols + build_cols]
+    nout = torch.empty(1, dtype=torch.int64, device=d)
+    bk, pk = col(build_key), col(probe_key)
+    barr = (Col * max(1, len(build_cols)))(*[col(c) for c in build_cols])
+    parr = (Col * max(1, len(probe_cols)))(*[col(c) for c in probe_cols])
+    oarr = (ctypes.c_void_p * max(1, len(outs)))(*[t.data_ptr() for t in outs])
+    _check(_lib.pyst_join_materialize(ctx.h, ctypes.byref(bk), barr, len(build_cols), ctypes.byref(pk), parr,
+                                      len(probe_cols), float(max_load), oarr, _ptr(prow), _ptr(brow), cap, _ptr(nout),
+                                      _stream(stream)))
+    return prow[:cap], brow[:cap], [o[:cap] for o in outs], nout
 
 
 def groupby_sum(ctx: Ctx, key, val, sel=None, nsel=None, max_groups=0, max_load=0.5, sort_by_key=False,

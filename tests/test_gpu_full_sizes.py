@@ -3,8 +3,12 @@ star query at 1.5M build / 60M probe rows (the headline workload), the hash
 partition of its probe table at F = 2, 8 and 64, the two-join chain at
 3M / 300k / 120M rows with Zipf s = 0 and 1, and the batch of 512 fragments
 (1.19e9 probe rows) run as a captured graph -- every output element against
-the oracle run on the whole tables.  These take seconds to tens of seconds
-each, most of it generating the tables and running the oracle on the host."""
+the oracle run on the whole tables -- and the materializing join of the join
+microbenchmark at one GPU's share (60M build / 160M probe rows, four 8-byte
+columns a side), checked by properties that fix its result at any size plus
+every gathered element against torch indexing and sampled rows against the
+oracle's definition.  These take seconds to tens of seconds each, most of it
+generating the tables and running the oracle on the host."""
 import numpy as np
 import pytest
 
@@ -117,3 +121,35 @@ def test_batch_full_size(gpu, ctx):
         g.close()
         del frags, batch
         torch.cuda.empty_cache()
+
+
+NJB, NJP, NJK = 60_000_000, 160_000_000, 4
+
+
+def test_join_materialize_full_size(gpu, ctx):
+    import torch
+    b, p = gen.join_tables(NJB, NJP, NJK)
+    bk, pk = dev(b["key"]), dev(p["key"])
+    bc = [dev(b["c%d" % c]) for c in range(NJK)]
+    pc = [dev(p["c%d" % c]) for c in range(NJK)]
+    prow, brow, cols, nout = gpu.join_materialize(ctx, bk, bc, pk, pc)  # bench.py's call
+    ctx.check()
+    m = int(nout.item())
+    # the build keys are exactly 1..Nb (the recipe's pin), so a probe row matches iff its key <= Nb;
+    # with ascending distinct probe rows that all match, the count fixes the whole set of matches
+    assert m == int(np.count_nonzero(p["key"] <= NJB))
+    pr, br = prow[:m].long(), brow[:m].long()
+    assert bool((pr[1:] > pr[:-1]).all())
+    assert bool((bk[br] == pk[pr]).all())
+    for g, src, r in zip(cols, pc + bc, [pr] * NJK + [br] * NJK):
+        assert torch.equal(g[:m], src[r])
+    del pr, br
+    # sampled output rows against the oracle's definition on the host
+    t = np.random.default_rng(0).integers(0, m, 200_000)
+    hp, hb = host(prow, m)[t], host(brow, m)[t]
+    np.testing.assert_array_equal(b["key"][hb], p["key"][hp])
+    for c in range(NJK):
+        np.testing.assert_array_equal(host(cols[c], m)[t], p["c%d" % c][hp])
+        np.testing.assert_array_equal(host(cols[NJK + c], m)[t], b["c%d" % c][hb])
+    del bk, pk, bc, pc, prow, brow, cols
+    torch.cuda.empty_cache()

@@ -1,0 +1,176 @@
+"""GPU parity of the materializing join (build + probe + gather of k payload
+columns per side, the join microbenchmark's per-GPU work) and of the gather
+primitive under it, element by element against the CPU oracle.  Unique build
+keys, so the match order (ascending probe row) is defined and compared as is.
+Sizes span several gather tiles (2048 rows) and a ragged tail."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t, n=None):
+    a = t.cpu().numpy()
+    return a if n is None else a[:n]
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = gpu.Ctx(0, 4 << 30)
+    yield c
+    c.close()
+
+
+def mixed_cols(rng, n, k):
+    # alternate int64 and int32 payload columns
+    return [rng.integers(-2**62, 2**62, n) if c % 2 == 0 else rng.integers(-2**31, 2**31, n).astype(np.int32)
+            for c in range(k)]
+
+
+@pytest.mark.parametrize("n,m,k,ordered", [(1, 1, 1, True), (5000, 255, 3, False), (5000, 2048, 8, True),
+                                           (70_001, 2049, 2, False), (1_000_000, 100_003, 8, False),
+                                           (300_000, 300_000, 5, True)])
+def test_gather_against_indexing(gpu, ctx, n, m, k, ordered):
+    rng = np.random.default_rng(n + m + k)
+    cols = mixed_cols(rng, n, k)
+    idx = rng.integers(0, n, m).astype(np.int32)
+    if ordered:
+        idx.sort()
+    outs = gpu.gather(ctx, dev(idx), [dev(c) for c in cols])
+    ctx.check()
+    for o, c in zip(outs, cols):
+        np.testing.assert_array_equal(host(o), c[idx])
+    # a device count below the capacity: only that prefix is written
+    cnt = m // 3
+    outs = gpu.gather(ctx, dev(idx), [dev(c) for c in cols], n=dev(np.array([cnt], np.int64)))
+    ctx.check()
+    for o, c in zip(outs, cols):
+        np.testing.assert_array_equal(host(o, cnt), c[idx[:cnt]])
+
+
+def test_gather_count_above_capacity_and_empty(gpu, ctx):
+    rng = np.random.default_rng(5)
+    cols = mixed_cols(rng, 1000, 2)
+    idx = rng.integers(0, 1000, 4097).astype(np.int32)
+    outs = gpu.gather(ctx, dev(idx), [dev(c) for c in cols], n=dev(np.array([10**9], np.int64)))
+    ctx.check()
+    for o, c in zip(outs, cols):
+        np.testing.assert_array_equal(host(o), c[idx])
+    outs = gpu.gather(ctx, dev(np.zeros(0, np.int32)), [dev(c) for c in cols])
+    ctx.check()
+    assert all(o.numel() == 0 for o in outs)
+
+
+def test_gather_bad_index_and_arguments(gpu, ctx):
+    import torch
+    c = np.arange(100, dtype=np.int64) * 7
+    idx = np.array([3, 100, 5, -1, 99] + [1] * 3000, np.int32)
+    dc, di = dev(c), dev(idx)
+    out = torch.full((len(idx),), -5, dtype=torch.int64, device="cuda")
+    carr = (gpu.Col * 1)(gpu.col(dc))
+    oarr = (gpu.ctypes.c_void_p * 1)(out.data_ptr())
+    lib = gpu.load()
+    st = lib.pyst_gather(ctx.h, gpu.ctypes.c_void_p(di.data_ptr()), None, len(idx), carr, 1, oarr,
+                         gpu._stream())
+    assert st == gpu.OK
+    with pytest.raises(gpu.PystError) as e:
+        ctx.check()
+    assert e.value.status == gpu.ERR_INDEX
+    got = host(out)
+    ok = (idx >= 0) & (idx < 100)
+    np.testing.assert_array_equal(got[ok], c[idx[ok]])
+    assert np.all(got[~ok] == -5)  # rows with a bad index are left unwritten
+    with pytest.raises(gpu.PystError) as e:
+        gpu.gather(ctx, dev(idx[:3]), [])
+    assert e.value.status == gpu.ERR_ARG
+    with pytest.raises(gpu.PystError) as e:
+        gpu.gather(ctx, dev(idx[:3]), [dc] * 9)
+    assert e.value.status == gpu.ERR_ARG
+    with pytest.raises(gpu.PystError) as e:
+        gpu.gather(ctx, dev(idx[:3]), [dc, dev(c[:50])])
+    assert e.value.status == gpu.ERR_ARG
+
+
+@pytest.mark.parametrize("nb,npr,k", [(1000, 5000, 1), (20_000, 100_003, 4), (50_000, 400_000, 8),
+                                      (3, 4097, 2), (300_000, 2_000_000, 3)])
+def test_join_materialize_matches_oracle(gpu, ctx, nb, npr, k):
+    b, p = gen.join_tables(nb, npr, k)
+    bc = [b["c%d" % c] for c in range(k)]
+    pc = [p["c%d" % c] for c in range(k)]
+    if k > 1:  # one int32 column per side
+        bc[1] = (bc[1] >> 33).astype(np.int32)
+        pc[1] = (pc[1] >> 33).astype(np.int32)
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), [dev(c) for c in bc], dev(p["key"]),
+                                                  [dev(c) for c in pc])
+    ctx.check()
+    wp, wb, wcols = oracle.join_materialize(b["key"], bc, p["key"], pc)
+    m = int(host(nout)[0])
+    assert m == len(wp)
+    np.testing.assert_array_equal(host(prow, m), wp)
+    np.testing.assert_array_equal(host(brow, m), wb)
+    assert len(cols) == len(wcols) == 2 * k
+    for g, w in zip(cols, wcols):
+        assert host(g, m).dtype == w.dtype
+        np.testing.assert_array_equal(host(g, m), w)
+
+
+def test_join_materialize_one_side_and_empty(gpu, ctx):
+    b, p = gen.join_tables(4000, 30_000, 2)
+    bc, pc = [b["c0"], b["c1"]], [p["c0"], p["c1"]]
+    wp, wb, wcols = oracle.join_materialize(b["key"], bc, p["key"], pc)
+    # build columns only
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), [dev(c) for c in bc], dev(p["key"]), [])
+    ctx.check()
+    m = int(host(nout)[0])
+    assert m == len(wp) and len(cols) == 2
+    for g, w in zip(cols, wcols[2:]):
+        np.testing.assert_array_equal(host(g, m), w)
+    # probe columns only, no columns at all
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), [], dev(p["key"]), [dev(c) for c in pc])
+    ctx.check()
+    for g, w in zip(cols, wcols[:2]):
+        np.testing.assert_array_equal(host(g, m), w)
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), [], dev(p["key"]), [])
+    ctx.check()
+    np.testing.assert_array_equal(host(brow, m), wb)
+    # an empty build side and an empty probe side
+    e32 = np.zeros(0, np.int32)
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(e32), [dev(np.zeros(0, np.int64))], dev(p["key"]),
+                                                  [dev(pc[0])])
+    ctx.check()
+    assert int(host(nout)[0]) == 0
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), [dev(bc[0])], dev(e32),
+                                                  [dev(np.zeros(0, np.int64))])
+    ctx.check()
+    assert int(host(nout)[0]) == 0
+
+
+def test_join_materialize_capacity_and_duplicate_key(gpu, ctx):
+    b, p = gen.join_tables(5000, 50_000, 1)
+    wp, wb, wcols = oracle.join_materialize(b["key"], [b["c0"]], p["key"], [p["c0"]])
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), [dev(b["c0"])], dev(p["key"]),
+                                                  [dev(p["c0"])], out_cap=1000)
+    with pytest.raises(gpu.PystError) as e:
+        ctx.check()
+    assert e.value.status == gpu.ERR_CAPACITY
+    assert int(host(nout)[0]) == len(wp)  # the count holds the need
+    np.testing.assert_array_equal(host(prow), wp[:1000])
+    for g, w in zip(cols, wcols):
+        np.testing.assert_array_equal(host(g), w[:1000])
+    key = b["key"].copy()
+    key[17] = key[4000]
+    gpu.join_materialize(ctx, dev(key), [dev(b["c0"])], dev(p["key"]), [dev(p["c0"])])
+    with pytest.raises(gpu.PystError) as e:
+        ctx.check()
+    assert e.value.status == gpu.ERR_DUP_KEY
+    with pytest.raises(gpu.PystError) as e:
+        gpu.join_materialize(ctx, dev(b["key"]), [dev(b["c0"][:10])], dev(p["key"]), [dev(p["c0"])])
+    assert e.value.status == gpu.ERR_ARG

@@ -150,6 +150,22 @@ def test_join_payload_and_capacity_error(gpu, ctx):
     t.destroy()
 
 
+@pytest.mark.parametrize("unique", [True, False])
+def test_join_probe_sentinel_key_matches_nothing(gpu, ctx, unique):
+    # the EMPTY sentinel as a probe key must not match an empty slot
+    bk = np.array([5, 6, 7], np.int32)
+    pk = np.array([-2**31, 5, -2**31, 7] + [-2**31] * 5000 + [6], np.int32)
+    t = gpu.join_build(ctx, dev(bk), unique_keys=unique)
+    rows, pays, nout = gpu.join_probe(ctx, t, dev(pk))
+    ctx.check()
+    wr, wb = oracle.join(bk, pk)
+    m = int(host(nout)[0])
+    assert m == len(wr) == 3
+    np.testing.assert_array_equal(host(rows, m), wr)
+    np.testing.assert_array_equal(host(pays, m), wb)
+    t.destroy()
+
+
 def test_join_sentinel_key_and_duplicate_promise(gpu, ctx):
     key = np.array([1, 2, -2**31, 4], np.int32)
     t = gpu.join_build(ctx, dev(key))

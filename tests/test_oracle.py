@@ -196,6 +196,42 @@ def test_join_cardinality_and_searchsorted():
     assert len(oracle.join(np.zeros(0, np.int32), pk)[0]) == 0
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_join_materialize_brute_force(seed):
+    # every output tuple is (probe columns at p, build columns at b) for each
+    # matching pair in ascending (p, b) order, written out with plain loops
+    rng = np.random.default_rng(300 + seed)
+    nb, npr, k = int(rng.integers(0, 200)), int(rng.integers(0, 400)), int(rng.integers(1, 9))
+    bk = rng.integers(0, 60, nb).astype(np.int32)
+    pk = rng.integers(0, 80, npr).astype(np.int32)
+    bc = [rng.integers(-2**62, 2**62, nb) if c % 2 else rng.integers(-2**31, 2**31, nb).astype(np.int32)
+          for c in range(k)]
+    pc = [rng.integers(-2**62, 2**62, npr) for _ in range(k)]
+    pr, br, cols = oracle.join_materialize(bk, bc, pk, pc)
+    want = [(i, j) for i in range(npr) for j in range(nb) if bk[j] == pk[i]]
+    assert list(zip(pr.tolist(), br.tolist())) == want
+    assert len(cols) == 2 * k
+    for t, (i, j) in enumerate(want):
+        assert [int(c[t]) for c in cols] == [int(c[i]) for c in pc] + [int(c[j]) for c in bc]
+    for c, src in zip(cols, pc + bc):
+        assert c.dtype == src.dtype
+
+
+def test_join_tables_recipe():
+    nb, npr, k = 20000, 400000, 3
+    b, p = gen.join_tables(nb, npr, k)
+    assert sorted(b["key"].tolist()) == list(range(1, nb + 1))
+    assert p["key"].min() >= 1 and p["key"].max() <= 2 * nb
+    assert abs(np.mean(p["key"] <= nb) - 0.5) < 0.005  # hit ratio 0.5
+    for c in range(k):
+        for t in (b, p):
+            assert t["c%d" % c].dtype == np.int64
+            assert np.abs(t["c%d" % c]).max() <= 2**62
+    assert not np.array_equal(b["c0"], b["c1"]) and not np.array_equal(p["c0"][:nb], b["c0"])
+    pr, br, cols = oracle.join_materialize(b["key"], [b["c0"]], p["key"], [p["c0"]])
+    assert len(pr) == int(np.sum(p["key"] <= nb))
+
+
 # ------------------------------------------------------------------ group-by
 
 @pytest.mark.parametrize("seed", range(5))
