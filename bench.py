@@ -14,6 +14,8 @@ Beside the headline line it reports, measured outside the timed region:
   cpu_baseline  : the CPU oracle (single thread) on a bounded sample
   partition     : hash partition of the probe table, fanout 2 / 8 / 64
   chain         : the two-join chain query (fact 120M, Zipf s = 0 and 1)
+  groupby       : GROUP BY orderkey SUM(quantity) over 60M lineitem-like rows
+                  (about 14.7M groups), radix-partitioned path vs HBM hash table
   join          : the materializing join of the join microbenchmark at one GPU's
                   share (build 60M / probe 160M, hit ratio 0.5, k = 1, 4, 8
                   8-byte columns a side)
@@ -153,7 +155,7 @@ def main():
     ap.add_argument("--probe-rows", type=int, default=60_000_000)
     ap.add_argument("--max-load", type=float, default=0.5)
     ap.add_argument("--no-extras", action="store_true", help="skip every measurement beside the headline")
-    ap.add_argument("--extras", default="partition,chain,join,stream,batch,serve",
+    ap.add_argument("--extras", default="partition,chain,groupby,join,stream,batch,serve",
                     help="comma-separated extra measurements to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=30_000_000)
@@ -264,6 +266,9 @@ def main():
     if "chain" in extras:
         result["chain"] = bench_chain(ctx, pyst, gen, log)
         torch.cuda.empty_cache()
+    if "groupby" in extras:
+        result["groupby"] = bench_groupby(ctx, pyst, gen, log)
+        torch.cuda.empty_cache()
     if "join" in extras:
         result["join"] = bench_join(ctx, pyst, gen, log, ks=[int(x) for x in args.join_k.split(",")])
         torch.cuda.empty_cache()
@@ -349,6 +354,39 @@ def bench_chain(ctx, pyst, gen, log):
     # when the kernel's source has changed since they were taken)
     out["fact_pass_traffic"] = counter_traffic("k_fast_fact<2, 8, 2", CHAIN_WORKLOAD)
     out["fact_pass_algorithmic_bytes"] = nf * 24
+    return out
+
+
+def bench_groupby(ctx, pyst, gen, log, n=60_000_000, n_orders=15_000_000):
+    """GROUP BY orderkey SUM(quantity), groups far beyond the caches: both group-by paths."""
+    import torch
+    li = gen.q18_lineitem(n, n_orders)
+    k, v = torch.from_numpy(li["orderkey"]).cuda(), torch.from_numpy(li["quantity"]).cuda()
+    del li
+    out = {"rows": n, "key_range": n_orders}
+    for path, hash_only in (("radix", False), ("hash", True)):
+        log("group-by %d rows, path %s" % (n, path))
+        ctx.groupby_hash_only(hash_only)
+
+        def step():
+            return pyst.groupby_sum(ctx, k, v, max_groups=n_orders)
+
+        r = step()
+        ctx.check()
+        groups = int(r[2].item())
+        del r
+        ctx.timing(True)
+        el = timed_loop(step, 5, 0)
+        ctx.timing(False)
+        g_ms, g_n = ctx.kernel_time("groupby_" + path)
+        ctx.check()
+        ms = el / 5 * 1e3
+        alg = n * 8 + groups * 16  # key and value read once, each group written once
+        out[path] = {"ms": ms, "rows_per_s": n / (ms / 1e3), "groups": groups, "algorithmic_bytes": alg,
+                     "gbs": alg / (ms / 1e3) / 1e9, "frac_of_peak": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "region_us": g_ms / max(g_n, 1) * 1e3}
+    ctx.groupby_hash_only(False)
+    out["radix_speedup"] = out["hash"]["ms"] / out["radix"]["ms"]
     return out
 
 

@@ -13,6 +13,8 @@ with a ~2407-day date, a scaled-cents price and a 0..10 discount):
 * join  : build {key = shuffled 1..Nb, c0..c(k-1) int64 U[-2^62, 2^62]},
           probe {key U[1, 2 Nb] (half the probe keys find a build key),
                  c0..c(k-1) int64 U[-2^62, 2^62]}
+* q18   : lineitem-like {orderkey U[1,No], quantity U[1,50]} (about 4 rows per key
+          at No = N/4, the TPC-H lineitem/orders ratio)
 * chain : A {key = shuffled 1..Na, date U[0,2406]},
           B {key = shuffled 1..Nb, segment U[0,4]},
           fact {a_fk U[1,Na], b_fk Zipf_s over 1..Nb, date U[0,2406],
@@ -196,6 +198,17 @@ def join_tables(n_build: int, n_probe: int, k: int, workload: int = JOIN_WORKLOA
         b["c%d" % c] = uniform_i64(n_build, -PAYLOAD_BOUND, PAYLOAD_BOUND, seed(workload, 0, 1 + c))
         p["c%d" % c] = uniform_i64(n_probe, -PAYLOAD_BOUND, PAYLOAD_BOUND, seed(workload, 1, 1 + c))
     return b, p
+
+
+Q18_WORKLOAD = 7
+QUANTITY_MAX = 50
+
+
+def q18_lineitem(n_rows: int, n_orders: int, workload: int = Q18_WORKLOAD):
+    """Rows of a group-by with many more groups than the caches hold: orderkey U[1,No] int32,
+    quantity U[1,50] int32."""
+    return {"orderkey": uniform_i32(n_rows, 1, n_orders, seed(workload, 0, 0)),
+            "quantity": uniform_i32(n_rows, 1, QUANTITY_MAX, seed(workload, 0, 1))}
 
 
 def fragment_sizes(n_frag: int, lo: float = 1e4, hi: float = 2e7, workload: int = 3):

@@ -123,9 +123,12 @@ const char *pyst_last_error(void);
 pyst_status pyst_ctx_timing(pyst_ctx *ctx, int enable);
 
 /* Context options.  PYST_OPT_GENERIC_ONLY != 0 makes pyst_query use its
-   generic fact pass even where a plan-shape-specialized kernel exists (both
-   compute the same result; tests compare them).  Errors: PYST_ERR_ARG. */
+   generic fact pass even where a plan-shape-specialized kernel exists.
+   PYST_OPT_GROUPBY_HASH_ONLY != 0 makes pyst_groupby_sum always use its HBM
+   hash table instead of the radix-partitioned path.  Both paths compute the
+   same result; tests compare them.  Errors: PYST_ERR_ARG. */
 #define PYST_OPT_GENERIC_ONLY 1
+#define PYST_OPT_GROUPBY_HASH_ONLY 2
 pyst_status pyst_ctx_option(pyst_ctx *ctx, int key, int64_t value);
 pyst_status pyst_ctx_kernel_time(pyst_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 

@@ -39,6 +39,7 @@ struct pyst_ctx {
   // optional per-kernel timing: name -> (start, stop) event pairs of each launch
   bool timing = false;
   bool generic_only = false;  // PYST_OPT_GENERIC_ONLY
+  bool groupby_hash_only = false;  // PYST_OPT_GROUPBY_HASH_ONLY
   hipStream_t copy_stream = nullptr;  // host-to-device chunk copies (created on first use)
   char *staging = nullptr;            // pinned host staging for descriptor uploads
   size_t staging_bytes = 0;
@@ -165,6 +166,7 @@ void ctx_free(pyst_ctx *c, void *p, hipStream_t stream) {
 
 uint32_t *ctx_err_word(pyst_ctx *c) { return c->d_err; }
 bool ctx_generic_only(const pyst_ctx *c) { return c->generic_only; }
+bool ctx_groupby_hash_only(const pyst_ctx *c) { return c->groupby_hash_only; }
 
 // Bytes not currently allocated (free or pending reuse); an allocation of this
 // size may still fail when the space is fragmented.
@@ -284,6 +286,7 @@ pyst_status pyst_ctx_option(pyst_ctx *c, int key, int64_t value) {
   if (!c) return set_error(PYST_ERR_ARG, "pyst_ctx_option: ctx is NULL");
   switch (key) {
     case PYST_OPT_GENERIC_ONLY: c->generic_only = value != 0; return PYST_OK;
+    case PYST_OPT_GROUPBY_HASH_ONLY: c->groupby_hash_only = value != 0; return PYST_OK;
   }
   return set_error(PYST_ERR_ARG, "pyst_ctx_option: unknown option");
 }

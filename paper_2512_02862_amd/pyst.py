@@ -23,6 +23,7 @@ I32, I64 = 0, 1
 G_NONE, G_JOIN_KEY, G_JOIN_PAYLOAD, G_FACT_COL = 0, 1, 2, 3
 V_COL, V_COL_TIMES_C_MINUS = 0, 1
 OPT_GENERIC_ONLY = 1
+OPT_GROUPBY_HASH_ONLY = 2
 
 EXPORTS = [
     "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
@@ -207,6 +208,9 @@ class Ctx:
     def generic_only(self, enable: bool):
         """Force pyst_query's generic fact pass (no plan-shape-specialized kernel)."""
         _check(_lib.pyst_ctx_option(self.h, OPT_GENERIC_ONLY, int(bool(enable))))
+
+    def groupby_hash_only(self, enable: bool):
+        _check(_lib.pyst_ctx_option(self.h, OPT_GROUPBY_HASH_ONLY, int(bool(enable))))
 
     def timing(self, enable: bool):
         """Record HIP events around the library's timed kernels (see kernel_time)."""

@@ -153,3 +153,23 @@ def test_join_materialize_full_size(gpu, ctx):
         np.testing.assert_array_equal(host(cols[NJK + c], m)[t], b["c%d" % c][hb])
     del bk, pk, bc, pc, prow, brow, cols
     torch.cuda.empty_cache()
+
+
+NQ18, NQ18_ORDERS = 60_000_000, 15_000_000
+
+
+def test_groupby_q18_full_size(gpu, ctx):
+    # GROUP BY orderkey SUM(quantity) over 60M rows and about 14.7M groups, as bench.py runs it
+    import torch
+    li = gen.q18_lineitem(NQ18, NQ18_ORDERS)
+    gk, gs, ng = gpu.groupby_sum(ctx, dev(li["orderkey"]), dev(li["quantity"]), max_groups=NQ18_ORDERS)
+    ctx.check()
+    m = int(ng.item())
+    a, s = host(gk, m), host(gs, m)
+    del gk, gs
+    torch.cuda.empty_cache()
+    o = np.argsort(a, kind="stable")
+    wk, ws = oracle.groupby_sum(li["orderkey"], li["quantity"])
+    assert m == len(wk)
+    np.testing.assert_array_equal(a[o], wk)
+    np.testing.assert_array_equal(s[o], ws)

@@ -217,6 +217,16 @@ def test_join_materialize_brute_force(seed):
         assert c.dtype == src.dtype
 
 
+def test_q18_recipe():
+    li = gen.q18_lineitem(400_000, 100_000)
+    assert li["orderkey"].min() >= 1 and li["orderkey"].max() <= 100_000
+    assert li["quantity"].min() == 1 and li["quantity"].max() == 50
+    k, s = oracle.groupby_sum(li["orderkey"], li["quantity"])
+    # keys drawn 4 times each on average: 1 - e^-4 of them occur
+    assert abs(len(k) / 100_000 - (1 - np.exp(-4.0))) < 0.01
+    assert int(s.sum()) == int(li["quantity"].astype(np.int64).sum())
+
+
 def test_join_tables_recipe():
     nb, npr, k = 20000, 400000, 3
     b, p = gen.join_tables(nb, npr, k)
