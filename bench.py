@@ -501,9 +501,34 @@ def bench_stream(ctx, pyst, gen, log, nrows):
                                 "frac_of_pinned_h2d": gbs / peak, "copy_busy_ms": copy_ms,
                                 "compute_busy_ms": fact_ms, "chunks": copies, "groups": int(ng.item())}
         del k, s
+    # the same columns bit-packed on the host: the link carries the packed bytes
+    log("stream: packing %d rows" % nrows)
+    t0 = time.perf_counter()
+    packed = [(*pyst.pack(t), nrows, t.dtype) for t in host]
+    pack_s = time.perf_counter() - t0
+    packed_bytes = sum(bl.numel() * 8 + w.numel() * 4 for bl, w, _, _ in packed)
+    for nbuf in (2, 3):
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        k, s, ng = pyst.query_streamed_packed(ctx, plan, packed, chunk_rows=chunk, nbuf=nbuf,
+                                              out_cap=plan.max_groups)
+        ctx.check()
+        dt = time.perf_counter() - t0
+        ctx.timing(False)
+        copy_ms, copies = ctx.kernel_time("h2d_chunk")
+        unpack_ms, unpacks = ctx.kernel_time("unpack")
+        fact_ms, _ = ctx.kernel_time("fact_pass")
+        out["packed_nbuf%d" % nbuf] = {
+            "seconds": dt, "fact_rows_per_s": nrows / dt, "link_gbs": packed_bytes / dt / 1e9,
+            "frac_of_pinned_h2d": packed_bytes / dt / 1e9 / peak, "copy_busy_ms": copy_ms,
+            "unpack_busy_ms": unpack_ms, "compute_busy_ms": fact_ms, "groups": int(ng.item()),
+            "speedup_vs_raw": out["nbuf%d" % nbuf]["seconds"] / dt}
+        del k, s
+    out["packed"] = {"bytes": packed_bytes, "bytes_per_row": packed_bytes / nrows,
+                     "ratio": nrows * 24 / packed_bytes, "host_encode_s": pack_s}
     out.update({"rows": nrows, "chunk_rows": chunk, "pinned_h2d_peak_gbs": peak,
                 "workload": "chain query, fact %d rows (24 B/row) in pinned host memory" % nrows})
-    del host
+    del host, packed
     return out
 
 

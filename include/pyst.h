@@ -310,6 +310,50 @@ pyst_status pyst_query(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col *fac
                        int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                        hipStream_t stream);
 
+/* ---------------------------------------------------------------- packed columns */
+
+/* A bit-packed column (the scan side: columns arrive compressed and are
+   decoded on the GPU, Sec. 4, with a self-made encoding in place of a file
+   format's).  Values are cut into blocks of PYST_PACK_BLOCK; block b stores
+   its minimum as `base` and each value's offset from it in `bits` bits, where
+   bits = 0..32 (int32) or 0..64 (int64) is the width of the block's range.
+   Value j of block b occupies bits [j * bits, (j + 1) * bits) of the 32-bit
+   little-endian words starting at words[blocks[b].word_off]; the block owns
+   32 * bits words, so blocks[b + 1].word_off - blocks[b].word_off = 32 * bits
+   and the block table has ceil(n / PYST_PACK_BLOCK) + 1 entries, the last
+   holding the total word count (and base 0). */
+#define PYST_PACK_BLOCK 1024
+
+typedef struct pyst_pack_block {
+  int64_t base;
+  int64_t word_off;
+} pyst_pack_block;
+
+typedef struct pyst_packed_col {
+  const pyst_pack_block *blocks; /* ceil(n / PYST_PACK_BLOCK) + 1 entries */
+  const uint32_t *words;         /* blocks[nblocks].word_off words */
+  int64_t n;                     /* values */
+  int32_t dtype;                 /* pyst_dtype of the decoded column */
+  int32_t reserved;
+} pyst_packed_col;
+
+/* Host only (no device work): the number of 32-bit words pyst_pack_encode
+   writes for the HOST column host_col, or -1 for a bad column. */
+int64_t pyst_pack_words(const pyst_col *host_col);
+
+/* Host only: encode the HOST column host_col into blocks
+   (ceil(n / PYST_PACK_BLOCK) + 1 entries) and words (pyst_pack_words(host_col)
+   entries), both host memory owned by the caller.  Errors: PYST_ERR_ARG. */
+pyst_status pyst_pack_encode(const pyst_col *host_col, pyst_pack_block *blocks, uint32_t *words);
+
+/* Decode a packed column held in DEVICE memory (d_blocks with
+   ceil(n / PYST_PACK_BLOCK) + 1 entries, d_words with nwords words) into the
+   device column d_out (n values of `dtype`).  A block whose header is
+   malformed or whose words fall outside [0, nwords) latches PYST_ERR_INDEX
+   and leaves its values unwritten.  Errors: PYST_ERR_ARG. */
+pyst_status pyst_pack_decode(pyst_ctx *ctx, const pyst_pack_block *d_blocks, const uint32_t *d_words, int64_t nwords,
+                             int64_t n, int dtype, void *d_out, hipStream_t stream);
+
 /* ---------------------------------------------------------------- streamed query */
 
 /* pyst_query over a fact table held in PINNED HOST memory (hipHostMalloc or
@@ -330,6 +374,18 @@ pyst_status pyst_query(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col *fac
 pyst_status pyst_query_streamed(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col *host_fact, int nfact,
                                 int64_t chunk_rows, int nbuf, int64_t *out_keys, int64_t *out_sums,
                                 int64_t out_cap, int64_t *d_ngroups, hipStream_t stream);
+
+/* pyst_query_streamed over PACKED fact columns in PINNED HOST memory (block
+   tables and words): each chunk of chunk_rows (a positive multiple of
+   PYST_PACK_BLOCK below 2^31) rows moves as its packed blocks on the copy
+   stream and is decoded on the device into the chunk ring before the fused
+   pass, so the host link carries the packed bytes.  The block tables are
+   checked on the host first (offsets from 0 in whole 32-word steps of at most
+   32 or 64 bits a value).  Otherwise as pyst_query_streamed.
+   Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED, PYST_ERR_NOMEM, PYST_ERR_HIP. */
+pyst_status pyst_query_streamed_packed(pyst_ctx *ctx, const pyst_plan *plan, const pyst_packed_col *host_fact,
+                                       int nfact, int64_t chunk_rows, int nbuf, int64_t *out_keys, int64_t *out_sums,
+                                       int64_t out_cap, int64_t *d_ngroups, hipStream_t stream);
 
 /* ---------------------------------------------------------------- batched fragments */
 

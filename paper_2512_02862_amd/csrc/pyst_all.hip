@@ -5,6 +5,7 @@
 #include "agg.hip"
 #include "query.hip"
 #include "fast.hip"
+#include "pack.hip"
 #include "stream.hip"
 #include "batch.hip"
 #include "server.hip"

@@ -28,7 +28,8 @@ OPT_GROUPBY_HASH_ONLY = 2
 EXPORTS = [
     "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
     "pyst_last_error", "pyst_filter", "pyst_partition", "pyst_join_build", "pyst_join_probe",
-    "pyst_gather", "pyst_join_materialize", "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
+    "pyst_gather", "pyst_join_materialize", "pyst_pack_words", "pyst_pack_encode", "pyst_pack_decode",
+    "pyst_query_streamed_packed", "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
     "pyst_server_create", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
@@ -45,6 +46,18 @@ class PystError(RuntimeError):
 class Col(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("dtype", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class PackBlock(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_int64), ("word_off", ctypes.c_int64)]
+
+
+class PackedCol(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_void_p), ("words", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+PACK_BLOCK = 1024
 
 
 class Pred(ctypes.Structure):
@@ -119,6 +132,10 @@ def load(path: str = LIB_PATH):
         "pyst_gather": ([p, p, p, i64, P(Col), i32, P(p), p], i32),
         "pyst_join_materialize": ([p, P(Col), P(Col), i32, P(Col), P(Col), i32, ctypes.c_double, P(p), p, p, i64, p,
                                    p], i32),
+        "pyst_pack_words": ([P(Col)], i64),
+        "pyst_pack_encode": ([P(Col), p, p], i32),
+        "pyst_pack_decode": ([p, p, p, i64, i64, i32, p, p], i32),
+        "pyst_query_streamed_packed": ([p, P(Plan), P(PackedCol), i32, i64, i32, p, p, i64, p, p], i32),
         "pyst_table_info": ([p, p, p], i32),
         "pyst_table_destroy": ([p, p], None),
         "pyst_groupby_sum": ([p, P(Col), P(Col), p, p, i64, ctypes.c_double, p, p, p, i32, p], i32),
@@ -455,6 +472,53 @@ def query_streamed(ctx: Ctx, plan: QueryPlan, host_fact, chunk_rows: int, nbuf: 
     farr = (Col * len(host_fact))(*[host_col(t) for t in host_fact])
     _check(_lib.pyst_query_streamed(ctx.h, ctypes.byref(cp), farr, len(host_fact), int(chunk_rows), int(nbuf),
                                     _ptr(ok), _ptr(osum), int(out_cap), _ptr(ng), _stream(stream)))
+    del keep
+    return ok, osum, ng
+
+
+def pack(t: torch.Tensor, pinned: bool = True):
+    """Bit-pack a contiguous int32/int64 host tensor: (blocks int64[nblocks + 1, 2] = (base, word_off),
+    words int32[...] holding the 32-bit words), in pinned host memory unless pinned=False."""
+    if t.is_cuda or not t.is_contiguous() or t.dtype not in (torch.int32, torch.int64):
+        raise ValueError("pack takes a contiguous int32/int64 host tensor")
+    c = Col(t.data_ptr(), t.numel(), I64 if t.dtype == torch.int64 else I32, 0)
+    nw = _lib.pyst_pack_words(ctypes.byref(c))
+    if nw < 0:
+        raise PystError(ERR_ARG, "pyst_pack_words: bad column")
+    nblk = (t.numel() + PACK_BLOCK - 1) // PACK_BLOCK
+    blocks = torch.empty((nblk + 1, 2), dtype=torch.int64, pin_memory=pinned)
+    words = torch.empty(max(nw, 1), dtype=torch.int32, pin_memory=pinned)
+    _check(_lib.pyst_pack_encode(ctypes.byref(c), blocks.data_ptr(), words.data_ptr()))
+    return blocks, words[:nw]
+
+
+def packed_col(blocks: torch.Tensor, words: torch.Tensor, n: int, dtype) -> PackedCol:
+    return PackedCol(blocks.data_ptr(), words.data_ptr() if words.numel() else blocks.data_ptr(), n,
+                     I64 if dtype == torch.int64 else I32, 0)
+
+
+def unpack(ctx: Ctx, blocks: torch.Tensor, words: torch.Tensor, n: int, dtype, stream=None):
+    """Decode a packed column held in device tensors into a new device column of n values."""
+    out = torch.empty(max(n, 1), dtype=dtype, device=_dev(ctx))
+    _check(_lib.pyst_pack_decode(ctx.h, _ptr(blocks), _ptr(words) if words.numel() else None, words.numel(), n,
+                                 I64 if dtype == torch.int64 else I32, _ptr(out), _stream(stream)))
+    return out[:n]
+
+
+def query_streamed_packed(ctx: Ctx, plan: QueryPlan, packed, chunk_rows: int, nbuf: int = 2, out_cap=None,
+                          stream=None):
+    """query_streamed over packed pinned host columns: packed = [(blocks, words, n, dtype), ...]."""
+    packed = list(packed)
+    cp, keep = plan.to_c()
+    if out_cap is None:
+        out_cap = plan.joins[0]["key"].numel() if plan.hi is None and plan.lo == ("join_key", 0) \
+            and len(plan.joins) == 1 else max(plan.max_groups, 1)
+    ok = torch.empty(max(out_cap, 1), dtype=torch.int64, device=_dev(ctx))
+    osum = torch.empty(max(out_cap, 1), dtype=torch.int64, device=_dev(ctx))
+    ng = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
+    farr = (PackedCol * len(packed))(*[packed_col(*x) for x in packed])
+    _check(_lib.pyst_query_streamed_packed(ctx.h, ctypes.byref(cp), farr, len(packed), int(chunk_rows), int(nbuf),
+                                           _ptr(ok), _ptr(osum), int(out_cap), _ptr(ng), _stream(stream)))
     del keep
     return ok, osum, ng
 
