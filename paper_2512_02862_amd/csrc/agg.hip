@@ -40,7 +40,23 @@ struct MoveArgs {
   int seg_stride;
   int bps;
   int shift;  // bucket = (hash >> shift) & (kRadix - 1)
+  // With kcol set, the pairs are read from the caller's columns instead: pair i
+  // is row row_of(sel, i) of (kcol, vcol), int64 or int32 (sign-extended), and
+  // an EMPTY key is latched in err (and skipped like any EMPTY key).
+  const void *kcol = nullptr;
+  const void *vcol = nullptr;
+  const int32_t *sel = nullptr;
+  int k64 = 0, v64 = 0;
+  uint32_t *err = nullptr;
 };
+
+__device__ __forceinline__ int64_t move_key(const MoveArgs &m, int64_t i) {
+  return m.kcol ? load_as_i64(m.kcol, m.k64, row_of(m.sel, i)) : m.keys[i];
+}
+
+__device__ __forceinline__ int64_t move_val(const MoveArgs &m, int64_t i) {
+  return m.kcol ? load_as_i64(m.vcol, m.v64, row_of(m.sel, i)) : m.vals[i];
+}
 
 __device__ __forceinline__ void move_range(const MoveArgs &m, int *seg, int *part, int64_t *lo, int64_t *hi) {
   *seg = blockIdx.x / m.bps;
@@ -77,7 +93,8 @@ __global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hi
 #pragma unroll
     for (int u = 0; u < kMoveItems; ++u) {
       const int64_t i = i0 + int64_t{u} * kAggBlock;
-      k[u] = i < hi ? m.keys[i] : kEmpty64;
+      k[u] = i < hi ? move_key(m, i) : kEmpty64;
+      if (m.kcol && i < hi && k[u] == kEmpty64) latch(m.err, kErrKey);
     }
 #pragma unroll
     for (int u = 0; u < kMoveItems; ++u)
@@ -115,8 +132,8 @@ __global__ __launch_bounds__(kAggBlock) void k_move_scatter(MoveArgs m, const in
 #pragma unroll
     for (int u = 0; u < kMoveTileItems; ++u) {
       const int64_t i = t0 + int64_t{u} * kAggBlock + tid;
-      k[u] = i < hi ? m.keys[i] : kEmpty64;
-      v[u] = i < hi ? m.vals[i] : 0;
+      k[u] = i < hi ? move_key(m, i) : kEmpty64;
+      v[u] = i < hi ? move_val(m, i) : 0;
     }
 #pragma unroll
     for (int u = 0; u < kMoveTileItems; ++u) {
@@ -260,9 +277,11 @@ __global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys
 // Fewer than 2^31 pairs; a bucket may hold at most kAggSlots distinct keys
 // (about 8192 x 4096 keys in all for keys that hash evenly), else the table-full
 // error is latched.
-pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *count, int64_t cap,
-                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
-                         hipStream_t stream) {
+// The moves and the bucket pass; the first move reads `first` (pairs or columns),
+// the second writes keys/vals (cap entries each).
+pyst_status pair_groupby_from(pyst_ctx *ctx, MoveArgs first, int64_t *keys, int64_t *vals, const int64_t *count,
+                              int64_t cap, int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
+                              int64_t *d_ngroups, hipStream_t stream) {
   if (cap >= (int64_t{1} << 31)) return set_error(PYST_ERR_ARG, "group-by: too many pairs");
   const int64_t n1 = int64_t{kRadix} * kAggBlocks1, n2 = int64_t{kAggBuckets} * kAggBlocks2;
   const size_t counts = static_cast<size_t>(n1 + 1 + n2 + 1) * 2 * sizeof(int32_t);
@@ -273,7 +292,13 @@ pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int6
   int64_t *tv = tk + cap;
   // First move: all pairs, by hash bits 58..63.  The scans run over one more
   // entry than the counts, so that the last offset is the total.
-  MoveArgs m1{keys, vals, count, cap, nullptr, 0, kAggBlocks1, 64 - kRadixLg};
+  MoveArgs m1 = first;
+  m1.count = count;
+  m1.cap = cap;
+  m1.seg_off = nullptr;
+  m1.seg_stride = 0;
+  m1.bps = kAggBlocks1;
+  m1.shift = 64 - kRadixLg;
   pyst_status st = fill_u32(reinterpret_cast<uint32_t *>(h1 + n1), 1, 0, stream);
   if (st == PYST_OK) st = fill_u32(reinterpret_cast<uint32_t *>(h2 + n2), 1, 0, stream);
   if (st != PYST_OK) return st;
@@ -296,6 +321,31 @@ pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int6
                                                      d_ngroups, ctx_err_word(ctx));
   PYST_LAUNCH_CHECK("k_bucket_groups");
   return PYST_OK;
+}
+
+pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *count, int64_t cap,
+                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                         hipStream_t stream) {
+  MoveArgs first{};
+  first.keys = keys;
+  first.vals = vals;
+  return pair_groupby_from(ctx, first, keys, vals, count, cap, out_keys, out_sums, out_cap, d_ngroups, stream);
+}
+
+// Group-by of the rows [0, *count) of a selection over (key, val) columns: the
+// first move reads the columns, so no widened copy of the pairs is written.
+// pk/pv: scratch for cap pairs.
+pyst_status column_groupby(pyst_ctx *ctx, const pyst_col *key, const pyst_col *val, const int32_t *sel,
+                           const int64_t *count, int64_t *pk, int64_t *pv, int64_t *out_keys, int64_t *out_sums,
+                           int64_t out_cap, int64_t *d_ngroups, hipStream_t stream) {
+  MoveArgs first{};
+  first.kcol = key->data;
+  first.vcol = val->data;
+  first.sel = sel;
+  first.k64 = key->dtype == PYST_I64;
+  first.v64 = val->dtype == PYST_I64;
+  first.err = ctx_err_word(ctx);
+  return pair_groupby_from(ctx, first, pk, pv, count, key->n, out_keys, out_sums, out_cap, d_ngroups, stream);
 }
 
 }  // namespace pyst

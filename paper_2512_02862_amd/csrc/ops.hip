@@ -1033,27 +1033,10 @@ __global__ __launch_bounds__(BLOCK) void k_gather_rows(const int64_t *rows, Gath
   }
 }
 
-// Selected rows of a (key, value) column pair as int64 pairs [0, count) for the
-// radix-partitioned group-by.  An EMPTY key is latched and stays EMPTY, which
-// the partitioning moves skip.
-__global__ __launch_bounds__(256) void k_gb_pairs(const void *key, int key64, const void *val, int val64,
-                                                  const int32_t *sel, const int64_t *d_nsel, int64_t n,
-                                                  int64_t *okeys, int64_t *ovals, uint32_t *err) {
-  int64_t cnt = count_of(d_nsel, n);
-  if (cnt > n) cnt = n;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = row_of(sel, i);
-    const int64_t k = load_as_i64(key, key64, row);
-    if (k == kEmpty64) latch(err, kErrKey);
-    __builtin_nontemporal_store(k, &okeys[i]);
-    __builtin_nontemporal_store(load_as_i64(val, val64, row), &ovals[i]);
-  }
-}
-
 // Defined with the pair aggregation and the context.
-pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *count, int64_t cap,
-                         int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
-                         hipStream_t stream);
+pyst_status column_groupby(pyst_ctx *ctx, const pyst_col *key, const pyst_col *val, const int32_t *sel,
+                           const int64_t *count, int64_t *pk, int64_t *pv, int64_t *out_keys, int64_t *out_sums,
+                           int64_t out_cap, int64_t *d_ngroups, hipStream_t stream);
 bool ctx_groupby_hash_only(const pyst_ctx *ctx);
 
 // The radix path groups 4096 hash buckets in an LDS table of 8192 slots each:
@@ -1374,8 +1357,9 @@ pyst_status pyst_groupby_sum(pyst_ctx *ctx, const pyst_col *key, const pyst_col 
   const int64_t out_cap = max_groups > 0 ? max_groups : key->n;
   if (out_cap > 0 && (!out_keys || !out_sums)) return set_error(PYST_ERR_ARG, "pyst_groupby_sum: NULL outputs");
   if (!ctx_groupby_hash_only(ctx) && key->n >= kRadixRowsMin && bound <= kRadixGroupsMax) {
-    // Radix-partitioned: the pairs are moved twice by hash bits into 4096 buckets
-    // and each bucket is summed in LDS, instead of two random L2 atomics per row.
+    // Radix-partitioned: the rows are moved twice by hash bits into 4096 buckets
+    // (the first move reading the columns) and each bucket is summed in LDS,
+    // instead of two random L2 atomics per row.
     TimedRegion timed(ctx, "groupby_radix", stream);
     Scratch pairs(ctx, static_cast<size_t>(key->n) * 16 + 256, stream);
     if (!pairs.p) return set_error(PYST_ERR_NOMEM, "pyst_groupby_sum: arena exhausted");
@@ -1383,11 +1367,8 @@ pyst_status pyst_groupby_sum(pyst_ctx *ctx, const pyst_col *key, const pyst_col 
     pyst_status st = fill_u64(d_ngroups, 1, 0, stream);
     if (st == PYST_OK && !d_nsel) st = fill_u64(d_cnt, 1, static_cast<uint64_t>(key->n), stream);
     if (st != PYST_OK) return st;
-    k_gb_pairs<<<grid_for(ctx, key->n, 256, 8), 256, 0, stream>>>(key->data, key->dtype == PYST_I64, val->data,
-                                                                   val->dtype == PYST_I64, sel, d_nsel, key->n, pk,
-                                                                   pv, ctx_err_word(ctx));
-    PYST_LAUNCH_CHECK("k_gb_pairs");
-    st = pair_groupby(ctx, pk, pv, d_nsel ? d_nsel : d_cnt, key->n, out_keys, out_sums, out_cap, d_ngroups, stream);
+    st = column_groupby(ctx, key, val, sel, d_nsel ? d_nsel : d_cnt, pk, pv, out_keys, out_sums, out_cap, d_ngroups,
+                        stream);
     if (st != PYST_OK) return st;
     if (sort_by_key) return sort_pairs_by_key(ctx, out_keys, out_sums, d_ngroups, out_cap, stream);
     return PYST_OK;
