@@ -90,12 +90,14 @@ pyst_status launch_unpack(pyst_ctx *ctx, const pyst_pack_block *blocks, const ui
 
 using namespace pyst;
 
+static bool pack_col_ok(const pyst_col *c) {
+  return c && c->n >= 0 && (c->n == 0 || c->data) && (c->dtype == PYST_I32 || c->dtype == PYST_I64);
+}
+
 extern "C" {
 
 int64_t pyst_pack_words(const pyst_col *host_col) {
-  if (!host_col || host_col->n < 0 || (host_col->n > 0 && !host_col->data) ||
-      !(host_col->dtype == PYST_I32 || host_col->dtype == PYST_I64))
-    return -1;
+  if (!pack_col_ok(host_col)) return -1;
   const int64_t n = host_col->n, nblk = ceil_div(n, kPackBlock);
   int64_t total = 0;
   for (int64_t b = 0; b < nblk; ++b) {
@@ -114,7 +116,7 @@ int64_t pyst_pack_words(const pyst_col *host_col) {
 }
 
 pyst_status pyst_pack_encode(const pyst_col *host_col, pyst_pack_block *blocks, uint32_t *words) {
-  if (pyst_pack_words(host_col) < 0) return set_error(PYST_ERR_ARG, "pyst_pack_encode: bad column");
+  if (!pack_col_ok(host_col)) return set_error(PYST_ERR_ARG, "pyst_pack_encode: bad column");
   if (!blocks || (host_col->n > 0 && !words)) return set_error(PYST_ERR_ARG, "pyst_pack_encode: NULL output");
   const int64_t n = host_col->n, nblk = ceil_div(n, kPackBlock);
   const bool is64 = host_col->dtype == PYST_I64;
