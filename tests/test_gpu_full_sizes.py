@@ -4,8 +4,8 @@ partition of its probe table at F = 2, 8 and 64, the two-join chain at
 3M / 300k / 120M rows with Zipf s = 0 and 1, and the batch of 512 fragments
 (1.19e9 probe rows) run as a captured graph -- every output element against
 the oracle run on the whole tables -- and the materializing join of the join
-microbenchmark at one GPU's share (60M build / 160M probe rows, four 8-byte
-columns a side), checked by properties that fix its result at any size plus
+microbenchmark at one GPU's share (60M build / 160M probe rows, 1, 4 and 8
+8-byte columns a side), checked by properties that fix its result at any size plus
 every gathered element against torch indexing and sampled rows against the
 oracle's definition.  These take seconds to tens of seconds each, most of it
 generating the tables and running the oracle on the host."""
@@ -123,10 +123,12 @@ def test_batch_full_size(gpu, ctx):
         torch.cuda.empty_cache()
 
 
-NJB, NJP, NJK = 60_000_000, 160_000_000, 4
+NJB, NJP = 60_000_000, 160_000_000
 
 
-def test_join_materialize_full_size(gpu, ctx):
+@pytest.mark.parametrize("NJK", [1, 4, 8])
+def test_join_materialize_full_size(gpu, ctx, NJK):
+    # k = 1 gathers the build column directly; k = 4 and 8 through 32- and 64-byte packed rows
     import torch
     b, p = gen.join_tables(NJB, NJP, NJK)
     bk, pk = dev(b["key"]), dev(p["key"])
@@ -151,7 +153,7 @@ def test_join_materialize_full_size(gpu, ctx):
     for c in range(NJK):
         np.testing.assert_array_equal(host(cols[c], m)[t], p["c%d" % c][hp])
         np.testing.assert_array_equal(host(cols[NJK + c], m)[t], b["c%d" % c][hb])
-    del bk, pk, bc, pc, prow, brow, cols
+    del bk, pk, bc, pc, prow, brow, cols, b, p
     torch.cuda.empty_cache()
 
 
