@@ -259,27 +259,26 @@ def main():
     }
 
     extras = [] if args.no_extras else args.extras.split(",")
-    if "partition" in extras:
-        result["partition"] = bench_partition(ctx, pyst, p, npr, log)
+    def extra(name, fn, *a):
+        # an extra that fails is recorded with its error; the headline line is still printed
+        if name not in extras:
+            return
+        try:
+            result[name] = fn(*a)
+        except Exception as e:  # noqa: BLE001
+            log("extra %s failed: %r" % (name, e))
+            result[name] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+
+    extra("partition", bench_partition, ctx, pyst, p, npr, log)
     del b, p, fact
     torch.cuda.empty_cache()
-    if "chain" in extras:
-        result["chain"] = bench_chain(ctx, pyst, gen, log)
-        torch.cuda.empty_cache()
-    if "groupby" in extras:
-        result["groupby"] = bench_groupby(ctx, pyst, gen, log)
-        torch.cuda.empty_cache()
-    if "join" in extras:
-        result["join"] = bench_join(ctx, pyst, gen, log, ks=[int(x) for x in args.join_k.split(",")])
-        torch.cuda.empty_cache()
-    if "stream" in extras:
-        result["stream"] = bench_stream(ctx, pyst, gen, log, args.stream_rows)
-        torch.cuda.empty_cache()
-    if "batch" in extras:
-        result["batch"] = bench_batch(ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
-        torch.cuda.empty_cache()
-    if "serve" in extras:
-        result["serve"] = bench_serve(pyst, gen, log, args.serve_rows, args.serve_requests)
+    extra("chain", bench_chain, ctx, pyst, gen, log)
+    extra("groupby", bench_groupby, ctx, pyst, gen, log)
+    extra("join", bench_join, ctx, pyst, gen, log, 60_000_000, 160_000_000, [int(x) for x in args.join_k.split(",")])
+    extra("stream", bench_stream, ctx, pyst, gen, log, args.stream_rows)
+    extra("batch", bench_batch, ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
+    extra("serve", bench_serve, pyst, gen, log, args.serve_rows, args.serve_requests)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(b_host, p_host, args.cpu_sample_rows, log)
