@@ -130,19 +130,22 @@ pyst_status streamed_query(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col 
         if (e != hipSuccess) st = hip_error(e, "pyst_query_streamed: hipMemcpyAsync");
       }
     }
-    // packed chunks are decoded on the copy stream, into the slot the fact pass reads
-    for (int c = 0; packed && c < nfact && st == PYST_OK; ++c) {
-      const int64_t b0 = off / PYST_PACK_BLOCK, b1 = ceil_div(off + rows, PYST_PACK_BLOCK);
-      const int64_t w0 = packed[c].blocks[b0].word_off, w1 = packed[c].blocks[b1].word_off;
-      st = launch_unpack(ctx, reinterpret_cast<const pyst_pack_block *>(hdr[b][c]),
-                         reinterpret_cast<const uint32_t *>(wbuf[b][c]), w1 - w0, w0, rows, host_fact[c].dtype,
-                         buf[b][c], cs);
-    }
     if (st != PYST_OK) break;
     if (hipEventRecord(copied[b], cs) != hipSuccess || hipStreamWaitEvent(stream, copied[b], 0) != hipSuccess) {
       st = set_error(PYST_ERR_HIP, "pyst_query_streamed: chunk event");
       break;
     }
+    // Packed chunks are decoded on `stream`, into the slot the fact pass reads, so
+    // the copy stream goes on with the next chunk meanwhile; the slot's packed
+    // buffers are reused only after `consumed`, recorded after the fact pass.
+    for (int c = 0; packed && c < nfact && st == PYST_OK; ++c) {
+      const int64_t b0 = off / PYST_PACK_BLOCK, b1 = ceil_div(off + rows, PYST_PACK_BLOCK);
+      const int64_t w0 = packed[c].blocks[b0].word_off, w1 = packed[c].blocks[b1].word_off;
+      st = launch_unpack(ctx, reinterpret_cast<const pyst_pack_block *>(hdr[b][c]),
+                         reinterpret_cast<const uint32_t *>(wbuf[b][c]), w1 - w0, w0, rows, host_fact[c].dtype,
+                         buf[b][c], stream);
+    }
+    if (st != PYST_OK) break;
     FastArgs ca;
     fast_shape(plan, dev_fact.data(), q, &ca);
     st = fast_fact_pass(ctx, plan->njoins, q.agg_mode, ca, d, s.g, s.po, stream);
