@@ -66,3 +66,26 @@ def test_context_creation_without_a_gpu_fails_cleanly(lib):
     h = ctypes.c_void_p()
     st = lib.pyst_ctx_create(0, 1 << 20, ctypes.byref(h))
     assert st != 0 and not h.value
+
+
+def test_new_entry_points_reject_bad_arguments_synchronously(lib):
+    from paper_2512_02862_amd import pyst
+    pyst.load(LIB)
+    L = pyst._lib
+    assert L.pyst_gather(None, None, None, 0, None, 1, None, None) == pyst.ERR_ARG
+    assert L.pyst_join_materialize(None, None, None, 0, None, None, 0, 0.5, None, None, None, 0, None, None) == \
+        pyst.ERR_ARG
+    assert L.pyst_pack_words(None) == -1
+    bad = pyst.Col(None, 5, pyst.I32, 0)  # data NULL with n > 0
+    assert L.pyst_pack_words(ctypes.byref(bad)) == -1
+    assert L.pyst_pack_encode(ctypes.byref(bad), None, None) == pyst.ERR_ARG
+    assert L.pyst_pack_decode(None, None, None, 0, 10, pyst.I32, None, None) == pyst.ERR_ARG
+    assert L.pyst_query_streamed_packed(None, None, None, 0, 1024, 2, None, None, 0, None, None) == pyst.ERR_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
