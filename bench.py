@@ -602,8 +602,9 @@ def bench_serve(pyst, gen, log, nrows, nreq):
         g = int(min(max(r // 8, 1024), 150_000_000))
         return pyst.chain_plan(a, b, max_groups=g), g
 
-    def run(max_active, arrivals):
-        srv = pyst.Server(host, budget=48 << 30, max_active=max_active, nbuf=2, chunk_rows=16_000_000)
+    def run(max_active, arrivals, packed=None):
+        srv = pyst.Server(None if packed else host, budget=48 << 30, max_active=max_active, nbuf=2,
+                          chunk_rows=16_000_000, packed=packed)
         # warm the resident dimension tables outside the trace
         for kind in ("star", "chain"):
             p, c = plan_for(kind, 1_000_000)
@@ -646,9 +647,15 @@ def bench_serve(pyst, gen, log, nrows, nreq):
     log("serve: Poisson rate %.2f req/s (0.9 x one-at-a-time capacity)" % lam)
     fifo = run(1, arrivals)
     cont = run(8, arrivals)
-    del host
+    # the same trace served from bit-packed host columns (decoded on the device per chunk)
+    log("serve: packing %d rows" % nrows)
+    packed = [(*pyst.pack(t), nrows, t.dtype) for t in host]
+    cont_packed = run(8, arrivals, packed)
+    packed_bytes = sum(bl.numel() * 8 + w.numel() * 4 for bl, w, _, _ in packed)
+    del host, packed
     return {"fact_rows": nrows, "requests": nreq, "arrival_rate_per_s": lam, "one_at_a_time": fifo,
-            "continuous_batching": cont, "burst_one_at_a_time": burst,
+            "continuous_batching": cont, "continuous_batching_packed": cont_packed,
+            "packed_bytes_per_row": packed_bytes / nrows, "burst_one_at_a_time": burst,
             "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]" % nrows}
 
 

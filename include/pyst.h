@@ -511,6 +511,15 @@ typedef struct pyst_server_stats {
 pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pyst_col *host_fact, int nfact,
                                pyst_server **out);
 
+/* pyst_server_create over PACKED fact columns in pinned host memory (see
+   pyst_pack_encode), kept alive by the caller until pyst_server_destroy: each
+   chunk moves over the host link as its packed blocks and is decoded on the
+   device before the requests that share it run.  cfg->chunk_rows must be a
+   multiple of PYST_PACK_BLOCK; block tables are checked on the host.
+   Errors: PYST_ERR_ARG, PYST_ERR_NOMEM, PYST_ERR_HIP. */
+pyst_status pyst_server_create_packed(int device, const pyst_server_cfg *cfg, const pyst_packed_col *host_fact,
+                                      int nfact, pyst_server **out);
+
 /* Queue a request (thread-safe, never blocks on the GPU); *ticket identifies
    it.  Only plans served by the specialized fact pass are accepted, and group
    keys other than the single join key need plan->max_groups > 0.

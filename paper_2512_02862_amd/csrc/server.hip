@@ -111,6 +111,7 @@ struct pyst_server {
   pyst_ctx *ctx = nullptr;
   pyst_server_cfg cfg{};
   std::vector<pyst_col> fact;
+  std::vector<pyst_packed_col> packed;  // with packed input: the columns' blocks (fact then gives shapes only)
   int64_t fact_rows = 0;
   size_t row_bytes = 0;
   std::vector<hipStream_t> slots;
@@ -118,6 +119,7 @@ struct pyst_server {
   // ring of chunk buffers
   void *ring = nullptr;
   std::vector<std::vector<char *>> buf;
+  std::vector<std::vector<char *>> hdr, wbuf;  // packed blocks of each slot and column
   std::vector<hipEvent_t> copied;
   std::vector<std::vector<hipEvent_t>> users;  // events of the streams that consumed each buffer
   int64_t next_ring = 0;
@@ -219,17 +221,40 @@ static void serve_chunk(pyst_server *sv, int64_t c) {
   int64_t need = 0;  // rows of this chunk that any active request reads
   for (auto &r : sv->active)
     if (c < r->nchunks && !r->done[c]) need = std::max(need, std::min(sv->cfg.chunk_rows, r->rows - off));
+  double bytes = 0;
   {
     TimedRegion timed(sv->ctx, "h2d_chunk", cs);
     for (size_t k = 0; k < sv->fact.size(); ++k) {
-      const size_t w = sv->fact[k].dtype == PYST_I64 ? 8 : 4;
-      (void)hipMemcpyAsync(sv->buf[b][k], static_cast<const char *>(sv->fact[k].data) + off * w,
-                           static_cast<size_t>(need) * w, hipMemcpyHostToDevice, cs);
+      if (sv->packed.empty()) {
+        const size_t w = sv->fact[k].dtype == PYST_I64 ? 8 : 4;
+        (void)hipMemcpyAsync(sv->buf[b][k], static_cast<const char *>(sv->fact[k].data) + off * w,
+                             static_cast<size_t>(need) * w, hipMemcpyHostToDevice, cs);
+        bytes += static_cast<double>(need) * w;
+      } else if (need > 0) {
+        const pyst_packed_col &pc = sv->packed[k];
+        const int64_t b0 = off / PYST_PACK_BLOCK, b1 = ceil_div(off + need, PYST_PACK_BLOCK);
+        const int64_t w0 = pc.blocks[b0].word_off, w1 = pc.blocks[b1].word_off;
+        (void)hipMemcpyAsync(sv->hdr[b][k], pc.blocks + b0, static_cast<size_t>(b1 - b0 + 1) * sizeof(pyst_pack_block),
+                             hipMemcpyHostToDevice, cs);
+        if (w1 > w0)
+          (void)hipMemcpyAsync(sv->wbuf[b][k], pc.words + w0, static_cast<size_t>(w1 - w0) * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, cs);
+        bytes += static_cast<double>(b1 - b0 + 1) * sizeof(pyst_pack_block) + static_cast<double>(w1 - w0) * 4;
+      }
     }
+  }
+  // packed chunks are decoded into the slot on the copy stream, before the slot is published
+  for (size_t k = 0; !sv->packed.empty() && need > 0 && k < sv->fact.size(); ++k) {
+    const pyst_packed_col &pc = sv->packed[k];
+    const int64_t b0 = off / PYST_PACK_BLOCK, b1 = ceil_div(off + need, PYST_PACK_BLOCK);
+    const int64_t w0 = pc.blocks[b0].word_off, w1 = pc.blocks[b1].word_off;
+    (void)launch_unpack(sv->ctx, reinterpret_cast<const pyst_pack_block *>(sv->hdr[b][k]),
+                        reinterpret_cast<const uint32_t *>(sv->wbuf[b][k]), w1 - w0, w0, need, pc.dtype, sv->buf[b][k],
+                        cs);
   }
   (void)hipEventRecord(sv->copied[b], cs);
   sv->stats.chunks_copied++;
-  sv->stats.bytes_copied += static_cast<double>(need) * sv->row_bytes;
+  sv->stats.bytes_copied += bytes;
   std::vector<pyst_col> dev(sv->fact);
   for (auto &r : sv->active) {
     if (c >= r->nchunks || r->done[c] || r->status != PYST_OK) continue;
@@ -360,8 +385,9 @@ using namespace pyst;
 
 extern "C" {
 
-pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pyst_col *host_fact, int nfact,
-                               pyst_server **out) {
+// host_fact gives the columns (raw input) or their shapes (with `packed`).
+static pyst_status server_create(int device, const pyst_server_cfg *cfg, const pyst_col *host_fact, int nfact,
+                                 const pyst_packed_col *packed, pyst_server **out) {
   if (!cfg || !host_fact || !out || nfact < 1 || nfact > PYST_MAX_COLS)
     return set_error(PYST_ERR_ARG, "pyst_server_create: bad argument");
   *out = nullptr;
@@ -372,12 +398,32 @@ pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pys
   for (int c = 0; c < nfact; ++c)
     if (host_fact[c].n != n || !(host_fact[c].dtype == PYST_I32 || host_fact[c].dtype == PYST_I64) || !host_fact[c].data)
       return set_error(PYST_ERR_ARG, "pyst_server_create: fact columns must be int32/int64 of equal length");
+  // Per slot and column: the decoded chunk, and with packed input its block
+  // headers and the most words any chunk of the column has.
+  auto round = [](size_t x) { return (x + 255) / 256 * 256; };
+  std::vector<size_t> col_bytes(nfact), hdr_bytes(nfact, 0), word_bytes(nfact, 0);
+  const int64_t nchunks = ceil_div(n, cfg->chunk_rows);
+  for (int c = 0; c < nfact; ++c) {
+    col_bytes[c] = round(static_cast<size_t>(cfg->chunk_rows) * (host_fact[c].dtype == PYST_I64 ? 8 : 4));
+    if (!packed) continue;
+    hdr_bytes[c] = round(static_cast<size_t>(cfg->chunk_rows / PYST_PACK_BLOCK + 1) * sizeof(pyst_pack_block));
+    int64_t most = 0;
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+      const int64_t b0 = ch * cfg->chunk_rows / PYST_PACK_BLOCK;
+      const int64_t b1 = ceil_div(std::min<int64_t>(n, (ch + 1) * cfg->chunk_rows), PYST_PACK_BLOCK);
+      most = std::max(most, packed[c].blocks[b1].word_off - packed[c].blocks[b0].word_off);
+    }
+    word_bytes[c] = round(static_cast<size_t>(most) * sizeof(uint32_t));
+  }
+  size_t slot_bytes = 0;
+  for (int c = 0; c < nfact; ++c) slot_bytes += col_bytes[c] + hdr_bytes[c] + word_bytes[c];
   auto *sv = new pyst_server();
   sv->cfg = *cfg;
   sv->fact.assign(host_fact, host_fact + nfact);
+  if (packed) sv->packed.assign(packed, packed + nfact);
   sv->fact_rows = n;
   for (int c = 0; c < nfact; ++c) sv->row_bytes += host_fact[c].dtype == PYST_I64 ? 8 : 4;
-  const size_t ring_bytes = static_cast<size_t>(cfg->nbuf) * cfg->chunk_rows * sv->row_bytes + 512 * nfact * cfg->nbuf;
+  const size_t ring_bytes = static_cast<size_t>(cfg->nbuf) * slot_bytes;
   pyst_status st = pyst_ctx_create(device, cfg->budget_bytes + ring_bytes, &sv->ctx);
   if (st != PYST_OK) {
     delete sv;
@@ -391,13 +437,17 @@ pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pys
   }
   char *p = static_cast<char *>(sv->ring);
   sv->buf.assign(cfg->nbuf, std::vector<char *>(nfact));
+  sv->hdr = sv->buf;
+  sv->wbuf = sv->buf;
   sv->copied.assign(cfg->nbuf, nullptr);
   sv->users.assign(cfg->nbuf, {});
   for (int b = 0; b < cfg->nbuf; ++b) {
     (void)hipEventCreateWithFlags(&sv->copied[b], hipEventDisableTiming);
     for (int c = 0; c < nfact; ++c) {
       sv->buf[b][c] = p;
-      p += (static_cast<size_t>(cfg->chunk_rows) * (host_fact[c].dtype == PYST_I64 ? 8 : 4) + 255) / 256 * 256;
+      sv->hdr[b][c] = p + col_bytes[c];
+      sv->wbuf[b][c] = p + col_bytes[c] + hdr_bytes[c];
+      p += col_bytes[c] + hdr_bytes[c] + word_bytes[c];
     }
   }
   sv->slots.resize(cfg->max_active);
@@ -408,6 +458,30 @@ pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pys
   sv->thr = std::thread(scheduler, sv);
   *out = sv;
   return PYST_OK;
+}
+
+pyst_status pyst_server_create(int device, const pyst_server_cfg *cfg, const pyst_col *host_fact, int nfact,
+                               pyst_server **out) {
+  return server_create(device, cfg, host_fact, nfact, nullptr, out);
+}
+
+pyst_status pyst_server_create_packed(int device, const pyst_server_cfg *cfg, const pyst_packed_col *host_fact,
+                                      int nfact, pyst_server **out) {
+  if (!cfg || !host_fact || !out || nfact < 1 || nfact > PYST_MAX_COLS)
+    return set_error(PYST_ERR_ARG, "pyst_server_create_packed: bad argument");
+  if (cfg->chunk_rows < PYST_PACK_BLOCK || cfg->chunk_rows % PYST_PACK_BLOCK != 0)
+    return set_error(PYST_ERR_ARG, "pyst_server_create_packed: chunk_rows must be a multiple of 1024");
+  std::vector<pyst_col> shape(nfact);
+  for (int c = 0; c < nfact; ++c) {
+    const pyst_packed_col &pc = host_fact[c];
+    if (!(pc.dtype == PYST_I32 || pc.dtype == PYST_I64) || pc.n < 0 || pc.n != host_fact[0].n || !pc.blocks ||
+        (pc.n > 0 && !pc.words))
+      return set_error(PYST_ERR_ARG, "pyst_server_create_packed: bad packed column");
+    if (!pack_blocks_ok(pc.blocks, ceil_div(pc.n, PYST_PACK_BLOCK), pc.dtype))
+      return set_error(PYST_ERR_ARG, "pyst_server_create_packed: malformed block table");
+    shape[c] = pyst_col{kShapeOnly, pc.n, pc.dtype, 0};  // shape only: the raw copy path is not taken
+  }
+  return server_create(device, cfg, shape.data(), nfact, host_fact, out);
 }
 
 pyst_status pyst_server_submit(pyst_server *sv, const pyst_request *req, uint64_t *ticket) {

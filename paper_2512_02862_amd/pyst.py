@@ -32,7 +32,7 @@ EXPORTS = [
     "pyst_query_streamed_packed", "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
-    "pyst_server_create", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
+    "pyst_server_create", "pyst_server_create_packed", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
     "pyst_server_destroy",
 ]
 
@@ -149,6 +149,7 @@ def load(path: str = LIB_PATH):
         "pyst_batch_graph_launch": ([p, p], i32),
         "pyst_batch_graph_destroy": ([p], i32),
         "pyst_server_create": ([i32, P(ServerCfg), P(Col), i32, P(p)], i32),
+        "pyst_server_create_packed": ([i32, P(ServerCfg), P(PackedCol), i32, P(p)], i32),
         "pyst_server_submit": ([p, P(Request), P(ctypes.c_uint64)], i32),
         "pyst_server_wait": ([p, ctypes.c_uint64, P(ctypes.c_double)], i32),
         "pyst_server_get_stats": ([p, P(ServerStats)], i32),
@@ -597,14 +598,23 @@ class Server:
     wait(ticket) -> (keys, sums, latency_ms).
     """
 
-    def __init__(self, host_fact, budget=4 << 30, max_active=8, nbuf=3, chunk_rows=1 << 24, device=0):
+    def __init__(self, host_fact, budget=4 << 30, max_active=8, nbuf=3, chunk_rows=1 << 24, device=0,
+                 packed=None):
+        """packed: [(blocks, words, n, dtype), ...] from pack() instead of host_fact (pass host_fact=None)."""
         load()
-        self.host_fact = list(host_fact)
+        self.host_fact = list(host_fact) if host_fact is not None else []
+        self.packed = list(packed) if packed is not None else None
         self.device = device
-        self._cols = (Col * len(self.host_fact))(*[host_col(t) for t in self.host_fact])
         cfg = ServerCfg(budget, max_active, nbuf, chunk_rows)
         h = ctypes.c_void_p()
-        _check(_lib.pyst_server_create(device, ctypes.byref(cfg), self._cols, len(self.host_fact), ctypes.byref(h)))
+        if self.packed is None:
+            self._cols = (Col * len(self.host_fact))(*[host_col(t) for t in self.host_fact])
+            _check(_lib.pyst_server_create(device, ctypes.byref(cfg), self._cols, len(self.host_fact),
+                                           ctypes.byref(h)))
+        else:
+            self._cols = (PackedCol * len(self.packed))(*[packed_col(*x) for x in self.packed])
+            _check(_lib.pyst_server_create_packed(device, ctypes.byref(cfg), self._cols, len(self.packed),
+                                                  ctypes.byref(h)))
         self.h = h
         self._live = {}
 

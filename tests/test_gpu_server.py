@@ -115,3 +115,35 @@ def test_server_rejects_request_that_cannot_fit(gpu, db):
     np.testing.assert_array_equal(got[0], wk)
     np.testing.assert_array_equal(got[1], ws)
     srv.close()
+
+
+def test_packed_server_matches_oracle(gpu, db):
+    # the same mix served from bit-packed host columns: each chunk crosses the link packed
+    # and is decoded on the device; a chunk of 262144 rows is a whole number of blocks
+    import torch
+    a, b, f, host, ad, bd = db
+    packed = [(*gpu.pack(t), NF, t.dtype) for t in host]
+    rng = np.random.default_rng(6)
+    reqs = [("star" if i % 2 == 0 else "chain", int(rng.integers(1, NF + 1))) for i in range(8)]
+    reqs[1] = ("chain", NF)
+    reqs[2] = ("star", 1)
+    srv = gpu.Server(None, budget=1 << 30, max_active=5, nbuf=3, chunk_rows=262_144, packed=packed)
+    tickets = []
+    for kind, rows in reqs:
+        plan, cap = plan_for(gpu, kind, ad, bd)
+        tickets.append(srv.submit(plan, rows, cap))
+    results = [srv.wait(t) for t in tickets]
+    srv.check()
+    st = srv.stats()
+    assert st["completed"] == len(reqs)
+    # packed chunks: fewer bytes per copied chunk than one raw chunk (24 B a row)
+    assert 0 < st["bytes_copied"] / st["chunks_copied"] < 262_144 * 24
+    srv.close()
+    for (kind, rows), (k, s, lat) in zip(reqs, results):
+        got = sorted_np(k, s)
+        wk, ws = expected(kind, a, b, f, rows)
+        np.testing.assert_array_equal(got[0], wk)
+        np.testing.assert_array_equal(got[1], ws)
+    with pytest.raises(gpu.PystError) as e:
+        gpu.Server(None, chunk_rows=250_000, packed=packed)  # not a multiple of 1024
+    assert e.value.status == gpu.ERR_ARG
