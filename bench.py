@@ -11,7 +11,8 @@ Beside the headline line it reports, measured outside the timed region:
   roofline      : the fused probe kernel's algorithmic bytes / its mean HIP-event
                   duration against the 8 TB/s HBM peak (+ counter traffic when
                   a committed counter profile matches the current kernel source)
-  cpu_baseline  : the CPU oracle (single thread) on a bounded sample
+  cpu_baseline  : the CPU oracle (single thread) on a bounded sample, and the
+                  threaded CPU baseline over every usable host core
   partition     : hash partition of the probe table, fanout 2 / 8 / 64
   chain         : the two-join chain query (fact 120M, Zipf s = 0 and 1)
   groupby       : GROUP BY orderkey SUM(quantity) over 60M lineitem-like rows
@@ -659,17 +660,50 @@ def bench_serve(pyst, gen, log, nrows, nreq):
             "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]" % nrows}
 
 
+def host_cpu_info():
+    """Cores this process may run on, the machine's count and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"affinity_cores": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(b_host, p_host, sample_rows, log):
+    """The oracle on one core over a bounded sample, and the threaded CPU
+    baseline (the same algorithm over every core this process may use) on the
+    whole probe table, checked equal to the oracle on the sample first."""
+    import numpy as np
+
     import oracle
+    info = host_cpu_info()
     sample_rows = min(sample_rows, len(p_host["fk"]))
     sample = {c: v[:sample_rows] for c, v in p_host.items()}
     log("cpu oracle on %d probe rows" % sample_rows)
     t0 = time.perf_counter()
-    oracle.star_query(b_host, sample)
+    ok, osum = oracle.star_query(b_host, sample)
     dt = time.perf_counter() - t0
-    return {"value": sample_rows / dt, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
-            "sample": "full build table (%d rows), first %d probe rows; %.1f s single-threaded"
-                      % (len(b_host["key"]), sample_rows, dt)}
+    out = {"value": sample_rows / dt, "unit": "probe rows/s", "cores": 1, "kind": "oracle",
+           "sample": "full build table (%d rows), first %d probe rows; %.1f s single-threaded"
+                     % (len(b_host["key"]), sample_rows, dt),
+           "host": info}
+    threads = info["affinity_cores"]
+    tk, ts, used = oracle.star_query_threaded(b_host, sample, threads=threads)
+    equal = bool(np.array_equal(tk, ok) and np.array_equal(ts, osum))
+    n = len(p_host["fk"])
+    log("threaded cpu baseline on %d probe rows, %d threads" % (n, threads))
+    t0 = time.perf_counter()
+    oracle.star_query_threaded(b_host, p_host, threads=threads)
+    dtm = time.perf_counter() - t0
+    out["threaded"] = {"value": n / dtm, "unit": "probe rows/s", "cores": used, "kind": "threaded baseline",
+                       "equal_to_oracle_on_sample": equal,
+                       "sample": "full build table, all %d probe rows; %.2f s on %d threads" % (n, dtm, used)}
+    return out
 
 
 if __name__ == "__main__":

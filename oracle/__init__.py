@@ -22,6 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
+_SRC_MT = os.path.join(_HERE, "threaded.cpp")  # the threaded CPU baseline (same algorithm)
 _LIB = os.path.join(_HERE, "liboracle.so")
 _OPS = {"==": 0, "!=": 1, "<": 2, "<=": 3, ">": 4, ">=": 5}
 
@@ -29,9 +30,10 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_MT))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, _SRC_MT])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -60,6 +62,8 @@ def _load():
         lib.oracle_chain_query.argtypes = ([p, p, i64, p, p, p, i32] + [p, p, i64, p, p, p, i32]
                                            + [p, p, p, p, p, i64, p, p, p, i32, i64, p, p])
         lib.oracle_chain_query.restype = i64
+        lib.baseline_star_query_mt.argtypes = [p, p, i64, p, p, p, i32, p, p, p, i64, p, p, p, i32, i32, p, p, p]
+        lib.baseline_star_query_mt.restype = i64
         _lib = lib
     return _lib
 
@@ -196,6 +200,29 @@ def star_query(build, probe, build_preds=(("segment", "==", 1),),
                                   len(fk), _ptr(pc), _ptr(po), _ptr(pv), npp, ok.ctypes.data,
                                   osum.ctypes.data)
     return ok[:g].copy(), osum[:g].copy()
+
+
+def star_query_threaded(build, probe, build_preds=(("segment", "==", 1),),
+                        probe_preds=(("date", "<", 1200),), threads=0):
+    """The star query on `threads` host threads (0: all), the threaded CPU
+    baseline of ``threaded.cpp``.  Returns (keys ascending, sums, threads used)."""
+    bnames, pnames = ["key", "segment"], ["fk", "date", "price"]
+    bk = np.ascontiguousarray(build["key"], dtype=np.int32)
+    bs = np.ascontiguousarray(build["segment"], dtype=np.int32)
+    fk = np.ascontiguousarray(probe["fk"], dtype=np.int32)
+    dt = np.ascontiguousarray(probe["date"], dtype=np.int32)
+    pr = np.ascontiguousarray(probe["price"], dtype=np.int64)
+    bc, bo, bv, nbp = _preds([(bnames.index(c), o, v) for c, o, v in build_preds])
+    pc, po, pv, npp = _preds([(pnames.index(c), o, v) for c, o, v in probe_preds])
+    n = max(len(fk), 1)
+    ok = np.empty(n, dtype=np.int64)
+    osum = np.empty(n, dtype=np.int64)
+    used = np.zeros(1, dtype=np.int32)
+    g = _load().baseline_star_query_mt(bk.ctypes.data, bs.ctypes.data, len(bk), _ptr(bc), _ptr(bo),
+                                       _ptr(bv), nbp, fk.ctypes.data, dt.ctypes.data, pr.ctypes.data,
+                                       len(fk), _ptr(pc), _ptr(po), _ptr(pv), npp, int(threads),
+                                       ok.ctypes.data, osum.ctypes.data, used.ctypes.data)
+    return ok[:g].copy(), osum[:g].copy(), int(used[0])
 
 
 def chain_query(a, b, fact, a_preds=(), b_preds=(("segment", "==", 1),),

@@ -1,7 +1,9 @@
 """Pins for the CPU oracle: it is checked against things other than itself.
 
-* the hash finalizer against published MurmurHash3 vectors and against its own
-  algebraic inverse (built from the constants' modular inverses);
+* the hash finalizers against published MurmurHash3 values (fmix32 by the
+  x86_32 empty-key vectors, fmix64 by the x64_128 SMHasher verification value)
+  and against their algebraic inverses (built from the constants' modular
+  inverses);
 * every operator against brute force on small inputs and against numpy
   library routines that compute the same result another way;
 * invariants (counts sum to n, join cardinality = sum_k b(k) p(k), sums of
@@ -68,6 +70,61 @@ def test_fmix64_is_inverted_by_its_algebraic_inverse():
     assert oracle.fmix64(0) == 0
     for x in [1, M64, 2**63] + [int(v) for v in rng.integers(0, 2**63, 300)]:
         assert _inv_fmix64(oracle.fmix64(x)) == x
+
+
+def _mm3_x64_128(data, seed, fmix):
+    """MurmurHash3_x64_128 (Appleby, public domain) written out from its
+    published definition, with the 64-bit finalizer passed in."""
+    c1, c2 = 0x87C37B91114253D5, 0x4CF5AD432745937F
+
+    def rotl(x, r):
+        return ((x << r) | (x >> (64 - r))) & M64
+
+    def mix_k1(k):
+        return (rotl((k * c1) & M64, 31) * c2) & M64
+
+    def mix_k2(k):
+        return (rotl((k * c2) & M64, 33) * c1) & M64
+
+    n = len(data)
+    h1 = h2 = seed & M32
+    for i in range(n // 16):
+        k1 = int.from_bytes(data[16 * i:16 * i + 8], "little")
+        k2 = int.from_bytes(data[16 * i + 8:16 * i + 16], "little")
+        h1 ^= mix_k1(k1)
+        h1 = (((rotl(h1, 27) + h2) & M64) * 5 + 0x52DCE729) & M64
+        h2 ^= mix_k2(k2)
+        h2 = (((rotl(h2, 31) + h1) & M64) * 5 + 0x38495AB5) & M64
+    tail = data[16 * (n // 16):]
+    if len(tail) > 8:
+        h2 ^= mix_k2(int.from_bytes(tail[8:], "little"))
+    if len(tail) > 0:
+        h1 ^= mix_k1(int.from_bytes(tail[:8], "little"))
+    h1 ^= n
+    h2 ^= n
+    h1 = (h1 + h2) & M64
+    h2 = (h2 + h1) & M64
+    h1, h2 = fmix(h1), fmix(h2)
+    h1 = (h1 + h2) & M64
+    h2 = (h2 + h1) & M64
+    return h1.to_bytes(8, "little") + h2.to_bytes(8, "little")
+
+
+def test_fmix64_reproduces_the_published_murmur3_x64_128_verification_value():
+    # The oracle's fmix64 is the finalizer of MurmurHash3_x64_128; with it the
+    # whole hash must reproduce SMHasher's published verification value.
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "murmur3_x64_128_verification.txt"))
+            if l.strip() and not l.startswith("#")]
+    expected = int(rows[0][0], 16)
+    key = bytes(range(256))
+    hashes = b"".join(_mm3_x64_128(key[:i], 256 - i, oracle.fmix64) for i in range(256))
+    final = _mm3_x64_128(hashes, 0, oracle.fmix64)
+    assert int.from_bytes(final[:4], "little") == expected
+    # a finalizer with one constant changed does not reproduce it
+    def bad(k):
+        return oracle.fmix64(k) ^ 1 if k else 0
+    final_bad = _mm3_x64_128(b"".join(_mm3_x64_128(key[:i], 256 - i, bad) for i in range(256)), 0, bad)
+    assert int.from_bytes(final_bad[:4], "little") != expected
 
 
 # ------------------------------------------------------------------ filter
@@ -318,6 +375,31 @@ def test_star_query_brute_force_and_composition(nb, np_):
     ck, cs = oracle.groupby_sum(b["key"][br], p["price"][pr])
     np.testing.assert_array_equal(ck, k)
     np.testing.assert_array_equal(cs, s)
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+def test_threaded_baseline_equals_the_oracle(threads):
+    # The threaded CPU baseline runs the oracle's algorithm over row ranges;
+    # its result must be the oracle's for any thread count, including ranges
+    # with no rows, duplicate build keys and wrap-around sums.
+    b, p = gen.star_tables(3000, 40000)
+    k, s = oracle.star_query(b, p)
+    tk, ts, used = oracle.star_query_threaded(b, p, threads=threads)
+    assert used == threads
+    np.testing.assert_array_equal(tk, k)
+    np.testing.assert_array_equal(ts, s)
+    tiny_b, tiny_p = gen.star_tables(1, 2)
+    np.testing.assert_array_equal(oracle.star_query_threaded(tiny_b, tiny_p, threads=threads)[1],
+                                  oracle.star_query(tiny_b, tiny_p)[1])
+    rng = np.random.default_rng(threads)
+    db = {"key": rng.integers(1, 50, 300).astype(np.int32), "segment": rng.integers(0, 2, 300).astype(np.int32)}
+    dp = {"fk": rng.integers(1, 60, 5000).astype(np.int32), "date": rng.integers(0, 2400, 5000).astype(np.int32),
+          "price": rng.integers(2**61, 2**62, 5000)}
+    preds = (("segment", "==", 1),)
+    k, s = oracle.star_query(db, dp, build_preds=preds)
+    tk, ts, _ = oracle.star_query_threaded(db, dp, build_preds=preds, threads=threads)
+    np.testing.assert_array_equal(tk, k)
+    np.testing.assert_array_equal(ts, s)
 
 
 def _brute_chain(a, b, f, vconst=100):
