@@ -129,6 +129,10 @@ pyst_status pyst_ctx_timing(pyst_ctx *ctx, int enable);
    same result; tests compare them.  Errors: PYST_ERR_ARG. */
 #define PYST_OPT_GENERIC_ONLY 1
 #define PYST_OPT_GROUPBY_HASH_ONLY 2
+/* Test hook for failure handling: value n > 0 makes the n-th fused fact pass
+   issued through the context from now on fail on the host with PYST_ERR_HIP
+   before it launches anything (0 clears it).  No device fault is involved. */
+#define PYST_OPT_FAIL_FACT_PASS 3
 pyst_status pyst_ctx_option(pyst_ctx *ctx, int key, int64_t value);
 pyst_status pyst_ctx_kernel_time(pyst_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 
@@ -527,12 +531,34 @@ pyst_status pyst_server_create_packed(int device, const pyst_server_cfg *cfg, co
 pyst_status pyst_server_submit(pyst_server *server, const pyst_request *req, uint64_t *ticket);
 
 /* Block until request `ticket` has completed (its outputs are then final);
-   *latency_ms = completion - submission.  Returns the request's status
-   (PYST_ERR_NOMEM if it can never fit the budget).  A ticket is waited once. */
+   *latency_ms = completion - submission.  Returns the request's own status:
+   PYST_ERR_NOMEM if it can never fit the budget, a host-side error of one of
+   its launches (the request then stops at that chunk and is finished), or an
+   error its kernels latched (each request has its own device error word, and
+   so has each resident dimension table: a capacity overflow of one request,
+   or a duplicate key in its dimension, fails that request and no other).
+   A ticket is waited once. */
 pyst_status pyst_server_wait(pyst_server *server, uint64_t ticket, double *latency_ms);
 
 /* Counters since creation.  Errors: PYST_ERR_ARG. */
 pyst_status pyst_server_get_stats(pyst_server *server, pyst_server_stats *out);
+
+/* Resident dimension tables are identified by the device addresses and lengths
+   of their dimension columns and by their predicates, not by the columns'
+   contents.  Before a caller frees, reuses or overwrites the memory of a
+   dimension column it has used in a request, it calls this with that column's
+   data pointer (NULL: every column): the cached tables built over it are
+   dropped (their memory is returned once the active requests using them have
+   finished), so a later request rebuilds them from the current contents.
+   Requests submitted after this call returns never see the dropped tables.
+   Tables that no active request uses are also dropped when a new one does not
+   fit the budget.  Errors: PYST_ERR_ARG. */
+pyst_status pyst_server_forget_tables(pyst_server *server, const void *dim_col_data);
+
+/* Set a context option (PYST_OPT_*) of the server's own context, e.g. the
+   PYST_OPT_FAIL_FACT_PASS test hook.  Takes effect for work the scheduler
+   issues after the call.  Errors: PYST_ERR_ARG. */
+pyst_status pyst_server_option(pyst_server *server, int key, int64_t value);
 
 /* Wait for the device and return the errors latched by the server's kernels. */
 pyst_status pyst_server_check(pyst_server *server);

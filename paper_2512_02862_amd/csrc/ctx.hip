@@ -26,6 +26,8 @@ struct pyst_ctx {
   size_t budget = 0;
   size_t used = 0;
   uint32_t *d_err = nullptr;    // device error word (first 256 B of the arena)
+  uint32_t *err_override = nullptr;  // when set, kernels latch here instead (per-request words of the server)
+  int64_t fail_pass_countdown = 0;   // test hook: > 0 makes the n-th fact pass from now fail on the host
   uint32_t *h_err = nullptr;    // pinned host copy
   std::map<size_t, size_t> free_blocks;          // offset -> size
   std::unordered_map<size_t, size_t> live;       // offset -> size
@@ -164,7 +166,22 @@ void ctx_free(pyst_ctx *c, void *p, hipStream_t stream) {
   }
 }
 
-uint32_t *ctx_err_word(pyst_ctx *c) { return c->d_err; }
+uint32_t *ctx_err_word(pyst_ctx *c) { return c->err_override ? c->err_override : c->d_err; }
+void ctx_set_err_word(pyst_ctx *c, uint32_t *word) { c->err_override = word; }
+
+bool ctx_fail_this_pass(pyst_ctx *c) {
+  if (c->fail_pass_countdown <= 0) return false;
+  return --c->fail_pass_countdown == 0;
+}
+
+pyst_status status_of_error_bits(uint32_t bits) {
+  if (bits == 0) return PYST_OK;
+  if (bits & kErrKey) return set_error(PYST_ERR_KEY, "a key equal to the reserved EMPTY sentinel was seen");
+  if (bits & kErrDup) return set_error(PYST_ERR_DUP_KEY, "duplicate build key under a unique-key promise");
+  if (bits & kErrTableFull) return set_error(PYST_ERR_TABLE_FULL, "hash table full");
+  if (bits & kErrIndex) return set_error(PYST_ERR_INDEX, "a gather index outside its columns");
+  return set_error(PYST_ERR_CAPACITY, "output capacity exceeded");
+}
 bool ctx_generic_only(const pyst_ctx *c) { return c->generic_only; }
 bool ctx_groupby_hash_only(const pyst_ctx *c) { return c->groupby_hash_only; }
 
@@ -203,7 +220,7 @@ hipStream_t ctx_copy_stream(pyst_ctx *c) {
 }
 
 TimedRegion::TimedRegion(pyst_ctx *c, const char *name, hipStream_t s) : ctx(c), stream(s), label(name) {
-  if (!c->timing) return;
+  if (!c || !c->timing) return;
   if (hipEventCreate(&start) != hipSuccess || hipEventCreate(&stop) != hipSuccess) return;
   (void)hipEventRecord(start, stream);
 }
@@ -287,6 +304,7 @@ pyst_status pyst_ctx_option(pyst_ctx *c, int key, int64_t value) {
   switch (key) {
     case PYST_OPT_GENERIC_ONLY: c->generic_only = value != 0; return PYST_OK;
     case PYST_OPT_GROUPBY_HASH_ONLY: c->groupby_hash_only = value != 0; return PYST_OK;
+    case PYST_OPT_FAIL_FACT_PASS: c->fail_pass_countdown = value > 0 ? value : 0; return PYST_OK;
   }
   return set_error(PYST_ERR_ARG, "pyst_ctx_option: unknown option");
 }
@@ -328,11 +346,7 @@ pyst_status pyst_ctx_check(pyst_ctx *c, hipStream_t stream) {
   pyst_status st = fill_u32(c->d_err, 1, 0u, stream);
   if (st != PYST_OK) return st;
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
-  if (bits & kErrKey) return set_error(PYST_ERR_KEY, "a key equal to the reserved EMPTY sentinel was seen");
-  if (bits & kErrDup) return set_error(PYST_ERR_DUP_KEY, "duplicate build key under a unique-key promise");
-  if (bits & kErrTableFull) return set_error(PYST_ERR_TABLE_FULL, "hash table full");
-  if (bits & kErrIndex) return set_error(PYST_ERR_INDEX, "a gather index outside its columns");
-  return set_error(PYST_ERR_CAPACITY, "output capacity exceeded");
+  return status_of_error_bits(bits);
 }
 
 }  // extern "C"

@@ -1647,6 +1647,7 @@ static void launch_fast(int grid, const FastArgs &a, const DimTables &d, const G
 pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastArgs &a, const DimTables &d,
                            const GroupDev &g, const PairsOut &po, hipStream_t stream) {
   if (a.n <= 0) return PYST_OK;
+  if (ctx_fail_this_pass(ctx)) return set_error(PYST_ERR_HIP, "fact pass: failure injected by PYST_OPT_FAIL_FACT_PASS");
   const int grid = fast_grid(ctx, a.n);
   uint32_t *err = ctx_err_word(ctx);
   const int sb1 = njoins > 1 ? d.t[1].slot_bytes : 4;

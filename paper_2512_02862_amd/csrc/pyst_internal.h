@@ -201,6 +201,13 @@ struct CtxImpl;  // defined in ctx.cpp
 void *ctx_alloc(pyst_ctx *ctx, size_t bytes, hipStream_t stream);
 void ctx_free(pyst_ctx *ctx, void *p, hipStream_t stream);
 uint32_t *ctx_err_word(pyst_ctx *ctx);
+// Make kernels launched through `ctx` latch errors into `word` (device memory)
+// until reset with nullptr; used by the server to give each request its own word.
+void ctx_set_err_word(pyst_ctx *ctx, uint32_t *word);
+// Test hook (PYST_OPT_FAIL_FACT_PASS): true for the one fact pass it names.
+bool ctx_fail_this_pass(pyst_ctx *ctx);
+// The status a set of latched error bits stands for (PYST_OK for none).
+pyst_status status_of_error_bits(uint32_t bits);
 int ctx_device(const pyst_ctx *ctx);
 int ctx_num_cus(const pyst_ctx *ctx);
 

@@ -82,7 +82,9 @@ struct PlanCopy {
 struct DimEntry {
   DimTables d;
   hipEvent_t ready = nullptr;
-  int64_t cap_alloc0 = 0;
+  uint32_t *d_err = nullptr;        // error word of the build (arena), read by every request using the tables
+  int users = 0;                    // active requests using the tables
+  std::vector<const void *> cols;   // device columns the tables were built over
 };
 
 struct Request {
@@ -130,6 +132,11 @@ struct pyst_server {
   std::unordered_map<uint64_t, std::shared_ptr<pyst::Request>> all;
   std::vector<std::shared_ptr<pyst::Request>> active;
   std::map<std::string, std::unique_ptr<pyst::DimEntry>> dim_cache;
+  std::vector<std::unique_ptr<pyst::DimEntry>> retired;  // dropped from the cache, freed once unused
+  std::vector<const void *> forget_q;                    // pyst_server_forget_tables calls not yet applied
+  std::vector<std::pair<int, int64_t>> option_q;         // pyst_server_option calls not yet applied
+  uint32_t *d_req_err = nullptr;  // per slot: the running request's error word (arena, 256 B apart)
+  uint32_t *h_req_err = nullptr;  // per slot, pinned: [2 s] its tables' word, [2 s + 1] its own word
   uint64_t next_id = 1;
   bool stop = false;
   std::thread thr;
@@ -142,6 +149,66 @@ static double ms_between(std::chrono::steady_clock::time_point a, std::chrono::s
   return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
+static uint32_t *req_err_word(pyst_server *sv, int slot) { return sv->d_req_err + static_cast<size_t>(slot) * 64; }
+
+// Kernels launched while one of these lives latch into the given word.
+struct ErrScope {
+  pyst_ctx *ctx;
+  ErrScope(pyst_ctx *c, uint32_t *word) : ctx(c) { ctx_set_err_word(ctx, word); }
+  ~ErrScope() { ctx_set_err_word(ctx, nullptr); }
+};
+
+static void free_entry(pyst_server *sv, DimEntry &e) {
+  if (e.ready) {
+    (void)hipEventSynchronize(e.ready);
+    (void)hipEventDestroy(e.ready);
+    e.ready = nullptr;
+  }
+  free_dimensions(sv->ctx, &e.d, nullptr);
+  if (e.d_err) ctx_free(sv->ctx, e.d_err, nullptr);
+  e.d_err = nullptr;
+}
+
+// Free the dropped tables that no active request uses any more.
+static void free_retired(pyst_server *sv) {
+  for (size_t i = 0; i < sv->retired.size();) {
+    if (sv->retired[i]->users == 0) {
+      free_entry(sv, *sv->retired[i]);
+      sv->retired.erase(sv->retired.begin() + static_cast<long>(i));
+    } else {
+      ++i;
+    }
+  }
+}
+
+// Drop cached tables built over column `col` (nullptr: all) or, with
+// idle_only, every table no active request uses.  Returns how many.
+static int drop_tables(pyst_server *sv, const void *col, bool idle_only) {
+  int n = 0;
+  for (auto it = sv->dim_cache.begin(); it != sv->dim_cache.end();) {
+    DimEntry &e = *it->second;
+    const bool match = idle_only ? e.users == 0
+                                 : (col == nullptr || std::find(e.cols.begin(), e.cols.end(), col) != e.cols.end());
+    if (match) {
+      sv->retired.push_back(std::move(it->second));
+      it = sv->dim_cache.erase(it);
+      ++n;
+    } else {
+      ++it;
+    }
+  }
+  free_retired(sv);
+  return n;
+}
+
+// Apply the forget and option calls made so far (scheduler thread, sv->mu held).
+static void apply_client_calls(pyst_server *sv) {
+  for (const void *col : sv->forget_q) drop_tables(sv, col, false);
+  sv->forget_q.clear();
+  for (auto &kv : sv->option_q) (void)pyst_ctx_option(sv->ctx, kv.first, kv.second);
+  sv->option_q.clear();
+}
+
 // Aggregation-state bytes a request reserves while active (its admission cost).
 static size_t request_bytes(const pyst_server *sv, const Request &r) {
   if (r.q.agg_mode == 0)
@@ -152,40 +219,89 @@ static size_t request_bytes(const pyst_server *sv, const Request &r) {
 }
 
 // Start a request: dimension tables (cached), own aggregation state, zeroed outputs.
+// Build the dimension tables of a plan into a new cache entry, or nullptr
+// with *ps set (PYST_ERR_NOMEM when the budget cannot hold them now).
+static std::unique_ptr<DimEntry> build_entry(pyst_server *sv, const Request &r, hipStream_t st, pyst_status *ps) {
+  auto e = std::make_unique<DimEntry>();
+  std::memset(&e->d, 0, sizeof(e->d));
+  e->d_err = static_cast<uint32_t *>(ctx_alloc(sv->ctx, 256, st));
+  if (!e->d_err) {
+    *ps = PYST_ERR_NOMEM;
+    return nullptr;
+  }
+  *ps = fill_u32(e->d_err, 1, 0u, st);
+  if (*ps == PYST_OK) {
+    ErrScope scope(sv->ctx, e->d_err);
+    *ps = fast_build_dimensions(sv->ctx, &r.pc.plan, r.q, &e->d, nullptr, nullptr, st);
+  }
+  if (*ps != PYST_OK) {
+    free_dimensions(sv->ctx, &e->d, st);
+    ctx_free(sv->ctx, e->d_err, st);
+    return nullptr;
+  }
+  for (int j = 0; j < r.pc.plan.njoins; ++j) {
+    e->cols.push_back(r.pc.plan.joins[j].key.data);
+    if (r.pc.plan.joins[j].payload.data) e->cols.push_back(r.pc.plan.joins[j].payload.data);
+    for (const auto &c : r.pc.jcols[j]) e->cols.push_back(c.data);
+  }
+  (void)hipEventCreateWithFlags(&e->ready, hipEventDisableTiming);
+  (void)hipEventRecord(e->ready, st);
+  return e;
+}
+
+static void *alloc_or_evict(pyst_server *sv, size_t bytes, hipStream_t st) {
+  void *p = ctx_alloc(sv->ctx, bytes, st);
+  if (!p && drop_tables(sv, nullptr, true) > 0) p = ctx_alloc(sv->ctx, bytes, st);
+  return p;
+}
+
 static bool admit(pyst_server *sv, const std::shared_ptr<Request> &r) {
   const std::string sig = r->pc.dim_signature();
   auto it = sv->dim_cache.find(sig);
   hipStream_t st = sv->slots[r->slot];
+  uint32_t *word = req_err_word(sv, r->slot);
+  if (fill_u32(word, 1, 0u, st) != PYST_OK) {
+    r->status = PYST_ERR_HIP;
+    return true;
+  }
   if (it == sv->dim_cache.end()) {
-    auto e = std::make_unique<DimEntry>();
-    std::memset(&e->d, 0, sizeof(e->d));
-    pyst_status ps = fast_build_dimensions(sv->ctx, &r->pc.plan, r->q, &e->d, nullptr, nullptr, st);
-    if (ps != PYST_OK) {
-      free_dimensions(sv->ctx, &e->d, st);
+    pyst_status ps = PYST_OK;
+    auto e = build_entry(sv, *r, st, &ps);
+    // tables that no active request uses give way to a new one that does not fit
+    if (!e && ps == PYST_ERR_NOMEM && drop_tables(sv, nullptr, true) > 0) e = build_entry(sv, *r, st, &ps);
+    if (!e) {
       if (ps == PYST_ERR_NOMEM) return false;  // retry once memory frees up
       r->status = ps;
       return true;
     }
-    (void)hipEventCreateWithFlags(&e->ready, hipEventDisableTiming);
-    (void)hipEventRecord(e->ready, st);
     it = sv->dim_cache.emplace(sig, std::move(e)).first;
   }
   r->dims = it->second.get();
+  r->dims->users++;
   (void)hipStreamWaitEvent(st, r->dims->ready, 0);
   r->d = r->dims->d;
   std::memset(&r->s, 0, sizeof(r->s));
+  ErrScope scope(sv->ctx, word);
   if (r->q.agg_mode == 0) {
     const int64_t cap = r->d.t[0].cap_alloc;
-    r->sums_mem = ctx_alloc(sv->ctx, static_cast<size_t>(cap) * (sizeof(uint64_t) + 1) + 256, st);
-    if (!r->sums_mem) return false;
+    r->sums_mem = alloc_or_evict(sv, static_cast<size_t>(cap) * (sizeof(uint64_t) + 1) + 256, st);
+    if (!r->sums_mem) {
+      r->dims->users--;
+      r->dims = nullptr;
+      return false;
+    }
     r->d.t[0].sums = static_cast<uint64_t *>(r->sums_mem);
     r->d.t[0].flags = reinterpret_cast<uint8_t *>(r->d.t[0].sums + cap);
     k_req_init<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(cap, 256), 2048)), 256, 0, st>>>(r->d.t[0], r->d_ngroups);
   } else {
     const int64_t bound = std::min<int64_t>(r->pc.plan.max_groups, std::max<int64_t>(r->rows, 1));
     const int64_t cap = table_capacity_host(bound, r->pc.plan.group_max_load);
-    r->s.mem = ctx_alloc(sv->ctx, group_bytes(cap), st);
-    if (!r->s.mem) return false;
+    r->s.mem = alloc_or_evict(sv, group_bytes(cap), st);
+    if (!r->s.mem) {
+      r->dims->users--;
+      r->dims = nullptr;
+      return false;
+    }
     r->s.g = group_view(r->s.mem, cap);
     (void)group_init(r->s.g, nullptr, bound, 0, r->pc.plan.group_max_load, st);
     TableDev t{};
@@ -203,6 +319,11 @@ static void release(pyst_server *sv, Request &r) {
   if (r.sums_mem) ctx_free(sv->ctx, r.sums_mem, st);
   if (r.s.mem) ctx_free(sv->ctx, r.s.mem, st);
   r.sums_mem = r.s.mem = nullptr;
+  if (r.dims) {
+    r.dims->users--;
+    r.dims = nullptr;
+    free_retired(sv);
+  }
   sv->slot_free.push_back(r.slot);
 }
 
@@ -267,8 +388,12 @@ static void serve_chunk(pyst_server *sv, int64_t c) {
     }
     FastArgs fa;
     fast_shape(&r->pc.plan, dev.data(), r->q, &fa);
-    pyst_status ps = fast_fact_pass(sv->ctx, r->pc.plan.njoins, r->q.agg_mode, fa, r->d, r->s.g, r->s.po, st);
-    if (ps != PYST_OK) r->status = ps;
+    pyst_status ps;
+    {
+      ErrScope scope(sv->ctx, req_err_word(sv, r->slot));
+      ps = fast_fact_pass(sv->ctx, r->pc.plan.njoins, r->q.agg_mode, fa, r->d, r->s.g, r->s.po, st);
+    }
+    if (ps != PYST_OK) r->status = ps;  // the request stops here and is finished without its later chunks
     hipEvent_t ev = nullptr;
     (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     (void)hipEventRecord(ev, st);
@@ -279,13 +404,24 @@ static void serve_chunk(pyst_server *sv, int64_t c) {
   }
 }
 
+// A request is finished when every chunk it reads has been through its fact
+// pass, or at once when one of its launches failed on the host (its later
+// chunks are skipped), so a failed request never holds its slot and memory.
 static void finish_ready(pyst_server *sv) {
   for (auto &r : sv->active) {
-    if (r->finish || r->remaining > 0) continue;
+    if (r->finish || (r->remaining > 0 && r->status == PYST_OK)) continue;
     hipStream_t st = sv->slots[r->slot];
-    if (r->status == PYST_OK)
+    uint32_t *word = req_err_word(sv, r->slot);
+    if (r->status == PYST_OK) {
+      ErrScope scope(sv->ctx, word);
       r->status = fast_finish(sv->ctx, &r->pc.plan, r->q, r->d, &r->s, r->out_keys, r->out_sums, r->out_cap,
                               r->d_ngroups, st);
+    }
+    // the request's error bits: its own word and that of the tables it used
+    uint32_t *h = sv->h_req_err + 2 * r->slot;
+    h[0] = h[1] = 0;
+    if (r->dims) (void)hipMemcpyAsync(h, r->dims->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(h + 1, word, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     (void)hipEventCreateWithFlags(&r->finish, hipEventDisableTiming);
     (void)hipEventRecord(r->finish, st);
   }
@@ -298,6 +434,8 @@ static void reap_done(pyst_server *sv) {
       (void)hipEventDestroy(r->finish);
       r->finish = nullptr;
       r->t_done = std::chrono::steady_clock::now();
+      const uint32_t bits = sv->h_req_err[2 * r->slot] | sv->h_req_err[2 * r->slot + 1];
+      if (r->status == PYST_OK && bits) r->status = status_of_error_bits(bits);
       release(sv, *r);
       {
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -319,13 +457,17 @@ static void scheduler(pyst_server *sv) {
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       if (sv->active.empty() && sv->pending.empty()) {
+        apply_client_calls(sv);
         if (sv->stop) break;
         sv->cv_submit.wait_for(lk, std::chrono::milliseconds(2));
         continue;
       }
+      apply_client_calls(sv);
       while (!sv->pending.empty() && !sv->slot_free.empty()) {
+        apply_client_calls(sv);  // a forget made before a submit applies before its admission
         auto r = sv->pending.front();
-        if (ctx_budget_free(sv->ctx) < request_bytes(sv, *r) && !sv->active.empty()) {
+        if (ctx_budget_free(sv->ctx) < request_bytes(sv, *r) && !sv->active.empty() &&
+            (drop_tables(sv, nullptr, true) == 0 || ctx_budget_free(sv->ctx) < request_bytes(sv, *r))) {
           sv->stats.admission_waits++;
           break;
         }
@@ -424,7 +566,8 @@ static pyst_status server_create(int device, const pyst_server_cfg *cfg, const p
   sv->fact_rows = n;
   for (int c = 0; c < nfact; ++c) sv->row_bytes += host_fact[c].dtype == PYST_I64 ? 8 : 4;
   const size_t ring_bytes = static_cast<size_t>(cfg->nbuf) * slot_bytes;
-  pyst_status st = pyst_ctx_create(device, cfg->budget_bytes + ring_bytes, &sv->ctx);
+  const size_t word_bytes_all = static_cast<size_t>(cfg->max_active) * 256;
+  pyst_status st = pyst_ctx_create(device, cfg->budget_bytes + ring_bytes + word_bytes_all, &sv->ctx);
   if (st != PYST_OK) {
     delete sv;
     return st;
@@ -449,6 +592,14 @@ static pyst_status server_create(int device, const pyst_server_cfg *cfg, const p
       sv->wbuf[b][c] = p + col_bytes[c] + hdr_bytes[c];
       p += col_bytes[c] + hdr_bytes[c] + word_bytes[c];
     }
+  }
+  sv->d_req_err = static_cast<uint32_t *>(ctx_alloc(sv->ctx, static_cast<size_t>(cfg->max_active) * 256, nullptr));
+  if (!sv->d_req_err ||
+      hipHostMalloc(reinterpret_cast<void **>(&sv->h_req_err), static_cast<size_t>(cfg->max_active) * 2 * sizeof(uint32_t),
+                    hipHostMallocDefault) != hipSuccess) {
+    pyst_ctx_destroy(sv->ctx);
+    delete sv;
+    return set_error(PYST_ERR_NOMEM, "pyst_server_create: error words");
   }
   sv->slots.resize(cfg->max_active);
   for (int i = 0; i < cfg->max_active; ++i) {
@@ -540,6 +691,28 @@ pyst_status pyst_server_get_stats(pyst_server *sv, pyst_server_stats *out) {
   return PYST_OK;
 }
 
+pyst_status pyst_server_forget_tables(pyst_server *sv, const void *dim_col_data) {
+  if (!sv) return set_error(PYST_ERR_ARG, "pyst_server_forget_tables: NULL server");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->forget_q.push_back(dim_col_data);
+  }
+  sv->cv_submit.notify_one();
+  return PYST_OK;
+}
+
+pyst_status pyst_server_option(pyst_server *sv, int key, int64_t value) {
+  if (!sv) return set_error(PYST_ERR_ARG, "pyst_server_option: NULL server");
+  if (key != PYST_OPT_GENERIC_ONLY && key != PYST_OPT_GROUPBY_HASH_ONLY && key != PYST_OPT_FAIL_FACT_PASS)
+    return set_error(PYST_ERR_ARG, "pyst_server_option: unknown option");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->option_q.emplace_back(key, value);
+  }
+  sv->cv_submit.notify_one();
+  return PYST_OK;
+}
+
 pyst_status pyst_server_check(pyst_server *sv) {
   if (!sv) return set_error(PYST_ERR_ARG, "pyst_server_check: NULL server");
   (void)hipDeviceSynchronize();
@@ -555,10 +728,9 @@ void pyst_server_destroy(pyst_server *sv) {
   sv->cv_submit.notify_all();
   if (sv->thr.joinable()) sv->thr.join();
   (void)hipDeviceSynchronize();
-  for (auto &kv : sv->dim_cache) {
-    free_dimensions(sv->ctx, &kv.second->d, nullptr);
-    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
-  }
+  for (auto &kv : sv->dim_cache) free_entry(sv, *kv.second);
+  for (auto &e : sv->retired) free_entry(sv, *e);
+  if (sv->h_req_err) (void)hipHostFree(sv->h_req_err);
   for (auto &u : sv->users)
     for (hipEvent_t e : u) (void)hipEventDestroy(e);
   for (hipEvent_t e : sv->copied) (void)hipEventDestroy(e);

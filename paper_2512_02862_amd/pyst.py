@@ -24,6 +24,7 @@ G_NONE, G_JOIN_KEY, G_JOIN_PAYLOAD, G_FACT_COL = 0, 1, 2, 3
 V_COL, V_COL_TIMES_C_MINUS = 0, 1
 OPT_GENERIC_ONLY = 1
 OPT_GROUPBY_HASH_ONLY = 2
+OPT_FAIL_FACT_PASS = 3
 
 EXPORTS = [
     "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
@@ -33,7 +34,7 @@ EXPORTS = [
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
     "pyst_server_create", "pyst_server_create_packed", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
-    "pyst_server_destroy",
+    "pyst_server_destroy", "pyst_server_forget_tables", "pyst_server_option",
 ]
 
 
@@ -155,6 +156,8 @@ def load(path: str = LIB_PATH):
         "pyst_server_get_stats": ([p, P(ServerStats)], i32),
         "pyst_server_check": ([p], i32),
         "pyst_server_destroy": ([p], None),
+        "pyst_server_forget_tables": ([p, p], i32),
+        "pyst_server_option": ([p, i32, i64], i32),
         "pyst_ctx_kernel_time": ([p, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
     }
     for name, (args, res) in sig.items():
@@ -633,10 +636,18 @@ class Server:
 
     def wait(self, ticket):
         lat = ctypes.c_double()
-        _check(_lib.pyst_server_wait(self.h, ticket, ctypes.byref(lat)))
+        st = _lib.pyst_server_wait(self.h, ticket, ctypes.byref(lat))
         ok, osum, ng, _ = self._live.pop(ticket)
+        _check(st)
         m = int(ng.item())
         return ok[:m], osum[:m], lat.value
+
+    def forget_tables(self, dim_col=None):
+        """Drop the resident tables built over dimension tensor `dim_col` (None: all)."""
+        _check(_lib.pyst_server_forget_tables(self.h, None if dim_col is None else ctypes.c_void_p(dim_col.data_ptr())))
+
+    def option(self, key, value):
+        _check(_lib.pyst_server_option(self.h, int(key), int(value)))
 
     def stats(self):
         s = ServerStats()

@@ -147,3 +147,107 @@ def test_packed_server_matches_oracle(gpu, db):
     with pytest.raises(gpu.PystError) as e:
         gpu.Server(None, chunk_rows=250_000, packed=packed)  # not a multiple of 1024
     assert e.value.status == gpu.ERR_ARG
+
+
+def test_server_request_failing_on_the_host_is_finished(gpu, db):
+    # The second fact pass of a six-chunk request fails on the host (test hook,
+    # no device work involved): the request must be finished with that error,
+    # give back its slot and memory, and leave the server serving.
+    a, b, f, host, ad, bd = db
+    srv = gpu.Server(host, budget=256 << 20, max_active=2, nbuf=2, chunk_rows=500_000)
+    srv.option(gpu.OPT_FAIL_FACT_PASS, 2)
+    plan, cap = plan_for(gpu, "chain", ad, bd)
+    t = srv.submit(plan, NF, cap)
+    with pytest.raises(gpu.PystError) as e:
+        srv.wait(t)
+    assert e.value.status == gpu.ERR_HIP
+    for kind, rows in (("star", NF), ("chain", 1_234_567)):
+        plan, cap = plan_for(gpu, kind, ad, bd)
+        k, s, _ = srv.wait(srv.submit(plan, rows, cap))
+        got = sorted_np(k, s)
+        wk, ws = expected(kind, a, b, f, rows)
+        np.testing.assert_array_equal(got[0], wk)
+        np.testing.assert_array_equal(got[1], ws)
+    st = srv.stats()
+    assert st["completed"] == 3
+    srv.close()  # returns: nothing is left active
+
+
+def test_server_device_errors_belong_to_their_request(gpu, db):
+    # In one mix: a request whose groups overflow its output capacity, and a
+    # request over a dimension with a duplicate key.  Each fails with its own
+    # error; every other request of the mix is exact.
+    import torch
+    a, b, f, host, ad, bd = db
+    bdup = {k: v.clone() for k, v in bd.items()}
+    bdup["key"][7] = bdup["key"][8]
+    bdup["segment"][7] = bdup["segment"][8] = 1  # both rows pass the dimension filter
+    srv = gpu.Server(host, budget=1 << 30, max_active=6, nbuf=3, chunk_rows=250_000)
+    good = []
+    plan, cap = plan_for(gpu, "chain", ad, bd)
+    good.append((("chain", 2_000_000), srv.submit(plan, 2_000_000, cap)))
+    t_cap = srv.submit(plan, 1_500_000, 10)  # far more than 10 groups
+    plan_s, cap_s = plan_for(gpu, "star", ad, bd)
+    good.append((("star", NF), srv.submit(plan_s, NF, cap_s)))
+    t_dup = srv.submit(gpu.fact_star_plan(bdup), 1_000_000, NB)
+    good.append((("star", 777_777), srv.submit(plan_s, 777_777, cap_s)))
+    with pytest.raises(gpu.PystError) as e:
+        srv.wait(t_cap)
+    assert e.value.status == gpu.ERR_CAPACITY
+    with pytest.raises(gpu.PystError) as e:
+        srv.wait(t_dup)
+    assert e.value.status == gpu.ERR_DUP_KEY
+    for (kind, rows), t in good:
+        k, s, _ = srv.wait(t)
+        got = sorted_np(k, s)
+        wk, ws = expected(kind, a, b, f, rows)
+        np.testing.assert_array_equal(got[0], wk)
+        np.testing.assert_array_equal(got[1], ws)
+    srv.check()  # nothing was latched in the server-wide word
+    srv.close()
+    del torch
+
+
+def test_server_forget_tables_rebuilds_over_new_contents(gpu, db):
+    # Resident tables are keyed by column addresses: after the caller changes a
+    # dimension column in place and says so, the next request sees the new
+    # contents.
+    a, b, f, host, ad, bd = db
+    b2 = {k: v.copy() for k, v in b.items()}
+    bd2 = {k: dev(v) for k, v in b2.items()}
+    srv = gpu.Server(host, budget=1 << 30, max_active=4, nbuf=2, chunk_rows=500_000)
+    plan = gpu.fact_star_plan(bd2)
+    k, s, _ = srv.wait(srv.submit(plan, 2_000_000, NB))
+    got = sorted_np(k, s)
+    wk, ws = expected("star", a, b2, f, 2_000_000)
+    np.testing.assert_array_equal(got[0], wk)
+    np.testing.assert_array_equal(got[1], ws)
+    addr = bd2["segment"].data_ptr()
+    b2["segment"] = ((b2["segment"] + 1) % 5).astype(np.int32)
+    bd2["segment"].copy_(dev(b2["segment"]))
+    assert bd2["segment"].data_ptr() == addr
+    srv.forget_tables(bd2["segment"])
+    k, s, _ = srv.wait(srv.submit(gpu.fact_star_plan(bd2), 2_000_000, NB))
+    got = sorted_np(k, s)
+    wk, ws = expected("star", a, b2, f, 2_000_000)
+    np.testing.assert_array_equal(got[0], wk)
+    np.testing.assert_array_equal(got[1], ws)
+    srv.forget_tables()  # everything
+    k, s, _ = srv.wait(srv.submit(gpu.fact_star_plan(bd2), 1_000, NB))
+    wk, ws = expected("star", a, b2, f, 1_000)
+    np.testing.assert_array_equal(sorted_np(k, s)[1], ws)
+    srv.close()
+
+
+def test_server_evicts_idle_tables_when_memory_is_short(gpu, db):
+    # Many distinct dimension tables in a row, each only used once: idle cached
+    # tables give way instead of failing new requests with NOMEM.
+    a, b, f, host, ad, bd = db
+    srv = gpu.Server(host, budget=3 << 20, max_active=1, nbuf=2, chunk_rows=500_000)
+    keep = []  # distinct live addresses: every request builds its own tables (about 0.2 MiB each)
+    for i in range(30):
+        keep.append({k: dev(v) for k, v in b.items()})
+        k, s, _ = srv.wait(srv.submit(gpu.fact_star_plan(keep[-1]), 300_000 + i, NB))
+        wk, ws = expected("star", a, b, f, 300_000 + i)
+        np.testing.assert_array_equal(sorted_np(k, s)[1], ws)
+    srv.close()
