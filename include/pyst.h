@@ -164,6 +164,25 @@ pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *p
                            const int32_t *sel, const int64_t *d_nsel, uint32_t fanout,
                            void *const *out_cols, int64_t *d_offsets, hipStream_t stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc: the same
+   partition as pyst_partition (same arguments and results, no context), which
+   allocates nothing.  Its scratch (per-tile destination counts, their scan and
+   the scan's look-back words: 8 * ceil(n / 4096) * fanout bytes plus 1/2048
+   of that) lives in a fixed device array of PYST_NOALLOC_SCRATCH_BYTES
+   that every GPU the library runs on holds until the process ends; the
+   current device's copy is used.  A call whose scratch would exceed it
+   returns PYST_ERR_CAPACITY before any work is enqueued (e.g. fanout 64 up to
+   about 260M rows, fanout 1024 up to about 16M rows).  Every call on one GPU
+   shares that GPU's array and leaves its contents behind (the kernels clear
+   what must start at zero), so calls that overlap on one GPU -- on different
+   streams or from different threads -- race and must be ordered by the
+   caller.  Errors: as pyst_partition, PYST_ERR_CAPACITY, PYST_ERR_HIP. */
+#define PYST_NOALLOC_SCRATCH_BYTES (32u << 20)
+pyst_status pyst_partition_noalloc(const pyst_col *key, const pyst_col *payloads, int npay, const int32_t *sel,
+                                   const int64_t *d_nsel, uint32_t fanout, void *const *out_cols,
+                                   int64_t *d_offsets, hipStream_t stream);
+
 /* ---------------------------------------------------------------- join */
 
 /* Hash-join build (Sec. 3.1 "Anatomy..."; the table is built over the fully

@@ -3,9 +3,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "pyst_internal.h"
 #include "table.h"
+
+// Scratch of pyst_partition_noalloc: every GPU the library runs on holds its
+// own copy until the process ends.
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[PYST_NOALLOC_SCRATCH_BYTES];
 
 namespace pyst {
 
@@ -494,19 +501,36 @@ static void launch_partition(const PartArgs &a, int32_t *hist, int32_t *scan, in
 pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_t len, int64_t *d_total,
                           hipStream_t stream);
 
-// histogram -> scan -> (offsets) -> stable scatter
-static pyst_status partition_run(pyst_ctx *ctx, const PartArgs &a, int64_t *d_offsets, hipStream_t stream) {
+constexpr int kScanBlock = 256, kScanItems = 8;
+
+// Scratch of one partition: per-tile destination counts, their exclusive scan
+// and the scan's look-back status words.
+static size_t partition_scratch_bytes(int64_t n, uint32_t fanout) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(n, kPartTile));
+  const int64_t hlen = ntiles * fanout;
+  const int64_t stiles = std::max<int64_t>(1, ceil_div(hlen, int64_t{kScanBlock} * kScanItems));
+  const size_t counts = (static_cast<size_t>(2 * hlen) * sizeof(int32_t) + 256 + 255) / 256 * 256;
+  return counts + static_cast<size_t>(stiles + 1) * sizeof(uint64_t);
+}
+
+pyst_status scan_excl_i32_ws(const int32_t *in, int32_t *out, int64_t len, int64_t *d_total, uint64_t *status,
+                             hipStream_t stream);
+
+// histogram -> scan -> (offsets) -> stable scatter, in `ws` of
+// partition_scratch_bytes(a.n, a.fanout) bytes; ctx (may be null) only for timing.
+static pyst_status partition_run_ws(pyst_ctx *ctx, const PartArgs &a, int64_t *d_offsets, void *ws,
+                                    hipStream_t stream) {
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(a.n, kPartTile));
   const int64_t hlen = ntiles * a.fanout;
-  Scratch sc(ctx, 2 * hlen * sizeof(int32_t) + 256, stream);
-  if (!sc.p) return set_error(PYST_ERR_NOMEM, "partition: arena exhausted");
-  int32_t *hist = sc.as<int32_t>();
+  int32_t *hist = static_cast<int32_t *>(ws);
   int32_t *scan = hist + hlen + 64;
+  uint64_t *status = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) +
+                                                  (static_cast<size_t>(2 * hlen) * sizeof(int32_t) + 256 + 255) / 256 * 256);
   if (a.fanout <= 64) launch_partition<64>(a, hist, scan, ntiles, stream, true);
   else if (a.fanout <= 256) launch_partition<256>(a, hist, scan, ntiles, stream, true);
   else launch_partition<1024>(a, hist, scan, ntiles, stream, true);
   PYST_LAUNCH_CHECK("k_part_hist");
-  pyst_status st = scan_excl_i32(ctx, hist, scan, hlen, nullptr, stream);
+  pyst_status st = scan_excl_i32_ws(hist, scan, hlen, nullptr, status, stream);
   if (st != PYST_OK) return st;
   if (d_offsets) {
     k_part_offsets<<<static_cast<unsigned>(ceil_div(a.fanout + 1, 256)), 256, 0, stream>>>(scan, a.fanout, ntiles,
@@ -519,6 +543,12 @@ static pyst_status partition_run(pyst_ctx *ctx, const PartArgs &a, int64_t *d_of
   else launch_partition<1024>(a, hist, scan, ntiles, stream, false);
   PYST_LAUNCH_CHECK("k_part_scatter");
   return PYST_OK;
+}
+
+static pyst_status partition_run(pyst_ctx *ctx, const PartArgs &a, int64_t *d_offsets, hipStream_t stream) {
+  Scratch sc(ctx, partition_scratch_bytes(a.n, a.fanout), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "partition: arena exhausted");
+  return partition_run_ws(ctx, a, d_offsets, sc.p, stream);
 }
 
 // LSD radix sort of (key, value) int64 pairs, 8 stable byte passes; the first
@@ -552,19 +582,25 @@ pyst_status sort_pairs_by_key(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const
   return PYST_OK;
 }
 
-pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_t len, int64_t *d_total,
-                          hipStream_t stream) {
-  constexpr int BLOCK = 256, ITEMS = 8;
-  const int64_t ntiles = std::max<int64_t>(1, ceil_div(len, int64_t{BLOCK} * ITEMS));
-  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
-  if (!sc.p) return set_error(PYST_ERR_NOMEM, "scan: arena exhausted");
-  pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
+// Exclusive scan with caller-provided look-back status: (tiles + 1) words,
+// cleared here by a kernel.
+pyst_status scan_excl_i32_ws(const int32_t *in, int32_t *out, int64_t len, int64_t *d_total, uint64_t *status,
+                             hipStream_t stream) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(len, int64_t{kScanBlock} * kScanItems));
+  pyst_status st = fill_u64(status, ntiles + 1, 0, stream);
   if (st != PYST_OK) return st;
-  uint64_t *status = sc.as<uint64_t>();
-  k_scan_excl_i32<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
+  k_scan_excl_i32<kScanBlock, kScanItems><<<static_cast<unsigned>(ntiles), kScanBlock, 0, stream>>>(
       in, out, len, status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles, d_total);
   PYST_LAUNCH_CHECK("k_scan_excl_i32");
   return PYST_OK;
+}
+
+pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_t len, int64_t *d_total,
+                          hipStream_t stream) {
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(len, int64_t{kScanBlock} * kScanItems));
+  Scratch sc(ctx, (ntiles + 1) * sizeof(uint64_t), stream);
+  if (!sc.p) return set_error(PYST_ERR_NOMEM, "scan: arena exhausted");
+  return scan_excl_i32_ws(in, out, len, d_total, sc.as<uint64_t>(), stream);
 }
 
 // ============================================================== join build / probe
@@ -1182,10 +1218,11 @@ pyst_status pyst_filter(pyst_ctx *ctx, const pyst_col *cols, int ncols, const py
   return filter_impl(ctx, ps, n, sel_out, d_nsel, stream);
 }
 
-pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payloads, int npay, const int32_t *sel,
-                           const int64_t *d_nsel, uint32_t fanout, void *const *out_cols, int64_t *d_offsets,
-                           hipStream_t stream) {
-  if (!ctx || !key || !out_cols || !d_offsets) return set_error(PYST_ERR_ARG, "pyst_partition: NULL argument");
+// Argument checks and kernel arguments shared by the partition entry points.
+static pyst_status partition_args(const pyst_col *key, const pyst_col *payloads, int npay, const int32_t *sel,
+                                  const int64_t *d_nsel, uint32_t fanout, void *const *out_cols, int64_t *d_offsets,
+                                  PartArgs *out) {
+  if (!key || !out_cols || !d_offsets) return set_error(PYST_ERR_ARG, "pyst_partition: NULL argument");
   if (fanout < 1 || fanout > PYST_MAX_FANOUT) return set_error(PYST_ERR_ARG, "pyst_partition: fanout must be 1..1024");
   if (npay < 0 || npay > PYST_MAX_COLS - 1 || (npay > 0 && !payloads))
     return set_error(PYST_ERR_ARG, "pyst_partition: 0..7 payload columns");
@@ -1196,8 +1233,7 @@ pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *p
       return set_error(PYST_ERR_ARG, "pyst_partition: payload length mismatch");
   for (int j = 0; j <= npay; ++j)
     if (!out_cols[j] && key->n > 0) return set_error(PYST_ERR_ARG, "pyst_partition: NULL output column");
-  TimedRegion timed(ctx, "partition", stream);
-  PartArgs a;
+  PartArgs &a = *out;
   std::memset(&a, 0, sizeof(a));
   a.key = key->data;
   a.key64 = key->dtype == PYST_I64;
@@ -1215,7 +1251,58 @@ pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *p
   while ((1u << bits) < fanout) ++bits;
   a.fbits = bits;
   a.radix_shift = -1;
+  return PYST_OK;
+}
+
+pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payloads, int npay, const int32_t *sel,
+                           const int64_t *d_nsel, uint32_t fanout, void *const *out_cols, int64_t *d_offsets,
+                           hipStream_t stream) {
+  if (!ctx) return set_error(PYST_ERR_ARG, "pyst_partition: NULL argument");
+  PartArgs a;
+  pyst_status st = partition_args(key, payloads, npay, sel, d_nsel, fanout, out_cols, d_offsets, &a);
+  if (st != PYST_OK) return st;
+  TimedRegion timed(ctx, "partition", stream);
   return partition_run(ctx, a, d_offsets, stream);
+}
+
+// The partition of callers that cannot allocate: its scratch is `scratch`, a
+// fixed array in every GPU's copy of the code object.  Host code must not pass
+// the array's name to a kernel (on the host it is only a stand-in): each
+// device's address is taken once with hipGetSymbolAddress and kept here.
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[kNoallocMaxDevices];
+
+static pyst_status noalloc_scratch(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "pyst_partition_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kNoallocMaxDevices) return set_error(PYST_ERR_UNSUPPORTED, "pyst_partition_noalloc: device id over 63");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_error(e, "pyst_partition_noalloc: hipGetSymbolAddress(scratch)");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return PYST_OK;
+}
+
+pyst_status pyst_partition_noalloc(const pyst_col *key, const pyst_col *payloads, int npay, const int32_t *sel,
+                                   const int64_t *d_nsel, uint32_t fanout, void *const *out_cols,
+                                   int64_t *d_offsets, hipStream_t stream) {
+  PartArgs a;
+  pyst_status st = partition_args(key, payloads, npay, sel, d_nsel, fanout, out_cols, d_offsets, &a);
+  if (st != PYST_OK) return st;
+  const size_t need = partition_scratch_bytes(a.n, a.fanout);
+  if (need > sizeof(scratch))
+    return set_error(PYST_ERR_CAPACITY, "pyst_partition_noalloc: " + std::to_string(a.n) + " rows at fanout " +
+                                            std::to_string(a.fanout) + " need " + std::to_string(need) +
+                                            " bytes of scratch, more than the fixed " +
+                                            std::to_string(sizeof(scratch)));
+  void *ws = nullptr;
+  if ((st = noalloc_scratch(&ws)) != PYST_OK) return st;
+  return partition_run_ws(nullptr, a, d_offsets, ws, stream);
 }
 
 pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payload, const int32_t *sel,

@@ -34,7 +34,7 @@ EXPORTS = [
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
     "pyst_server_create", "pyst_server_create_packed", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
-    "pyst_server_destroy", "pyst_server_forget_tables", "pyst_server_option",
+    "pyst_server_destroy", "pyst_server_forget_tables", "pyst_server_option", "pyst_partition_noalloc",
 ]
 
 
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
         "pyst_last_error": ([], ctypes.c_char_p),
         "pyst_filter": ([p, P(Col), i32, P(Pred), i32, p, p, p], i32),
         "pyst_partition": ([p, P(Col), P(Col), i32, p, p, u32, P(p), p, p], i32),
+        "pyst_partition_noalloc": ([P(Col), P(Col), i32, p, p, u32, P(p), p, p], i32),
         "pyst_join_build": ([p, P(Col), P(Col), p, p, ctypes.c_double, i32, P(p), p], i32),
         "pyst_join_probe": ([p, p, P(Col), p, p, p, p, i64, p, p], i32),
         "pyst_gather": ([p, p, p, i64, P(Col), i32, P(p), p], i32),
@@ -291,6 +292,20 @@ def partition(ctx: Ctx, key, payloads, fanout: int, sel=None, nsel=None, stream=
     _check(_lib.pyst_partition(ctx.h, ctypes.byref(kc), parr, len(payloads), _sel_ptr(sel), _ptr(nsel), fanout, oarr,
                                _ptr(offsets), _stream(stream)))
     return outs[0][:n], [o[:n] for o in outs[1:]], offsets
+
+
+def partition_noalloc(key, payloads, fanout: int, outs, offsets, sel=None, nsel=None, stream=None):
+    """pyst_partition_noalloc: the stable hash partition into caller-provided
+    outputs (outs = [key out] + payload outs, each with room for key.numel()
+    values; offsets int64[F+1]), with no context and no device allocation."""
+    payloads = list(payloads)
+    if len(outs) != 1 + len(payloads):
+        raise ValueError("one output per key and payload column")
+    kc = col(key)
+    parr = (Col * max(1, len(payloads)))(*[col(t) for t in payloads])
+    oarr = (ctypes.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    _check(_lib.pyst_partition_noalloc(ctypes.byref(kc), parr, len(payloads), _sel_ptr(sel), _ptr(nsel), fanout,
+                                       oarr, _ptr(offsets), _stream(stream)))
 
 
 class Table:
