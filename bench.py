@@ -27,6 +27,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -156,16 +157,15 @@ def main():
     ap.add_argument("--probe-rows", type=int, default=60_000_000)
     ap.add_argument("--max-load", type=float, default=0.5)
     ap.add_argument("--no-extras", action="store_true", help="skip every measurement beside the headline")
-    ap.add_argument("--extras", default="partition,chain,groupby,join,stream,batch,serve",
+    ap.add_argument("--extras", default="partition,chain,groupby,join,batch,config4",
                     help="comma-separated extra measurements to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=30_000_000)
-    ap.add_argument("--stream-rows", type=int, default=240_000_000, help="chain fact rows streamed from pinned host")
     ap.add_argument("--join-k", default="1,4,8", help="8-byte columns a side of the join microbenchmark")
     ap.add_argument("--batch-fragments", type=int, default=512)
     ap.add_argument("--batch-max-rows", type=float, default=2e7, help="largest fragment probe size")
-    ap.add_argument("--serve-rows", type=int, default=512_000_000, help="pinned host fact rows of the server")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--config4-rows", type=int, default=2_000_000_000, help="pinned host fact rows, streamed and served")
+    ap.add_argument("--config4-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -277,9 +277,8 @@ def main():
     extra("chain", bench_chain, ctx, pyst, gen, log)
     extra("groupby", bench_groupby, ctx, pyst, gen, log)
     extra("join", bench_join, ctx, pyst, gen, log, 60_000_000, 160_000_000, [int(x) for x in args.join_k.split(",")])
-    extra("stream", bench_stream, ctx, pyst, gen, log, args.stream_rows)
     extra("batch", bench_batch, ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
-    extra("serve", bench_serve, pyst, gen, log, args.serve_rows, args.serve_requests)
+    extra("config4", bench_config4, pyst, gen, log, args.config4_rows, args.config4_requests, 64_000_000, 32 << 30)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(b_host, p_host, args.cpu_sample_rows, log)
@@ -390,8 +389,54 @@ def bench_groupby(ctx, pyst, gen, log, n=60_000_000, n_orders=15_000_000):
     return out
 
 
-def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8)):
-    """Build + probe + materialize of k 8-byte columns per side (one pyst_join_materialize call)."""
+def partitioned_join(ctx, pyst, bk, bc, pk, pc, fanout):
+    """One GPU's whole share of the distributed join: both sides hash-partitioned
+    into `fanout` destinations (the send side; the per-destination counts come
+    back to the host, as the count exchange of a shuffle needs them), then each
+    destination's build and probe segments joined and materialized (the receive
+    side's work, here on the segments this GPU holds).  Returns per destination
+    (probe, build, columns, count) of pyst_join_materialize and the offsets."""
+    ob = pyst.partition(ctx, bk, bc, fanout)
+    op = pyst.partition(ctx, pk, pc, fanout)
+    offs_b, offs_p = ob[2].cpu().tolist(), op[2].cpu().tolist()
+    res = []
+    for q in range(fanout):
+        b0, b1, p0, p1 = offs_b[q], offs_b[q + 1], offs_p[q], offs_p[q + 1]
+        res.append(pyst.join_materialize(ctx, ob[0][b0:b1], [c[b0:b1] for c in ob[1]], op[0][p0:p1],
+                                         [c[p0:p1] for c in op[1]]))
+    return res, ob, op, offs_b, offs_p
+
+
+def bench_partitioned_join(ctx, pyst, log, bk, bc, pk, pc, fanout, m_expect):
+    """partition(build) + partition(probe) + build + probe + materialize per destination."""
+    nb, npr, k = bk.numel(), pk.numel(), len(bc)
+    log("join microbenchmark with the partition leg: fanout %d, k = %d" % (fanout, k))
+
+    def step():
+        return partitioned_join(ctx, pyst, bk, bc, pk, pc, fanout)
+
+    r = step()
+    ctx.check()
+    m = sum(int(x[3].item()) for x in r[0])
+    del r
+    ctx.timing(True)
+    el = timed_loop(step, 3, 0)
+    ctx.timing(False)
+    part_ms, part_n = ctx.kernel_time("partition")
+    for name in ("part_scatter", "join_build", "join_probe", "gather", "gather_rows", "pack_rows"):
+        ctx.kernel_time(name)
+    ctx.check()
+    ms = el / 3 * 1e3
+    part_bytes = 2 * (nb + npr) * (4 + 8 * k)  # each side read and written once
+    return {"fanout": fanout, "ms": ms, "matches": m, "matches_equal_unpartitioned": m == m_expect,
+            "partition_ms_both_sides": part_ms / 3, "partition_bytes": part_bytes,
+            "partition_gbs": part_bytes / (part_ms / 3 / 1e3) / 1e9 if part_n else None,
+            "probe_rows_per_s": npr / (ms / 1e3), "output_tuples_per_s": m / (ms / 1e3)}
+
+
+def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8), fanout=2):
+    """Build + probe + materialize of k 8-byte columns per side (one pyst_join_materialize call),
+    and the same join with its partition leg (both sides partitioned first, fanout 2: two GPUs)."""
     import torch
     out = {"build_rows": nb, "probe_rows": npr, "hit_ratio": 0.5}
     for k in ks:
@@ -435,6 +480,7 @@ def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8)
             # gathers: the build side at k > 1, after packing its columns row-major
             "gather_us": g_us, "gather_gbs": gather_bytes / (g_us / 1e6) / 1e9 if g_us > 0 else None,
             "gather_rows_us": r_ms / r_n * 1e3 if r_n else None, "pack_rows_us": k_ms / k_n * 1e3 if k_n else None}
+        out["k%d" % k]["with_partition"] = bench_partitioned_join(ctx, pyst, log, bk, bc, pk, pc, fanout, m)
         del bk, pk, bc, pc
         torch.cuda.empty_cache()
     # HBM bytes per launch from committed counters of the k = 4 run (null once the kernels changed)
@@ -473,63 +519,6 @@ def h2d_peak(host_t, log):
     gbs = host_t.numel() * host_t.element_size() / dt / 1e9
     log("pinned H2D copy: %.1f GB/s" % gbs)
     return gbs
-
-
-def bench_stream(ctx, pyst, gen, log, nrows):
-    """Chain query over a pinned host fact table streamed in 64M-row chunks, double-buffered."""
-    import torch
-    na, nbd = 3_000_000, 300_000
-    a_h, b_h = gen.chain_dims(na, nbd)
-    a, b = to_dev(a_h), to_dev(b_h)
-    log("stream: generating %d pinned fact rows" % nrows)
-    host = chain_fact_pinned(gen, nrows, na, nbd, 0.0)
-    peak = h2d_peak(host[3], log)
-    plan = pyst.chain_plan(a, b, max_groups=min(nrows // 8, 150_000_000))
-    chunk = 64_000_000
-    out = {}
-    for nbuf in (2, 3):
-        ctx.timing(True)
-        t0 = time.perf_counter()
-        k, s, ng = pyst.query_streamed(ctx, plan, host, chunk_rows=chunk, nbuf=nbuf, out_cap=plan.max_groups)
-        ctx.check()
-        dt = time.perf_counter() - t0
-        ctx.timing(False)
-        copy_ms, copies = ctx.kernel_time("h2d_chunk")
-        fact_ms, _ = ctx.kernel_time("fact_pass")
-        gbs = nrows * 24 / dt / 1e9
-        out["nbuf%d" % nbuf] = {"seconds": dt, "fact_rows_per_s": nrows / dt, "h2d_gbs": gbs,
-                                "frac_of_pinned_h2d": gbs / peak, "copy_busy_ms": copy_ms,
-                                "compute_busy_ms": fact_ms, "chunks": copies, "groups": int(ng.item())}
-        del k, s
-    # the same columns bit-packed on the host: the link carries the packed bytes
-    log("stream: packing %d rows" % nrows)
-    t0 = time.perf_counter()
-    packed = [(*pyst.pack(t), nrows, t.dtype) for t in host]
-    pack_s = time.perf_counter() - t0
-    packed_bytes = sum(bl.numel() * 8 + w.numel() * 4 for bl, w, _, _ in packed)
-    for nbuf in (2, 3):
-        ctx.timing(True)
-        t0 = time.perf_counter()
-        k, s, ng = pyst.query_streamed_packed(ctx, plan, packed, chunk_rows=chunk, nbuf=nbuf,
-                                              out_cap=plan.max_groups)
-        ctx.check()
-        dt = time.perf_counter() - t0
-        ctx.timing(False)
-        copy_ms, copies = ctx.kernel_time("h2d_chunk")
-        unpack_ms, unpacks = ctx.kernel_time("unpack")
-        fact_ms, _ = ctx.kernel_time("fact_pass")
-        out["packed_nbuf%d" % nbuf] = {
-            "seconds": dt, "fact_rows_per_s": nrows / dt, "link_gbs": packed_bytes / dt / 1e9,
-            "frac_of_pinned_h2d": packed_bytes / dt / 1e9 / peak, "copy_busy_ms": copy_ms,
-            "unpack_busy_ms": unpack_ms, "compute_busy_ms": fact_ms, "groups": int(ng.item()),
-            "speedup_vs_raw": out["nbuf%d" % nbuf]["seconds"] / dt}
-        del k, s
-    out["packed"] = {"bytes": packed_bytes, "bytes_per_row": packed_bytes / nrows,
-                     "ratio": nrows * 24 / packed_bytes, "host_encode_s": pack_s}
-    out.update({"rows": nrows, "chunk_rows": chunk, "pinned_h2d_peak_gbs": peak,
-                "workload": "chain query, fact %d rows (24 B/row) in pinned host memory" % nrows})
-    del host, packed
-    return out
 
 
 def bench_batch(ctx, pyst, gen, log, nfrag, max_rows):
@@ -582,34 +571,168 @@ def bench_batch(ctx, pyst, gen, log, nfrag, max_rows):
             "batched_gbs": total_rows * 16 / batched_s / 1e9, "result_mismatches": mismatches}
 
 
-def bench_serve(pyst, gen, log, nrows, nreq):
-    """Poisson stream of star/chain requests over a pinned host fact table: continuous batching
-    (shared scan, up to 8 active) vs one-at-a-time FIFO on the same trace."""
-    import threading
+def host_memory(log):
+    """Host memory this process may still take: MemAvailable, capped by the
+    cgroup limit minus its current use when one is set (bytes, and the figures)."""
+    info = {}
+    with open("/proc/meminfo") as f:
+        for line in f:
+            k, v = line.split(":", 1)
+            if k in ("MemTotal", "MemAvailable"):
+                info[k] = int(v.split()[0]) * 1024
+    avail = info.get("MemAvailable", 0)
+    for lim_p, cur_p in (("/sys/fs/cgroup/memory.max", "/sys/fs/cgroup/memory.current"),
+                         ("/sys/fs/cgroup/memory/memory.limit_in_bytes", "/sys/fs/cgroup/memory/memory.usage_in_bytes")):
+        try:
+            lim = open(lim_p).read().strip()
+            cur = int(open(cur_p).read().strip())
+        except (OSError, ValueError):
+            continue
+        if lim.isdigit() and int(lim) < (1 << 60):
+            info["cgroup_limit"] = int(lim)
+            info["cgroup_used"] = cur
+            avail = min(avail, int(lim) - cur)
+        break
+    info["usable"] = avail
+    log("host memory: %s" % {k: "%.1f GB" % (v / 1e9) for k, v in info.items()})
+    return avail, info
 
+
+class PinnedHost:
+    """Exact-size pinned host buffers from hipHostMalloc, returned to the system by
+    free_all().  (torch's pinned allocator rounds sizes up to powers of two and keeps
+    freed blocks, while the GPU machine pins at most about 64 GiB in all.)"""
+
+    def __init__(self):
+        import ctypes
+        self.ct = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipHostMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_uint]
+        self.hip.hipHostMalloc.restype = ctypes.c_int
+        self.hip.hipHostFree.argtypes = [ctypes.c_void_p]
+        self.hip.hipHostFree.restype = ctypes.c_int
+        self.ptrs = []
+
+    def empty(self, n, dtype):
+        import numpy as np
+        import torch
+        ct = self.ct
+        nbytes = max(int(n), 1) * torch.tensor([], dtype=dtype).element_size()
+        p = ct.c_void_p()
+        if self.hip.hipHostMalloc(ct.byref(p), nbytes, 0) != 0:
+            raise MemoryError("hipHostMalloc of %d bytes failed" % nbytes)
+        self.ptrs.append(p.value)
+        npt = {torch.int32: (ct.c_int32, np.int32), torch.int64: (ct.c_int64, np.int64)}[dtype]
+        arr = np.ctypeslib.as_array(ct.cast(p, ct.POINTER(npt[0])), shape=(max(int(n), 1),))[:n]
+        return torch.from_numpy(arr)
+
+    def free_all(self):
+        for p in self.ptrs:
+            self.hip.hipHostFree(p)
+        self.ptrs = []
+
+
+def _digest(k, s):
+    """Order-independent fingerprint of a (keys, sums) result (wrapping int64 sums on the device)."""
+    if k.numel() == 0:
+        return (0, 0, 0, 0)
+    return (int(k.numel()), int(k.sum()), int(s.sum()), int((k * 0x9E3779B1 + s).sum()))
+
+
+def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total):
+    """The served workload at its stated size: a 2e9-row chain fact table in
+    pinned host memory streamed in 64M-row chunks under a 32 GiB device
+    budget; the chain query streamed over all of it (raw and bit-packed); then
+    Poisson streams of star/chain requests (sizes log-uniform in [1e6, rows])
+    at 0.5 and 0.9 of the one-at-a-time capacity, FIFO against continuous
+    batching, plus back-to-back bursts of both; every request of the
+    continuous-batching runs compared with its FIFO (alone) result, and a
+    seeded sample of requests checked against the oracle on its fact prefix."""
     import numpy as np
     import torch
+
+    import oracle
     na, nbd = 3_000_000, 300_000
+    # Bytes a row: raw columns (pinned), and in the packed phase the packed copy (about
+    # 10.2 B) pageable and pinned.  The raw table is unpinned before the packed one is
+    # pinned: the box pins at most about 64 GiB.
+    raw_b, packed_b = 24, 11
+    pin_limit = 60 << 30
+    avail, mem = host_memory(log)
+    margin = 24 << 30
+    fit = min((avail - margin) // (raw_b + 2 * packed_b), pin_limit // raw_b)
+    nrows = int(min(want_rows, max(fit // 1_000_000 * 1_000_000, 64_000_000)))
+    if nrows < want_rows:
+        log("config4: host memory holds %d rows, not %d" % (nrows, want_rows))
     a_h, b_h = gen.chain_dims(na, nbd)
     a, b = to_dev(a_h), to_dev(b_h)
-    log("serve: generating %d pinned fact rows" % nrows)
-    host = chain_fact_pinned(gen, nrows, na, nbd, 0.0)
+    t0 = time.perf_counter()
+    log("config4: generating %d pinned fact rows" % nrows)
+    pinned = PinnedHost()
+    names = ("a_fk", "b_fk", "date", "price", "discount")
+    dts = (torch.int32, torch.int32, torch.int32, torch.int64, torch.int32)
+    host = [pinned.empty(nrows, d) for d in dts]
+    gen.chain_fact(nrows, na, nbd, 0.0, out={c: t.numpy() for c, t in zip(names, host)})
+    gen_s = time.perf_counter() - t0
+    peak = h2d_peak(host[3][:min(nrows, 500_000_000)], log)
+    out = {"rows": nrows, "requested_rows": want_rows, "host_memory": mem, "generate_s": gen_s,
+           "chunk_rows": chunk, "device_budget_bytes": budget_total, "pinned_h2d_peak_gbs": peak}
+
+    # --- the chain query streamed over the whole table
+    ring = 2 * chunk * raw_b
+    max_groups = 150_000_000
+    sctx = pyst.Ctx(0, budget_total)
+    plan = pyst.chain_plan(a, b, max_groups=max_groups)
+    stream = {}
+    for nbuf in (2, 3):
+        sctx.timing(True)
+        t0 = time.perf_counter()
+        k, s_, ng = pyst.query_streamed(sctx, plan, host, chunk_rows=chunk, nbuf=nbuf, out_cap=max_groups)
+        sctx.check()
+        dt = time.perf_counter() - t0
+        sctx.timing(False)
+        copy_ms, copies = sctx.kernel_time("h2d_chunk")
+        fact_ms, _ = sctx.kernel_time("fact_pass")
+        gbs = nrows * raw_b / dt / 1e9
+        stream["nbuf%d" % nbuf] = {"seconds": dt, "fact_rows_per_s": nrows / dt, "h2d_gbs": gbs,
+                                   "frac_of_pinned_h2d": gbs / peak, "copy_busy_ms": copy_ms,
+                                   "compute_busy_ms": fact_ms, "chunks": copies, "groups": int(ng.item())}
+        stream_digest = _digest(k[:int(ng.item())], s_[:int(ng.item())])
+        del k, s_
+    torch.cuda.empty_cache()
+    stream["workload"] = "chain query, fact %d rows (24 B/row) from pinned host, %d-row chunks, %d GiB arena" % (
+        nrows, chunk, budget_total >> 30)
+    out["stream"] = stream
+
+    # --- serving
     rows = np.minimum(gen.loguniform_i64(nreq, 1e6, nrows, gen.seed(4, 7, 0)), nrows)
     kinds = ["star" if i % 2 == 0 else "chain" for i in range(nreq)]
+    srv_budget = budget_total - ring - (1 << 20)
 
     def plan_for(kind, r):
         if kind == "star":
             return pyst.fact_star_plan(b), nbd
-        g = int(min(max(r // 8, 1024), 150_000_000))
+        g = int(min(max(r // 8, 1024), max_groups))
         return pyst.chain_plan(a, b, max_groups=g), g
 
-    def run(max_active, arrivals, packed=None):
-        srv = pyst.Server(None if packed else host, budget=48 << 30, max_active=max_active, nbuf=2,
-                          chunk_rows=16_000_000, packed=packed)
-        # warm the resident dimension tables outside the trace
-        for kind in ("star", "chain"):
+    # seeded oracle sample: two star and two chain requests small enough for the
+    # single-threaded oracle (star <= 1.5e8 rows, chain <= 4e7 rows)
+    rng = np.random.default_rng(gen.seed(4, 9, 0))
+    small_star = [i for i in range(nreq) if kinds[i] == "star" and rows[i] <= 150_000_000]
+    small_chain = [i for i in range(nreq) if kinds[i] == "chain" and rows[i] <= 40_000_000]
+    sample = sorted(list(rng.choice(small_star, min(2, len(small_star)), replace=False)) +
+                    list(rng.choice(small_chain, min(2, len(small_chain)), replace=False)))
+    sample = [int(i) for i in sample]
+    star_ids = [i for i in range(nreq) if kinds[i] == "star"]
+    big_star = max(star_ids, key=lambda i: rows[i]) if star_ids else None
+
+    def run(max_active, arrivals, packed_cols=None, keep=()):
+        srv = pyst.Server(None if packed_cols else host, budget=srv_budget, max_active=max_active, nbuf=2,
+                          chunk_rows=chunk, packed=packed_cols)
+        for kind in ("star", "chain"):  # warm the resident dimension tables outside the trace
             p, c = plan_for(kind, 1_000_000)
             srv.wait(srv.submit(p, 1_000_000, c))
+        base = srv.stats()
         t_start = time.perf_counter()
         tickets = [None] * nreq
 
@@ -623,41 +746,129 @@ def bench_serve(pyst, gen, log, nrows, nreq):
 
         th = threading.Thread(target=producer)
         th.start()
-        lat = []
+        lat, digests, kept = [], [], {}
         for i in range(nreq):
             while tickets[i] is None:
                 time.sleep(0.0005)
-            lat.append(srv.wait(tickets[i])[2])
+            k, s_, l_ = srv.wait(tickets[i])
+            lat.append(l_)
+            digests.append(_digest(k, s_))
+            if i in keep:
+                kept[i] = (k.cpu().numpy(), s_.cpu().numpy())
+            del k, s_
         th.join()
         makespan = time.perf_counter() - t_start
         st = srv.stats()
         srv.check()
         srv.close()
+        torch.cuda.empty_cache()
         lat = np.array(lat)
-        return {"p50_ms": float(np.percentile(lat, 50, method="nearest")),
-                "p99_ms": float(np.percentile(lat, 99, method="nearest")),
-                "mean_ms": float(lat.mean()), "makespan_s": makespan,
-                "requests_per_s": nreq / makespan, "rows_per_s": float(rows.sum()) / makespan,
-                "chunks_copied": st["chunks_copied"], "h2d_gb": st["bytes_copied"] / 1e9,
-                "max_active_seen": st["max_active_seen"], "admission_waits": st["admission_waits"]}
+        res = {"p50_ms": float(np.percentile(lat, 50, method="nearest")),
+               "p99_ms": float(np.percentile(lat, 99, method="nearest")),
+               "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "makespan_s": makespan,
+               "requests_per_s": nreq / makespan, "rows_per_s": float(rows.sum()) / makespan,
+               "chunks_copied": st["chunks_copied"] - base["chunks_copied"],
+               "h2d_gb": (st["bytes_copied"] - base["bytes_copied"]) / 1e9,
+               "max_active_seen": st["max_active_seen"],
+               "admission_waits": st["admission_waits"] - base["admission_waits"]}
+        log("config4: served %d requests, max_active %d: makespan %.1f s, p50 %.0f ms, p99 %.0f ms, "
+            "admission waits %d" % (nreq, max_active, makespan, res["p50_ms"], res["p99_ms"], res["admission_waits"]))
+        return res, digests, kept
 
-    # service rate of one-at-a-time execution, from a back-to-back burst
-    burst = run(1, np.zeros(nreq))
-    lam = 0.9 * burst["requests_per_s"]
-    arrivals = gen.poisson_arrivals(nreq, lam, gen.seed(4, 8, 0))
-    log("serve: Poisson rate %.2f req/s (0.9 x one-at-a-time capacity)" % lam)
-    fifo = run(1, arrivals)
-    cont = run(8, arrivals)
-    # the same trace served from bit-packed host columns (decoded on the device per chunk)
-    log("serve: packing %d rows" % nrows)
-    packed = [(*pyst.pack(t), nrows, t.dtype) for t in host]
-    cont_packed = run(8, arrivals, packed)
+    serve = {}
+    traces = {}
+    burst_fifo, fifo_digests, _ = run(1, np.zeros(nreq))
+    serve["burst_one_at_a_time"] = burst_fifo
+    capacity = burst_fifo["requests_per_s"]
+    burst_cb, d, kept = run(8, np.zeros(nreq), keep=set(sample + ([big_star] if big_star is not None else [])))
+    burst_cb["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
+    serve["burst_continuous_batching"] = burst_cb
+    for rho in (0.5, 0.9):
+        lam = rho * capacity
+        arrivals = gen.poisson_arrivals(nreq, lam, gen.seed(4, 8, int(rho * 10)))
+        traces[rho] = arrivals
+        log("config4: Poisson rate %.2f req/s (%.1f x one-at-a-time capacity)" % (lam, rho))
+        fifo, _, _ = run(1, arrivals)
+        cb, d, _ = run(8, arrivals)
+        cb["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
+        serve["rho%.1f" % rho] = {"arrival_rate_per_s": lam, "one_at_a_time": fifo, "continuous_batching": cb}
+
+    # the oracle on the sampled requests' fact prefixes (results of the burst run)
+    checks = []
+    for i in sample:
+        pref = {c: v[:int(rows[i])].numpy() for c, v in zip(("a_fk", "b_fk", "date", "price", "discount"), host)}
+        t0 = time.perf_counter()
+        if kinds[i] == "star":
+            wk, ws = oracle.star_query(b_h, {"fk": pref["b_fk"], "date": pref["date"], "price": pref["price"]})
+        else:
+            wk, ws = oracle.chain_query(a_h, b_h, pref)
+        k, s_ = kept[i]
+        o = np.argsort(k)
+        ok = bool(len(k) == len(wk) and np.array_equal(k[o], wk) and np.array_equal(s_[o], ws))
+        checks.append({"request": i, "kind": kinds[i], "rows": int(rows[i]), "groups": int(len(wk)), "equal": ok,
+                       "oracle_s": time.perf_counter() - t0})
+    if big_star is not None:
+        i = big_star
+        pref = {c: v[:int(rows[i])].numpy() for c, v in zip(("b_fk", "date", "price"), host[1:4])}
+        t0 = time.perf_counter()
+        wk, ws, used = oracle.star_query_threaded(b_h, {"fk": pref["b_fk"], "date": pref["date"],
+                                                        "price": pref["price"]}, threads=len(os.sched_getaffinity(0)))
+        k, s_ = kept[i]
+        o = np.argsort(k)
+        checks.append({"request": i, "kind": "star", "rows": int(rows[i]), "groups": int(len(wk)),
+                       "equal": bool(np.array_equal(k[o], wk) and np.array_equal(s_[o], ws)),
+                       "checked_by": "threaded baseline (%d threads; equal to the oracle by test)" % used,
+                       "seconds": time.perf_counter() - t0})
+    serve["oracle_checks"] = checks
+    serve["result_mismatches"] = sum(not c["equal"] for c in checks)
+
+    # --- the same table bit-packed: encoded into pageable memory, the raw table
+    # unpinned, the packed one pinned; streamed and served again
+    log("config4: packing %d rows" % nrows)
+    t0 = time.perf_counter()
+    packed_pageable = [pyst.pack(t, pinned=False) for t in host]
+    pack_s = time.perf_counter() - t0
+    host = None
+    pinned.free_all()
+    packed = []
+    for (bl, w), d in zip(packed_pageable, dts):
+        pb, pw = pinned.empty(bl.numel(), torch.int64).view(bl.shape), pinned.empty(w.numel(), torch.int32)
+        pb.copy_(bl)
+        pw.copy_(w)
+        packed.append((pb, pw, nrows, d))
+    del packed_pageable
     packed_bytes = sum(bl.numel() * 8 + w.numel() * 4 for bl, w, _, _ in packed)
-    del host, packed
-    return {"fact_rows": nrows, "requests": nreq, "arrival_rate_per_s": lam, "one_at_a_time": fifo,
-            "continuous_batching": cont, "continuous_batching_packed": cont_packed,
-            "packed_bytes_per_row": packed_bytes / nrows, "burst_one_at_a_time": burst,
-            "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]" % nrows}
+    for nbuf in (2, 3):
+        sctx.timing(True)
+        t0 = time.perf_counter()
+        k, s_, ng = pyst.query_streamed_packed(sctx, plan, packed, chunk_rows=chunk, nbuf=nbuf, out_cap=max_groups)
+        sctx.check()
+        dt = time.perf_counter() - t0
+        sctx.timing(False)
+        copy_ms, _ = sctx.kernel_time("h2d_chunk")
+        unpack_ms, _ = sctx.kernel_time("unpack")
+        fact_ms, _ = sctx.kernel_time("fact_pass")
+        stream["packed_nbuf%d" % nbuf] = {
+            "seconds": dt, "fact_rows_per_s": nrows / dt, "link_gbs": packed_bytes / dt / 1e9,
+            "frac_of_pinned_h2d": packed_bytes / dt / 1e9 / peak, "copy_busy_ms": copy_ms,
+            "unpack_busy_ms": unpack_ms, "compute_busy_ms": fact_ms, "groups": int(ng.item()),
+            "equal_to_raw": _digest(k[:int(ng.item())], s_[:int(ng.item())]) == stream_digest,
+            "speedup_vs_raw": stream["nbuf%d" % nbuf]["seconds"] / dt}
+        del k, s_
+    sctx.close()
+    stream["packed"] = {"bytes": packed_bytes, "bytes_per_row": packed_bytes / nrows,
+                        "ratio": nrows * raw_b / packed_bytes, "host_encode_s": pack_s}
+    cbp, d, _ = run(8, traces[0.9], packed)
+    cbp["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
+    serve["rho0.9"]["continuous_batching_packed"] = cbp
+    serve.update({"requests": nreq, "server_budget_bytes": srv_budget, "ring_bytes": ring, "max_active": 8,
+                  "request_rows_mean": float(rows.mean()), "request_rows_max": int(rows.max()),
+                  "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]; device arena %d "
+                              "GiB in total (chunk ring of 2 x %d rows included)" % (nrows, budget_total >> 30, chunk)})
+    out["serve"] = serve
+    del packed
+    pinned.free_all()
+    return out
 
 
 def host_cpu_info():

@@ -11,6 +11,7 @@
 // for a file format's).
 #include <algorithm>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "pyst_internal.h"
@@ -94,27 +95,55 @@ static bool pack_col_ok(const pyst_col *c) {
   return c && c->n >= 0 && (c->n == 0 || c->data) && (c->dtype == PYST_I32 || c->dtype == PYST_I64);
 }
 
+// Bits of block b's frame of reference: the width of its range (0 when constant).
+static int block_bits(const pyst_col &c, int64_t b) {
+  const int64_t a = b * kPackBlock, e = std::min<int64_t>(c.n, a + kPackBlock);
+  int64_t mn = INT64_MAX, mx = INT64_MIN;
+  for (int64_t i = a; i < e; ++i) {
+    const int64_t v = c.dtype == PYST_I64 ? static_cast<const int64_t *>(c.data)[i] : static_cast<const int32_t *>(c.data)[i];
+    mn = std::min(mn, v);
+    mx = std::max(mx, v);
+  }
+  const uint64_t range = static_cast<uint64_t>(mx) - static_cast<uint64_t>(mn);
+  return range == 0 ? 0 : 64 - __builtin_clzll(range);
+}
+
+// Host threads for nblk blocks: one per 4096 blocks (4M values), at most the
+// machine's hardware threads and 64.
+static int pack_threads(int64_t nblk) {
+  const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({hw, 64, ceil_div(nblk, 4096)})));
+}
+
+// Run fn(thread, first block, end block) over contiguous ranges of [0, nblk).
+template <typename F>
+static void parallel_blocks(int64_t nblk, F fn) {
+  const int nt = pack_threads(nblk);
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back([&, t] { fn(t, nblk * t / nt, nblk * (t + 1) / nt); });
+  fn(0, 0, nblk / nt);
+  for (auto &th : pool) th.join();
+}
+
 extern "C" {
 
 int64_t pyst_pack_words(const pyst_col *host_col) {
   if (!pack_col_ok(host_col)) return -1;
-  const int64_t n = host_col->n, nblk = ceil_div(n, kPackBlock);
+  const int64_t nblk = ceil_div(host_col->n, kPackBlock);
+  std::vector<int64_t> part(pack_threads(nblk), 0);
+  parallel_blocks(nblk, [&](int t, int64_t b0, int64_t b1) {
+    int64_t total = 0;
+    for (int64_t b = b0; b < b1; ++b) total += 32 * block_bits(*host_col, b);
+    part[t] = total;
+  });
   int64_t total = 0;
-  for (int64_t b = 0; b < nblk; ++b) {
-    const int64_t a = b * kPackBlock, e = std::min<int64_t>(n, a + kPackBlock);
-    int64_t mn = INT64_MAX, mx = INT64_MIN;
-    for (int64_t i = a; i < e; ++i) {
-      const int64_t v = host_col->dtype == PYST_I64 ? static_cast<const int64_t *>(host_col->data)[i]
-                                                    : static_cast<const int32_t *>(host_col->data)[i];
-      mn = std::min(mn, v);
-      mx = std::max(mx, v);
-    }
-    const uint64_t range = static_cast<uint64_t>(mx) - static_cast<uint64_t>(mn);
-    total += 32 * (range == 0 ? 0 : 64 - __builtin_clzll(range));
-  }
+  for (int64_t x : part) total += x;
   return total;
 }
 
+// Two passes over the blocks, each split across host threads: every block's
+// width (kept in word_off for the moment), a prefix sum that turns widths into
+// word offsets, then every block's words.
 pyst_status pyst_pack_encode(const pyst_col *host_col, pyst_pack_block *blocks, uint32_t *words) {
   if (!pack_col_ok(host_col)) return set_error(PYST_ERR_ARG, "pyst_pack_encode: bad column");
   if (!blocks || (host_col->n > 0 && !words)) return set_error(PYST_ERR_ARG, "pyst_pack_encode: NULL output");
@@ -123,21 +152,30 @@ pyst_status pyst_pack_encode(const pyst_col *host_col, pyst_pack_block *blocks, 
   auto at = [&](int64_t i) -> int64_t {
     return is64 ? static_cast<const int64_t *>(host_col->data)[i] : static_cast<const int32_t *>(host_col->data)[i];
   };
+  parallel_blocks(nblk, [&](int, int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) {
+      int64_t mn = INT64_MAX;
+      for (int64_t i = b * kPackBlock, e = std::min<int64_t>(n, (b + 1) * kPackBlock); i < e; ++i) mn = std::min(mn, at(i));
+      blocks[b].base = mn;
+      blocks[b].word_off = 32 * block_bits(*host_col, b);
+    }
+  });
   int64_t off = 0;
   for (int64_t b = 0; b < nblk; ++b) {
-    const int64_t a = b * kPackBlock, e = std::min<int64_t>(n, a + kPackBlock);
-    int64_t mn = INT64_MAX, mx = INT64_MIN;
-    for (int64_t i = a; i < e; ++i) {
-      mn = std::min(mn, at(i));
-      mx = std::max(mx, at(i));
-    }
-    const uint64_t range = static_cast<uint64_t>(mx) - static_cast<uint64_t>(mn);
-    const int bits = range == 0 ? 0 : 64 - __builtin_clzll(range);
-    blocks[b].base = mn;
+    const int64_t w = blocks[b].word_off;
     blocks[b].word_off = off;
-    uint32_t *w = words + off;
-    std::memset(w, 0, sizeof(uint32_t) * 32 * bits);
-    if (bits > 0)
+    off += w;
+  }
+  blocks[nblk].base = 0;
+  blocks[nblk].word_off = off;
+  parallel_blocks(nblk, [&](int, int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t a = b * kPackBlock, e = std::min<int64_t>(n, a + kPackBlock);
+      const int bits = static_cast<int>((blocks[b + 1].word_off - blocks[b].word_off) / 32);
+      const int64_t mn = blocks[b].base;
+      uint32_t *w = words + blocks[b].word_off;
+      std::memset(w, 0, sizeof(uint32_t) * 32 * bits);
+      if (bits == 0) continue;
       for (int64_t i = a; i < e; ++i) {
         const uint64_t x = static_cast<uint64_t>(at(i)) - static_cast<uint64_t>(mn);
         const int64_t pos = (i - a) * bits;
@@ -147,10 +185,8 @@ pyst_status pyst_pack_encode(const pyst_col *host_col, pyst_pack_block *blocks, 
         if (sh + bits > 32) w[q + 1] |= static_cast<uint32_t>(x >> (32 - sh));
         if (sh + bits > 64) w[q + 2] |= static_cast<uint32_t>(x >> (64 - sh));
       }
-    off += 32 * bits;
-  }
-  blocks[nblk].base = 0;
-  blocks[nblk].word_off = off;
+    }
+  });
   return PYST_OK;
 }
 
