@@ -84,6 +84,7 @@ typedef struct pyst_pred {
 } pyst_pred;
 
 #define PYST_MAX_COLS 8
+#define PYST_MAX_PART_PAYLOADS 15 /* payload columns one pyst_partition call carries */
 #define PYST_MAX_PREDS 8
 #define PYST_MAX_FANOUT 1024
 
@@ -159,7 +160,7 @@ pyst_status pyst_filter(pyst_ctx *ctx, const pyst_col *cols, int ncols, const py
    each output has room for key->n values of its column's dtype.
    d_offsets: device int64[fanout + 1]; segment p is [d_offsets[p], d_offsets[p+1]).
    Errors: PYST_ERR_ARG (fanout outside 1..PYST_MAX_FANOUT, npay over
-   PYST_MAX_COLS - 1, lengths disagree), PYST_ERR_NOMEM. */
+   PYST_MAX_PART_PAYLOADS, lengths disagree), PYST_ERR_NOMEM. */
 pyst_status pyst_partition(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payloads, int npay,
                            const int32_t *sel, const int64_t *d_nsel, uint32_t fanout,
                            void *const *out_cols, int64_t *d_offsets, hipStream_t stream);

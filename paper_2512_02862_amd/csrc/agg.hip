@@ -323,6 +323,300 @@ pyst_status pair_groupby_from(pyst_ctx *ctx, MoveArgs first, int64_t *keys, int6
   return PYST_OK;
 }
 
+// ---------------------------------------------------------------- narrow pairs
+// Group-by of int32 keys with int32 values: a pair travels as ONE 8-byte word
+// (key << 32 | value), half the bytes of the (int64, int64) pairs above, and
+// both moves take their counts from one pass over the keys.  The bucket of a
+// key is the top 12 bits of a 32-bit hash: bits 26..31 pick its part in the
+// first move, bits 20..25 its bucket within the part in the second, bits 0..12
+// its LDS slot.  The second move's block j of part p reads exactly the pairs
+// that the first move's blocks [j G, (j + 1) G) wrote to part p (G = kNB1 /
+// kNB2), so its counts are sums of the first pass's per-block counts and no
+// second pass over the pairs is needed to count them.
+constexpr int kNB1 = 512;                // blocks of the first move (and of the counting pass)
+constexpr int kNB2 = 8;                  // blocks per part in the second move
+constexpr int kNG = kNB1 / kNB2;         // first-move blocks behind one second-move block
+constexpr int kNItems = 8;               // rows per thread and round of the counting pass
+constexpr uint32_t kNarrowSeed = 0x6b43a9b5u;
+static_assert(kNB1 % kNB2 == 0, "second-move blocks cover whole groups of first-move blocks");
+
+__device__ __forceinline__ uint32_t narrow_hash(int32_t key) { return fmix32(static_cast<uint32_t>(key) ^ kNarrowSeed); }
+
+struct NarrowArgs {
+  const int32_t *kcol;
+  const int32_t *vcol;
+  const int32_t *sel;    // nullptr: rows 0..count-1
+  const int64_t *count;  // rows (or selected rows) to group
+  int64_t cap;           // upper bound of *count
+};
+
+__device__ __forceinline__ void narrow_range(const NarrowArgs &a, int blk, int nblk, int64_t *lo, int64_t *hi) {
+  const int64_t n = *a.count < a.cap ? *a.count : a.cap;
+  const int64_t per = (n + nblk - 1) / nblk;
+  *lo = per * blk < n ? per * blk : n;
+  *hi = *lo + per < n ? *lo + per : n;
+}
+
+// Per first-move block: counts of its rows in each of the 4096 buckets.
+__global__ __launch_bounds__(kAggBlock) void k_narrow_hist(NarrowArgs a, int32_t *counts) {
+  __shared__ int32_t s_c[kAggBuckets];
+  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) s_c[i] = 0;
+  __syncthreads();
+  int64_t lo, hi;
+  narrow_range(a, blockIdx.x, kNB1, &lo, &hi);
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * kNItems) {
+    int32_t k[kNItems];
+#pragma unroll
+    for (int u = 0; u < kNItems; ++u) {
+      const int64_t i = i0 + int64_t{u} * kAggBlock;
+      k[u] = i < hi ? a.kcol[row_of(a.sel, i)] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kNItems; ++u)
+      if (i0 + int64_t{u} * kAggBlock < hi) atomicAdd(&s_c[narrow_hash(k[u]) >> 20], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) counts[int64_t{blockIdx.x} * kAggBuckets + i] = s_c[i];
+}
+
+// c1[p * kNB1 + b]: rows of first-move block b in part p; c2[(p * 64 + q) * kNB2
+// + j]: rows of bucket (p, q) that second-move block j of part p moves.  The
+// entry after each array is zero so that its exclusive scan ends in the total.
+__global__ void k_narrow_counts(const int32_t *counts, int32_t *c1, int32_t *c2) {
+  const int64_t t = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
+  constexpr int64_t n1 = int64_t{kRadix} * kNB1, n2 = int64_t{kAggBuckets} * kNB2;
+  if (t < n1) {
+    const int p = static_cast<int>(t / kNB1), b = static_cast<int>(t % kNB1);
+    int32_t c = 0;
+    for (int q = 0; q < kRadix; ++q) c += counts[int64_t{b} * kAggBuckets + p * kRadix + q];
+    c1[t] = c;
+  } else if (t < n1 + n2) {
+    const int64_t u = t - n1;
+    const int bucket = static_cast<int>(u / kNB2), j = static_cast<int>(u % kNB2);
+    int32_t c = 0;
+    for (int b = j * kNG; b < (j + 1) * kNG; ++b) c += counts[int64_t{b} * kAggBuckets + bucket];
+    c2[u] = c;
+  } else if (t == n1 + n2) {
+    c1[n1] = 0;
+    c2[n2] = 0;
+  }
+}
+
+// One move of narrow pairs.  FIRST: block b reads its rows of the columns and
+// writes them by part (bits 26..31) at pos1; else block p * kNB2 + j reads the
+// pairs of its range of part p and writes them by bucket (bits 20..25) at pos2.
+// Each 4096-pair tile is ranked by destination in LDS and every destination's
+// pairs of the tile leave as one contiguous run (as k_move_scatter does).
+template <bool FIRST>
+__global__ __launch_bounds__(kAggBlock) void k_narrow_move(NarrowArgs a, const uint64_t *in, const int32_t *pos1,
+                                                          const int32_t *pos2, uint64_t *out) {
+  __shared__ uint64_t s_p[kMoveTile];
+  __shared__ uint8_t s_b[kMoveTile];
+  __shared__ int32_t s_base[kRadix], s_cnt[kRadix], s_off[kRadix + 1];
+  const int tid = static_cast<int>(threadIdx.x);
+  int64_t lo, hi;
+  int part = 0;
+  if (FIRST) {
+    narrow_range(a, blockIdx.x, kNB1, &lo, &hi);
+    if (tid < kRadix) s_base[tid] = pos1[int64_t{tid} * kNB1 + blockIdx.x];
+  } else {
+    part = static_cast<int>(blockIdx.x) / kNB2;
+    const int j = static_cast<int>(blockIdx.x) % kNB2;
+    lo = pos1[int64_t{part} * kNB1 + j * kNG];
+    hi = pos1[int64_t{part} * kNB1 + (j + 1) * kNG];
+    if (tid < kRadix) s_base[tid] = pos2[(int64_t{part} * kRadix + tid) * kNB2 + j];
+  }
+  const int shift = FIRST ? 26 : 20;
+  for (int64_t t0 = lo; t0 < hi; t0 += kMoveTile) {  // block-uniform
+    if (tid < kRadix) s_cnt[tid] = 0;
+    __syncthreads();
+    uint64_t pr[kMoveTileItems];
+    int bk[kMoveTileItems], rk[kMoveTileItems];
+#pragma unroll
+    for (int u = 0; u < kMoveTileItems; ++u) {
+      const int64_t i = t0 + int64_t{u} * kAggBlock + tid;
+      if (FIRST) {
+        const int64_t r = i < hi ? row_of(a.sel, i) : 0;
+        const int32_t k = i < hi ? a.kcol[r] : 0, v = i < hi ? a.vcol[r] : 0;
+        pr[u] = (static_cast<uint64_t>(static_cast<uint32_t>(k)) << 32) | static_cast<uint32_t>(v);
+      } else {
+        pr[u] = i < hi ? in[i] : 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMoveTileItems; ++u) {
+      const int64_t i = t0 + int64_t{u} * kAggBlock + tid;
+      bk[u] = i < hi ? static_cast<int>((narrow_hash(static_cast<int32_t>(pr[u] >> 32)) >> shift) & (kRadix - 1)) : -1;
+      rk[u] = bk[u] >= 0 ? atomicAdd(&s_cnt[bk[u]], 1) : 0;
+    }
+    __syncthreads();
+    if (tid < kWave) {
+      const int c = s_cnt[tid];
+      const int incl = wave_inclusive_scan(c);
+      s_off[tid] = incl - c;
+      if (tid == kWave - 1) s_off[kRadix] = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMoveTileItems; ++u)
+      if (bk[u] >= 0) {
+        const int p = s_off[bk[u]] + rk[u];
+        s_p[p] = pr[u];
+        s_b[p] = static_cast<uint8_t>(bk[u]);
+      }
+    __syncthreads();
+    const int n = s_off[kRadix];
+    for (int t = tid; t < n; t += kAggBlock) {
+      const int b = s_b[t];
+      out[int64_t{s_base[b]} + (t - s_off[b])] = s_p[t];
+    }
+    __syncthreads();
+    if (tid < kRadix) s_base[tid] += s_cnt[tid];
+  }
+}
+
+// Sums every bucket's narrow pairs in an LDS table (slot: low 13 hash bits)
+// and writes its groups, one block per CU walking the buckets as
+// k_bucket_groups does.  *d_ngroups must be zero on entry.
+__global__ __launch_bounds__(kAggBlock) void k_narrow_groups(const uint64_t *pairs, const int32_t *pos2,
+                                                            int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
+                                                            int64_t *d_ngroups, uint32_t *err) {
+  __shared__ uint64_t s_key[kAggSlots];
+  __shared__ uint64_t s_sum[kAggSlots];
+  __shared__ int32_t s_w[kAggBlock / kWave];
+  __shared__ int64_t s_base;
+  constexpr int U = 8;
+  constexpr int PER = kAggSlots / kAggBlock;
+  const int tid = static_cast<int>(threadIdx.x);
+  for (int s = tid; s < kAggSlots; s += kAggBlock) {
+    s_key[s] = static_cast<uint64_t>(kEmpty64);
+    s_sum[s] = 0;
+  }
+  bool full = false;
+  uint64_t pp[U];
+  bool have[U];
+  auto load_round = [&](int64_t i0, int64_t hi) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + int64_t{u} * kAggBlock;
+      have[u] = i < hi;
+      pp[u] = have[u] ? pairs[i] : 0;
+    }
+  };
+  auto insert_round = [&]() {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!have[u]) continue;
+      const int32_t k32 = static_cast<int32_t>(pp[u] >> 32);
+      const uint64_t key = static_cast<uint64_t>(static_cast<int64_t>(k32));
+      const uint64_t val = static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(pp[u] & 0xffffffffu)));
+      uint32_t s = narrow_hash(k32) & (kAggSlots - 1);
+      for (int probes = 0;; ++probes) {
+        if (probes == kAggSlots) {
+          full = true;
+          break;
+        }
+        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[s]),
+                                       static_cast<unsigned long long>(kEmpty64), static_cast<unsigned long long>(key));
+        if (old == static_cast<uint64_t>(kEmpty64) || old == key) {
+          atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(val));
+          break;
+        }
+        s = (s + 1) & (kAggSlots - 1);
+      }
+    }
+  };
+  int b = static_cast<int>(blockIdx.x);
+  if (b < kAggBuckets) load_round(pos2[int64_t{b} * kNB2] + tid, pos2[int64_t{b + 1} * kNB2]);
+  __syncthreads();
+  for (; b < kAggBuckets; b += static_cast<int>(gridDim.x)) {  // block-uniform
+    const int64_t lo = pos2[int64_t{b} * kNB2], hi = pos2[int64_t{b + 1} * kNB2];
+    insert_round();
+    for (int64_t i0 = lo + tid + int64_t{kAggBlock} * U; i0 < hi; i0 += int64_t{kAggBlock} * U) {
+      load_round(i0, hi);
+      insert_round();
+    }
+    __syncthreads();
+    const int s0 = tid * PER;
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c += s_key[s0 + j] != static_cast<uint64_t>(kEmpty64);
+    const int incl = wave_inclusive_scan(c);
+    const int w = tid / kWave;
+    if (lane_id() == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    const int nb = b + static_cast<int>(gridDim.x);
+    if (nb < kAggBuckets) load_round(pos2[int64_t{nb} * kNB2] + tid, pos2[int64_t{nb + 1} * kNB2]);
+    if (tid == 0) {
+      int64_t tot = 0;
+      for (int k = 0; k < kAggBlock / kWave; ++k) tot += s_w[k];
+      s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
+                                                    static_cast<unsigned long long>(tot)))
+                   : 0;
+    }
+    __syncthreads();
+    int64_t p = s_base + incl - c;
+    for (int k = 0; k < w; ++k) p += s_w[k];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint64_t k = s_key[s0 + j];
+      if (k == static_cast<uint64_t>(kEmpty64)) continue;
+      if (p < out_cap) {
+        out_keys[p] = static_cast<int64_t>(k);
+        out_sums[p] = static_cast<int64_t>(s_sum[s0 + j]);
+      } else {
+        latch(err, kErrCapacity);
+      }
+      ++p;
+      s_key[s0 + j] = static_cast<uint64_t>(kEmpty64);
+      s_sum[s0 + j] = 0;
+    }
+    __syncthreads();
+  }
+  if (full) latch(err, kErrTableFull);
+}
+
+// Bytes of scratch narrow_groupby needs for up to `cap` rows.
+size_t narrow_groupby_bytes(int64_t cap) {
+  const int64_t n1 = int64_t{kRadix} * kNB1, n2 = int64_t{kAggBuckets} * kNB2;
+  const size_t counts = static_cast<size_t>(kNB1) * kAggBuckets + 2 * static_cast<size_t>(n1 + 1 + n2 + 1);
+  return (counts * sizeof(int32_t) + 255) / 256 * 256 + static_cast<size_t>(cap) * 16 + 256;
+}
+
+// GROUP BY key SUM(val) of the rows [0, *count) (of the selection sel) of int32
+// columns through narrow pairs, in scratch `ws` of narrow_groupby_bytes(cap).
+// *d_ngroups must be zero on entry.  Fewer than 2^31 rows.
+pyst_status narrow_groupby(pyst_ctx *ctx, const int32_t *kcol, const int32_t *vcol, const int32_t *sel,
+                           const int64_t *count, int64_t cap, void *ws, int64_t *out_keys, int64_t *out_sums,
+                           int64_t out_cap, int64_t *d_ngroups, hipStream_t stream) {
+  if (cap >= (int64_t{1} << 31)) return set_error(PYST_ERR_ARG, "group-by: too many rows");
+  const int64_t n1 = int64_t{kRadix} * kNB1, n2 = int64_t{kAggBuckets} * kNB2;
+  int32_t *counts = static_cast<int32_t *>(ws);
+  int32_t *c1 = counts + static_cast<int64_t>(kNB1) * kAggBuckets, *p1 = c1 + n1 + 1, *c2 = p1 + n1 + 1,
+          *p2 = c2 + n2 + 1;
+  const size_t cbytes = (static_cast<size_t>(kNB1) * kAggBuckets + 2 * static_cast<size_t>(n1 + 1 + n2 + 1)) *
+                        sizeof(int32_t);
+  uint64_t *tmp = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + (cbytes + 255) / 256 * 256);
+  uint64_t *pairs = tmp + cap;
+  NarrowArgs a{kcol, vcol, sel, count, cap};
+  k_narrow_hist<<<kNB1, kAggBlock, 0, stream>>>(a, counts);
+  PYST_LAUNCH_CHECK("k_narrow_hist");
+  k_narrow_counts<<<static_cast<unsigned>(ceil_div(n1 + n2 + 1, 256)), 256, 0, stream>>>(counts, c1, c2);
+  PYST_LAUNCH_CHECK("k_narrow_counts");
+  pyst_status st = scan_excl_i32(ctx, c1, p1, n1 + 1, nullptr, stream);
+  if (st == PYST_OK) st = scan_excl_i32(ctx, c2, p2, n2 + 1, nullptr, stream);
+  if (st != PYST_OK) return st;
+  k_narrow_move<true><<<kNB1, kAggBlock, 0, stream>>>(a, nullptr, p1, p2, tmp);
+  PYST_LAUNCH_CHECK("k_narrow_move<1>");
+  k_narrow_move<false><<<kRadix * kNB2, kAggBlock, 0, stream>>>(a, tmp, p1, p2, pairs);
+  PYST_LAUNCH_CHECK("k_narrow_move<2>");
+  const int gblocks = static_cast<int>(std::min<int64_t>(kAggBuckets, std::max(1, ctx_num_cus(ctx))));
+  k_narrow_groups<<<gblocks, kAggBlock, 0, stream>>>(pairs, p2, out_keys, out_sums, out_cap, d_ngroups,
+                                                     ctx_err_word(ctx));
+  PYST_LAUNCH_CHECK("k_narrow_groups");
+  return PYST_OK;
+}
+
 pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int64_t *count, int64_t cap,
                          int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                          hipStream_t stream) {

@@ -164,9 +164,9 @@ struct PartArgs {
   const void *key;
   int32_t key64;
   int32_t npay;
-  const void *pay[PYST_MAX_COLS - 1];
-  int32_t pay64[PYST_MAX_COLS - 1];
-  void *out[PYST_MAX_COLS];
+  const void *pay[PYST_MAX_PART_PAYLOADS];
+  int32_t pay64[PYST_MAX_PART_PAYLOADS];
+  void *out[PYST_MAX_PART_PAYLOADS + 1];
   const int32_t *sel;
   const int64_t *d_nsel;
   int64_t n;
@@ -1075,6 +1075,11 @@ pyst_status column_groupby(pyst_ctx *ctx, const pyst_col *key, const pyst_col *v
                            int64_t out_cap, int64_t *d_ngroups, hipStream_t stream);
 bool ctx_groupby_hash_only(const pyst_ctx *ctx);
 
+size_t narrow_groupby_bytes(int64_t cap);
+pyst_status narrow_groupby(pyst_ctx *ctx, const int32_t *kcol, const int32_t *vcol, const int32_t *sel,
+                           const int64_t *count, int64_t cap, void *ws, int64_t *out_keys, int64_t *out_sums,
+                           int64_t out_cap, int64_t *d_ngroups, hipStream_t stream);
+
 // The radix path groups 4096 hash buckets in an LDS table of 8192 slots each:
 // up to 16M groups a bucket holds 4096 keys on average, 64 standard deviations
 // below its capacity.  Below 1M rows the HBM hash table stays in the L2.
@@ -1224,8 +1229,8 @@ static pyst_status partition_args(const pyst_col *key, const pyst_col *payloads,
                                   PartArgs *out) {
   if (!key || !out_cols || !d_offsets) return set_error(PYST_ERR_ARG, "pyst_partition: NULL argument");
   if (fanout < 1 || fanout > PYST_MAX_FANOUT) return set_error(PYST_ERR_ARG, "pyst_partition: fanout must be 1..1024");
-  if (npay < 0 || npay > PYST_MAX_COLS - 1 || (npay > 0 && !payloads))
-    return set_error(PYST_ERR_ARG, "pyst_partition: 0..7 payload columns");
+  if (npay < 0 || npay > PYST_MAX_PART_PAYLOADS || (npay > 0 && !payloads))
+    return set_error(PYST_ERR_ARG, "pyst_partition: 0..15 payload columns");
   if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_partition: sel and d_nsel go together");
   if (!col_ok(key)) return set_error(PYST_ERR_ARG, "pyst_partition: bad key column");
   for (int j = 0; j < npay; ++j)
@@ -1448,6 +1453,19 @@ pyst_status pyst_groupby_sum(pyst_ctx *ctx, const pyst_col *key, const pyst_col 
     // (the first move reading the columns) and each bucket is summed in LDS,
     // instead of two random L2 atomics per row.
     TimedRegion timed(ctx, "groupby_radix", stream);
+    if (key->dtype == PYST_I32 && val->dtype == PYST_I32) {  // 8-byte pairs
+      Scratch ws(ctx, narrow_groupby_bytes(key->n) + 256, stream);
+      if (!ws.p) return set_error(PYST_ERR_NOMEM, "pyst_groupby_sum: arena exhausted");
+      int64_t *d_cnt = reinterpret_cast<int64_t *>(static_cast<char *>(ws.p) + narrow_groupby_bytes(key->n));
+      pyst_status st = fill_u64(d_ngroups, 1, 0, stream);
+      if (st == PYST_OK && !d_nsel) st = fill_u64(d_cnt, 1, static_cast<uint64_t>(key->n), stream);
+      if (st == PYST_OK)
+        st = narrow_groupby(ctx, static_cast<const int32_t *>(key->data), static_cast<const int32_t *>(val->data), sel,
+                            d_nsel ? d_nsel : d_cnt, key->n, ws.p, out_keys, out_sums, out_cap, d_ngroups, stream);
+      if (st != PYST_OK) return st;
+      if (sort_by_key) return sort_pairs_by_key(ctx, out_keys, out_sums, d_ngroups, out_cap, stream);
+      return PYST_OK;
+    }
     Scratch pairs(ctx, static_cast<size_t>(key->n) * 16 + 256, stream);
     if (!pairs.p) return set_error(PYST_ERR_NOMEM, "pyst_groupby_sum: arena exhausted");
     int64_t *pk = pairs.as<int64_t>(), *pv = pk + key->n, *d_cnt = pv + key->n;

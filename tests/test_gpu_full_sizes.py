@@ -157,6 +157,65 @@ def test_join_materialize_full_size(gpu, ctx, NJK):
     torch.cuda.empty_cache()
 
 
+def test_partitioned_join_full_size(gpu, ctx):
+    # bench.py's join with its partition leg at k = 8, fanout 2: both sides
+    # partitioned, then each destination joined.  Row ids ride along as a ninth
+    # payload column so that the matches can be mapped back to the input.
+    import torch
+    k, F = 8, 2
+    b, p = gen.join_tables(NJB, NJP, k)
+    rid_b = torch.arange(NJB, dtype=torch.int32, device="cuda")
+    rid_p = torch.arange(NJP, dtype=torch.int32, device="cuda")
+    ob = gpu.partition(ctx, dev(b["key"]), [dev(b["c%d" % c]) for c in range(k)] + [rid_b], F)
+    op = gpu.partition(ctx, dev(p["key"]), [dev(p["c%d" % c]) for c in range(k)] + [rid_p], F)
+    ctx.check()
+    offs_b, offs_p = host(ob[2]), host(op[2])
+    # send side: exact counts, every row in its destination, stable (row ids ascend per segment)
+    for keys, offs, n in ((b["key"], offs_b, NJB), (p["key"], offs_p, NJP)):
+        h = keys.astype(np.uint32)
+        h ^= h >> 16
+        h *= np.uint32(0x85EBCA6B)
+        h ^= h >> 13
+        h *= np.uint32(0xC2B2AE35)
+        h ^= h >> 16
+        np.testing.assert_array_equal(np.diff(offs), np.bincount(h % F, minlength=F))
+        assert int(offs[-1]) == n
+    for got, offs in ((ob, offs_b), (op, offs_p)):
+        rid = got[1][k]
+        for q in range(F):
+            seg = rid[int(offs[q]):int(offs[q + 1])]
+            assert bool((seg[1:] > seg[:-1]).all())
+    total, seen = 0, []
+    for q in range(F):
+        b0, b1, p0, p1 = int(offs_b[q]), int(offs_b[q + 1]), int(offs_p[q]), int(offs_p[q + 1])
+        prow, brow, cols, nout = gpu.join_materialize(ctx, ob[0][b0:b1], [c[b0:b1] for c in ob[1][:k]],
+                                                      op[0][p0:p1], [c[p0:p1] for c in op[1][:k]])
+        ctx.check()
+        m = int(nout.item())
+        total += m
+        pr, br = prow[:m].long() + p0, brow[:m].long() + b0
+        assert bool((ob[0][br] == op[0][pr]).all())
+        for c in range(k):
+            assert torch.equal(cols[c][:m], op[1][c][pr])
+            assert torch.equal(cols[k + c][:m], ob[1][c][br])
+        seen.append(op[1][k][pr].cpu().numpy())
+        # sampled matches against the oracle's definition on the original tables
+        t = np.random.default_rng(q).integers(0, m, 50_000)
+        orig_p = op[1][k][pr].cpu().numpy()[t]
+        orig_b = ob[1][k][br].cpu().numpy()[t]
+        np.testing.assert_array_equal(b["key"][orig_b], p["key"][orig_p])
+        for c in range(k):
+            np.testing.assert_array_equal(host(cols[c], m)[t], p["c%d" % c][orig_p])
+            np.testing.assert_array_equal(host(cols[k + c], m)[t], b["c%d" % c][orig_b])
+        del prow, brow, cols, pr, br
+    # unique build keys 1..Nb: exactly the probe rows with key <= Nb match, each once
+    allp = np.sort(np.concatenate(seen))
+    np.testing.assert_array_equal(allp, np.nonzero(p["key"] <= NJB)[0])
+    assert total == len(allp)
+    del ob, op, b, p
+    torch.cuda.empty_cache()
+
+
 NQ18, NQ18_ORDERS = 60_000_000, 15_000_000
 
 

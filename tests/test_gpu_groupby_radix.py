@@ -88,3 +88,25 @@ def test_groupby_radix_errors(gpu, ctx):
     assert int(host(ng)[0]) == n
     got = host(gk)
     assert len(np.unique(got)) == 1000 and got.min() >= 0 and got.max() < n
+
+
+@pytest.mark.parametrize("n,nkeys,sel_every", [(1 << 20, 300_000, 0), (2_000_003, 2**32, 0), (3_000_001, 7, 3),
+                                               (1_200_000, 1, 0), (5_000_000, 4_000_000, 2)])
+def test_groupby_narrow_pairs_match_oracle(gpu, ctx, n, nkeys, sel_every):
+    # int32 keys and values: the radix path moves 8-byte pairs; keys span the
+    # whole int32 range (INT32_MIN included: only the int64 EMPTY key is reserved)
+    rng = np.random.default_rng(n ^ nkeys)
+    if nkeys >= 2**32:
+        k = rng.integers(-2**31, 2**31, n).astype(np.int32)
+        k[:5] = [-2**31, 2**31 - 1, 0, -1, -2**31]
+    else:
+        k = (rng.integers(0, nkeys, n) - nkeys // 2).astype(np.int32)
+    v = rng.integers(-2**31, 2**31, n).astype(np.int32)
+    kw = {}
+    sel = None
+    if sel_every:
+        sel = np.nonzero(rng.integers(0, sel_every, n) == 0)[0].astype(np.int32)
+        kw = {"sel": dev(sel), "nsel": dev(np.array([len(sel)], np.int64))}
+    want = oracle.groupby_sum(k, v, sel)
+    check(run(gpu, ctx, k, v, False, **kw), want)
+    check(run(gpu, ctx, k, v, True, **kw), want)

@@ -174,3 +174,69 @@ def test_join_materialize_capacity_and_duplicate_key(gpu, ctx):
     with pytest.raises(gpu.PystError) as e:
         gpu.join_materialize(ctx, dev(b["key"]), [dev(b["c0"][:10])], dev(p["key"]), [dev(p["c0"])])
     assert e.value.status == gpu.ERR_ARG
+
+
+def _partitioned_join(gpu, ctx, b, p, k, fanout):
+    """Both sides partitioned by key (each carrying its original row ids as a
+    last payload column), then every destination joined and materialized; the
+    matches mapped back to original rows and put in canonical order."""
+    rid_b = dev(np.arange(len(b["key"]), dtype=np.int32))
+    rid_p = dev(np.arange(len(p["key"]), dtype=np.int32))
+    ob = gpu.partition(ctx, dev(b["key"]), [dev(b["c%d" % c]) for c in range(k)] + [rid_b], fanout)
+    op = gpu.partition(ctx, dev(p["key"]), [dev(p["c%d" % c]) for c in range(k)] + [rid_p], fanout)
+    offs_b, offs_p = host(ob[2]), host(op[2])
+    pr_all, br_all, cols_all = [], [], [[] for _ in range(2 * k)]
+    for q in range(fanout):
+        b0, b1, p0, p1 = int(offs_b[q]), int(offs_b[q + 1]), int(offs_p[q]), int(offs_p[q + 1])
+        prow, brow, cols, nout = gpu.join_materialize(ctx, ob[0][b0:b1], [c[b0:b1] for c in ob[1][:k]],
+                                                      op[0][p0:p1], [c[p0:p1] for c in op[1][:k]])
+        ctx.check()
+        m = int(nout.item())
+        pr_all.append(host(op[1][k])[p0:p1][host(prow, m)])
+        br_all.append(host(ob[1][k])[b0:b1][host(brow, m)])
+        for c in range(2 * k):
+            cols_all[c].append(host(cols[c], m))
+    pr, br = np.concatenate(pr_all), np.concatenate(br_all)
+    o = np.argsort(pr, kind="stable")
+    return ob, op, offs_b, offs_p, pr[o], br[o], [np.concatenate(c)[o] for c in cols_all]
+
+
+@pytest.mark.parametrize("nb,np_,k,fanout", [(50_000, 130_001, 8, 2), (20_000, 70_003, 3, 16), (3_000, 5_000, 1, 1),
+                                             (40_000, 90_000, 8, 8)])
+def test_partitioned_join_matches_oracle(gpu, ctx, nb, np_, k, fanout):
+    # the join microbenchmark's whole per-GPU flow: partition + build + probe + materialize
+    b, p = gen.join_tables(nb, np_, k)
+    ob, op, offs_b, offs_p, pr, br, cols = _partitioned_join(gpu, ctx, b, p, k, fanout)
+    # the send side is the oracle's stable partition, counts included
+    for side, tab, got, offs in (("build", b, ob, offs_b), ("probe", p, op, offs_p)):
+        rid = np.arange(len(tab["key"]), dtype=np.int32)
+        wk, wp, woffs = oracle.partition(tab["key"], [tab["c%d" % c] for c in range(k)] + [rid], fanout)
+        np.testing.assert_array_equal(offs, woffs)
+        np.testing.assert_array_equal(host(got[0]), wk)
+        for c in range(k + 1):
+            np.testing.assert_array_equal(host(got[1][c]), wp[c])
+    # the receive side's result equals the oracle's join of the unpartitioned tables
+    wpr, wbr, wcols = oracle.join_materialize(b["key"], [b["c%d" % c] for c in range(k)], p["key"],
+                                              [p["c%d" % c] for c in range(k)])
+    np.testing.assert_array_equal(pr, wpr)
+    np.testing.assert_array_equal(br, wbr)
+    for g, w in zip(cols, wcols):
+        np.testing.assert_array_equal(g, w)
+
+
+def test_partition_carries_fifteen_payload_columns(gpu, ctx):
+    # the most payload columns one call carries (a key and k = 8 columns plus row ids fit easily)
+    rng = np.random.default_rng(15)
+    n = 123_457
+    key = rng.integers(1, 50_000, n).astype(np.int32)
+    pays = mixed_cols(rng, n, 15)
+    ok, op, offs = gpu.partition(ctx, dev(key), [dev(c) for c in pays], 64)
+    ctx.check()
+    wk, wp, woffs = oracle.partition(key, pays, 64)
+    np.testing.assert_array_equal(host(offs), woffs)
+    np.testing.assert_array_equal(host(ok), wk)
+    for g, w in zip(op, wp):
+        np.testing.assert_array_equal(host(g), w)
+    with pytest.raises(gpu.PystError) as e:
+        gpu.partition(ctx, dev(key), [dev(c) for c in pays] + [dev(key)], 64)
+    assert e.value.status == gpu.ERR_ARG
