@@ -475,21 +475,46 @@ __global__ __launch_bounds__(kAggBlock) void k_narrow_move(NarrowArgs a, const u
   }
 }
 
-// Sums every bucket's narrow pairs in an LDS table (slot: low 13 hash bits)
-// and writes its groups, one block per CU walking the buckets as
-// k_bucket_groups does.  *d_ngroups must be zero on entry.
+// Inverse of the narrow hash: fmix32 is a bijection (xor-shifts and odd
+// multipliers), undone step by step with the multipliers' inverses mod 2^32.
+__host__ __device__ constexpr uint32_t inv_odd32(uint32_t c) {
+  uint32_t x = c;  // Newton's iteration for the inverse mod 2^32 (c odd): 3, 6, 12, 24, 48 bits
+  for (int i = 0; i < 5; ++i) x *= 2u - c * x;
+  return x;
+}
+static_assert(0x85ebca6bu * inv_odd32(0x85ebca6bu) == 1u && 0xc2b2ae35u * inv_odd32(0xc2b2ae35u) == 1u, "inverse");
+__device__ __forceinline__ int32_t narrow_unhash(uint32_t h) {
+  h ^= h >> 16;
+  h *= inv_odd32(0xc2b2ae35u);
+  h ^= (h >> 13) ^ (h >> 26);
+  h *= inv_odd32(0x85ebca6bu);
+  h ^= h >> 16;
+  return static_cast<int32_t>(h ^ kNarrowSeed);
+}
+
+// Sums every bucket's narrow pairs in an LDS table and writes its groups, one
+// block per CU walking the buckets as k_bucket_groups does.  The table holds
+// each key's 32-bit hash (slot: its low 13 bits), which identifies the key
+// because the hash is a bijection; every hash of bucket b has b as its top 12
+// bits, so a hash with other top bits marks an empty slot of that bucket.  A
+// slot is read before it is claimed: a key seen before in the bucket costs one
+// LDS read and one add instead of a compare-and-swap and an add.  *d_ngroups
+// must be zero on entry.
+__device__ __forceinline__ uint32_t narrow_empty(int b) { return static_cast<uint32_t>(~b & (kAggBuckets - 1)) << 20; }
+
 __global__ __launch_bounds__(kAggBlock) void k_narrow_groups(const uint64_t *pairs, const int32_t *pos2,
                                                             int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
                                                             int64_t *d_ngroups, uint32_t *err) {
-  __shared__ uint64_t s_key[kAggSlots];
+  __shared__ uint32_t s_h[kAggSlots];
   __shared__ uint64_t s_sum[kAggSlots];
   __shared__ int32_t s_w[kAggBlock / kWave];
   __shared__ int64_t s_base;
-  constexpr int U = 8;
+  constexpr int U = 16;  // a whole bucket (14.6k pairs on average at 60M rows) in one round
   constexpr int PER = kAggSlots / kAggBlock;
   const int tid = static_cast<int>(threadIdx.x);
+  int b = static_cast<int>(blockIdx.x);
   for (int s = tid; s < kAggSlots; s += kAggBlock) {
-    s_key[s] = static_cast<uint64_t>(kEmpty64);
+    s_h[s] = narrow_empty(b);
     s_sum[s] = 0;
   }
   bool full = false;
@@ -503,73 +528,98 @@ __global__ __launch_bounds__(kAggBlock) void k_narrow_groups(const uint64_t *pai
       pp[u] = have[u] ? pairs[i] : 0;
     }
   };
-  auto insert_round = [&]() {
+  // The home slots of all U pairs are read together first; a pair whose key
+  // already sits in its home slot (most of them: keys repeat) is added at once,
+  // the others walk their runs one by one, claiming an empty slot with a CAS.
+  auto insert_round = [&](uint32_t empty) {
+    uint32_t h[U], cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      h[u] = narrow_hash(static_cast<int32_t>(pp[u] >> 32));
+      cur[u] = have[u] ? s_h[h[u] & (kAggSlots - 1)] : 0u;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (!have[u]) continue;
-      const int32_t k32 = static_cast<int32_t>(pp[u] >> 32);
-      const uint64_t key = static_cast<uint64_t>(static_cast<int64_t>(k32));
       const uint64_t val = static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(pp[u] & 0xffffffffu)));
-      uint32_t s = narrow_hash(k32) & (kAggSlots - 1);
+      uint32_t s = h[u] & (kAggSlots - 1);
+      uint32_t c = cur[u];
       for (int probes = 0;; ++probes) {
-        if (probes == kAggSlots) {
-          full = true;
-          break;
-        }
-        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[s]),
-                                       static_cast<unsigned long long>(kEmpty64), static_cast<unsigned long long>(key));
-        if (old == static_cast<uint64_t>(kEmpty64) || old == key) {
+        if (c == empty) c = atomicCAS(&s_h[s], empty, h[u]);
+        if (c == empty || c == h[u]) {
           atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]), static_cast<unsigned long long>(val));
           break;
         }
+        if (probes + 1 == kAggSlots) {
+          full = true;
+          break;
+        }
         s = (s + 1) & (kAggSlots - 1);
+        c = s_h[s];
       }
     }
   };
-  int b = static_cast<int>(blockIdx.x);
   if (b < kAggBuckets) load_round(pos2[int64_t{b} * kNB2] + tid, pos2[int64_t{b + 1} * kNB2]);
   __syncthreads();
   for (; b < kAggBuckets; b += static_cast<int>(gridDim.x)) {  // block-uniform
+    const uint32_t empty = narrow_empty(b);
     const int64_t lo = pos2[int64_t{b} * kNB2], hi = pos2[int64_t{b + 1} * kNB2];
-    insert_round();
+    insert_round(empty);
     for (int64_t i0 = lo + tid + int64_t{kAggBlock} * U; i0 < hi; i0 += int64_t{kAggBlock} * U) {
       load_round(i0, hi);
-      insert_round();
+      insert_round(empty);
     }
     __syncthreads();
+    // Compact the bucket's groups to the front of the table (each thread holds
+    // its PER slots in registers across the barrier), then write them out with
+    // consecutive threads on consecutive positions.
     const int s0 = tid * PER;
+    uint32_t hh[PER];
+    uint64_t ss[PER];
     int c = 0;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) c += s_key[s0 + j] != static_cast<uint64_t>(kEmpty64);
+    for (int j = 0; j < PER; ++j) {
+      hh[j] = s_h[s0 + j];
+      ss[j] = s_sum[s0 + j];
+      c += hh[j] != empty;
+    }
     const int incl = wave_inclusive_scan(c);
     const int w = tid / kWave;
     if (lane_id() == kWave - 1) s_w[w] = incl;
     __syncthreads();
     const int nb = b + static_cast<int>(gridDim.x);
     if (nb < kAggBuckets) load_round(pos2[int64_t{nb} * kNB2] + tid, pos2[int64_t{nb + 1} * kNB2]);
-    if (tid == 0) {
-      int64_t tot = 0;
-      for (int k = 0; k < kAggBlock / kWave; ++k) tot += s_w[k];
+    int tot = 0, q = incl - c;
+    for (int k = 0; k < kAggBlock / kWave; ++k) {
+      tot += s_w[k];
+      if (k < w) q += s_w[k];
+    }
+    if (tid == 0)
       s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
                                                     static_cast<unsigned long long>(tot)))
                    : 0;
-    }
-    __syncthreads();
-    int64_t p = s_base + incl - c;
-    for (int k = 0; k < w; ++k) p += s_w[k];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const uint64_t k = s_key[s0 + j];
-      if (k == static_cast<uint64_t>(kEmpty64)) continue;
-      if (p < out_cap) {
-        out_keys[p] = static_cast<int64_t>(k);
-        out_sums[p] = static_cast<int64_t>(s_sum[s0 + j]);
+    for (int j = 0; j < PER; ++j)
+      if (hh[j] != empty) {
+        s_h[q] = hh[j];
+        s_sum[q] = ss[j];
+        ++q;
+      }
+    __syncthreads();
+    const int64_t base = s_base;
+    for (int i = tid; i < tot; i += kAggBlock) {
+      if (base + i < out_cap) {
+        out_keys[base + i] = narrow_unhash(s_h[i]);
+        out_sums[base + i] = static_cast<int64_t>(s_sum[i]);
       } else {
         latch(err, kErrCapacity);
       }
-      ++p;
-      s_key[s0 + j] = static_cast<uint64_t>(kEmpty64);
-      s_sum[s0 + j] = 0;
+    }
+    __syncthreads();
+    const uint32_t next_empty = narrow_empty(nb);
+    for (int i = tid; i < kAggSlots; i += kAggBlock) {
+      s_h[i] = next_empty;
+      s_sum[i] = 0;
     }
     __syncthreads();
   }

@@ -36,6 +36,7 @@ struct BatFrag {
   int64_t *out_keys, *out_sums;
   int64_t out_cap;
   int64_t *d_ngroups;
+  BucketPool bp;           // staged batches: the fragment's pool of pair chunks (next == nullptr: none)
 };
 
 // Per-kernel block prefixes: blocks of fragment f are [pre[f], pre[f+1]).
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
     t.hdr[0] = cap;
     t.hdr[1] = s_total;
     *fr.d_ngroups = 0;
+    if (fr.bp.next) *fr.bp.next = 0;
   }
   int32_t *keys = static_cast<int32_t *>(t.slots);
   const int64_t words = bloom_words(cap);
@@ -184,6 +186,66 @@ __global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int
                               int64_t{BS} * 4, end, nullptr, nullptr);
 }
 
+// The staged fact pass of a batch (blocks of kFastBlock threads): as the
+// single star query's pass, every work unit stages its matching (slot, value)
+// pairs in LDS and moves them bucket by bucket into its fragment's chunk pool,
+// instead of one global atomic per matching row; k_bat_sums then adds each
+// fragment's buckets up.
+template <bool V64>
+__global__ __launch_bounds__(kFastBlock) void k_bat_fact_staged(const BatFrag *frags, const int64_t *pre, int nfrag,
+                                                                uint32_t *err) {
+  PYST_BLOCK_FRAG(kPreFact)
+  (void)nloc;
+  __shared__ uint32_t s_bloom[kBloomWords];
+  __shared__ uint64_t s_ent[kStageCap];
+  __shared__ uint32_t s_bk[5 * kMaxBuckets + 1];
+  StageLds sl;
+  sl.ent = (PYST_LDS uint64_t *)s_ent;
+  sl.chunk = (PYST_LDS uint32_t *)s_bk;
+  sl.fill = sl.chunk + kMaxBuckets;
+  sl.hist = sl.fill + kMaxBuckets;
+  sl.rank = sl.hist + kMaxBuckets;
+  sl.newbase = sl.rank + kMaxBuckets;
+  sl.cnt = sl.newbase + kMaxBuckets;
+  const BucketPool &bp = fr.bp;
+  const uint32_t nb = bucket_count(fr.t.hdr[0]);
+  if (nb <= bp.stride && threadIdx.x < bp.stride) {  // the unit's first chunks, one per bucket
+    const uint32_t c = static_cast<uint32_t>(local) * bp.stride + threadIdx.x;
+    bp.bucket[c] = threadIdx.x < nb ? threadIdx.x : kNoChunk;
+    bp.fill[c] = 0;
+    if (threadIdx.x < nb) {
+      sl.chunk[threadIdx.x] = c;
+      sl.fill[threadIdx.x] = 0;
+      sl.hist[threadIdx.x] = 0;
+    }
+  }
+  if (threadIdx.x == 0) *sl.cnt = 0;
+  const bool use_bloom = fr.t.hdr[1] <= kBloomMaxKeys;
+  if (use_bloom) {
+    const int64_t words = bloom_words(fr.t.hdr[0]);
+    for (int64_t i = threadIdx.x; i < words; i += kFastBlock) s_bloom[i] = gmem(fr.t.bloom)[i];
+  }
+  __syncthreads();
+  const int64_t begin = local * fr.rows_per_unit;
+  const int64_t end = begin + fr.rows_per_unit < fr.fa.n ? begin + fr.rows_per_unit : fr.fa.n;
+  star_range<3, V64, true, 4>(fr.fa, fr.t, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
+                              int64_t{kFastBlock} * 4, end, &bp, &sl);
+}
+
+// Bucket b of a staged fragment per block: its pairs and direct sums added
+// up in LDS and its groups written out.
+__global__ __launch_bounds__(kFastBlock) void k_bat_sums(const BatFrag *frags, const int64_t *pre, int nfrag,
+                                                         uint32_t *err) {
+  PYST_BLOCK_FRAG(kPreCompact)
+  (void)nloc;
+  __shared__ uint64_t s_sum[kBucketSlots];
+  __shared__ uint32_t s_bits[kBucketSlots / 32];
+  __shared__ uint32_t s_wsum[kFastBlock / kWave];
+  __shared__ int64_t s_base;
+  bucket_sums_block(fr.t, fr.bp, static_cast<uint32_t>(local), fr.out_keys, fr.out_sums, fr.out_cap, fr.d_ngroups,
+                    err, s_sum, s_bits, s_wsum, &s_base);
+}
+
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
   PYST_BLOCK_FRAG(kPreCompact)
   // whole tiles per block, one counter atomic per tile
@@ -246,8 +308,16 @@ __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const
 struct BatchPlan {
   std::vector<BatFrag> frags;
   std::vector<int64_t> pre;  // kPreKinds * (nfrag + 1)
-  size_t table_bytes_total = 0, sel_bytes_total = 0;
+  size_t table_bytes_total = 0, sel_bytes_total = 0, pool_bytes_total = 0;
+  std::vector<int64_t> pool_chunks;  // staged: chunks of each fragment's pool
+  bool staged = false;
 };
+
+// A staged batch gives each fragment a pool of pair chunks: every work unit's
+// first chunk per bucket, plus shared chunks for a quarter of its fact rows
+// (a fragment whose matching rows outgrow that adds the rest directly).
+constexpr int64_t kBatchPoolRowShare = 8;
+constexpr uint32_t kBatchChunkLg = 7;  // 128-pair chunks: a partly filled chunk per unit and bucket wastes less
 
 static bool batch_shape(const pyst_fragment &fg, QueryShape *q, FastArgs *fa) {
   if (prepare_query(fg.plan, fg.fact, fg.nfact, q) != PYST_OK) return false;
@@ -255,10 +325,20 @@ static bool batch_shape(const pyst_fragment &fg, QueryShape *q, FastArgs *fa) {
   return fast_shape(fg.plan, fg.fact, *q, fa);
 }
 
-static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu, BatchPlan *bp) {
+static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu, bool allow_staged,
+                                BatchPlan *bp) {
   bp->frags.resize(nfrag);
   bp->pre.assign(static_cast<size_t>(kPreKinds) * (nfrag + 1), 0);
   const int64_t cus = ctx_num_cus(ctx);
+  // Staged pair sums need kFastBlock-thread fact blocks and tables of at most
+  // kMaxSumBuckets buckets (decided for the whole batch).
+  bp->staged = allow_staged && tu.block == kFastBlock;
+  for (int f = 0; f < nfrag && bp->staged; ++f)
+    if (fr[f].plan && fr[f].plan->njoins >= 1)
+      bp->staged = table_capacity_host(fr[f].plan->joins[0].key.n,
+                                       tu.max_load > 0 ? tu.max_load : fr[f].plan->joins[0].max_load) <=
+                   kBucketSlots * kMaxSumBuckets;
+  bp->pool_chunks.assign(nfrag, 0);
   for (int f = 0; f < nfrag; ++f) {
     QueryShape q;
     FastArgs fa;
@@ -293,13 +373,28 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
     bp->table_bytes_total += (table_bytes(cap_alloc, 4, true) + 255) / 256 * 256 +
                              (static_cast<size_t>(bloom_words(cap_alloc)) * 4 + 255) / 256 * 256;
     bp->sel_bytes_total += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
+    const int64_t fact_units = ceil_div(std::max<int64_t>(fa.n, 1), b.rows_per_unit);
     const int64_t blocks[kPreKinds] = {
         b.nblk,
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus)),
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(b.nb, 256), 16 * cus)),
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(bloom_words(cap_alloc), 256), 4 * cus)),
-        ceil_div(std::max<int64_t>(fa.n, 1), b.rows_per_unit),
-        std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus))};
+        fact_units,
+        bp->staged ? static_cast<int64_t>(bucket_count(cap_alloc))
+                   : std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus))};
+    if (bp->staged) {
+      const int64_t stride = std::min<int64_t>(kMaxBuckets, bucket_count(cap_alloc));
+      const int64_t nchunks =
+          fact_units * stride + ceil_div(ceil_div(fa.n, kBatchPoolRowShare), int64_t{1} << kBatchChunkLg) + 1;
+      if (nchunks >= (int64_t{1} << 31)) return set_error(PYST_ERR_UNSUPPORTED, "pyst_query_batch: fragment too large");
+      bp->pool_chunks[f] = nchunks;
+      b.bp.nchunks = static_cast<uint32_t>(nchunks);
+      b.bp.chunk_lg = kBatchChunkLg;
+      b.bp.blocks = static_cast<uint32_t>(fact_units);
+      b.bp.stride = static_cast<uint32_t>(stride);
+      bp->pool_bytes_total +=
+          256 + (static_cast<size_t>(nchunks) * ((size_t{8} << kBatchChunkLg) + 8) + 255) / 256 * 256;
+    }
     for (int k = 0; k < kPreKinds; ++k) bp->pre[k * (nfrag + 1) + f + 1] = bp->pre[k * (nfrag + 1) + f] + blocks[k];
   }
   return PYST_OK;
@@ -314,6 +409,7 @@ struct BatchRun {
   unsigned grid[kPreKinds] = {};
   int nfrag = 0, block = 0;
   bool v64 = false;
+  bool staged = false;  // staged pair sums (k_bat_fact_staged + k_bat_sums) instead of atomics + compaction
 };
 
 // Lays the fragments out, allocates their device memory and uploads the
@@ -321,7 +417,7 @@ struct BatchRun {
 static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfrag, const pyst_tuning &tu,
                                  hipStream_t stream, BatchRun *run) {
   BatchPlan bp;
-  pyst_status st = batch_layout(ctx, fr, nfrag, tu, &bp);
+  pyst_status st = batch_layout(ctx, fr, nfrag, tu, true, &bp);
   if (st != PYST_OK) return st;
   const bool v64 = bp.frags[0].fa.v0_64 != 0;
   for (int f = 1; f < nfrag; ++f)
@@ -330,7 +426,13 @@ static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfr
   const size_t desc_bytes = sizeof(BatFrag) * nfrag;
   const size_t pre_bytes = sizeof(int64_t) * bp.pre.size();
   const size_t meta = (desc_bytes + 255) / 256 * 256 + (pre_bytes + 255) / 256 * 256;
-  char *mem = static_cast<char *>(ctx_alloc(ctx, meta + bp.table_bytes_total + bp.sel_bytes_total, stream));
+  char *mem = static_cast<char *>(
+      ctx_alloc(ctx, meta + bp.table_bytes_total + bp.sel_bytes_total + bp.pool_bytes_total, stream));
+  if (!mem && bp.staged) {  // no room for the pair pools: per-row atomics instead
+    bp = BatchPlan();
+    if ((st = batch_layout(ctx, fr, nfrag, tu, false, &bp)) != PYST_OK) return st;
+    mem = static_cast<char *>(ctx_alloc(ctx, meta + bp.table_bytes_total + bp.sel_bytes_total, stream));
+  }
   if (!mem) return set_error(PYST_ERR_NOMEM, "pyst_query_batch: arena cannot hold the batch");
   char *p = mem + meta;
   for (int f = 0; f < nfrag; ++f) {
@@ -345,6 +447,15 @@ static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfr
     b.cnt = reinterpret_cast<int32_t *>(p);
     b.sel = b.cnt + (b.nblk + 63) / 64 * 64;
     p += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
+  }
+  for (int f = 0; f < nfrag && bp.staged; ++f) {  // pools: next counter, records, chunk tags, fills
+    BatFrag &b = bp.frags[f];
+    const size_t nchunks = static_cast<size_t>(bp.pool_chunks[f]);
+    b.bp.next = reinterpret_cast<uint32_t *>(p);
+    b.bp.rec = reinterpret_cast<uint64_t *>(p + 256);
+    b.bp.bucket = reinterpret_cast<uint32_t *>(b.bp.rec + (nchunks << kBatchChunkLg));
+    b.bp.fill = b.bp.bucket + nchunks;
+    p += 256 + (nchunks * ((size_t{8} << kBatchChunkLg) + 8) + 255) / 256 * 256;
   }
   // Descriptors go up through pinned staging (a pageable copy would stall other streams).
   char *stage = ctx_pinned_staging(ctx, meta);
@@ -367,6 +478,7 @@ static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfr
   run->nfrag = nfrag;
   run->block = tu.block;
   run->v64 = v64;
+  run->staged = bp.staged;
   return PYST_OK;
 }
 
@@ -383,6 +495,12 @@ static hipError_t batch_enqueue(const BatchRun &r, uint32_t *err, hipStream_t st
   if (r.block == BS_) {                                                                                       \
     if (r.v64) k_bat_fact<BS_, true><<<r.grid[kPreFact], BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);        \
     else k_bat_fact<BS_, false><<<r.grid[kPreFact], BS_, 0, stream>>>(d_frags, d_pre, nfrag, err);             \
+  }
+  if (r.staged) {
+    if (r.v64) k_bat_fact_staged<true><<<r.grid[kPreFact], kFastBlock, 0, stream>>>(d_frags, d_pre, nfrag, err);
+    else k_bat_fact_staged<false><<<r.grid[kPreFact], kFastBlock, 0, stream>>>(d_frags, d_pre, nfrag, err);
+    k_bat_sums<<<r.grid[kPreCompact], kFastBlock, 0, stream>>>(d_frags, d_pre, nfrag, err);
+    return hipGetLastError();
   }
   PYST_BAT_FACT(256)
   PYST_BAT_FACT(512)

@@ -55,7 +55,8 @@ constexpr uint32_t kFlushAt = 1024;                         // staged pairs that
 constexpr uint32_t kCheckMax = 8;                           // most steps between the block's staging checks
 constexpr int kStageSlotBits = 20;                          // slot bits of a staged pair: kMaxBuckets buckets
 constexpr int kStarRows = 4;                                // rows per lane and step of the staged fact pass
-constexpr uint32_t kChunk = 512;                            // pairs per chunk
+constexpr uint32_t kChunkLg = 9;                            // pairs per chunk of the single query: 512
+constexpr uint32_t kChunk = 1u << kChunkLg;
 constexpr uint32_t kNoChunk = 0xffffffffu;
 
 static_assert((int64_t{kMaxBuckets} << kBucketLg) == (int64_t{1} << kStageSlotBits), "staged slot bits");
@@ -70,7 +71,7 @@ __device__ __forceinline__ bool fits_stage(int64_t v) {
 }
 
 struct BucketPool {
-  uint64_t *rec;     // pair e of chunk c at [c * kChunk + e]: value << kBucketLg | slot within the bucket
+  uint64_t *rec;     // pair e of chunk c at [c * chunk + e]: value << kBucketLg | slot within the bucket
   uint32_t *bucket;  // bucket of each chunk
   uint32_t *fill;    // pairs in each chunk
   uint32_t *next;    // chunks handed out beyond the blocks' first ones (zeroed with the table)
@@ -78,6 +79,7 @@ struct BucketPool {
   uint32_t blocks;   // fact-pass blocks; block k starts with chunks [k * stride, k * stride + nb)
   uint32_t stride;   // buckets a block's first chunks are reserved for; a table with more
                      // buckets than this (its size is only known on the device) is not staged
+  uint32_t chunk_lg; // log2 of the pairs per chunk
 };
 
 __host__ __device__ inline uint32_t bucket_count(int64_t cap) {
@@ -416,9 +418,13 @@ struct StageLds {
 };
 
 // Moves the staged pairs into the block's chunks, bucket by bucket.  Every
-// thread of the block calls it; it leaves the staging area empty.
-__device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool &bp, uint32_t nb, uint32_t *err) {
+// thread of the block calls it; it leaves the staging area empty.  Pairs that
+// find the pool used up are added straight into the table's slot sums (the
+// second kernel merges those in), so a pool smaller than the worst case only
+// costs atomics.
+__device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool &bp, const TableDev &t, uint32_t nb) {
   const uint32_t tid = threadIdx.x;
+  const uint32_t CH = 1u << bp.chunk_lg;
   const uint32_t n = *sl.cnt < kStageCap ? *sl.cnt : kStageCap;
   constexpr uint64_t slot_mask = (uint64_t{1} << kStageSlotBits) - 1;
   for (uint32_t i = tid; i < n; i += kFastBlock)
@@ -426,18 +432,18 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
   __syncthreads();
   if (tid < nb) {
     const uint32_t t = sl.fill[tid] + sl.hist[tid];
-    const uint32_t k = t > kChunk ? (t - 1) / kChunk : 0;  // chunks to add once the current one is full
+    const uint32_t k = t > CH ? (t - 1) >> bp.chunk_lg : 0;  // chunks to add once the current one is full
     uint32_t first = 0;
     if (k) {
       first = bp.blocks * bp.stride + atomicAdd(bp.next, k);
-      if (first + k > bp.nchunks) {
-        latch(err, kErrTableFull);
+      if (first + k > bp.nchunks) {  // chunks of this range that do exist are marked unused
+        for (uint32_t j = first; j < bp.nchunks; ++j) bp.bucket[j] = kNoChunk;
         first = kNoChunk;
       } else {
-        bp.fill[sl.chunk[tid]] = kChunk;
+        bp.fill[sl.chunk[tid]] = CH;
         for (uint32_t j = 0; j < k; ++j) {
           bp.bucket[first + j] = tid;
-          if (j + 1 < k) bp.fill[first + j] = kChunk;
+          if (j + 1 < k) bp.fill[first + j] = CH;
         }
       }
     }
@@ -449,21 +455,26 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
     const uint64_t en = sl.ent[i];
     const uint32_t s = static_cast<uint32_t>(en & slot_mask), b = s >> kBucketLg;
     const uint32_t pos = sl.fill[b] + lds_add(&sl.rank[b], 1u);
-    if (pos >= kChunk && sl.newbase[b] == kNoChunk) continue;  // pool exhausted (error latched)
-    const uint32_t c = pos < kChunk ? sl.chunk[b] : sl.newbase[b] + pos / kChunk - 1;
-    const size_t e = size_t{c} * kChunk + pos % kChunk;
+    if (pos >= CH && sl.newbase[b] == kNoChunk) {  // pool used up: add directly
+      atomicAdd(reinterpret_cast<unsigned long long *>(&t.sums[s]),
+                static_cast<unsigned long long>(static_cast<int64_t>(en) >> kStageSlotBits));
+      t.flags[s] = 1;
+      continue;
+    }
+    const uint32_t c = pos < CH ? sl.chunk[b] : sl.newbase[b] + (pos >> bp.chunk_lg) - 1;
+    const size_t e = (size_t{c} << bp.chunk_lg) + (pos & (CH - 1));
     bp.rec[e] = static_cast<uint64_t>((static_cast<int64_t>(en) >> kStageSlotBits) << kBucketLg) |
                 (s & (kBucketSlots - 1));
   }
   __syncthreads();
   if (tid < nb) {
     const uint32_t t = sl.fill[tid] + sl.hist[tid];
-    if (t > kChunk && sl.newbase[tid] != kNoChunk) {
-      const uint32_t k = (t - 1) / kChunk;
+    if (t > CH && sl.newbase[tid] != kNoChunk) {
+      const uint32_t k = (t - 1) >> bp.chunk_lg;
       sl.chunk[tid] = sl.newbase[tid] + k - 1;
-      sl.fill[tid] = t - k * kChunk;
+      sl.fill[tid] = t - (k << bp.chunk_lg);
     } else {
-      sl.fill[tid] = t < kChunk ? t : kChunk;
+      sl.fill[tid] = t < CH ? t : CH;
     }
     sl.hist[tid] = 0;
   }
@@ -939,7 +950,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
       const uint32_t fit = kStageCap / (c / since + 1);
       every = fit < 1 ? 1 : fit > kCheckMax ? kCheckMax : fit;
       since = 0;
-      if (c >= kFlushAt) stage_flush(*sl, *bp, nb, err);
+      if (c >= kFlushAt) stage_flush(*sl, *bp, t0, nb);
     }
     cur = nxt;
   }
@@ -952,7 +963,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
   }
   if (AGG == 3 && stage_cap > 0) {
     __syncthreads();
-    if (*sl->cnt > 0) stage_flush(*sl, *bp, nb, err);  // block-uniform
+    if (*sl->cnt > 0) stage_flush(*sl, *bp, t0, nb);  // block-uniform
     if (threadIdx.x < nb) bp->fill[sl->chunk[threadIdx.x]] = sl->fill[threadIdx.x];
   }
 }
@@ -1237,7 +1248,7 @@ __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t 
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     f[i] = c[i] != kNoChunk ? bp.fill[c[i]] : 0;
-    base[i] = size_t{c[i] != kNoChunk ? c[i] : 0} * kChunk;
+    base[i] = size_t{c[i] != kNoChunk ? c[i] : 0} << bp.chunk_lg;
     fmax = f[i] > fmax ? f[i] : fmax;
   }
   for (uint32_t e0 = 0; e0 < fmax; e0 += U * kWave) {  // wave-uniform
@@ -1262,17 +1273,16 @@ __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t 
 
 // Second kernel of the bucketed slot sums: block b adds up the pairs of bucket
 // b in LDS, adds the sums the fact pass made directly, and writes the groups
-// present with one counter atomic.  *d_ngroups must be zero on entry.
-__global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPool bp, int64_t *out_keys,
-                                                           int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
-                                                           uint32_t *err) {
-  __shared__ uint64_t s_sum[kBucketSlots];
-  __shared__ uint32_t s_bits[kBucketSlots / 32];
-  __shared__ uint32_t s_wsum[kFastBlock / kWave];
-  __shared__ int64_t s_base;
+// present with one counter atomic.  *d_ngroups must be zero on entry.  The LDS
+// arrays come from the calling kernel (s_sum: kBucketSlots, s_bits:
+// kBucketSlots / 32, s_wsum: kFastBlock / kWave, s_base: 1); blockDim.x is
+// kFastBlock.
+__device__ __forceinline__ void bucket_sums_block(const TableDev &t, const BucketPool &bp, uint32_t b,
+                                                  int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
+                                                  int64_t *d_ngroups, uint32_t *err, uint64_t *s_sum,
+                                                  uint32_t *s_bits, uint32_t *s_wsum, int64_t *s_base) {
   const int64_t cap = t.hdr[0];
   const uint32_t nb = bucket_count(cap);
-  const uint32_t b = blockIdx.x;
   if (b >= nb) return;  // block-uniform
   const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
   const int64_t lo = int64_t{b} << kBucketLg;
@@ -1325,12 +1335,12 @@ __global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPo
   if (tid == 0) {
     uint32_t tot = 0;
     for (int k = 0; k < kFastBlock / kWave; ++k) tot += s_wsum[k];
-    s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
-                                                  static_cast<unsigned long long>(tot)))
-                 : 0;
+    *s_base = tot ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long *>(d_ngroups),
+                                                   static_cast<unsigned long long>(tot)))
+                  : 0;
   }
   __syncthreads();
-  int64_t pos = s_base + incl - c;
+  int64_t pos = *s_base + incl - c;
   for (uint32_t k = 0; k < wv; ++k) pos += s_wsum[k];
   const int32_t *keys = static_cast<const int32_t *>(t.slots);
   while (m) {
@@ -1345,6 +1355,17 @@ __global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPo
     ++pos;
   }
 }
+
+__global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPool bp, int64_t *out_keys,
+                                                           int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
+                                                           uint32_t *err) {
+  __shared__ uint64_t s_sum[kBucketSlots];
+  __shared__ uint32_t s_bits[kBucketSlots / 32];
+  __shared__ uint32_t s_wsum[kFastBlock / kWave];
+  __shared__ int64_t s_base;
+  bucket_sums_block(t, bp, blockIdx.x, out_keys, out_sums, out_cap, d_ngroups, err, s_sum, s_bits, s_wsum, &s_base);
+}
+
 // Unordered compaction of groups (slot sums or a group table): one counter
 // atomic per wave; *d_ngroups must be zero on entry.
 template <bool SLOTS>
@@ -1555,6 +1576,7 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
       bp.bucket = reinterpret_cast<uint32_t *>(bp.rec + static_cast<size_t>(nchunks) * kChunk);
       bp.fill = bp.bucket + nchunks;
       bp.nchunks = static_cast<uint32_t>(nchunks);
+      bp.chunk_lg = kChunkLg;
       bp.blocks = static_cast<uint32_t>(grid);
       bp.stride = static_cast<uint32_t>(stride);
     }
