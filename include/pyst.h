@@ -36,7 +36,10 @@
  *   on the order in which the device adds them.
  * - A context is not thread-safe; use one per host thread.  Its arena
  *   allocations are stream ordered: memory freed by work on one stream is
- *   reused by another stream only after that work has completed.
+ *   reused by another stream only after that work has completed.  The context
+ *   marks that point with an event on the freeing stream only when another
+ *   stream needs the memory, so a stream used with a context must stay valid
+ *   until pyst_ctx_check(ctx, that stream) returns or the context is destroyed.
  */
 #ifndef PYST_H
 #define PYST_H

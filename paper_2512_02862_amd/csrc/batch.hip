@@ -126,35 +126,11 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
   }
 }
 
+// One dimension tile of one fragment per block (as k_fast_build).
 __global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
   PYST_BLOCK_FRAG(kPreBuild)
-  const TableDev &t = fr.t;
-  const int64_t mask = t.hdr[0] - 1;
-  int32_t *keys = static_cast<int32_t *>(t.slots);
-  for (int64_t i = local * 256 + threadIdx.x; i < fr.nb; i += nloc * 256) {
-    if ((i % kDimTile) >= fr.cnt[i / kDimTile]) continue;
-    const int32_t k = fr.bkey[fr.sel[i]];
-    if (k == kEmpty32) {
-      latch(err, kErrKey);
-      continue;
-    }
-    int64_t s = (table_hash32(k) & mask) & ~int64_t{3};
-    bool done = false;
-    for (int64_t step = 0; step <= mask; ++step) {
-      const int32_t cur = atomicCAS(&keys[s], kEmpty32, k);  // fresh table: CAS first
-      if (cur == kEmpty32) {
-        done = true;
-        break;
-      }
-      if (cur == k) {
-        latch(err, kErrDup);
-        done = true;
-        break;
-      }
-      s = (s + 1) & mask;
-    }
-    if (!done) latch(err, kErrTableFull);
-  }
+  (void)nloc;
+  build_tile<4>(fr.bkey, nullptr, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
 }
 
 // Each fragment's Bloom filter, from its finished table (words past the ones
@@ -377,7 +353,7 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
     const int64_t blocks[kPreKinds] = {
         b.nblk,
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(cap_alloc, 256 * 8), 4 * cus)),
-        std::max<int64_t>(1, std::min<int64_t>(ceil_div(b.nb, 256), 16 * cus)),
+        b.nb > 0 ? b.nblk : 0,  // build: one block per dimension tile
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(bloom_words(cap_alloc), 256), 4 * cus)),
         fact_units,
         bp->staged ? static_cast<int64_t>(bucket_count(cap_alloc))
@@ -489,7 +465,7 @@ static hipError_t batch_enqueue(const BatchRun &r, uint32_t *err, hipStream_t st
   const int nfrag = r.nfrag;
   k_bat_filter<<<r.grid[kPreFilter], 256, 0, stream>>>(d_frags, d_pre, nfrag);
   k_bat_init<<<r.grid[kPreInit], 256, 0, stream>>>(d_frags, d_pre, nfrag);
-  k_bat_build<<<r.grid[kPreBuild], 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
+  if (r.grid[kPreBuild] > 0) k_bat_build<<<r.grid[kPreBuild], 256, 0, stream>>>(d_frags, d_pre, nfrag, err);
   k_bat_bloom<<<r.grid[kPreBloom], 256, 0, stream>>>(d_frags, d_pre, nfrag);
 #define PYST_BAT_FACT(BS_)                                                                                      \
   if (r.block == BS_) {                                                                                       \
@@ -627,7 +603,7 @@ pyst_status pyst_batch_graph_destroy(pyst_batch_graph *g) {
   const hipError_t e = hipDeviceSynchronize();  // no launch of the graph may still run
   (void)hipGraphExecDestroy(g->exec);
   (void)hipGraphDestroy(g->graph);
-  ctx_free(g->ctx, g->mem, nullptr);
+  ctx_free_eager(g->ctx, g->mem, nullptr);
   delete g;
   return e == hipSuccess ? PYST_OK : hip_error(e, "pyst_batch_graph_destroy");
 }
@@ -665,6 +641,7 @@ pyst_status pyst_autotune(pyst_ctx *ctx, const pyst_fragment *frags, int nfrag, 
         }
       }
   (void)hipStreamSynchronize(s);
+  ctx_stream_idle(ctx, s);  // before the private stream goes away
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   (void)hipStreamDestroy(s);

@@ -7,10 +7,15 @@
 // and the hard budget is what admission control and backpressure account
 // against (Sec. 5.4, "Adaptive Regulation").
 //
-// Frees are stream ordered: a freed block carries an event recorded on the
-// freeing stream and is reused by another stream only after that event has
-// completed; the same stream may reuse it at once, because its later work is
-// ordered after the earlier work.
+// Frees are stream ordered: a freed block stays pending on the freeing stream.
+// That stream may reuse it at once (its later work is ordered after the
+// earlier work), and an allocation on a stream first takes back the smallest
+// block that stream freed; no event is recorded for this, since each event
+// record is a packet of its own in the stream (a query that freed three blocks
+// ran 20 us slower per call for them).  Only when another stream needs the
+// memory is one event recorded per stream that holds pending blocks; those
+// blocks return to the shared free list once it has completed.
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -34,7 +39,7 @@ struct pyst_ctx {
   struct Pending {
     size_t off, size;
     hipStream_t stream;
-    hipEvent_t ev;
+    hipEvent_t ev;  // nullptr until another stream needs the memory
   };
   std::deque<Pending> pending;
   std::vector<hipEvent_t> events;
@@ -82,16 +87,54 @@ void insert_free(pyst_ctx *c, size_t off, size_t size) {
   }
 }
 
+// Pending blocks whose event has completed go back to the free list; an event
+// shared by several blocks returns to the event pool with the last of them.
 void reap(pyst_ctx *c) {
+  std::vector<hipEvent_t> done;
   for (auto it = c->pending.begin(); it != c->pending.end();) {
-    if (hipEventQuery(it->ev) == hipSuccess) {
+    if (it->ev && (std::find(done.begin(), done.end(), it->ev) != done.end() || hipEventQuery(it->ev) == hipSuccess)) {
+      if (std::find(done.begin(), done.end(), it->ev) == done.end()) done.push_back(it->ev);
       insert_free(c, it->off, it->size);
-      c->events.push_back(it->ev);
       it = c->pending.erase(it);
     } else {
       ++it;
     }
   }
+  for (hipEvent_t e : done) {
+    bool used = false;
+    for (const auto &p : c->pending) used = used || p.ev == e;
+    if (!used) c->events.push_back(e);
+  }
+}
+
+// Every pending block back to the free list (the device is idle).
+void release_all_pending(pyst_ctx *c) {
+  std::vector<hipEvent_t> evs;
+  for (const auto &p : c->pending) {
+    insert_free(c, p.off, p.size);
+    if (p.ev && std::find(evs.begin(), evs.end(), p.ev) == evs.end()) evs.push_back(p.ev);
+  }
+  c->pending.clear();
+  for (hipEvent_t e : evs) c->events.push_back(e);
+}
+
+// Record one event on every stream that holds pending blocks without one.
+// Returns false when an event could not be recorded (the caller then waits
+// for the device instead).
+bool mark_pending(pyst_ctx *c) {
+  bool ok = true;
+  for (auto &p : c->pending) {
+    if (p.ev) continue;
+    hipEvent_t e = take_event(c);
+    if (!e || hipEventRecord(e, p.stream) != hipSuccess) {
+      if (e) c->events.push_back(e);
+      ok = false;
+      continue;
+    }
+    for (auto &q : c->pending)
+      if (!q.ev && q.stream == p.stream) q.ev = e;
+  }
+  return ok;
 }
 
 bool take_first_fit(pyst_ctx *c, size_t bytes, size_t *off) {
@@ -125,23 +168,35 @@ void *ctx_alloc(pyst_ctx *c, size_t bytes, hipStream_t stream) {
   size_t off = 0;
   while (true) {
     reap(c);
-    if (take_first_fit(c, bytes, &off)) break;
-    // Same-stream reuse of a pending block is safe without waiting.
-    bool got = false;
-    for (auto it = c->pending.begin(); it != c->pending.end(); ++it) {
-      if (it->stream == stream && it->size >= bytes) {
-        off = it->off;
-        c->live[off] = it->size;
-        c->events.push_back(it->ev);
-        bytes = it->size;
-        c->pending.erase(it);
-        got = true;
-        break;
+    // The smallest block this stream freed that fits: no wait, no event.
+    auto best = c->pending.end();
+    for (auto it = c->pending.begin(); it != c->pending.end(); ++it)
+      if (it->stream == stream && it->size >= bytes && (best == c->pending.end() || it->size < best->size)) best = it;
+    if (best != c->pending.end()) {  // the front part; the rest stays pending on the stream
+      off = best->off;
+      c->live[off] = bytes;
+      if (best->size > bytes) {
+        best->off += bytes;
+        best->size -= bytes;
+      } else {
+        const hipEvent_t e = best->ev;
+        c->pending.erase(best);
+        if (e) {
+          bool used = false;
+          for (const auto &p : c->pending) used = used || p.ev == e;
+          if (!used) c->events.push_back(e);
+        }
       }
+      break;
     }
-    if (got) break;
+    if (take_first_fit(c, bytes, &off)) break;
     if (c->pending.empty()) return nullptr;
-    // Backpressure: wait for the oldest outstanding free, then retry.
+    // Backpressure: give every pending block an event, wait for the oldest, retry.
+    if (!mark_pending(c)) {  // an event could not be recorded: wait for the whole device
+      (void)hipDeviceSynchronize();
+      release_all_pending(c);
+      continue;
+    }
     (void)hipEventSynchronize(c->pending.front().ev);
   }
   c->used += c->live[off];
@@ -156,13 +211,32 @@ void ctx_free(pyst_ctx *c, void *p, hipStream_t stream) {
   const size_t size = it->second;
   c->live.erase(it);
   c->used -= size;
+  c->pending.push_back({off, size, stream, nullptr});
+}
+
+void ctx_free_eager(pyst_ctx *c, void *p, hipStream_t stream) {
+  if (!p) return;
+  ctx_free(c, p, stream);
   hipEvent_t ev = take_event(c);
   if (ev && hipEventRecord(ev, stream) == hipSuccess) {
-    c->pending.push_back({off, size, stream, ev});
+    c->pending.back().ev = ev;
   } else {
     if (ev) c->events.push_back(ev);
     (void)hipStreamSynchronize(stream);
-    insert_free(c, off, size);
+    const auto blk = c->pending.back();
+    c->pending.pop_back();
+    insert_free(c, blk.off, blk.size);
+  }
+}
+
+void ctx_stream_idle(pyst_ctx *c, hipStream_t stream) {
+  for (auto it = c->pending.begin(); it != c->pending.end();) {
+    if (it->stream == stream && !it->ev) {
+      insert_free(c, it->off, it->size);
+      it = c->pending.erase(it);
+    } else {
+      ++it;
+    }
   }
 }
 
@@ -282,7 +356,12 @@ void pyst_ctx_destroy(pyst_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (auto &p : c->pending) (void)hipEventDestroy(p.ev);
+  {
+    std::vector<hipEvent_t> evs;
+    for (auto &p : c->pending)
+      if (p.ev && std::find(evs.begin(), evs.end(), p.ev) == evs.end()) evs.push_back(p.ev);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
   for (auto e : c->events) (void)hipEventDestroy(e);
   for (auto &kv : c->timed)
     for (auto &pr : kv.second) {
@@ -341,6 +420,7 @@ pyst_status pyst_ctx_check(pyst_ctx *c, hipStream_t stream) {
   hipError_t e = hipMemcpyAsync(c->h_err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(error word)");
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  ctx_stream_idle(c, stream);  // what was freed on it is free for every stream now
   const uint32_t bits = *c->h_err;
   if (bits == 0) return PYST_OK;
   pyst_status st = fill_u32(c->d_err, 1, 0u, stream);

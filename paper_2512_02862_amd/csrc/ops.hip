@@ -1433,7 +1433,7 @@ void pyst_table_destroy(pyst_table *table, hipStream_t stream) {
   if (!table) return;
   (void)hipStreamSynchronize(stream);
   if (table->stream && table->stream != stream) (void)hipStreamSynchronize(table->stream);
-  ctx_free(table->ctx, table->mem, stream);
+  ctx_free_eager(table->ctx, table->mem, stream);  // the caller's stream may go away after this
   delete table;
 }
 

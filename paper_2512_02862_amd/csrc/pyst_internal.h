@@ -199,7 +199,15 @@ struct CtxImpl;  // defined in ctx.cpp
 
 // Stream-ordered sub-allocation from the context arena (see ctx.cpp).
 void *ctx_alloc(pyst_ctx *ctx, size_t bytes, hipStream_t stream);
+// ctx_free keeps the block for `stream` (reused by it at once; other streams
+// get it after an event that is recorded only when they need the memory), so
+// `stream` must stay valid until pyst_ctx_check on it or the context's end.
+// ctx_free_eager records that event at once (for streams the context does not
+// outlive, and where other streams reuse memory all the time).
 void ctx_free(pyst_ctx *ctx, void *p, hipStream_t stream);
+void ctx_free_eager(pyst_ctx *ctx, void *p, hipStream_t stream);
+// All work on `stream` has completed: what was freed on it goes to the free list.
+void ctx_stream_idle(pyst_ctx *ctx, hipStream_t stream);
 uint32_t *ctx_err_word(pyst_ctx *ctx);
 // Make kernels launched through `ctx` latch errors into `word` (device memory)
 // until reset with nullptr; used by the server to give each request its own word.

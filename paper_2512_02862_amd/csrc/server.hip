@@ -316,8 +316,9 @@ static bool admit(pyst_server *sv, const std::shared_ptr<Request> &r) {
 
 static void release(pyst_server *sv, Request &r) {
   hipStream_t st = sv->slots[r.slot];
-  if (r.sums_mem) ctx_free(sv->ctx, r.sums_mem, st);
-  if (r.s.mem) ctx_free(sv->ctx, r.s.mem, st);
+  // an event at once: other slots' requests reuse this memory all the time
+  if (r.sums_mem) ctx_free_eager(sv->ctx, r.sums_mem, st);
+  if (r.s.mem) ctx_free_eager(sv->ctx, r.s.mem, st);
   r.sums_mem = r.s.mem = nullptr;
   if (r.dims) {
     r.dims->users--;
