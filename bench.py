@@ -434,6 +434,47 @@ def bench_partitioned_join(ctx, pyst, log, bk, bc, pk, pc, fanout, m_expect):
             "probe_rows_per_s": npr / (ms / 1e3), "output_tuples_per_s": m / (ms / 1e3)}
 
 
+def bench_many_to_many(ctx, pyst, gen, log, nb, npr, ks=(1, 4)):
+    """The materializing join with duplicate build keys: nb build rows over nb / 4 keys
+    (uniform, about 4 rows a key), npr probe rows over 2 * nb / 4 keys, k columns a side."""
+    import numpy as np
+    import torch
+    nkeys = nb // 4
+    out = {"build_rows": nb, "probe_rows": npr, "build_keys": nkeys}
+    for k in ks:
+        log("many-to-many join: build %d over %d keys, probe %d, k = %d" % (nb, nkeys, npr, k))
+        b_h, p_h = gen.join_tables_dup(nb, npr, k, nkeys)
+        need = int(np.bincount(b_h["key"], minlength=2 * nkeys + 1)[p_h["key"]].sum())
+        bk, pk = torch.from_numpy(b_h["key"]).cuda(), torch.from_numpy(p_h["key"]).cuda()
+        bc = [torch.from_numpy(b_h["c%d" % c]).cuda() for c in range(k)]
+        pc = [torch.from_numpy(p_h["c%d" % c]).cuda() for c in range(k)]
+        del b_h, p_h
+
+        def step():
+            return pyst.join_materialize(ctx, bk, bc, pk, pc, unique_keys=False, out_cap=need)
+
+        r = step()
+        ctx.check()
+        m = int(r[3].item())
+        del r
+        torch.cuda.empty_cache()
+        ctx.timing(True)
+        el = timed_loop(step, 3, 0)
+        ctx.timing(False)
+        b_ms, b_n = ctx.kernel_time("join_build")
+        p_ms, p_n = ctx.kernel_time("join_probe")
+        for name in ("gather", "gather_rows", "pack_rows"):
+            ctx.kernel_time(name)
+        ctx.check()
+        ms = el / 3 * 1e3
+        out["k%d" % k] = {"ms": ms, "matches": m, "matches_expected": need, "output_tuples_per_s": m / (ms / 1e3),
+                          "probe_rows_per_s": npr / (ms / 1e3), "build_us": b_ms / max(b_n, 1) * 1e3,
+                          "probe_us": p_ms / max(p_n, 1) * 1e3}
+        del bk, pk, bc, pc
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8), fanout=2):
     """Build + probe + materialize of k 8-byte columns per side (one pyst_join_materialize call),
     and the same join with its partition leg (both sides partitioned first, fanout 2: two GPUs)."""
@@ -483,6 +524,7 @@ def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8)
         out["k%d" % k]["with_partition"] = bench_partitioned_join(ctx, pyst, log, bk, bc, pk, pc, fanout, m)
         del bk, pk, bc, pc
         torch.cuda.empty_cache()
+    out["many_to_many"] = bench_many_to_many(ctx, pyst, gen, log, nb, npr)
     # HBM bytes per launch from committed counters of the k = 4 run (null once the kernels changed)
     out["k4_counter_traffic"] = {"k_join_probe": counter_traffic("k_join_probe", JOIN_WORKLOAD),
                                  "k_gather_rows": counter_traffic("k_gather_rows<4", JOIN_WORKLOAD),

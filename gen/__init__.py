@@ -200,6 +200,22 @@ def join_tables(n_build: int, n_probe: int, k: int, workload: int = JOIN_WORKLOA
     return b, p
 
 
+JOIN_DUP_WORKLOAD = 8
+
+
+def join_tables_dup(n_build: int, n_probe: int, k: int, n_keys: int, zipf_s: float = 0.0,
+                    workload: int = JOIN_DUP_WORKLOAD):
+    """Tables of the many-to-many join: build keys drawn Zipf_s over 1..n_keys (s = 0:
+    uniform, so each key appears about n_build / n_keys times), probe keys uniform over
+    1..2 n_keys (half of them hit a key that occurs), k 8-byte payload columns a side."""
+    b = {"key": zipf_i32(n_build, max(n_keys, 1), zipf_s, seed(workload, 0, 0))}
+    p = {"key": uniform_i32(n_probe, 1, 2 * max(n_keys, 1), seed(workload, 1, 0))}
+    for c in range(k):
+        b["c%d" % c] = uniform_i64(n_build, -PAYLOAD_BOUND, PAYLOAD_BOUND, seed(workload, 0, 1 + c))
+        p["c%d" % c] = uniform_i64(n_probe, -PAYLOAD_BOUND, PAYLOAD_BOUND, seed(workload, 1, 1 + c))
+    return b, p
+
+
 Q18_WORKLOAD = 7
 QUANTITY_MAX = 50
 

@@ -234,22 +234,30 @@ pyst_status pyst_gather(pyst_ctx *ctx, const int32_t *idx, const int64_t *d_n, i
 
 /* One-call materializing equi-join, the receive-side work of one GPU in the
    join microbenchmark of Sec. 3 (build + probe + materialize; the send side is
-   pyst_partition): builds a table over the unique int32 build_key (a duplicate
-   latches PYST_ERR_DUP_KEY), probes it with every row of probe_key, and for
-   each match, in ascending probe row, writes the probe row, the build row and
-   the tuple npcols probe columns then nbcols build columns (each 0..8, int32
-   or int64, of their key's length): out_cols[c] for c < npcols holds
-   probe_cols[c] at the probe row, out_cols[npcols + c] build_cols[c] at the
-   build row.  out_probe_row / out_build_row: device int32[out_cap]; out_cols:
-   device buffers of their source's dtype with room for out_cap values, all
-   owned by the caller.  d_nout: device int64, receives the number of matches;
-   above out_cap only the first out_cap are written and PYST_ERR_CAPACITY is
-   latched.  The table lives in the context's arena for the call only.
+   pyst_partition): builds a table over the int32 build_key, probes it with
+   every row of probe_key, and for each match, in ascending probe row, writes
+   the probe row, the build row and the tuple npcols probe columns then nbcols
+   build columns (each 0..8, int32 or int64, of their key's length):
+   out_cols[c] for c < npcols holds probe_cols[c] at the probe row,
+   out_cols[npcols + c] build_cols[c] at the build row.
+   unique_keys != 0 promises distinct build keys (a duplicate latches
+   PYST_ERR_DUP_KEY) and lets a probe stop at its first match; with
+   unique_keys == 0 duplicate build keys are joined with SQL semantics (a
+   many-to-many join): a probe row emits one tuple per matching build row, the
+   tuples of one probe row consecutive in table order (so the canonical order
+   of the result is by (probe row, build row) after a sort within each probe
+   row's run).
+   out_probe_row / out_build_row: device int32[out_cap]; out_cols: device
+   buffers of their source's dtype with room for out_cap values, all owned by
+   the caller.  d_nout: device int64, receives the number of matches; above
+   out_cap only the first out_cap are written and PYST_ERR_CAPACITY is
+   latched (read the count and call again with room for it).  The table lives
+   in the context's arena for the call only.
    Errors: PYST_ERR_ARG, PYST_ERR_NOMEM. */
 pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, const pyst_col *build_cols, int nbcols,
                                   const pyst_col *probe_key, const pyst_col *probe_cols, int npcols, double max_load,
-                                  void *const *out_cols, int32_t *out_probe_row, int32_t *out_build_row,
-                                  int64_t out_cap, int64_t *d_nout, hipStream_t stream);
+                                  int unique_keys, void *const *out_cols, int32_t *out_probe_row,
+                                  int32_t *out_build_row, int64_t out_cap, int64_t *d_nout, hipStream_t stream);
 
 /* Enqueue a copy of the table's header into d_out (device int64[2]):
    [0] the effective capacity chosen on the device, [1] the number of rows

@@ -1372,8 +1372,8 @@ pyst_status pyst_gather(pyst_ctx *ctx, const int32_t *idx, const int64_t *d_n, i
 
 pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, const pyst_col *build_cols, int nbcols,
                                   const pyst_col *probe_key, const pyst_col *probe_cols, int npcols, double max_load,
-                                  void *const *out_cols, int32_t *out_probe_row, int32_t *out_build_row,
-                                  int64_t out_cap, int64_t *d_nout, hipStream_t stream) {
+                                  int unique_keys, void *const *out_cols, int32_t *out_probe_row,
+                                  int32_t *out_build_row, int64_t out_cap, int64_t *d_nout, hipStream_t stream) {
   if (!ctx || !build_key || !probe_key || !d_nout) return set_error(PYST_ERR_ARG, "pyst_join_materialize: NULL argument");
   if (!col_ok(build_key) || !col_ok(probe_key) || build_key->dtype != PYST_I32 || probe_key->dtype != PYST_I32)
     return set_error(PYST_ERR_ARG, "pyst_join_materialize: keys are int32 columns");
@@ -1401,13 +1401,13 @@ pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, cons
   pyst_status st;
   {
     TimedRegion timed(ctx, "join_build", stream);
-    st = launch_join_build(ctx, t, build_key, nullptr, nullptr, nullptr, max_load, 1, stream);
+    st = launch_join_build(ctx, t, build_key, nullptr, nullptr, nullptr, max_load, unique_keys != 0, stream);
   }
   if (st != PYST_OK) return st;
   {
     TimedRegion timed(ctx, "join_probe", stream);
-    st = launch_join_probe(ctx, t, 1, probe_key, nullptr, nullptr, out_probe_row, out_build_row, out_cap, d_nout,
-                           stream);
+    st = launch_join_probe(ctx, t, unique_keys != 0, probe_key, nullptr, nullptr, out_probe_row, out_build_row, out_cap,
+                           d_nout, stream);
   }
   if (st != PYST_OK) return st;
   if (npcols > 0 && (st = launch_gather(ctx, ga[0], out_probe_row, d_nout, out_cap, stream)) != PYST_OK) return st;

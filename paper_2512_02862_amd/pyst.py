@@ -132,8 +132,8 @@ def load(path: str = LIB_PATH):
         "pyst_join_build": ([p, P(Col), P(Col), p, p, ctypes.c_double, i32, P(p), p], i32),
         "pyst_join_probe": ([p, p, P(Col), p, p, p, p, i64, p, p], i32),
         "pyst_gather": ([p, p, p, i64, P(Col), i32, P(p), p], i32),
-        "pyst_join_materialize": ([p, P(Col), P(Col), i32, P(Col), P(Col), i32, ctypes.c_double, P(p), p, p, i64, p,
-                                   p], i32),
+        "pyst_join_materialize": ([p, P(Col), P(Col), i32, P(Col), P(Col), i32, ctypes.c_double, i32, P(p), p, p, i64,
+                                   p, p], i32),
         "pyst_pack_words": ([P(Col)], i64),
         "pyst_pack_encode": ([P(Col), p, p], i32),
         "pyst_pack_decode": ([p, p, p, i64, i64, i32, p, p], i32),
@@ -367,9 +367,10 @@ def gather(ctx: Ctx, idx, cols, n=None, stream=None):
 
 
 def join_materialize(ctx: Ctx, build_key, build_cols, probe_key, probe_cols, max_load=0.5, out_cap=None,
-                     stream=None):
+                     stream=None, unique_keys=True):
     """(probe rows int32, build rows int32, [probe columns..., build columns...], count int64[1]) of the
-    unique-key equi-join, in ascending probe row; outputs have out_cap (default: probe rows) entries."""
+    equi-join, in ascending probe row; outputs have out_cap (default: probe rows) entries.  With
+    unique_keys=False duplicate build keys are joined many-to-many (pass an out_cap that holds them)."""
     build_cols, probe_cols = list(build_cols), list(probe_cols)
     cap = probe_key.numel() if out_cap is None else out_cap
     d = _dev(ctx)
@@ -382,8 +383,8 @@ def join_materialize(ctx: Ctx, build_key, build_cols, probe_key, probe_cols, max
     parr = (Col * max(1, len(probe_cols)))(*[col(c) for c in probe_cols])
     oarr = (ctypes.c_void_p * max(1, len(outs)))(*[t.data_ptr() for t in outs])
     _check(_lib.pyst_join_materialize(ctx.h, ctypes.byref(bk), barr, len(build_cols), ctypes.byref(pk), parr,
-                                      len(probe_cols), float(max_load), oarr, _ptr(prow), _ptr(brow), cap, _ptr(nout),
-                                      _stream(stream)))
+                                      len(probe_cols), float(max_load), int(bool(unique_keys)), oarr, _ptr(prow),
+                                      _ptr(brow), cap, _ptr(nout), _stream(stream)))
     return prow[:cap], brow[:cap], [o[:cap] for o in outs], nout
 
 

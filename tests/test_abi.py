@@ -73,7 +73,7 @@ def test_new_entry_points_reject_bad_arguments_synchronously(lib):
     pyst.load(LIB)
     L = pyst._lib
     assert L.pyst_gather(None, None, None, 0, None, 1, None, None) == pyst.ERR_ARG
-    assert L.pyst_join_materialize(None, None, None, 0, None, None, 0, 0.5, None, None, None, 0, None, None) == \
+    assert L.pyst_join_materialize(None, None, None, 0, None, None, 0, 0.5, 1, None, None, None, 0, None, None) == \
         pyst.ERR_ARG
     assert L.pyst_pack_words(None) == -1
     bad = pyst.Col(None, 5, pyst.I32, 0)  # data NULL with n > 0

@@ -216,6 +216,39 @@ def test_partitioned_join_full_size(gpu, ctx):
     torch.cuda.empty_cache()
 
 
+def test_many_to_many_join_full_size(gpu, ctx):
+    # bench.py's many-to-many join: 60M build rows over 15M keys (about 4 rows a key),
+    # 160M probe rows, k = 1; checked by properties that fix the result at any size
+    import torch
+    nkeys = NJB // 4
+    b, p = gen.join_tables_dup(NJB, NJP, 1, nkeys)
+    bcnt = np.bincount(b["key"], minlength=2 * nkeys + 1).astype(np.int64)
+    per_probe = bcnt[p["key"]]
+    need = int(per_probe.sum())
+    bk, pk = dev(b["key"]), dev(p["key"])
+    prow, brow, cols, nout = gpu.join_materialize(ctx, bk, [dev(b["c0"])], pk, [dev(p["c0"])], unique_keys=False,
+                                                  out_cap=need)
+    ctx.check()
+    m = int(nout.item())
+    assert m == need
+    pr, br = prow[:m].long(), brow[:m].long()
+    assert bool((pr[1:] >= pr[:-1]).all())
+    assert bool((bk[br] == pk[pr]).all())
+    # each probe row appears exactly once per build row with its key
+    got = torch.bincount(pr, minlength=NJP).cpu().numpy()
+    np.testing.assert_array_equal(got, per_probe)
+    # no (probe, build) pair twice: within a probe row the build rows are distinct
+    key = pr * NJB + br
+    assert int(torch.unique(key).numel()) == m
+    del key
+    t = np.random.default_rng(3).integers(0, m, 200_000)
+    hp, hb = host(prow, m)[t], host(brow, m)[t]
+    np.testing.assert_array_equal(host(cols[0], m)[t], p["c0"][hp])
+    np.testing.assert_array_equal(host(cols[1], m)[t], b["c0"][hb])
+    del bk, pk, prow, brow, cols, pr, br, b, p
+    torch.cuda.empty_cache()
+
+
 NQ18, NQ18_ORDERS = 60_000_000, 15_000_000
 
 

@@ -240,3 +240,56 @@ def test_partition_carries_fifteen_payload_columns(gpu, ctx):
     with pytest.raises(gpu.PystError) as e:
         gpu.partition(ctx, dev(key), [dev(c) for c in pays] + [dev(key)], 64)
     assert e.value.status == gpu.ERR_ARG
+
+
+def _canonical(prow, brow, cols, m):
+    pr, br = host(prow, m), host(brow, m)
+    o = np.lexsort((br, pr))
+    return pr[o], br[o], [host(c, m)[o] for c in cols]
+
+
+@pytest.mark.parametrize("nb,npr,k,nkeys,zs", [(20_000, 50_003, 3, 5_000, 0.0), (30_000, 40_000, 2, 3_000, 1.0),
+                                               (4_097, 9_000, 1, 4_097, 0.0), (100_000, 250_000, 4, 25_000, 0.5)])
+def test_many_to_many_join_matches_oracle(gpu, ctx, nb, npr, k, nkeys, zs):
+    # duplicate build keys: every (probe row, build row) pair with equal keys, element by element
+    # against the oracle once both are in canonical (probe row, build row) order
+    b, p = gen.join_tables_dup(nb, npr, k, nkeys, zs)
+    bc = [dev(b["c%d" % c]) for c in range(k)]
+    pc = [dev(p["c%d" % c]) for c in range(k)]
+    wpr, wbr, wcols = oracle.join_materialize(b["key"], [b["c%d" % c] for c in range(k)], p["key"],
+                                              [p["c%d" % c] for c in range(k)])
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(b["key"]), bc, dev(p["key"]), pc, unique_keys=False,
+                                                  out_cap=len(wpr) + 7)
+    ctx.check()
+    m = int(nout.item())
+    assert m == len(wpr)
+    pr = host(prow, m)
+    assert (np.diff(pr) >= 0).all()  # ascending probe row, each row's matches together
+    gpr, gbr, gcols = _canonical(prow, brow, cols, m)
+    np.testing.assert_array_equal(gpr, wpr)
+    np.testing.assert_array_equal(gbr, wbr)
+    for g, w in zip(gcols, wcols):
+        np.testing.assert_array_equal(g, w)
+
+
+def test_many_to_many_capacity_and_unique_agreement(gpu, ctx):
+    b, p = gen.join_tables_dup(10_000, 30_000, 1, 2_500)
+    bk, pk = dev(b["key"]), dev(p["key"])
+    need = len(oracle.join(b["key"], p["key"])[0])
+    # too little room: the count holds the need and the error is latched
+    prow, brow, cols, nout = gpu.join_materialize(ctx, bk, [dev(b["c0"])], pk, [dev(p["c0"])], unique_keys=False,
+                                                  out_cap=need // 3)
+    with pytest.raises(gpu.PystError) as e:
+        ctx.check()
+    assert e.value.status == gpu.ERR_CAPACITY
+    assert int(nout.item()) == need
+    # on unique keys the many-to-many path gives the unique-key result
+    b, p = gen.join_tables(20_000, 60_000, 2)
+    args = (ctx, dev(b["key"]), [dev(b["c0"]), dev(b["c1"])], dev(p["key"]), [dev(p["c0"]), dev(p["c1"])])
+    r1 = gpu.join_materialize(*args)
+    r2 = gpu.join_materialize(*args, unique_keys=False)
+    ctx.check()
+    m = int(r1[3].item())
+    assert m == int(r2[3].item())
+    for x, y in zip([r1[0], r1[1]] + r1[2], [r2[0], r2[1]] + r2[2]):
+        np.testing.assert_array_equal(host(x, m), host(y, m))
