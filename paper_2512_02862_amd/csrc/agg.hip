@@ -4,10 +4,11 @@
 // A hash table in HBM takes two L2 atomics per pair (claim the key, add the
 // value), and random atomics on MI355X retire at about 23e9/s chip-wide, so 12M
 // pairs cost a millisecond however the table is laid out.  Here the pairs are
-// moved twice, 64 ways each time, by 6 bits of a hash of the key (per-block
-// counts, one exclusive scan, a scatter): the first move splits all pairs, the
-// second splits each of the 64 parts in place of the first, so that pairs end
-// in 4096 contiguous buckets.  One block per bucket then adds its pairs up in
+// moved twice, 64 ways each time, by 6 bits of a hash of the key: one counting
+// pass gives every first-move block's count per final bucket, two exclusive
+// scans turn them into both moves' positions, then the first move splits all
+// pairs and the second splits each of the 64 parts, so that pairs end in 4096
+// contiguous buckets.  One block per bucket then adds its pairs up in
 // an LDS hash table (indexed by low bits of the same hash) and writes out the
 // groups.  64 ways keep every block's writes to a bucket in a few active lines
 // that the L2 combines; one 4096-way move would write 8-byte fragments.
@@ -40,6 +41,10 @@ struct MoveArgs {
   int seg_stride;
   int bps;
   int shift;  // bucket = (hash >> shift) & (kRadix - 1)
+  // With `aligned`, block part of segment seg reads the rows that the first
+  // move's blocks [part * G, (part + 1) * G) wrote to it, G = seg_stride / bps
+  // (their counts are known from the first pass), instead of an even split.
+  int aligned = 0;
   // With kcol set, the pairs are read from the caller's columns instead: pair i
   // is row row_of(sel, i) of (kcol, vcol), int64 or int32 (sign-extended), and
   // an EMPTY key is latched in err (and skipped like any EMPTY key).
@@ -62,6 +67,12 @@ __device__ __forceinline__ void move_range(const MoveArgs &m, int *seg, int *par
   *seg = blockIdx.x / m.bps;
   *part = blockIdx.x % m.bps;
   int64_t a, b;
+  if (m.seg_off && m.aligned) {
+    const int g = m.seg_stride / m.bps;
+    *lo = m.seg_off[int64_t{*seg} * m.seg_stride + int64_t{*part} * g];
+    *hi = m.seg_off[int64_t{*seg} * m.seg_stride + int64_t{*part + 1} * g];
+    return;
+  }
   if (m.seg_off) {
     a = m.seg_off[int64_t{*seg} * m.seg_stride];
     b = m.seg_off[int64_t{*seg + 1} * m.seg_stride];
@@ -75,15 +86,16 @@ __device__ __forceinline__ void move_range(const MoveArgs &m, int *seg, int *par
   if (*lo > b) *lo = b;
 }
 
-// Counts per (segment, bucket, part), in that order: the exclusive scan of the
-// array is then where each block writes each bucket.  kEmpty64 keys are skipped.
-// Each thread handles kMoveItems consecutive-by-stride pairs per round, all
-// loads first.
+// Pairs a thread of the counting pass takes per round, all loads first.
 constexpr int kMoveItems = 8;
 
-__global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hist) {
-  __shared__ int32_t s_h[kRadix];
-  if (threadIdx.x < kRadix) s_h[threadIdx.x] = 0;
+// Per first-move block: counts of its pairs in each of the 4096 final buckets
+// (top 12 bits of the hash: the first move's 6 and the second's 6), from
+// which both moves' positions follow (k_narrow_counts), so the second move
+// needs no counting pass of its own.
+__global__ __launch_bounds__(kAggBlock) void k_move_hist_both(MoveArgs m, int32_t *counts) {
+  __shared__ int32_t s_c[kAggBuckets];
+  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) s_c[i] = 0;
   __syncthreads();
   int seg, part;
   int64_t lo, hi;
@@ -98,14 +110,14 @@ __global__ __launch_bounds__(kAggBlock) void k_move_hist(MoveArgs m, int32_t *hi
     }
 #pragma unroll
     for (int u = 0; u < kMoveItems; ++u)
-      if (k[u] != kEmpty64) atomicAdd(&s_h[(agg_hash(k[u]) >> m.shift) & (kRadix - 1)], 1);
+      if (k[u] != kEmpty64) atomicAdd(&s_c[agg_hash(k[u]) >> (64 - 2 * kRadixLg)], 1);
   }
   __syncthreads();
-  if (threadIdx.x < kRadix) hist[(int64_t{seg} * kRadix + threadIdx.x) * m.bps + part] = s_h[threadIdx.x];
+  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) counts[int64_t{blockIdx.x} * kAggBuckets + i] = s_c[i];
 }
 
-// Writes each block's pairs to its positions (pos: the exclusive scan of
-// k_move_hist's counts).  A tile of kMoveTile pairs is ranked by bucket in LDS
+// Writes each block's pairs to its positions (pos: the exclusive scan of the
+// per-(segment, bucket, block) counts, in that order).  A tile of kMoveTile pairs is ranked by bucket in LDS
 // (per-bucket counts with LDS atomics, one scan over kRadix buckets), laid out
 // bucket-major in LDS, and written so that consecutive threads write
 // consecutive slots of each bucket's run: every bucket's pairs of a tile leave
@@ -279,19 +291,27 @@ __global__ __launch_bounds__(kAggBlock) void k_bucket_groups(const int64_t *keys
 // error is latched.
 // The moves and the bucket pass; the first move reads `first` (pairs or columns),
 // the second writes keys/vals (cap entries each).
+__global__ void k_narrow_counts(const int32_t *counts, int32_t *c1, int32_t *c2);
+
 pyst_status pair_groupby_from(pyst_ctx *ctx, MoveArgs first, int64_t *keys, int64_t *vals, const int64_t *count,
                               int64_t cap, int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
                               int64_t *d_ngroups, hipStream_t stream) {
   if (cap >= (int64_t{1} << 31)) return set_error(PYST_ERR_ARG, "group-by: too many pairs");
   const int64_t n1 = int64_t{kRadix} * kAggBlocks1, n2 = int64_t{kAggBuckets} * kAggBlocks2;
-  const size_t counts = static_cast<size_t>(n1 + 1 + n2 + 1) * 2 * sizeof(int32_t);
+  const size_t counts = (static_cast<size_t>(kAggBlocks1) * kAggBuckets + static_cast<size_t>(n1 + 1 + n2 + 1) * 2) *
+                        sizeof(int32_t);
   Scratch sc(ctx, (counts + 255) / 256 * 256 + static_cast<size_t>(cap) * 16, stream);
   if (!sc.p) return set_error(PYST_ERR_NOMEM, "group-by: arena exhausted");
-  int32_t *h1 = sc.as<int32_t>(), *p1 = h1 + n1 + 1, *h2 = p1 + n1 + 1, *p2 = h2 + n2 + 1;
+  int32_t *cnt = sc.as<int32_t>();
+  int32_t *h1 = cnt + static_cast<int64_t>(kAggBlocks1) * kAggBuckets, *p1 = h1 + n1 + 1, *h2 = p1 + n1 + 1,
+          *p2 = h2 + n2 + 1;
   int64_t *tk = reinterpret_cast<int64_t *>(static_cast<char *>(sc.p) + (counts + 255) / 256 * 256);
   int64_t *tv = tk + cap;
-  // First move: all pairs, by hash bits 58..63.  The scans run over one more
-  // entry than the counts, so that the last offset is the total.
+  // One counting pass over all pairs gives every first-move block's counts
+  // per final bucket; the first move's positions are per part (hash bits
+  // 58..63), the second's per bucket (bits 52..57) and second-move block.
+  // The scans run over one more entry than the counts (zero), so that the
+  // last offset is the total.
   MoveArgs m1 = first;
   m1.count = count;
   m1.cap = cap;
@@ -299,21 +319,19 @@ pyst_status pair_groupby_from(pyst_ctx *ctx, MoveArgs first, int64_t *keys, int6
   m1.seg_stride = 0;
   m1.bps = kAggBlocks1;
   m1.shift = 64 - kRadixLg;
-  pyst_status st = fill_u32(reinterpret_cast<uint32_t *>(h1 + n1), 1, 0, stream);
-  if (st == PYST_OK) st = fill_u32(reinterpret_cast<uint32_t *>(h2 + n2), 1, 0, stream);
-  if (st != PYST_OK) return st;
-  k_move_hist<<<kAggBlocks1, kAggBlock, 0, stream>>>(m1, h1);
-  PYST_LAUNCH_CHECK("k_move_hist");
-  st = scan_excl_i32(ctx, h1, p1, n1 + 1, nullptr, stream);
+  k_move_hist_both<<<kAggBlocks1, kAggBlock, 0, stream>>>(m1, cnt);
+  PYST_LAUNCH_CHECK("k_move_hist_both");
+  k_narrow_counts<<<static_cast<unsigned>(ceil_div(n1 + n2 + 1, 256)), 256, 0, stream>>>(cnt, h1, h2);
+  PYST_LAUNCH_CHECK("k_narrow_counts");
+  pyst_status st = scan_excl_i32(ctx, h1, p1, n1 + 1, nullptr, stream);
+  if (st == PYST_OK) st = scan_excl_i32(ctx, h2, p2, n2 + 1, nullptr, stream);
   if (st != PYST_OK) return st;
   k_move_scatter<<<kAggBlocks1, kAggBlock, 0, stream>>>(m1, p1, tk, tv);
   PYST_LAUNCH_CHECK("k_move_scatter");
-  // Second move: each of the 64 parts of the first, by hash bits 52..57, back into keys/vals.
+  // Second move: block j of part p reads what the first move's blocks
+  // [64 j, 64 (j + 1)) wrote to part p, and writes it by bucket into keys/vals.
   MoveArgs m2{tk, tv, count, cap, p1, kAggBlocks1, kAggBlocks2, 64 - 2 * kRadixLg};
-  k_move_hist<<<kRadix * kAggBlocks2, kAggBlock, 0, stream>>>(m2, h2);
-  PYST_LAUNCH_CHECK("k_move_hist");
-  st = scan_excl_i32(ctx, h2, p2, n2 + 1, nullptr, stream);
-  if (st != PYST_OK) return st;
+  m2.aligned = 1;
   k_move_scatter<<<kRadix * kAggBlocks2, kAggBlock, 0, stream>>>(m2, p2, keys, vals);
   PYST_LAUNCH_CHECK("k_move_scatter");
   const int gblocks = static_cast<int>(std::min<int64_t>(kAggBuckets, std::max(1, ctx_num_cus(ctx))));
@@ -339,6 +357,7 @@ constexpr int kNG = kNB1 / kNB2;         // first-move blocks behind one second-
 constexpr int kNItems = 8;               // rows per thread and round of the counting pass
 constexpr uint32_t kNarrowSeed = 0x6b43a9b5u;
 static_assert(kNB1 % kNB2 == 0, "second-move blocks cover whole groups of first-move blocks");
+static_assert(kNB1 == kAggBlocks1 && kNB2 == kAggBlocks2, "the wide pair moves share the count layout");
 
 __device__ __forceinline__ uint32_t narrow_hash(int32_t key) { return fmix32(static_cast<uint32_t>(key) ^ kNarrowSeed); }
 

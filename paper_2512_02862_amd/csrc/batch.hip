@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
 __global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
   PYST_BLOCK_FRAG(kPreBuild)
   (void)nloc;
-  build_tile<4>(fr.bkey, nullptr, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
+  build_tile(fr.bkey, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
 }
 
 // Each fragment's Bloom filter, from its finished table (words past the ones

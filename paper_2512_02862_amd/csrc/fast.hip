@@ -181,18 +181,15 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
     for (int64_t i = tid; i < kBloomWords; i += nthr) t.bloom[i] = 0;
 }
 
-// Build from a block-local selection (or all rows): block b inserts the rows
-// of dimension tile b (kDimTile rows, the dimension filter's tile), 16 per
-// thread.  Each thread loads all of its row ids, then all of its keys, then
-// issues the first compare-and-swap (4-byte slots: the CAS straight away, a
-// fresh table is mostly empty; 8-byte slots: a read first) of every row before
-// it looks at any result, so that a thread keeps 16 inserts in flight instead
-// of one chain of dependent accesses; only rows whose first slot was taken
-// walk on.
-template <int SB>
-__device__ __forceinline__ void build_tile(const int32_t *key, const int32_t *payload, const int32_t *sel,
-                                           const int32_t *cnt, int64_t n, int64_t tile, const TableDev &t,
-                                           uint32_t *err) {
+// Build of a keys-only table from a block-local selection (or all rows): block
+// b inserts the rows of dimension tile b (kDimTile rows, the dimension
+// filter's tile), 16 per thread.  Each thread loads all of its row ids, then
+// all of its keys, then issues the compare-and-swap of every row's home slot
+// (a fresh table is mostly empty, so no read first) before it looks at any
+// result: 16 inserts in flight per thread instead of one chain of dependent
+// accesses; only rows whose home slot was taken walk on.
+__device__ __forceinline__ void build_tile(const int32_t *key, const int32_t *sel, const int32_t *cnt, int64_t n,
+                                           int64_t tile, const TableDev &t, uint32_t *err) {
   constexpr int ITEMS = kDimTile / 256;
   const int64_t mask = t.hdr[0] - 1;
   const int64_t base = tile * kDimTile;
@@ -215,78 +212,84 @@ __device__ __forceinline__ void build_tile(const int32_t *key, const int32_t *pa
       latch(err, kErrKey);
       v[j] = false;
     }
-  if (SB == 4) {
-    int32_t *keys = static_cast<int32_t *>(t.slots);
-    int64_t s[ITEMS];
-    int32_t cur[ITEMS];
+  int32_t *keys = static_cast<int32_t *>(t.slots);
+  int64_t s[ITEMS];
+  int32_t cur[ITEMS];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      s[j] = (table_hash32(k[j]) & mask) & ~int64_t{3};
-      cur[j] = v[j] ? atomicCAS(&keys[s[j]], kEmpty32, k[j]) : kEmpty32;
-    }
+  for (int j = 0; j < ITEMS; ++j) {
+    s[j] = (table_hash32(k[j]) & mask) & ~int64_t{3};
+    cur[j] = v[j] ? atomicCAS(&keys[s[j]], kEmpty32, k[j]) : kEmpty32;
+  }
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (!v[j]) continue;
-      bool done = false;
-      for (int64_t step = 0; step <= mask; ++step) {
-        if (cur[j] == kEmpty32) {
-          done = true;
-          break;
-        }
-        if (cur[j] == k[j]) {
-          latch(err, kErrDup);
-          done = true;
-          break;
-        }
-        s[j] = (s[j] + 1) & mask;
-        cur[j] = atomicCAS(&keys[s[j]], kEmpty32, k[j]);
+  for (int j = 0; j < ITEMS; ++j) {
+    if (!v[j]) continue;
+    bool done = false;
+    for (int64_t step = 0; step <= mask; ++step) {
+      if (cur[j] == kEmpty32) {
+        done = true;
+        break;
       }
-      if (!done) latch(err, kErrTableFull);
-    }
-  } else {
-    uint64_t *slots = static_cast<uint64_t *>(t.slots);
-    const uint64_t empty = static_cast<uint32_t>(kEmpty32);
-    int64_t s[ITEMS];
-    uint64_t cur[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      s[j] = (table_hash32(k[j]) & mask) & ~int64_t{1};
-      cur[j] = v[j] ? slots[s[j]] : empty;
-    }
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (!v[j]) continue;
-      const uint64_t packed = uint64_t{static_cast<uint32_t>(k[j])} |
-                              (uint64_t{static_cast<uint32_t>(payload ? payload[row[j]] : static_cast<int32_t>(row[j]))}
-                               << 32);
-      bool done = false;
-      for (int64_t step = 0; step <= mask; ++step) {
-        uint64_t c = cur[j];
-        if (static_cast<int32_t>(c) == kEmpty32) {
-          const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&slots[s[j]]), empty, packed);
-          if (old == empty) {
-            done = true;
-            break;
-          }
-          c = old;
-        }
-        if (static_cast<int32_t>(c) == k[j]) {
-          latch(err, kErrDup);
-          done = true;
-          break;
-        }
-        s[j] = (s[j] + 1) & mask;
-        cur[j] = slots[s[j]];
+      if (cur[j] == k[j]) {
+        latch(err, kErrDup);
+        done = true;
+        break;
       }
-      if (!done) latch(err, kErrTableFull);
+      s[j] = (s[j] + 1) & mask;
+      cur[j] = atomicCAS(&keys[s[j]], kEmpty32, k[j]);
     }
+    if (!done) latch(err, kErrTableFull);
   }
 }
 
-template <int SB>
-__global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const int32_t *payload, const int32_t *sel,
-                                                    const int32_t *cnt, int64_t n, TableDev t, uint32_t *err) {
-  build_tile<SB>(key, payload, sel, cnt, n, blockIdx.x, t, err);
+__global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const int32_t *sel, const int32_t *cnt, int64_t n,
+                                                    TableDev t, uint32_t *err) {
+  build_tile(key, sel, cnt, n, blockIdx.x, t, err);
+}
+
+// Build of a key + payload table (8-byte slots), one row per thread: the
+// slot is read first and claimed with a compare-and-swap where empty (a CAS
+// straight to a cold line measured slower; so did 16 rows per thread, whose
+// reads wait for each other before any claim).
+__global__ __launch_bounds__(256) void k_fast_build_payload(const int32_t *key, const int32_t *payload,
+                                                            const int32_t *sel, const int32_t *cnt, int64_t n,
+                                                            TableDev t, uint32_t *err) {
+  const int64_t mask = t.hdr[0] - 1;
+  uint64_t *slots = static_cast<uint64_t *>(t.slots);
+  const uint64_t empty = static_cast<uint32_t>(kEmpty32);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t row = i;
+    if (sel) {
+      if ((i % kDimTile) >= cnt[i / kDimTile]) continue;
+      row = sel[i];
+    }
+    const int32_t k = key[row];
+    if (k == kEmpty32) {
+      latch(err, kErrKey);
+      continue;
+    }
+    const uint64_t packed = uint64_t{static_cast<uint32_t>(k)} |
+                            (uint64_t{static_cast<uint32_t>(payload ? payload[row] : static_cast<int32_t>(row))} << 32);
+    int64_t s = (table_hash32(k) & mask) & ~int64_t{1};
+    bool done = false;
+    for (int64_t step = 0; step <= mask; ++step) {
+      uint64_t cur = slots[s];
+      if (static_cast<int32_t>(cur) == kEmpty32) {
+        const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&slots[s]), empty, packed);
+        if (old == empty) {
+          done = true;
+          break;
+        }
+        cur = old;
+      }
+      if (static_cast<int32_t>(cur) == k) {
+        latch(err, kErrDup);
+        done = true;
+        break;
+      }
+      s = (s + 1) & mask;
+    }
+    if (!done) latch(err, kErrTableFull);
+  }
 }
 
 // Bloom filter of a built keys-only table: thread w reads the slots whose home
@@ -1685,12 +1688,14 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
                                                    j == 0 ? zero1 : nullptr);
     PYST_LAUNCH_CHECK("k_fast_table_init");
     if (nb > 0) {
-      // one block per dimension tile (the filter's tiles)
-      const int blocks = static_cast<int>(nblk);
       const int32_t *key = static_cast<const int32_t *>(js.key.data);
       const int32_t *pay = static_cast<const int32_t *>(js.payload.data);
-      if (sb == 4) k_fast_build<4><<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
-      else k_fast_build<8><<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
+      if (sb == 4) {  // one block per dimension tile (the filter's tiles)
+        k_fast_build<<<static_cast<unsigned>(nblk), 256, 0, stream>>>(key, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
+      } else {
+        const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(nb, 256), int64_t{1} << 20));
+        k_fast_build_payload<<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
+      }
       PYST_LAUNCH_CHECK("k_fast_build");
       if (d->t[j].bloom) {  // keys-only (join 0)
         k_fast_bloom<<<kBloomWords / 256, 256, 0, stream>>>(d->t[j]);
