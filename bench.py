@@ -46,7 +46,19 @@ KERNEL_SOURCES = {  # the files that define each profiled kernel (name patterns 
     "k_join_build": ["ops.hip", "pyst_internal.h", "table.h"],
     "k_gather_rows<4": ["ops.hip", "pyst_internal.h"],
     "k_gather<": ["ops.hip", "pyst_internal.h"],
+    "k_narrow_hist": ["agg.hip", "pyst_internal.h"],
+    "k_narrow_move<true>": ["agg.hip", "pyst_internal.h"],
+    "k_narrow_move<false>": ["agg.hip", "pyst_internal.h"],
+    "k_narrow_groups": ["agg.hip", "pyst_internal.h"],
+    "k_move_hist_both": ["agg.hip", "pyst_internal.h"],
+    "k_move_scatter": ["agg.hip", "pyst_internal.h"],
+    "k_bucket_groups": ["agg.hip", "pyst_internal.h"],
+    "k_bat_fact_staged": ["batch.hip", "fast.hip", "pyst_internal.h", "table.h", "query.h"],
 }
+Q18_WORKLOAD = "q18_n60000000_g15000000"
+BATCH_WORKLOAD = "batch_512"
+Q18_KERNELS = ("k_narrow_hist", "k_narrow_move<true>", "k_narrow_move<false>", "k_narrow_groups")
+PAIR_KERNELS = ("k_move_hist_both", "k_move_scatter", "k_bucket_groups")
 CHAIN_WORKLOAD = "chain_a3000000_b300000_f120000000"  # fact-pass counters averaged over s = 0 and 1
 JOIN_WORKLOAD = "join_b60000000_p160000000_k4"  # counters of the k = 4 materializing join
 
@@ -352,6 +364,8 @@ def bench_chain(ctx, pyst, gen, log):
     # HBM bytes per launch of the chain's fact pass from committed counters (null
     # when the kernel's source has changed since they were taken)
     out["fact_pass_traffic"] = counter_traffic("k_fast_fact<2, 8, 2", CHAIN_WORKLOAD)
+    # the pair group-by's kernels (the two moves share one name: their mean per launch)
+    out["pair_groupby_traffic"] = {k: counter_traffic(k, CHAIN_WORKLOAD) for k in PAIR_KERNELS}
     out["fact_pass_algorithmic_bytes"] = nf * 24
     return out
 
@@ -386,6 +400,8 @@ def bench_groupby(ctx, pyst, gen, log, n=60_000_000, n_orders=15_000_000):
                      "region_us": g_ms / max(g_n, 1) * 1e3}
     ctx.groupby_hash_only(False)
     out["radix_speedup"] = out["hash"]["ms"] / out["radix"]["ms"]
+    # HBM bytes per launch of the radix path's kernels, from committed counters
+    out["radix"]["counter_traffic"] = {k: counter_traffic(k, Q18_WORKLOAD) for k in Q18_KERNELS}
     return out
 
 
@@ -610,7 +626,8 @@ def bench_batch(ctx, pyst, gen, log, nfrag, max_rows):
             "batched_fragments_per_s": nfrag / batched_s, "sequential_fragments_per_s": nfrag / seq_s,
             "speedup": seq_s / batched_s, "graph_ms": graph_s * 1e3, "graph_speedup": seq_s / graph_s,
             "batched_probe_rows_per_s": total_rows / batched_s,
-            "batched_gbs": total_rows * 16 / batched_s / 1e9, "result_mismatches": mismatches}
+            "batched_gbs": total_rows * 16 / batched_s / 1e9, "result_mismatches": mismatches,
+            "fact_pass_traffic": counter_traffic("k_bat_fact_staged", BATCH_WORKLOAD)}
 
 
 def host_memory(log):
