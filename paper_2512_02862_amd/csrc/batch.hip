@@ -61,6 +61,22 @@ __device__ __forceinline__ int frag_of(const int64_t *pre, int nfrag, int64_t b)
   const int64_t local = blockIdx.x - pre[(kind) * (nfrag + 1) + f];        \
   const int64_t nloc = pre[(kind) * (nfrag + 1) + f + 1] - pre[(kind) * (nfrag + 1) + f];
 
+// The fact pass lays its blocks out by fragment in the order kept after the
+// prefixes (pre[kPreKinds * (nfrag + 1) + i]: the fragment at position i),
+// largest work units first, so that the long units start early and the end
+// of the launch is made of short ones.
+#define PYST_BLOCK_FRAG_ORDERED(kind)                                                        \
+  __shared__ int s_frag, s_pos;                                                              \
+  if (threadIdx.x == 0) {                                                                    \
+    s_pos = frag_of(pre + (kind) * (nfrag + 1), nfrag, blockIdx.x);                          \
+    s_frag = static_cast<int>(pre[kPreKinds * (nfrag + 1) + s_pos]);                         \
+  }                                                                                          \
+  __syncthreads();                                                                           \
+  const int f = s_frag;                                                                      \
+  const BatFrag &fr = frags[f];                                                              \
+  const int64_t local = blockIdx.x - pre[(kind) * (nfrag + 1) + s_pos];                      \
+  const int64_t nloc = pre[(kind) * (nfrag + 1) + s_pos + 1] - pre[(kind) * (nfrag + 1) + s_pos];
+
 __global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const int64_t *pre, int nfrag) {
   PYST_BLOCK_FRAG(kPreFilter)
   (void)nloc;
@@ -147,7 +163,7 @@ __global__ __launch_bounds__(256) void k_bat_bloom(const BatFrag *frags, const i
 // per slot, so a small fragment copies little).
 template <int BS, bool V64>
 __global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
-  PYST_BLOCK_FRAG(kPreFact)
+  PYST_BLOCK_FRAG_ORDERED(kPreFact)
   (void)nloc;
   __shared__ uint32_t s_bloom[kBloomWords];
   const bool use_bloom = fr.t.hdr[1] <= kBloomMaxKeys;
@@ -170,7 +186,7 @@ __global__ __launch_bounds__(BS) void k_bat_fact(const BatFrag *frags, const int
 template <bool V64>
 __global__ __launch_bounds__(kFastBlock) void k_bat_fact_staged(const BatFrag *frags, const int64_t *pre, int nfrag,
                                                                 uint32_t *err) {
-  PYST_BLOCK_FRAG(kPreFact)
+  PYST_BLOCK_FRAG_ORDERED(kPreFact)
   (void)nloc;
   __shared__ uint32_t s_bloom[kBloomWords];
   __shared__ uint64_t s_ent[kStageCap];
@@ -373,6 +389,17 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
     }
     for (int k = 0; k < kPreKinds; ++k) bp->pre[k * (nfrag + 1) + f + 1] = bp->pre[k * (nfrag + 1) + f] + blocks[k];
   }
+  // fact blocks: fragments by work-unit size, largest first (their order follows the prefixes)
+  std::vector<int> order(nfrag);
+  for (int f = 0; f < nfrag; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return bp->frags[x].rows_per_unit > bp->frags[y].rows_per_unit; });
+  int64_t *fp = bp->pre.data() + kPreFact * (nfrag + 1);
+  for (int i = 0; i < nfrag; ++i) {
+    const BatFrag &b = bp->frags[order[i]];
+    fp[i + 1] = fp[i] + ceil_div(std::max<int64_t>(b.fa.n, 1), b.rows_per_unit);
+  }
+  for (int i = 0; i < nfrag; ++i) bp->pre.push_back(order[i]);
   return PYST_OK;
 }
 
