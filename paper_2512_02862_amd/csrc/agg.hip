@@ -29,7 +29,7 @@ constexpr uint64_t kAggSeed = 0xd6e8feb86659fd93ull;
 
 __device__ __forceinline__ uint64_t agg_hash(int64_t key) { return fmix64(static_cast<uint64_t>(key) ^ kAggSeed); }
 
-// The rows a block of a move reads: segment blockIdx.x / bps of the input
+// The rows a block of a move reads: with b = xcd_block(blockIdx.x), segment b / bps of the input
 // (segment s is [seg_off[s * seg_stride], seg_off[(s + 1) * seg_stride]), or the
 // whole input [0, min(*count, cap)) without seg_off), split evenly into bps parts.
 struct MoveArgs {
@@ -64,8 +64,9 @@ __device__ __forceinline__ int64_t move_val(const MoveArgs &m, int64_t i) {
 }
 
 __device__ __forceinline__ void move_range(const MoveArgs &m, int *seg, int *part, int64_t *lo, int64_t *hi) {
-  *seg = blockIdx.x / m.bps;
-  *part = blockIdx.x % m.bps;
+  const int blk = static_cast<int>(xcd_block(blockIdx.x, gridDim.x));  // neighbouring ranges on one XCD
+  *seg = blk / m.bps;
+  *part = blk % m.bps;
   int64_t a, b;
   if (m.seg_off && m.aligned) {
     const int g = m.seg_stride / m.bps;
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(kAggBlock) void k_move_hist_both(MoveArgs m, int32_
       if (k[u] != kEmpty64) atomicAdd(&s_c[agg_hash(k[u]) >> (64 - 2 * kRadixLg)], 1);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) counts[int64_t{blockIdx.x} * kAggBuckets + i] = s_c[i];
+  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) counts[(int64_t{seg} * m.bps + part) * kAggBuckets + i] = s_c[i];
 }
 
 // Writes each block's pairs to its positions (pos: the exclusive scan of the
@@ -382,7 +383,8 @@ __global__ __launch_bounds__(kAggBlock) void k_narrow_hist(NarrowArgs a, int32_t
   for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) s_c[i] = 0;
   __syncthreads();
   int64_t lo, hi;
-  narrow_range(a, blockIdx.x, kNB1, &lo, &hi);
+  const int blk = static_cast<int>(xcd_block(blockIdx.x, gridDim.x));  // as k_narrow_move<true>
+  narrow_range(a, blk, kNB1, &lo, &hi);
   for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += int64_t{kAggBlock} * kNItems) {
     int32_t k[kNItems];
 #pragma unroll
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(kAggBlock) void k_narrow_hist(NarrowArgs a, int32_t
       if (i0 + int64_t{u} * kAggBlock < hi) atomicAdd(&s_c[narrow_hash(k[u]) >> 20], 1);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) counts[int64_t{blockIdx.x} * kAggBuckets + i] = s_c[i];
+  for (int i = threadIdx.x; i < kAggBuckets; i += kAggBlock) counts[int64_t{blk} * kAggBuckets + i] = s_c[i];
 }
 
 // c1[p * kNB1 + b]: rows of first-move block b in part p; c2[(p * 64 + q) * kNB2
@@ -435,12 +437,13 @@ __global__ __launch_bounds__(kAggBlock) void k_narrow_move(NarrowArgs a, const u
   const int tid = static_cast<int>(threadIdx.x);
   int64_t lo, hi;
   int part = 0;
+  const int blk = static_cast<int>(xcd_block(blockIdx.x, gridDim.x));  // neighbouring ranges on one XCD
   if (FIRST) {
-    narrow_range(a, blockIdx.x, kNB1, &lo, &hi);
-    if (tid < kRadix) s_base[tid] = pos1[int64_t{tid} * kNB1 + blockIdx.x];
+    narrow_range(a, blk, kNB1, &lo, &hi);
+    if (tid < kRadix) s_base[tid] = pos1[int64_t{tid} * kNB1 + blk];
   } else {
-    part = static_cast<int>(blockIdx.x) / kNB2;
-    const int j = static_cast<int>(blockIdx.x) % kNB2;
+    part = blk / kNB2;
+    const int j = blk % kNB2;
     lo = pos1[int64_t{part} * kNB1 + j * kNG];
     hi = pos1[int64_t{part} * kNB1 + (j + 1) * kNG];
     if (tid < kRadix) s_base[tid] = pos2[(int64_t{part} * kRadix + tid) * kNB2 + j];

@@ -390,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
   __shared__ int64_t s_stage[TILE];
 
   const int F = static_cast<int>(a.fanout);
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x);  // consecutive tiles on one XCD
   const int64_t cnt = count_of(a.d_nsel, a.n);
   for (int p = threadIdx.x; p < F; p += BLOCK) {
     for (int w = 0; w < NW; ++w) s_cnt[w][p] = 0;

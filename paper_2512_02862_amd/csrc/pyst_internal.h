@@ -118,6 +118,20 @@ __device__ __forceinline__ bool eval_preds(const PredSet &ps, int64_t row) {
   return keep;
 }
 
+// ------------------------------------------------------------------ XCD-aware block order
+// Workgroups are dispatched round-robin over the chip's 8 XCDs (block b runs
+// on XCD b mod 8), and every XCD has its own L2.  xcd_block maps the launch
+// order to a work order in which each XCD takes one contiguous range of the
+// n work items, in order: kernels whose consecutive items write neighbouring
+// addresses (the pieces that consecutive tiles write into each destination)
+// then have those writes meet in one L2, which merges them into whole lines.
+// A bijection on [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t q = n / kXcds, r = n % kXcds, x = b % kXcds, i = b / kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x) & (kWave - 1); }
 
