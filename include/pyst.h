@@ -191,31 +191,38 @@ pyst_status pyst_partition_noalloc(const pyst_col *key, const pyst_col *payloads
 
 /* Hash-join build (Sec. 3.1 "Anatomy..."; the table is built over the fully
    materialized build side, Sec. 3.2 "Scheduling Overlap With GPU Streams").
-   Inserts the selected rows of the int32 `key` column into a power-of-two
-   open-addressing table with linear probing and atomic compare-and-swap.
-   payload: int32 column stored with each key, or NULL to store the row id.
+   Inserts the selected rows of the int32 or int64 `key` column into a
+   power-of-two open-addressing table with linear probing and atomic
+   compare-and-swap.  payload: int32 or int64 column of the key's length
+   stored with each key, or NULL to store the row id.  Layout: int32 keys with
+   int32 (or no) payloads take 8-byte slots; int64 keys or int64 payloads take
+   16-byte slots {int64 key, int64 payload}.
    max_load in (0, 0.95]: the capacity is the smallest power of two with
    load <= max_load for the number of rows actually selected (read on the
    device, so no host synchronization is needed; memory is reserved for the
    unfiltered n).  unique_keys != 0 promises distinct keys: probes stop at
    the first match, and a duplicate latches PYST_ERR_DUP_KEY.
-   The key INT32_MIN is reserved as EMPTY and latches PYST_ERR_KEY.
+   The key INT32_MIN (int32 key column) or INT64_MIN (int64 key column) is
+   reserved as EMPTY and latches PYST_ERR_KEY.
    *out receives a table owned by the caller (pyst_table_destroy).
-   Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED (int64 keys), PYST_ERR_NOMEM. */
+   Errors: PYST_ERR_ARG, PYST_ERR_NOMEM. */
 pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *payload,
                             const int32_t *sel, const int64_t *d_nsel, double max_load,
                             int unique_keys, pyst_table **out, hipStream_t stream);
 
-/* Hash-join probe: for every selected row of the int32 `key` column, in
-   ascending row order, emit one (probe row, stored payload) pair per matching
-   build row.  out_probe_row / out_payload: device int32[out_cap].
+/* Hash-join probe: for every selected row of the int32 or int64 `key` column,
+   in ascending row order, emit one (probe row, stored payload) pair per
+   matching build row.  Keys compare by value whatever the two columns' types;
+   a probe key equal to its own column's EMPTY sentinel matches nothing.
+   out_probe_row: device int32[out_cap]; out_payload: device int64[out_cap]
+   (int32 payloads sign-extended, row ids as they are).
    d_nout: device int64, receives the number of matches; when it exceeds
    out_cap only the first out_cap pairs are written and PYST_ERR_CAPACITY is
    latched.  With duplicate build keys the matches of one probe row come in
-   table order.  Errors: PYST_ERR_ARG, PYST_ERR_UNSUPPORTED (int64 keys). */
+   table order.  Errors: PYST_ERR_ARG. */
 pyst_status pyst_join_probe(pyst_ctx *ctx, const pyst_table *table, const pyst_col *key,
                             const int32_t *sel, const int64_t *d_nsel, int32_t *out_probe_row,
-                            int32_t *out_payload, int64_t out_cap, int64_t *d_nout,
+                            int64_t *out_payload, int64_t out_cap, int64_t *d_nout,
                             hipStream_t stream);
 
 /* Materialize join results (Sec. 3.1 "Anatomy...": the probe emits matching
@@ -234,7 +241,8 @@ pyst_status pyst_gather(pyst_ctx *ctx, const int32_t *idx, const int64_t *d_n, i
 
 /* One-call materializing equi-join, the receive-side work of one GPU in the
    join microbenchmark of Sec. 3 (build + probe + materialize; the send side is
-   pyst_partition): builds a table over the int32 build_key, probes it with
+   pyst_partition): builds a table over build_key (int32 or int64; keys
+   compare by value as in pyst_join_probe), probes it with
    every row of probe_key, and for each match, in ascending probe row, writes
    the probe row, the build row and the tuple npcols probe columns then nbcols
    build columns (each 0..8, int32 or int64, of their key's length):
@@ -570,6 +578,16 @@ pyst_status pyst_server_submit(pyst_server *server, const pyst_request *req, uin
    or a duplicate key in its dimension, fails that request and no other).
    A ticket is waited once. */
 pyst_status pyst_server_wait(pyst_server *server, uint64_t ticket, double *latency_ms);
+
+/* Non-blocking form of pyst_server_wait (the scheduler's queues are polled,
+   Sec. 5.4 "Queue-Based Scheduling"): never waits for the GPU, only for the
+   server's own lock.  While request `ticket` runs, *done = 0 and PYST_OK is
+   returned; once it has completed, *done = 1, *latency_ms (may be NULL) is
+   set, and the request's own status is returned exactly as pyst_server_wait
+   would, after which the ticket is forgotten.
+   Errors: PYST_ERR_ARG (NULL server or done, unknown or already reported
+   ticket), else the request's status. */
+pyst_status pyst_server_poll(pyst_server *server, uint64_t ticket, int *done, double *latency_ms);
 
 /* Counters since creation.  Errors: PYST_ERR_ARG. */
 pyst_status pyst_server_get_stats(pyst_server *server, pyst_server_stats *out);

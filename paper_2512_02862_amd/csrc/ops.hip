@@ -5,6 +5,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "pyst_internal.h"
 #include "table.h"
@@ -604,7 +605,12 @@ pyst_status scan_excl_i32(pyst_ctx *ctx, const int32_t *in, int32_t *out, int64_
 }
 
 // ============================================================== join build / probe
-// Key + payload table: 8-byte slots, (uint32 key) | (uint32 payload) << 32.
+// Key + payload table of int32 keys and int32 payloads (or row ids): 8-byte
+// slots, (uint32 key) | (uint32 payload) << 32, EMPTY key INT32_MIN.
+// A table keyed by int64, or carrying int64 payloads, takes 16-byte slots
+// {int64 key, int64 payload} with EMPTY key INT64_MIN instead ("wide"): the
+// key word is claimed by CAS and the payload stored after it, which a probe
+// (a later launch) then sees.
 constexpr uint64_t kEmptySlot = static_cast<uint32_t>(kEmpty32);
 
 __global__ void k_table_init(TableDev t, const int64_t *d_nsel, int64_t n, double max_load) {
@@ -614,8 +620,10 @@ __global__ void k_table_init(TableDev t, const int64_t *d_nsel, int64_t n, doubl
     t.hdr[0] = cap;
     t.hdr[1] = cnt;
   }
-  const int64_t words = t.slot_bytes == 4 ? cap / 2 : cap;  // in 8-byte words
-  const uint64_t fillv = t.slot_bytes == 4 ? (uint64_t{static_cast<uint32_t>(kEmpty32)} * 0x100000001ull) : kEmptySlot;
+  const int64_t words = t.slot_bytes == 4 ? cap / 2 : t.slot_bytes == 16 ? 2 * cap : cap;  // in 8-byte words
+  const uint64_t fillv = t.slot_bytes == 4    ? (uint64_t{static_cast<uint32_t>(kEmpty32)} * 0x100000001ull)
+                         : t.slot_bytes == 16 ? static_cast<uint64_t>(kEmpty64)
+                                              : kEmptySlot;
   uint64_t *p = static_cast<uint64_t *>(t.slots);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = fillv;
@@ -691,6 +699,70 @@ __global__ __launch_bounds__(BLOCK) void k_join_build(const int32_t *key, const 
   }
 }
 
+// Key of `row` in an int32 or int64 column, sign-extended; false for the
+// column type's EMPTY sentinel, which is never stored and matches nothing.
+__device__ __forceinline__ bool join_key(const void *key, int key64, int64_t row, int64_t &k) {
+  if (key64) {
+    k = static_cast<const int64_t *>(key)[row];
+    return k != kEmpty64;
+  }
+  k = static_cast<const int32_t *>(key)[row];
+  return k != kEmpty32;
+}
+
+// Insertion into a wide table, ITEMS rows per lane as in k_join_build.
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_join_build_wide(const void *key, int key64, const void *payload, int pay64,
+                                                           const int32_t *sel, const int64_t *d_nsel, int64_t n,
+                                                           TableDev t, int unique, uint32_t *err) {
+  const int64_t cnt = count_of(d_nsel, n);
+  const int64_t mask = t.hdr[0] - 1;
+  auto *slots = reinterpret_cast<unsigned long long *>(t.slots);  // slot s: words 2s (key), 2s + 1 (payload)
+  constexpr unsigned long long kE = static_cast<unsigned long long>(kEmpty64);
+  constexpr int64_t TILE = int64_t{BLOCK} * ITEMS;
+  for (int64_t base = int64_t{blockIdx.x} * TILE + threadIdx.x; base < cnt; base += int64_t{gridDim.x} * TILE) {
+    int64_t k[ITEMS], pl[ITEMS], s[ITEMS];
+    unsigned long long old[ITEMS];
+    bool live[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int64_t i = base + int64_t{j} * BLOCK;
+      const int64_t row = i < cnt ? row_of(sel, i) : 0;
+      k[j] = kEmpty64;
+      live[j] = i < cnt && join_key(key, key64, row, k[j]);
+      if (i < cnt && !live[j]) latch(err, kErrKey);
+      pl[j] = payload ? (live[j] ? load_as_i64(payload, pay64, row) : 0) : row;
+      s[j] = static_cast<int64_t>(table_hash64(k[j])) & mask;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) old[j] = live[j] ? slots[2 * s[j]] : kE;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (live[j] && old[j] == kE) old[j] = atomicCAS(&slots[2 * s[j]], kE, static_cast<unsigned long long>(k[j]));
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (!live[j]) continue;
+      int64_t p = s[j];
+      bool done = old[j] == kE, dup = false;  // done: took its home slot
+      unsigned long long cur = old[j];
+      for (int64_t step = 0; !done && step <= mask; ++step) {
+        if (unique && static_cast<int64_t>(cur) == k[j]) {
+          dup = true;
+          break;
+        }
+        p = (p + 1) & mask;
+        cur = slots[2 * p];
+        if (cur == kE) {
+          cur = atomicCAS(&slots[2 * p], kE, static_cast<unsigned long long>(k[j]));
+          done = cur == kE;
+        }
+      }
+      if (done) slots[2 * p + 1] = static_cast<unsigned long long>(pl[j]);
+      else latch(err, dup ? kErrDup : kErrTableFull);
+    }
+  }
+}
+
 // Probe the key+payload table two slots (16 bytes) per load; calls on_match(payload)
 // for each match in table order until on_match returns false or an EMPTY slot ends the run.
 template <typename F>
@@ -732,13 +804,44 @@ __device__ __forceinline__ bool visit_pair(ulonglong2 pair, int32_t k, int uniqu
   return true;
 }
 
+// The same for one slot {key, payload} of a wide table.
+__device__ __forceinline__ bool visit_wide(ulonglong2 slot, int64_t k, int unique, int32_t &c, int64_t &first) {
+  const int64_t key = static_cast<int64_t>(slot.x);
+  if (key == k) {
+    if (c == 0) first = static_cast<int64_t>(slot.y);
+    ++c;
+    return !unique;
+  }
+  return key != kEmpty64;
+}
+
+// Walks the run of k in a wide table, calling on_match(payload) per match
+// until it returns false or an EMPTY slot ends the run.
+template <typename F>
+__device__ __forceinline__ void probe_wide(const uint64_t *slots, int64_t mask, int64_t k, F &&on_match) {
+  int64_t s = static_cast<int64_t>(table_hash64(k)) & mask;
+  for (int64_t step = 0; step <= mask; ++step) {
+    const ulonglong2 sl = *reinterpret_cast<const ulonglong2 *>(&slots[2 * s]);
+    if (static_cast<int64_t>(sl.x) == k) {
+      if (!on_match(static_cast<int64_t>(sl.y))) return;
+    } else if (static_cast<int64_t>(sl.x) == kEmpty64) {
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
 // Each lane probes ITEMS rows, one wave64 row apart: the keys, then the ITEMS
-// home groups are loaded together, and only rows whose run goes on past their
-// home group walk on.  A probe key equal to EMPTY matches nothing.
-template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_join_probe(const int32_t *key, const int32_t *sel, const int64_t *d_nsel,
-                                                     int64_t n, TableDev t, int unique, int32_t *out_row,
-                                                     int32_t *out_pay, int64_t out_cap, int64_t *d_nout,
+// home groups (narrow table: two slots; wide: one) are loaded together, and
+// only rows whose run goes on past their home group walk on.  Keys compare by
+// value: an int64 probe key outside int32 range matches nothing in a narrow
+// table, and a probe key equal to its column's EMPTY sentinel matches nothing.
+// K64: the probe key column is int64.  PayT: int64 for stored payloads, int32
+// for the build rows of a materializing join.
+template <int BLOCK, int ITEMS, bool WIDE, bool K64, typename PayT>
+__global__ __launch_bounds__(BLOCK) void k_join_probe(const void *key, const int32_t *sel,
+                                                     const int64_t *d_nsel, int64_t n, TableDev t, int unique,
+                                                     int32_t *out_row, PayT *out_pay, int64_t out_cap, int64_t *d_nout,
                                                      uint64_t *status, unsigned long long *ticket, int64_t ntiles,
                                                      uint32_t *err) {
   constexpr int NW = BLOCK / kWave;
@@ -753,32 +856,51 @@ __global__ __launch_bounds__(BLOCK) void k_join_probe(const int32_t *key, const 
   const uint64_t *slots = static_cast<const uint64_t *>(t.slots);
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = tile * TILE + int64_t{w} * kWave * ITEMS;
-  int32_t kk[ITEMS], c[ITEMS], first_pay[ITEMS];
+  constexpr int64_t GS = WIDE ? 1 : 2;  // slots per 16-byte group
+  using KeyT = std::conditional_t<K64, int64_t, int32_t>;              // probe column
+  using CmpT = std::conditional_t<WIDE || K64, int64_t, int32_t>;      // key as held
+  using StoredT = std::conditional_t<WIDE, int64_t, int32_t>;          // table payload
+  constexpr KeyT kColEmpty = K64 ? kEmpty64 : kEmpty32;
+  CmpT kk[ITEMS];
+  StoredT first_pay[ITEMS];
+  int32_t c[ITEMS];
   int64_t s[ITEMS];
   ulonglong2 g[ITEMS];
   bool live[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const int64_t i = wbase + int64_t{j} * kWave + lane;
-    kk[j] = i < cnt ? key[row_of(sel, i)] : kEmpty32;
-    live[j] = kk[j] != kEmpty32;
+    const KeyT v = i < cnt ? static_cast<const KeyT *>(key)[row_of(sel, i)] : kColEmpty;
+    kk[j] = v;
+    live[j] = v != kColEmpty;
+    if (!WIDE && K64) live[j] = live[j] && v > kEmpty32 && v <= INT32_MAX;  // fits the int32 table keys
   }
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    s[j] = (table_hash32(kk[j]) & mask) & ~int64_t{1};
-    g[j] = live[j] ? *reinterpret_cast<const ulonglong2 *>(&slots[s[j]]) : ulonglong2{kEmptySlot, kEmptySlot};
+    if (WIDE) {
+      s[j] = static_cast<int64_t>(table_hash64(static_cast<int64_t>(kk[j]))) & mask;
+      g[j] = live[j] ? *reinterpret_cast<const ulonglong2 *>(&slots[2 * s[j]])
+                     : ulonglong2{static_cast<uint64_t>(kEmpty64), 0};
+    } else {
+      s[j] = (table_hash32(static_cast<int32_t>(kk[j])) & mask) & ~int64_t{1};
+      g[j] = live[j] ? *reinterpret_cast<const ulonglong2 *>(&slots[s[j]]) : ulonglong2{kEmptySlot, kEmptySlot};
+    }
   }
+  auto visit = [&](ulonglong2 x, int j) {
+    if constexpr (WIDE) return visit_wide(x, kk[j], unique, c[j], first_pay[j]);
+    else return visit_pair(x, static_cast<int32_t>(kk[j]), unique, c[j], first_pay[j]);
+  };
   int64_t wave_total = 0;
   int64_t lane_off[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     c[j] = 0;
     first_pay[j] = 0;
-    if (live[j] && visit_pair(g[j], kk[j], unique, c[j], first_pay[j])) {
+    if (live[j] && visit(g[j], j)) {
       int64_t p = s[j];
-      for (int64_t step = 2; step <= mask; step += 2) {
-        p = (p + 2) & mask;
-        if (!visit_pair(*reinterpret_cast<const ulonglong2 *>(&slots[p]), kk[j], unique, c[j], first_pay[j])) break;
+      for (int64_t step = GS; step <= mask; step += GS) {
+        p = (p + GS) & mask;
+        if (!visit(*reinterpret_cast<const ulonglong2 *>(&slots[WIDE ? 2 * p : p]), j)) break;
       }
     }
     const int64_t incl = wave_inclusive_scan<int64_t>(c[j]);
@@ -811,17 +933,19 @@ __global__ __launch_bounds__(BLOCK) void k_join_probe(const int32_t *key, const 
     if (c[j] == 1) {
       if (p < out_cap) {
         out_row[p] = row;
-        out_pay[p] = first_pay[j];
+        out_pay[p] = static_cast<PayT>(first_pay[j]);
       }
     } else {
-      probe_kp(slots, mask, key[row], [&](int32_t pl) {
+      auto emit = [&](int64_t pl) {
         if (p < out_cap) {
           out_row[p] = row;
-          out_pay[p] = pl;
+          out_pay[p] = static_cast<PayT>(pl);
         }
         ++p;
         return true;
-      });
+      };
+      if constexpr (WIDE) probe_wide(slots, mask, kk[j], emit);
+      else probe_kp(slots, mask, static_cast<int32_t>(kk[j]), emit);
     }
   }
 }
@@ -1098,21 +1222,36 @@ pyst_status table_init(const TableDev &t, const int64_t *d_nsel, int64_t n, doub
   return PYST_OK;
 }
 
-// Table init + insertion of the selected rows of an int32 key column.
-pyst_status launch_join_build(pyst_ctx *ctx, const TableDev &t, const pyst_col *key, const int32_t *payload,
+// Slot size of a join table: 8 bytes for int32 keys with int32 payloads (or
+// row ids), 16 for int64 keys or int64 payloads.
+static int join_slot_bytes(const pyst_col *key, const pyst_col *payload) {
+  return key->dtype == PYST_I64 || (payload && payload->dtype == PYST_I64) ? 16 : 8;
+}
+
+// Table init + insertion of the selected rows (payload: a column of the key's
+// length, or null for row ids); t.slot_bytes is join_slot_bytes of the columns.
+pyst_status launch_join_build(pyst_ctx *ctx, const TableDev &t, const pyst_col *key, const pyst_col *payload,
                               const int32_t *sel, const int64_t *d_nsel, double max_load, int unique,
                               hipStream_t stream) {
   pyst_status st = table_init(t, d_nsel, key->n, max_load, stream);
   if (st != PYST_OK || key->n == 0) return st;
   const int blocks = grid_for(ctx, ceil_div(key->n, int64_t{kBuildItems}), 256, 8);
-  k_join_build<256, kBuildItems><<<blocks, 256, 0, stream>>>(static_cast<const int32_t *>(key->data), payload, sel,
-                                                             d_nsel, key->n, t, unique, ctx_err_word(ctx));
+  if (t.slot_bytes == 16) {
+    k_join_build_wide<256, kBuildItems><<<blocks, 256, 0, stream>>>(
+        key->data, key->dtype == PYST_I64, payload ? payload->data : nullptr, payload && payload->dtype == PYST_I64,
+        sel, d_nsel, key->n, t, unique, ctx_err_word(ctx));
+  } else {
+    k_join_build<256, kBuildItems><<<blocks, 256, 0, stream>>>(
+        static_cast<const int32_t *>(key->data), payload ? static_cast<const int32_t *>(payload->data) : nullptr, sel,
+        d_nsel, key->n, t, unique, ctx_err_word(ctx));
+  }
   PYST_LAUNCH_CHECK("k_join_build");
   return PYST_OK;
 }
 
+template <typename PayT>
 pyst_status launch_join_probe(pyst_ctx *ctx, const TableDev &t, int unique, const pyst_col *key, const int32_t *sel,
-                              const int64_t *d_nsel, int32_t *out_row, int32_t *out_pay, int64_t out_cap,
+                              const int64_t *d_nsel, int32_t *out_row, PayT *out_pay, int64_t out_cap,
                               int64_t *d_nout, hipStream_t stream) {
   constexpr int BLOCK = 256, ITEMS = 8;
   const int64_t ntiles = std::max<int64_t>(1, ceil_div(key->n, int64_t{BLOCK} * ITEMS));
@@ -1121,9 +1260,22 @@ pyst_status launch_join_probe(pyst_ctx *ctx, const TableDev &t, int unique, cons
   pyst_status st = fill_u64(sc.p, ntiles + 1, 0, stream);
   if (st != PYST_OK) return st;
   uint64_t *status = sc.as<uint64_t>();
-  k_join_probe<BLOCK, ITEMS><<<static_cast<unsigned>(ntiles), BLOCK, 0, stream>>>(
-      static_cast<const int32_t *>(key->data), sel, d_nsel, key->n, t, unique, out_row, out_pay, out_cap, d_nout,
-      status, reinterpret_cast<unsigned long long *>(status + ntiles), ntiles, ctx_err_word(ctx));
+  auto *ticket = reinterpret_cast<unsigned long long *>(status + ntiles);
+  const unsigned grid = static_cast<unsigned>(ntiles);
+  uint32_t *err = ctx_err_word(ctx);
+  const bool wide = t.slot_bytes == 16, k64 = key->dtype == PYST_I64;
+  if (wide && k64)
+    k_join_probe<BLOCK, ITEMS, true, true, PayT><<<grid, BLOCK, 0, stream>>>(
+        key->data, sel, d_nsel, key->n, t, unique, out_row, out_pay, out_cap, d_nout, status, ticket, ntiles, err);
+  else if (wide)
+    k_join_probe<BLOCK, ITEMS, true, false, PayT><<<grid, BLOCK, 0, stream>>>(
+        key->data, sel, d_nsel, key->n, t, unique, out_row, out_pay, out_cap, d_nout, status, ticket, ntiles, err);
+  else if (k64)
+    k_join_probe<BLOCK, ITEMS, false, true, PayT><<<grid, BLOCK, 0, stream>>>(
+        key->data, sel, d_nsel, key->n, t, unique, out_row, out_pay, out_cap, d_nout, status, ticket, ntiles, err);
+  else
+    k_join_probe<BLOCK, ITEMS, false, false, PayT><<<grid, BLOCK, 0, stream>>>(
+        key->data, sel, d_nsel, key->n, t, unique, out_row, out_pay, out_cap, d_nout, status, ticket, ntiles, err);
   PYST_LAUNCH_CHECK("k_join_probe");
   return PYST_OK;
 }
@@ -1316,24 +1468,23 @@ pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *
   if (!ctx || !key || !out) return set_error(PYST_ERR_ARG, "pyst_join_build: NULL argument");
   *out = nullptr;
   if (!col_ok(key)) return set_error(PYST_ERR_ARG, "pyst_join_build: bad key column");
-  if (key->dtype != PYST_I32) return set_error(PYST_ERR_UNSUPPORTED, "pyst_join_build: join keys are int32");
-  if (payload && (!col_ok(payload) || payload->dtype != PYST_I32 || payload->n != key->n))
-    return set_error(PYST_ERR_ARG, "pyst_join_build: payload must be int32 with the key's length");
+  if (payload && (!col_ok(payload) || payload->n != key->n))
+    return set_error(PYST_ERR_ARG, "pyst_join_build: payload must be a column of the key's length");
   if (!(max_load > 0.0 && max_load <= 0.95)) return set_error(PYST_ERR_ARG, "pyst_join_build: max_load in (0, 0.95]");
   if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_join_build: sel and d_nsel go together");
   TimedRegion timed(ctx, "join_build", stream);
   const int64_t cap_alloc = table_capacity_host(key->n, max_load);
-  const size_t bytes = table_bytes(cap_alloc, 8, false);
+  const int slot_bytes = join_slot_bytes(key, payload);
+  const size_t bytes = table_bytes(cap_alloc, slot_bytes, false);
   void *mem = ctx_alloc(ctx, bytes, stream);
   if (!mem) return set_error(PYST_ERR_NOMEM, "pyst_join_build: arena exhausted");
   auto *t = new pyst_table();
   t->ctx = ctx;
   t->mem = mem;
-  t->dev = table_view(mem, cap_alloc, 8, false);
+  t->dev = table_view(mem, cap_alloc, slot_bytes, false);
   t->unique = unique_keys != 0;
   t->stream = stream;
-  pyst_status st = launch_join_build(ctx, t->dev, key, payload ? static_cast<const int32_t *>(payload->data) : nullptr,
-                                     sel, d_nsel, max_load, t->unique, stream);
+  pyst_status st = launch_join_build(ctx, t->dev, key, payload, sel, d_nsel, max_load, t->unique, stream);
   if (st != PYST_OK) {
     pyst_table_destroy(t, stream);
     return st;
@@ -1343,11 +1494,10 @@ pyst_status pyst_join_build(pyst_ctx *ctx, const pyst_col *key, const pyst_col *
 }
 
 pyst_status pyst_join_probe(pyst_ctx *ctx, const pyst_table *table, const pyst_col *key, const int32_t *sel,
-                            const int64_t *d_nsel, int32_t *out_probe_row, int32_t *out_payload, int64_t out_cap,
+                            const int64_t *d_nsel, int32_t *out_probe_row, int64_t *out_payload, int64_t out_cap,
                             int64_t *d_nout, hipStream_t stream) {
   if (!ctx || !table || !key || !d_nout) return set_error(PYST_ERR_ARG, "pyst_join_probe: NULL argument");
   if (!col_ok(key)) return set_error(PYST_ERR_ARG, "pyst_join_probe: bad key column");
-  if (key->dtype != PYST_I32) return set_error(PYST_ERR_UNSUPPORTED, "pyst_join_probe: join keys are int32");
   if (out_cap < 0 || (out_cap > 0 && (!out_probe_row || !out_payload)))
     return set_error(PYST_ERR_ARG, "pyst_join_probe: bad output");
   if ((sel == nullptr) != (d_nsel == nullptr)) return set_error(PYST_ERR_ARG, "pyst_join_probe: sel and d_nsel go together");
@@ -1375,8 +1525,7 @@ pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, cons
                                   int unique_keys, void *const *out_cols, int32_t *out_probe_row,
                                   int32_t *out_build_row, int64_t out_cap, int64_t *d_nout, hipStream_t stream) {
   if (!ctx || !build_key || !probe_key || !d_nout) return set_error(PYST_ERR_ARG, "pyst_join_materialize: NULL argument");
-  if (!col_ok(build_key) || !col_ok(probe_key) || build_key->dtype != PYST_I32 || probe_key->dtype != PYST_I32)
-    return set_error(PYST_ERR_ARG, "pyst_join_materialize: keys are int32 columns");
+  if (!col_ok(build_key) || !col_ok(probe_key)) return set_error(PYST_ERR_ARG, "pyst_join_materialize: bad key column");
   if (!(max_load > 0.0 && max_load <= 0.95)) return set_error(PYST_ERR_ARG, "pyst_join_materialize: max_load in (0, 0.95]");
   if (out_cap < 0 || out_cap > INT32_MAX || (out_cap > 0 && (!out_probe_row || !out_build_row)))
     return set_error(PYST_ERR_ARG, "pyst_join_materialize: bad output");
@@ -1395,9 +1544,10 @@ pyst_status pyst_join_materialize(pyst_ctx *ctx, const pyst_col *build_key, cons
     if (ga[side].nsrc != keys[side]->n) return set_error(PYST_ERR_ARG, "pyst_join_materialize: column length differs from its key");
   }
   const int64_t cap_alloc = table_capacity_host(build_key->n, max_load);
-  Scratch mem(ctx, table_bytes(cap_alloc, 8, false), stream);
+  const int slot_bytes = join_slot_bytes(build_key, nullptr);
+  Scratch mem(ctx, table_bytes(cap_alloc, slot_bytes, false), stream);
   if (!mem.p) return set_error(PYST_ERR_NOMEM, "pyst_join_materialize: arena exhausted");
-  const TableDev t = table_view(mem.p, cap_alloc, 8, false);
+  const TableDev t = table_view(mem.p, cap_alloc, slot_bytes, false);
   pyst_status st;
   {
     TimedRegion timed(ctx, "join_build", stream);

@@ -685,6 +685,21 @@ pyst_status pyst_server_wait(pyst_server *sv, uint64_t ticket, double *latency_m
   return PYST_OK;
 }
 
+pyst_status pyst_server_poll(pyst_server *sv, uint64_t ticket, int *done, double *latency_ms) {
+  if (!sv || !done) return set_error(PYST_ERR_ARG, "pyst_server_poll: NULL argument");
+  *done = 0;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return set_error(PYST_ERR_ARG, "pyst_server_poll: unknown ticket");
+  auto r = it->second;
+  if (!r->completed) return PYST_OK;
+  *done = 1;
+  if (latency_ms) *latency_ms = ms_between(r->t_submit, r->t_done);
+  sv->all.erase(it);
+  if (r->status != PYST_OK) return set_error(r->status, "pyst_server_poll: request failed");
+  return PYST_OK;
+}
+
 pyst_status pyst_server_get_stats(pyst_server *sv, pyst_server_stats *out) {
   if (!sv || !out) return set_error(PYST_ERR_ARG, "pyst_server_get_stats: NULL argument");
   std::lock_guard<std::mutex> lk(sv->mu);

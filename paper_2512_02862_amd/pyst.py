@@ -33,7 +33,7 @@ EXPORTS = [
     "pyst_query_streamed_packed", "pyst_table_info", "pyst_table_destroy", "pyst_groupby_sum", "pyst_query", "pyst_ctx_timing",
     "pyst_ctx_kernel_time", "pyst_ctx_option", "pyst_query_streamed", "pyst_query_batch", "pyst_autotune",
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
-    "pyst_server_create", "pyst_server_create_packed", "pyst_server_submit", "pyst_server_wait", "pyst_server_get_stats", "pyst_server_check",
+    "pyst_server_create", "pyst_server_create_packed", "pyst_server_submit", "pyst_server_wait", "pyst_server_poll", "pyst_server_get_stats", "pyst_server_check",
     "pyst_server_destroy", "pyst_server_forget_tables", "pyst_server_option", "pyst_partition_noalloc",
 ]
 
@@ -154,6 +154,7 @@ def load(path: str = LIB_PATH):
         "pyst_server_create_packed": ([i32, P(ServerCfg), P(PackedCol), i32, P(p)], i32),
         "pyst_server_submit": ([p, P(Request), P(ctypes.c_uint64)], i32),
         "pyst_server_wait": ([p, ctypes.c_uint64, P(ctypes.c_double)], i32),
+        "pyst_server_poll": ([p, ctypes.c_uint64, P(ctypes.c_int), P(ctypes.c_double)], i32),
         "pyst_server_get_stats": ([p, P(ServerStats)], i32),
         "pyst_server_check": ([p], i32),
         "pyst_server_destroy": ([p], None),
@@ -341,11 +342,11 @@ def join_build(ctx: Ctx, key, payload=None, sel=None, nsel=None, max_load=0.5, u
 
 
 def join_probe(ctx: Ctx, table: Table, key, sel=None, nsel=None, out_cap=None, stream=None):
-    """(probe rows int32, payloads int32, count int64[1]); outputs have out_cap entries."""
+    """(probe rows int32, payloads int64, count int64[1]); outputs have out_cap entries."""
     n = key.numel()
     cap = n if out_cap is None else out_cap
     rows = torch.empty(max(cap, 1), dtype=torch.int32, device=_dev(ctx))
-    pays = torch.empty(max(cap, 1), dtype=torch.int32, device=_dev(ctx))
+    pays = torch.empty(max(cap, 1), dtype=torch.int64, device=_dev(ctx))
     nout = torch.empty(1, dtype=torch.int64, device=_dev(ctx))
     kc = col(key)
     _check(_lib.pyst_join_probe(ctx.h, table.h, ctypes.byref(kc), _sel_ptr(sel), _ptr(nsel), _ptr(rows), _ptr(pays),
@@ -653,6 +654,17 @@ class Server:
     def wait(self, ticket):
         lat = ctypes.c_double()
         st = _lib.pyst_server_wait(self.h, ticket, ctypes.byref(lat))
+        ok, osum, ng, _ = self._live.pop(ticket)
+        _check(st)
+        m = int(ng.item())
+        return ok[:m], osum[:m], lat.value
+
+    def poll(self, ticket):
+        """None while the request runs; then (keys, sums, latency_ms) as wait() returns them."""
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        st = _lib.pyst_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(lat))
+        if st == OK and not done.value:
+            return None
         ok, osum, ng, _ = self._live.pop(ticket)
         _check(st)
         m = int(ng.item())

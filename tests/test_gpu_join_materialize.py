@@ -122,6 +122,48 @@ def test_join_materialize_matches_oracle(gpu, ctx, nb, npr, k):
         np.testing.assert_array_equal(host(g, m), w)
 
 
+@pytest.mark.parametrize("unique", [True, False])
+def test_join_materialize_int64_keys(gpu, ctx, unique):
+    # int64 keys (16-byte table slots): keys above 2^32 and a mixed-width probe
+    rng = np.random.default_rng(44)
+    nb, npr = 40_000, 300_000
+    base = np.unique(np.concatenate([rng.integers(-2**62, 2**62, nb, dtype=np.int64),
+                                     rng.integers(-2**31 + 1, 2**31, 1000, dtype=np.int64), [-2**31]]))
+    bk = base if unique else base[rng.integers(0, len(base), len(base))]
+    pk = np.concatenate([bk[rng.integers(0, len(bk), npr // 2)], rng.integers(-2**62, 2**62, npr // 2, dtype=np.int64)])
+    pk = pk[rng.permutation(len(pk))]
+    bc = [rng.integers(-2**40, 2**40, len(bk), dtype=np.int64)]
+    pc = [rng.integers(-2**31, 2**31 - 1, len(pk), dtype=np.int64).astype(np.int32)]
+    wp, wb, wcols = oracle.join_materialize(bk, bc, pk, pc)
+    prow, brow, cols, nout = gpu.join_materialize(ctx, dev(bk), [dev(c) for c in bc], dev(pk), [dev(c) for c in pc],
+                                                  unique_keys=unique, out_cap=len(wp) + 8)
+    ctx.check()
+    m = int(host(nout)[0])
+    assert m == len(wp) and m > npr // 4
+    gp, gb = host(prow, m), host(brow, m)
+    o = np.lexsort((gb, gp))
+    np.testing.assert_array_equal(gp[o], wp)
+    np.testing.assert_array_equal(gb[o], wb)
+    for g, w in zip(cols, wcols):
+        np.testing.assert_array_equal(host(g, m)[o], w)
+    # an int32 probe column against the int64 table compares by value
+    # (INT32_MIN, an ordinary int64 build key, is the int32 probe column's EMPTY: no match)
+    small = bk[(bk > -2**31) & (bk < 2**31)]
+    assert len(small) >= 900
+    pk32 = np.concatenate([small, [0, 1]]).astype(np.int32)
+    wp, wb, _ = oracle.join_materialize(bk, [], pk32, [])  # without the last probe row below
+    pk32 = np.append(pk32, np.int32(-2**31))
+    prow, brow, _, nout = gpu.join_materialize(ctx, dev(bk), [], dev(pk32), [], unique_keys=unique,
+                                               out_cap=len(wp) + 8)
+    ctx.check()
+    m = int(host(nout)[0])
+    assert m == len(wp)
+    gp, gb = host(prow, m), host(brow, m)
+    o = np.lexsort((gb, gp))
+    np.testing.assert_array_equal(gp[o], wp)
+    np.testing.assert_array_equal(gb[o], wb)
+
+
 def test_join_materialize_one_side_and_empty(gpu, ctx):
     b, p = gen.join_tables(4000, 30_000, 2)
     bc, pc = [b["c0"], b["c1"]], [p["c0"], p["c1"]]

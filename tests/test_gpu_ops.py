@@ -181,6 +181,77 @@ def test_join_sentinel_key_and_duplicate_promise(gpu, ctx):
     ctx.check()  # the latch was cleared
 
 
+@pytest.mark.parametrize("bdt,pdt,paydt,unique", [
+    (np.int64, np.int64, None, True),
+    (np.int64, np.int64, np.int64, False),
+    (np.int32, np.int32, np.int64, True),
+    (np.int32, np.int64, None, False),
+    (np.int64, np.int32, np.int32, True),
+])
+def test_join_int64_keys_and_payloads(gpu, ctx, bdt, pdt, paydt, unique):
+    # keys spread over the whole int64 (or int32) range; the probe also holds
+    # keys no build row has, keys outside int32 range and each column's EMPTY
+    rng = np.random.default_rng(31)
+    lo, hi = (np.iinfo(bdt).min + 1, np.iinfo(bdt).max)
+    n_keys = 30_000
+    pool = np.unique(np.concatenate([rng.integers(lo, hi, n_keys, dtype=np.int64, endpoint=True),
+                                     rng.integers(-2**31 + 1, 2**31 - 1, n_keys, dtype=np.int64, endpoint=True)]))
+    if unique:
+        bk = rng.permutation(pool).astype(bdt)
+    else:
+        bk = pool[rng.integers(0, len(pool), 2 * len(pool))].astype(bdt)
+    plo, phi = np.iinfo(pdt).min + 1, np.iinfo(pdt).max
+    hits = bk.astype(np.int64)[rng.integers(0, len(bk), 150_000)]
+    hits = hits[(hits >= plo) & (hits <= phi)]
+    miss = rng.integers(plo, phi, 50_000, dtype=np.int64, endpoint=True)
+    pk = np.concatenate([hits, miss, [np.iinfo(pdt).min] * 7]).astype(pdt)
+    pk = pk[rng.permutation(len(pk))]
+    pay = None
+    if paydt is not None:
+        pay = rng.integers(np.iinfo(paydt).min, np.iinfo(paydt).max, len(bk), dtype=np.int64, endpoint=True).astype(paydt)
+    t = gpu.join_build(ctx, dev(bk), dev(pay) if pay is not None else None, max_load=0.5, unique_keys=unique)
+    wr, wb = oracle.join(bk, pk)
+    rows, pays, nout = gpu.join_probe(ctx, t, dev(pk), out_cap=len(wr) + 16)
+    ctx.check()
+    m = int(host(nout)[0])
+    assert m == len(wr) and m > 50_000
+    got_r, got_p = host(rows, m), host(pays, m)
+    assert np.all(np.diff(got_r) >= 0)  # ascending probe row
+    want_p = (pay.astype(np.int64) if pay is not None else np.arange(len(bk), dtype=np.int64))[wb]
+    o = np.lexsort((got_p, got_r))
+    w = np.lexsort((want_p, wr))
+    np.testing.assert_array_equal(got_r[o], wr[w])
+    np.testing.assert_array_equal(got_p[o], want_p[w])
+    t.destroy()
+
+
+def test_join_int64_sentinel_and_duplicate_promise(gpu, ctx):
+    e64 = np.iinfo(np.int64).min
+    t = gpu.join_build(ctx, dev(np.array([1, e64, 3], np.int64)))
+    with pytest.raises(gpu.PystError) as e:
+        ctx.check()
+    assert e.value.status == gpu.ERR_KEY
+    t.destroy()
+    t = gpu.join_build(ctx, dev(np.array([2**40, 7, 2**40], np.int64)), unique_keys=True)
+    with pytest.raises(gpu.PystError) as e:
+        ctx.check()
+    assert e.value.status == gpu.ERR_DUP_KEY
+    t.destroy()
+    # INT32_MIN is an ordinary key in an int64 column; in an int32 probe column
+    # it is that column's EMPTY and matches nothing
+    t = gpu.join_build(ctx, dev(np.array([-2**31, 5], np.int64)))
+    rows, pays, nout = gpu.join_probe(ctx, t, dev(np.array([-2**31, 5, 6], np.int64)))
+    ctx.check()
+    assert int(host(nout)[0]) == 2
+    np.testing.assert_array_equal(host(rows, 2), [0, 1])
+    np.testing.assert_array_equal(host(pays, 2), [0, 1])
+    rows, pays, nout = gpu.join_probe(ctx, t, dev(np.array([-2**31, 5], np.int32)))
+    ctx.check()
+    assert int(host(nout)[0]) == 1
+    assert host(rows, 1)[0] == 1 and host(pays, 1)[0] == 1
+    t.destroy()
+
+
 # ------------------------------------------------------------------ group-by
 
 @pytest.mark.parametrize("n,nkeys", [(1, 1), (10_000, 10), (500_000, 200_000), (2_000_000, 1_000_000)])

@@ -251,3 +251,41 @@ def test_server_evicts_idle_tables_when_memory_is_short(gpu, db):
         wk, ws = expected("star", a, b, f, 300_000 + i)
         np.testing.assert_array_equal(sorted_np(k, s)[1], ws)
     srv.close()
+
+
+def test_server_poll_reports_each_request_once(gpu, db):
+    # poll never blocks: a client loop collects every request by polling alone
+    import time
+    a, b, f, host, ad, bd = db
+    rows = [NF, 700_001, 1, 2_000_000]
+    srv = gpu.Server(host, budget=1 << 30, max_active=2, nbuf=2, chunk_rows=250_000)
+    kinds = ["chain", "star", "star", "chain"]
+    tickets = {}
+    for kind, r in zip(kinds, rows):
+        plan, cap = plan_for(gpu, kind, ad, bd)
+        tickets[srv.submit(plan, r, cap)] = (kind, r)
+    got, polls = {}, 0
+    deadline = time.monotonic() + 60
+    while len(got) < len(tickets) and time.monotonic() < deadline:
+        for t in tickets:
+            if t in got:
+                continue
+            polls += 1
+            res = srv.poll(t)
+            if res is not None:
+                got[t] = res
+        time.sleep(0.001)
+    assert len(got) == len(tickets)
+    assert polls > len(tickets)  # the first poll of the full-size chain request found it running
+    for t, (kind, r) in tickets.items():
+        k, s, lat = got[t]
+        assert lat > 0
+        wk, ws = expected(kind, a, b, f, r)
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, wk)
+        np.testing.assert_array_equal(gs, ws)
+    with pytest.raises(gpu.PystError) as e:  # reported once, then unknown
+        gpu._check(gpu._lib.pyst_server_poll(srv.h, next(iter(tickets)), gpu.ctypes.byref(gpu.ctypes.c_int()), None))
+    assert e.value.status == gpu.ERR_ARG
+    srv.check()
+    srv.close()
