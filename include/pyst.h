@@ -137,6 +137,12 @@ pyst_status pyst_ctx_timing(pyst_ctx *ctx, int enable);
    issued through the context from now on fail on the host with PYST_ERR_HIP
    before it launches anything (0 clears it).  No device fault is involved. */
 #define PYST_OPT_FAIL_FACT_PASS 3
+/* PYST_OPT_HASH_JOIN_ONLY != 0 keeps pyst_query's join tables hash tables:
+   without it, a one-join query grouped by the join key direct-addresses its
+   dimension table (key k in slot k - min key) when the selected dimension
+   keys span at most 2^21 values and no more than the table's reserved slots.
+   Both compute the same result; tests compare them. */
+#define PYST_OPT_HASH_JOIN_ONLY 4
 pyst_status pyst_ctx_option(pyst_ctx *ctx, int key, int64_t value);
 pyst_status pyst_ctx_kernel_time(pyst_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 

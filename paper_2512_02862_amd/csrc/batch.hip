@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kFastBlock) void k_bat_sums(const BatFrag *frags, c
   __shared__ uint32_t s_wsum[kFastBlock / kWave];
   __shared__ int64_t s_base;
   bucket_sums_block(fr.t, fr.bp, static_cast<uint32_t>(local), fr.out_keys, fr.out_sums, fr.out_cap, fr.d_ngroups,
-                    err, s_sum, s_bits, s_wsum, &s_base);
+                    err, s_sum, s_bits, s_wsum, &s_base, false);
 }
 
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {

@@ -47,6 +47,7 @@ struct pyst_ctx {
   bool timing = false;
   bool generic_only = false;  // PYST_OPT_GENERIC_ONLY
   bool groupby_hash_only = false;  // PYST_OPT_GROUPBY_HASH_ONLY
+  bool hash_join_only = false;  // PYST_OPT_HASH_JOIN_ONLY
   hipStream_t copy_stream = nullptr;  // host-to-device chunk copies (created on first use)
   char *staging = nullptr;            // pinned host staging for descriptor uploads
   size_t staging_bytes = 0;
@@ -258,6 +259,7 @@ pyst_status status_of_error_bits(uint32_t bits) {
 }
 bool ctx_generic_only(const pyst_ctx *c) { return c->generic_only; }
 bool ctx_groupby_hash_only(const pyst_ctx *c) { return c->groupby_hash_only; }
+bool ctx_hash_join_only(const pyst_ctx *c) { return c->hash_join_only; }
 
 // Bytes not currently allocated (free or pending reuse); an allocation of this
 // size may still fail when the space is fragmented.
@@ -383,6 +385,7 @@ pyst_status pyst_ctx_option(pyst_ctx *c, int key, int64_t value) {
   switch (key) {
     case PYST_OPT_GENERIC_ONLY: c->generic_only = value != 0; return PYST_OK;
     case PYST_OPT_GROUPBY_HASH_ONLY: c->groupby_hash_only = value != 0; return PYST_OK;
+    case PYST_OPT_HASH_JOIN_ONLY: c->hash_join_only = value != 0; return PYST_OK;
     case PYST_OPT_FAIL_FACT_PASS: c->fail_pass_countdown = value > 0 ? value : 0; return PYST_OK;
   }
   return set_error(PYST_ERR_ARG, "pyst_ctx_option: unknown option");

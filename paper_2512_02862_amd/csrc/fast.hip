@@ -45,19 +45,32 @@ constexpr int kBufferDword3 = 0x00020000;           // raw buffer resource word 
 // stages (slot, value) pairs in LDS and moves them, bucket by bucket of
 // kBucketSlots slots, into chunks in HBM; a second kernel adds each bucket up
 // in LDS.  That costs 8 bytes written and read per matching row (a value that
-// does not fit in 51 bits is added directly).
+// does not fit in 43 bits is added directly).
 constexpr int kBucketLg = 13;
 constexpr int64_t kBucketSlots = int64_t{1} << kBucketLg;  // 64 KiB of LDS sums in the second kernel
-constexpr int kMaxBuckets = 128;                            // staged join tables: up to 2^20 slots
+constexpr int kMaxBuckets = 256;                            // staged join tables: up to 2^21 slots
 constexpr int kMaxSumBuckets = 512;                         // second-kernel blocks: tables up to 2^22 slots
-constexpr uint32_t kStageCap = 3712;                        // staged pairs per block (29 KiB: the LDS the filter leaves)
+constexpr uint32_t kStageCap = 3448;                        // staged pairs per block (27 KiB: the LDS the filter leaves)
 constexpr uint32_t kFlushAt = 1024;                         // staged pairs that trigger a move to HBM
 constexpr uint32_t kCheckMax = 8;                           // most steps between the block's staging checks
-constexpr int kStageSlotBits = 20;                          // slot bits of a staged pair: kMaxBuckets buckets
+constexpr int kStageSlotBits = 21;                          // slot bits of a staged pair: kMaxBuckets buckets
 constexpr int kStarRows = 4;                                // rows per lane and step of the staged fact pass
 constexpr uint32_t kChunkLg = 9;                            // pairs per chunk of the single query: 512
 constexpr uint32_t kChunk = 1u << kChunkLg;
 constexpr uint32_t kNoChunk = 0xffffffffu;
+
+// Direct addressing (the first join table of a query summed in its slots):
+// when the selected dimension keys span a range [kmin, kmin + range) with
+// range <= the memory reserved for the hash table and <= 2^kStageSlotBits,
+// key k owns slot k - kmin.  The table is then a bitmap of the selected keys
+// over the range (in the key array's memory), so a probe is one bit and never
+// walks; the LDS filter holds the bitmap itself (range <= 2^20 bits: exact) or
+// each pair of its bits ORed into one (range <= 2^21: the exact bit is read
+// from the bitmap in the L2).  The table initializer decides on the device,
+// from the selected keys' minimum and maximum, and records the mode in the
+// table header (TableDev::hdr[kHdrDirect], [kHdrKmin], [kHdrRange]).
+constexpr int kHdrDirect = 2, kHdrKmin = 3, kHdrRange = 4;
+constexpr int64_t kFilterBits = int64_t{32} << kBloomLgw;  // 2^20
 
 static_assert((int64_t{kMaxBuckets} << kBucketLg) == (int64_t{1} << kStageSlotBits), "staged slot bits");
 
@@ -109,10 +122,25 @@ __device__ __forceinline__ const PYST_GLOBAL T *gmem(const T *p) { return (const
 
 // ------------------------------------------------------------------ dimension filter (block-local)
 // Block b writes its selected row ids, in order, to sel[b*kDimTile ...] and their
-// number to cnt[b]; no global counter.
-__global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32_t *sel, int32_t *cnt) {
+// number to cnt[b]; no global counter.  With `key`, also the least and the
+// greatest selected key of the block to kmin_b[b] / kmax_b[b] (INT32_MAX /
+// INT32_MIN when it selects none), from which the table initializer decides
+// on direct addressing.
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32_t *sel, int32_t *cnt,
+                                                    const int32_t *key, int32_t *kmin_b, int32_t *kmax_b) {
   constexpr int NW = 256 / kWave, ITEMS = kDimTile / 256;
-  __shared__ int32_t s_cnt[NW];
+  __shared__ int32_t s_cnt[NW], s_min[NW], s_max[NW];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t wbase = int64_t{blockIdx.x} * kDimTile + int64_t{w} * kWave * ITEMS;
   int64_t rows[ITEMS];
@@ -120,6 +148,24 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
   for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
   bool keep[ITEMS];
   eval_preds_items<ITEMS>(ps, rows, n, keep);
+  if (key) {  // uniform
+    int32_t kv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) kv[j] = keep[j] ? key[rows[j]] : 0;
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (keep[j]) {
+        mn = min(mn, kv[j]);
+        mx = max(mx, kv[j]);
+      }
+    mn = wave_min_i32(mn);
+    mx = wave_max_i32(mx);
+    if (lane == 0) {
+      s_min[w] = mn;
+      s_max[w] = mx;
+    }
+  }
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll
@@ -135,6 +181,15 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
     int tot = 0;
     for (int k = 0; k < NW; ++k) tot += s_cnt[k];
     cnt[blockIdx.x] = tot;
+    if (key) {
+      int32_t mn = INT32_MAX, mx = INT32_MIN;
+      for (int k = 0; k < NW; ++k) {
+        mn = min(mn, s_min[k]);
+        mx = max(mx, s_max[k]);
+      }
+      kmin_b[blockIdx.x] = mn;
+      kmax_b[blockIdx.x] = mx;
+    }
   }
   int32_t *out = sel + int64_t{blockIdx.x} * kDimTile;
 #pragma unroll
@@ -145,27 +200,62 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
 }
 
 // Table initialization sized from the per-block counts (or n without a filter);
-// also clears the Bloom words and the caller's group/pair counters.
+// also clears the Bloom words and the caller's group/pair counters.  With the
+// per-block key bounds (kmin_b / kmax_b) it chooses direct addressing when the
+// selected keys' range allows it: the header then holds the mode, kmin and
+// the range, hdr[0] the power of two covering the range (the slot count the
+// sums and their buckets use), and the bitmap words are cleared instead of keys.
 __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblocks, int64_t n, double max_load,
-                                  int64_t *zero0, int64_t *zero1) {
-  __shared__ int64_t s_total;
+                                  int64_t *zero0, int64_t *zero1, const int32_t *kmin_b, const int32_t *kmax_b) {
+  __shared__ int64_t s_total, s_kmin, s_kmax;
   if (threadIdx.x < kWave) {
     int64_t part = 0;
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
     if (cnt)
-      for (int64_t b = threadIdx.x; b < nblocks; b += kWave) part += cnt[b];
+      for (int64_t b = threadIdx.x; b < nblocks; b += kWave) {
+        part += cnt[b];
+        if (kmin_b) {
+          mn = min(mn, kmin_b[b]);
+          mx = max(mx, kmax_b[b]);
+        }
+      }
     part = wave_sum(part);
-    if (threadIdx.x == 0) s_total = cnt ? part : n;
+    mn = wave_min_i32(mn);
+    mx = wave_max_i32(mx);
+    if (threadIdx.x == 0) {
+      s_total = cnt ? part : n;
+      s_kmin = mn;
+      s_kmax = mx;
+    }
   }
   __syncthreads();
   const int64_t total = s_total;
-  const int64_t cap = table_capacity(total, max_load, t.cap_alloc);
+  const int64_t range = s_kmax - s_kmin + 1;  // <= 0: no key selected
+  const bool direct = kmin_b && t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc &&
+                      range <= (int64_t{1} << kStageSlotBits);
+  const int64_t cap = direct ? next_pow2(range < 64 ? 64 : range) : table_capacity(total, max_load, t.cap_alloc);
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
   if (tid == 0) {
     t.hdr[0] = cap;
     t.hdr[1] = total;
+    t.hdr[kHdrDirect] = direct;
+    t.hdr[kHdrKmin] = direct ? s_kmin : 0;
+    t.hdr[kHdrRange] = direct ? range : 0;
     if (zero0) *zero0 = 0;
     if (zero1) *zero1 = 0;
+  }
+  if (direct) {  // uniform: the bitmap, the slot sums, the filter
+    uint32_t *bm = static_cast<uint32_t *>(t.slots);
+    for (int64_t i = tid; i < (range + 31) / 32; i += nthr) bm[i] = 0;
+    if (t.sums)
+      for (int64_t i = tid; i < cap; i += nthr) {
+        t.sums[i] = 0;
+        t.flags[i] = 0;
+      }
+    if (t.bloom)
+      for (int64_t i = tid; i < kBloomWords; i += nthr) t.bloom[i] = 0;
+    return;
   }
   const int64_t words = t.slot_bytes == 4 ? cap / 2 : cap;
   const uint64_t fillv = t.slot_bytes == 4 ? (uint64_t{static_cast<uint32_t>(kEmpty32)} * 0x100000001ull)
@@ -241,9 +331,49 @@ __device__ __forceinline__ void build_tile(const int32_t *key, const int32_t *se
   }
 }
 
+// The same tile into a direct-addressed table: one atomic OR per key sets its
+// bit (every key's OR is issued before any result is looked at); a bit that
+// was already set is a duplicate key.
+__device__ __forceinline__ void build_tile_direct(const int32_t *key, const int32_t *sel, const int32_t *cnt,
+                                                  int64_t n, int64_t tile, const TableDev &t, uint32_t *err) {
+  constexpr int ITEMS = kDimTile / 256;
+  const uint32_t kmin = static_cast<uint32_t>(t.hdr[kHdrKmin]);
+  const int64_t base = tile * kDimTile;
+  const int64_t rest = n - base;
+  const int64_t have = sel ? cnt[tile] : (rest < kDimTile ? rest : kDimTile);
+  int64_t row[ITEMS];
+  bool v[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t i = int64_t{j} * 256 + threadIdx.x;
+    v[j] = i < have;
+    row[j] = v[j] ? (sel ? static_cast<int64_t>(sel[base + i]) : base + i) : 0;
+  }
+  int32_t k[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) k[j] = v[j] ? key[row[j]] : kEmpty32;
+  uint32_t *bm = static_cast<uint32_t *>(t.slots);
+  uint32_t bit[ITEMS], old[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (v[j] && k[j] == kEmpty32) {
+      latch(err, kErrKey);
+      v[j] = false;
+    }
+    const uint32_t d = static_cast<uint32_t>(k[j]) - kmin;  // < range: the range spans the selected keys
+    bit[j] = 1u << (d & 31);
+    old[j] = v[j] ? atomicOr(&bm[d >> 5], bit[j]) : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (v[j] && (old[j] & bit[j])) latch(err, kErrDup);
+}
+
+// Tables built here always went through k_fast_table_init, which set the mode.
 __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const int32_t *sel, const int32_t *cnt, int64_t n,
                                                     TableDev t, uint32_t *err) {
-  build_tile(key, sel, cnt, n, blockIdx.x, t, err);
+  if (t.hdr[kHdrDirect]) build_tile_direct(key, sel, cnt, n, blockIdx.x, t, err);
+  else build_tile(key, sel, cnt, n, blockIdx.x, t, err);
 }
 
 // Build of a key + payload table (8-byte slots), one row per thread: the
@@ -338,7 +468,34 @@ __host__ __device__ __forceinline__ int64_t bloom_words(int64_t cap) {
   return cap < kBloomWords ? cap : kBloomWords;
 }
 
+// The 16 bits of x's bit pairs, each pair ORed into one bit (pair i -> bit i).
+__device__ __forceinline__ uint32_t pair_or16(uint32_t x) {
+  x = (x | (x >> 1)) & 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
+}
+
+// One thread per filter word.  A direct-addressed table's filter is its
+// bitmap (range <= 2^20 bits) or the bitmap with each bit pair ORed into one
+// (range <= 2^21): filter bit j stands for the keys kmin + 2j and kmin + 2j + 1.
 __global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
+  if (t.hdr[kHdrDirect]) {
+    const int64_t w = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
+    const int64_t range = t.hdr[kHdrRange], nwords = (range + 31) / 32;
+    const uint32_t *bm = static_cast<const uint32_t *>(t.slots);
+    uint32_t f;
+    if (range <= kFilterBits) {
+      f = w < nwords ? bm[w] : 0u;
+    } else {
+      const uint32_t lo = 2 * w < nwords ? bm[2 * w] : 0u, hi = 2 * w + 1 < nwords ? bm[2 * w + 1] : 0u;
+      f = pair_or16(lo) | (pair_or16(hi) << 16);
+    }
+    t.bloom[w] = f;
+    return;
+  }
   if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter
   bloom_build_word(t, blockIdx.x * int64_t{blockDim.x} + threadIdx.x);
 }
@@ -1017,6 +1174,150 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
   }
 }
 
+// star_range over a direct-addressed table (staged sums only).  Row r of a
+// lane is live when it passes the predicates and key - kmin falls in the range
+// with its filter bit set; the live rows are pushed together as in star_range,
+// and when the filter is not exact each reads its one bitmap word (an L2 hit:
+// the bitmap of 2^21 keys is 256 KiB).  A live row's slot is key - kmin, so
+// nothing walks.  The loads of a step's live rows (value, bitmap word) are
+// consumed one step later: the step issues them, then the next step's column
+// loads, then stages the previous step's rows, whose loads have long
+// completed, so no step waits a memory round trip of its own.
+template <bool V64, bool VX, int R>
+__device__ __forceinline__ void star_direct(const FastArgs &a, const TableDev &t0, const PYST_LDS uint32_t *s_filt,
+                                            int64_t begin, int64_t step, int64_t end, const BucketPool *bp,
+                                            const StageLds *sl) {
+  constexpr int64_t WR = int64_t{kWave} * R;
+  const uint32_t kmin = static_cast<uint32_t>(t0.hdr[kHdrKmin]);
+  const uint32_t range = static_cast<uint32_t>(t0.hdr[kHdrRange]);
+  const int fshift = range > kFilterBits ? 1 : 0;
+  const __amdgpu_buffer_rsrc_t rbm = rsrc(t0.slots, fshift ? (int64_t{range} + 31) / 32 * 4 : 0);
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  int64_t wbase = begin + int64_t{wv} * WR;
+  FactRows<R> cur = load_rows<1, R>(a, wbase, end, lane);
+  const uint32_t nb = bucket_count(t0.hdr[0]);
+  const uint32_t stage_cap = nb <= bp->stride ? kStageCap : 0;  // 0: every pair is added directly
+  // Stages this lane's pair (slot < 0: none), or adds it directly when it does not fit a staged word.
+  auto add = [&](int32_t es, int64_t ev) {
+    const bool st = es >= 0 && fits_stage(ev);
+    const uint64_t m = __ballot(st);
+    const uint32_t cw = static_cast<uint32_t>(__popcll(m));
+    uint32_t off = 0;
+    if (cw) {  // wave-uniform
+      if (lane == 0) off = lds_add(sl->cnt, cw);
+      off = __builtin_amdgcn_readfirstlane(off);
+    }
+    if (es >= 0) {
+      const uint32_t p = st ? off + mbcnt(m) : stage_cap;
+      if (p < stage_cap) {
+        sl->ent[p] = (static_cast<uint64_t>(ev) << kStageSlotBits) | static_cast<uint32_t>(es);
+      } else {  // staging full: add directly (the second kernel adds these in)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[es]), static_cast<unsigned long long>(ev));
+        t0.flags[es] = 1;
+      }
+    }
+  };
+  auto value = [&](int64_t x, int32_t w) -> int64_t {
+    return !VX || a.vexpr == PYST_V_COL
+               ? x
+               : static_cast<int64_t>(static_cast<uint64_t>(x) * static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w)));
+  };
+  // the compacted row of lane `lane` in pass w0: its slot if it is a member, else -1
+  auto probe = [&](int32_t d, bool ok, __amdgpu_buffer_rsrc_t rv, __amdgpu_buffer_rsrc_t rw, int32_t crow,
+                   int64_t *x, int32_t *w) -> int32_t {
+    const uint32_t bw = fshift ? __builtin_amdgcn_raw_buffer_load_b32(rbm, ok ? (d >> 5) * 4 : kBufOob, 0, 0) : 1u;
+    if (V64) {
+      const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, ok ? crow * 8 : kBufOob, 0, kNonTemporal);
+      *x = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
+    } else {
+      *x = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rv, ok ? crow * 4 : kBufOob, 0, 0));
+    }
+    *w = VX ? static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, ok ? crow * 4 : kBufOob, 0, 0)) : 0;
+    const bool hit = ok && (fshift == 0 || ((bw >> (d & 31)) & 1u));
+    return hit ? d : -1;
+  };
+  uint32_t since = 0, every = 2;  // steps since the last staging check; steps between checks
+  // the previous step's first 64 live rows: slot, bitmap word, value, whether the lane holds one
+  int32_t pd = 0;
+  uint32_t pbw = 0;
+  int64_t px = 0;
+  int32_t pw = 0;
+  bool pok = false;
+  for (; wbase - int64_t{wv} * WR < end; wbase += step) {  // the whole block steps together
+    const int64_t left64 = end - wbase;
+    const int left = static_cast<int>(left64 < WR ? left64 : WR);
+    uint64_t m[R];
+    uint32_t b[R], n = 0;
+    int32_t dk[1][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t d = static_cast<uint32_t>(row_of(cur.f0, r)) - kmin;
+      const uint32_t fb = d >> fshift;
+      const bool l = lane * R + r < left && in_range(row_of(cur.c0, r), a.plo[0], a.pspan[0], a.pneg[0]) &&
+                     in_range(row_of(cur.c1, r), a.plo[1], a.pspan[1], a.pneg[1]) && d < range &&
+                     ((s_filt[(fb >> 5) & (kBloomWords - 1)] >> (fb & 31)) & 1u);
+      dk[0][r] = static_cast<int32_t>(d);
+      m[r] = __ballot(l);
+      b[r] = n;
+      n += static_cast<uint32_t>(__popcll(m[r]));
+    }
+    n = __builtin_amdgcn_readfirstlane(n);
+    const __amdgpu_buffer_rsrc_t rv = window(a.v0, V64 ? 8 : 4, wbase, end, WR);
+    const __amdgpu_buffer_rsrc_t rw = window(VX ? a.v1 : nullptr, 4, wbase, end, WR);
+    // the first 64 live rows, then the next step's columns
+    int32_t cd, crow;
+    {
+      int32_t o[1];
+      compact_rows<R, 1>(m, b, dk, lane, 0, o, &crow);
+      cd = o[0];
+    }
+    const bool ok = static_cast<uint32_t>(lane) < n;
+    const uint32_t bw = fshift ? __builtin_amdgcn_raw_buffer_load_b32(rbm, ok ? (cd >> 5) * 4 : kBufOob, 0, 0) : 1u;
+    int64_t x;
+    if (V64) {
+      const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, ok ? crow * 8 : kBufOob, 0, kNonTemporal);
+      x = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
+    } else {
+      x = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rv, ok ? crow * 4 : kBufOob, 0, 0));
+    }
+    const int32_t w = VX ? static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rw, ok ? crow * 4 : kBufOob, 0, 0)) : 0;
+    const FactRows<R> nxt = load_rows<1, R>(a, wbase + step, end, lane);
+    add(pok && (fshift == 0 || ((pbw >> (pd & 31)) & 1u)) ? pd : -1, value(px, pw));
+    pd = cd;
+    pbw = bw;
+    px = x;
+    pw = w;
+    pok = ok;
+    for (uint32_t w0 = kWave; w0 < n; w0 += kWave) {  // more than 64 live rows (wave-uniform, rare)
+      {
+        int32_t o[1];
+        compact_rows<R, 1>(m, b, dk, lane, w0, o, &crow);
+        cd = o[0];
+      }
+      int64_t x2;
+      int32_t w2;
+      const int32_t es2 = probe(cd, w0 + static_cast<uint32_t>(lane) < n, rv, rw, crow, &x2, &w2);
+      add(es2, value(x2, w2));
+    }
+    if (stage_cap > 0 && ++since == every) {  // block-uniform: as in star_range
+      __syncthreads();
+      const uint32_t c = *sl->cnt;
+      const uint32_t fit = kStageCap / (c / since + 1);
+      every = fit < 1 ? 1 : fit > kCheckMax ? kCheckMax : fit;
+      since = 0;
+      if (c >= kFlushAt) stage_flush(*sl, *bp, t0, nb);
+    }
+    cur = nxt;
+  }
+  add(pok && (fshift == 0 || ((pbw >> (pd & 31)) & 1u)) ? pd : -1, value(px, pw));  // the last step's rows
+  if (stage_cap > 0) {
+    __syncthreads();
+    if (*sl->cnt > 0) stage_flush(*sl, *bp, t0, nb);  // block-uniform
+    if (threadIdx.x < nb) bp->fill[sl->chunk[threadIdx.x]] = sl->fill[threadIdx.x];
+  }
+}
+
 // The two-join fact pass writing (group key, value) pairs (the chain query).
 // Rows that pass the predicates and join 0's Bloom filter are pushed to
 // consecutive lanes (compact_rows), probe join 0 and, when found there, join 1.
@@ -1272,12 +1573,17 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
     }
     if (threadIdx.x == 0) *sl.cnt = 0;
   }
-  const bool use_bloom = t0.bloom != nullptr && t0.hdr[1] <= kBloomMaxKeys;
+  // (only the staged one-join pass, whose tables come from k_fast_table_init, meets direct addressing)
+  const bool direct = NJ == 1 && AGG == 3 && t0.hdr[kHdrDirect] != 0;
+  const bool use_bloom = direct || (t0.bloom != nullptr && t0.hdr[1] <= kBloomMaxKeys);
   if (use_bloom)
     for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];
   if (use_bloom || AGG == 3) __syncthreads();
   const int64_t begin = int64_t{blockIdx.x} * kFastBlock * R, step = int64_t{gridDim.x} * kFastBlock * R;
-  if constexpr (NJ == 1 && (AGG == 0 || AGG == 3))
+  if constexpr (NJ == 1 && AGG == 3) {
+    if (direct) star_direct<V64, VX, R>(a, t0, (const PYST_LDS uint32_t *)s_bloom, begin, step, a.n, &bp, &sl);
+    else star_range<AGG, V64, VX, R>(a, t0, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n, &bp, &sl);
+  } else if constexpr (NJ == 1 && AGG == 0)
     star_range<AGG, V64, VX, R>(a, t0, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n, &bp, &sl);
   else if constexpr (NJ == 2 && AGG == 2)
     chain_range<SB1, V64, VX, R>(a, t0, t1, po, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin, step, a.n);
@@ -1325,11 +1631,13 @@ __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t 
 // present with one counter atomic.  *d_ngroups must be zero on entry.  The LDS
 // arrays come from the calling kernel (s_sum: kBucketSlots, s_bits:
 // kBucketSlots / 32, s_wsum: kFastBlock / kWave, s_base: 1); blockDim.x is
-// kFastBlock.
+// kFastBlock.  may_direct: the table's header records its mode (tables from
+// k_fast_table_init); a direct-addressed slot s holds the key kmin + s.
 __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const BucketPool &bp, uint32_t b,
                                                   int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
                                                   int64_t *d_ngroups, uint32_t *err, uint64_t *s_sum,
-                                                  uint32_t *s_bits, uint32_t *s_wsum, int64_t *s_base) {
+                                                  uint32_t *s_bits, uint32_t *s_wsum, int64_t *s_base,
+                                                  bool may_direct) {
   const int64_t cap = t.hdr[0];
   const uint32_t nb = bucket_count(cap);
   if (b >= nb) return;  // block-uniform
@@ -1392,11 +1700,14 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
   int64_t pos = *s_base + incl - c;
   for (uint32_t k = 0; k < wv; ++k) pos += s_wsum[k];
   const int32_t *keys = static_cast<const int32_t *>(t.slots);
+  const bool direct = may_direct && t.hdr[kHdrDirect] != 0;
+  const int32_t kmin = direct ? static_cast<int32_t>(t.hdr[kHdrKmin]) : 0;
   while (m) {
     const uint32_t j = static_cast<uint32_t>(__ffs(m) - 1);
     m &= m - 1;
     if (pos < out_cap) {
-      out_keys[pos] = keys[lo + s0 + j];
+      out_keys[pos] = direct ? static_cast<int32_t>(static_cast<uint32_t>(kmin) + static_cast<uint32_t>(lo + s0 + j))
+                             : keys[lo + s0 + j];
       out_sums[pos] = static_cast<int64_t>(s_sum[s0 + j]);
     } else {
       latch(err, kErrCapacity);
@@ -1412,7 +1723,8 @@ __global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPo
   __shared__ uint32_t s_bits[kBucketSlots / 32];
   __shared__ uint32_t s_wsum[kFastBlock / kWave];
   __shared__ int64_t s_base;
-  bucket_sums_block(t, bp, blockIdx.x, out_keys, out_sums, out_cap, d_ngroups, err, s_sum, s_bits, s_wsum, &s_base);
+  bucket_sums_block(t, bp, blockIdx.x, out_keys, out_sums, out_cap, d_ngroups, err, s_sum, s_bits, s_wsum, &s_base,
+                    true);
 }
 
 // Unordered compaction of groups (slot sums or a group table): one counter
@@ -1631,7 +1943,8 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     }
   }
   int64_t *zero1 = pool ? reinterpret_cast<int64_t *>(bp.next) : s.po.count;
-  if (st == PYST_OK) st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, zero1, stream);
+  if (st == PYST_OK)
+    st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, zero1, stream, pool != nullptr && !ctx_hash_join_only(ctx));
   if (pool) {
     if (st == PYST_OK) st = bucketed_sums(ctx, fa, d, bp, out_keys, out_sums, out_cap, d_ngroups, stream);
     ctx_free(ctx, pool, stream);
@@ -1644,9 +1957,11 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
   return st;
 }
 
-// Dimension tables of the fast path: join 0 keys-only with a Bloom filter.
+// Dimension tables of the fast path: join 0 keys-only with a Bloom filter, or,
+// with allow_direct (its consumers handle the direct-addressed mode) and keys
+// that allow it, direct-addressed.
 pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
-                                  int64_t *zero0, int64_t *zero1, hipStream_t stream) {
+                                  int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct) {
   for (int j = 0; j < plan->njoins; ++j) {
     const pyst_join_spec &js = plan->joins[j];
     const int64_t nb = js.key.n;
@@ -1661,13 +1976,20 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
     d->t[j] = table_view(d->mem[j], cap_alloc, sb, sums);
     if (j == 0) d->t[j].bloom = reinterpret_cast<uint32_t *>(static_cast<char *>(d->mem[j]) + bloom_off);
     const int32_t *sel = nullptr;
-    int32_t *cnt = nullptr;
+    int32_t *cnt = nullptr, *kmin_b = nullptr, *kmax_b = nullptr;
     const int64_t nblk = std::max<int64_t>(1, ceil_div(nb, kDimTile));
-    if (js.npreds > 0) {
-      d->sel_mem[j] = ctx_alloc(ctx, static_cast<size_t>(nblk) * (kDimTile + 1) * sizeof(int32_t) + 256, stream);
+    const bool direct_ok = allow_direct && j == 0 && sb == 4 && sums && nb > 0 && js.key.dtype == PYST_I32;
+    if (js.npreds > 0 || direct_ok) {  // (direct addressing needs the selected keys' bounds from the filter)
+      const int64_t nblk64 = (nblk + 63) / 64 * 64;
+      d->sel_mem[j] = ctx_alloc(ctx, static_cast<size_t>(nblk) * kDimTile * sizeof(int32_t) +
+                                         static_cast<size_t>(3 * nblk64) * sizeof(int32_t) + 256, stream);
       if (!d->sel_mem[j]) return set_error(PYST_ERR_NOMEM, "pyst_query: arena exhausted (dimension selection)");
       cnt = static_cast<int32_t *>(d->sel_mem[j]);
-      int32_t *s = cnt + (nblk + 63) / 64 * 64;
+      if (direct_ok) {
+        kmin_b = cnt + nblk64;
+        kmax_b = kmin_b + nblk64;
+      }
+      int32_t *s = cnt + 3 * nblk64;
       PredSet ps;
       std::memset(&ps, 0, sizeof(ps));
       ps.n = js.npreds;
@@ -1679,13 +2001,14 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
         ps.op[k] = js.preds[k].cmp;
         ps.val[k] = js.preds[k].value;
       }
-      k_dim_filter<<<static_cast<unsigned>(nblk), 256, 0, stream>>>(ps, nb, s, cnt);
+      k_dim_filter<<<static_cast<unsigned>(nblk), 256, 0, stream>>>(
+          ps, nb, s, cnt, direct_ok ? static_cast<const int32_t *>(js.key.data) : nullptr, kmin_b, kmax_b);
       PYST_LAUNCH_CHECK("k_dim_filter");
       sel = s;
     }
     const int iblocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(cap_alloc, 256), 64), 2048));
     k_fast_table_init<<<iblocks, 256, 0, stream>>>(d->t[j], cnt, nblk, nb, js.max_load, j == 0 ? zero0 : nullptr,
-                                                   j == 0 ? zero1 : nullptr);
+                                                   j == 0 ? zero1 : nullptr, kmin_b, kmax_b);
     PYST_LAUNCH_CHECK("k_fast_table_init");
     if (nb > 0) {
       const int32_t *key = static_cast<const int32_t *>(js.key.data);

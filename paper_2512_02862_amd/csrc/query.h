@@ -78,7 +78,7 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
                        int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                        hipStream_t stream);
 pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
-                                  int64_t *zero0, int64_t *zero1, hipStream_t stream);
+                                  int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct);
 pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastArgs &a, const DimTables &d,
                            const GroupDev &g, const PairsOut &po, hipStream_t stream);
 pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const DimTables &d, AggState *s,
@@ -88,6 +88,7 @@ pyst_status pair_groupby(pyst_ctx *ctx, int64_t *keys, int64_t *vals, const int6
                          int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                          hipStream_t stream);
 bool ctx_generic_only(const pyst_ctx *ctx);
+bool ctx_hash_join_only(const pyst_ctx *ctx);
 int fast_grid(pyst_ctx *ctx, int64_t n);
 hipStream_t ctx_copy_stream(pyst_ctx *ctx);
 char *ctx_pinned_staging(pyst_ctx *ctx, size_t bytes);

@@ -232,7 +232,7 @@ static std::unique_ptr<DimEntry> build_entry(pyst_server *sv, const Request &r, 
   *ps = fill_u32(e->d_err, 1, 0u, st);
   if (*ps == PYST_OK) {
     ErrScope scope(sv->ctx, e->d_err);
-    *ps = fast_build_dimensions(sv->ctx, &r.pc.plan, r.q, &e->d, nullptr, nullptr, st);
+    *ps = fast_build_dimensions(sv->ctx, &r.pc.plan, r.q, &e->d, nullptr, nullptr, st, false);
   }
   if (*ps != PYST_OK) {
     free_dimensions(sv->ctx, &e->d, st);
@@ -719,7 +719,8 @@ pyst_status pyst_server_forget_tables(pyst_server *sv, const void *dim_col_data)
 
 pyst_status pyst_server_option(pyst_server *sv, int key, int64_t value) {
   if (!sv) return set_error(PYST_ERR_ARG, "pyst_server_option: NULL server");
-  if (key != PYST_OPT_GENERIC_ONLY && key != PYST_OPT_GROUPBY_HASH_ONLY && key != PYST_OPT_FAIL_FACT_PASS)
+  if (key != PYST_OPT_GENERIC_ONLY && key != PYST_OPT_GROUPBY_HASH_ONLY && key != PYST_OPT_FAIL_FACT_PASS &&
+      key != PYST_OPT_HASH_JOIN_ONLY)
     return set_error(PYST_ERR_ARG, "pyst_server_option: unknown option");
   {
     std::lock_guard<std::mutex> lk(sv->mu);

@@ -25,6 +25,7 @@ V_COL, V_COL_TIMES_C_MINUS = 0, 1
 OPT_GENERIC_ONLY = 1
 OPT_GROUPBY_HASH_ONLY = 2
 OPT_FAIL_FACT_PASS = 3
+OPT_HASH_JOIN_ONLY = 4
 
 EXPORTS = [
     "pyst_ctx_create", "pyst_ctx_destroy", "pyst_ctx_check", "pyst_ctx_used", "pyst_ctx_budget",
@@ -234,6 +235,10 @@ class Ctx:
 
     def groupby_hash_only(self, enable: bool):
         _check(_lib.pyst_ctx_option(self.h, OPT_GROUPBY_HASH_ONLY, int(bool(enable))))
+
+    def hash_join_only(self, enable: bool):
+        """Keep pyst_query's join tables hash tables (no direct addressing of dense keys)."""
+        _check(_lib.pyst_ctx_option(self.h, OPT_HASH_JOIN_ONLY, int(bool(enable))))
 
     def timing(self, enable: bool):
         """Record HIP events around the library's timed kernels (see kernel_time)."""

@@ -27,19 +27,24 @@ def ctx(gpu):
 
 
 def run(gpu, ctx, plan, fact, path, out_cap=None):
+    # "fast": the specialized kernel, which direct-addresses a dimension table
+    # whose selected keys span a small enough range; "fast_hash": the same
+    # kernel with hash tables only; "generic": the generic fact pass
     ctx.generic_only(path == "generic")
+    ctx.hash_join_only(path == "fast_hash")
     try:
         k, s, ng = gpu.query(ctx, plan, fact, out_cap=out_cap)
         ctx.check()
     finally:
         ctx.generic_only(False)
+        ctx.hash_join_only(False)
     m = int(ng.item())
     k, s = k[:m].cpu().numpy(), s[:m].cpu().numpy()
     o = np.argsort(k, kind="stable")
     return k[o], s[o]
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("nb,np_", [(2, 3), (30_000, 300_001), (150_000, 1_500_000)])
 def test_star_both_paths(gpu, ctx, path, nb, np_):
     b, p = gen.star_tables(nb, np_)
@@ -50,7 +55,7 @@ def test_star_both_paths(gpu, ctx, path, nb, np_):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_star_predicate_on_join_column_and_no_predicate(gpu, ctx, path):
     b, p = gen.star_tables(20_000, 400_000)
     bd = {k: dev(v) for k, v in b.items()}
@@ -68,7 +73,7 @@ def test_star_predicate_on_join_column_and_no_predicate(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_star_int32_value_column(gpu, ctx, path):
     b, p = gen.star_tables(10_000, 200_003)
     bd = {k: dev(v) for k, v in b.items()}
@@ -83,7 +88,7 @@ def test_star_int32_value_column(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_star_every_comparison_at_its_boundaries(gpu, ctx, path):
     # date is U[0, 2406]; constants at, inside and outside the int32 range
     b, p = gen.star_tables(5_000, 60_001)
@@ -100,7 +105,7 @@ def test_star_every_comparison_at_its_boundaries(gpu, ctx, path):
             np.testing.assert_array_equal(s, ws, err_msg="%s %d" % (op, c))
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("np_", [1, 4, 255, 256, 257, 258, 259, 4095, 4097, 262_143, 262_145])
 def test_star_ragged_fact_lengths(gpu, ctx, path, np_):
     # wave steps of 256 rows, 4 rows per lane: every remainder of the last step
@@ -112,7 +117,7 @@ def test_star_ragged_fact_lengths(gpu, ctx, path, np_):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_star_every_row_matches(gpu, ctx, path):
     # no predicate on either side: every fact row joins, so the fast path's LDS
     # staging overflows every step and the excess is added directly
@@ -127,7 +132,7 @@ def test_star_every_row_matches(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_star_groups_whose_sum_is_zero(gpu, ctx, path):
     # each fact row is followed by a copy with the negated price: every group
     # that exists sums to 0 and must still be reported
@@ -142,10 +147,10 @@ def test_star_groups_whose_sum_is_zero(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_star_values_of_every_width(gpu, ctx, path):
     # values shifted left by 0..62 bits (wrapping): the fast path stages the
-    # ones that fit in 51 bits and adds the others directly; sums wrap mod 2^64
+    # ones that fit in 43 bits and adds the others directly; sums wrap mod 2^64
     b, p = gen.star_tables(20_000, 400_003)
     shift = (np.arange(len(p["price"])) % 63).astype(np.uint64)
     q = dict(p)
@@ -157,7 +162,7 @@ def test_star_values_of_every_width(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("nb", [600_000, 2_200_000])
 def test_star_tables_too_large_to_stage(gpu, ctx, path, nb):
     # no dimension predicate: 600k keys make a 2^21-slot table (sized on the
@@ -173,7 +178,7 @@ def test_star_tables_too_large_to_stage(gpu, ctx, path, nb):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("preds", [True, False])
 def test_star_nearly_full_table(gpu, ctx, path, preds):
     # the join table at load ~0.92: many probes run past their first 16-byte
@@ -193,6 +198,91 @@ def test_star_nearly_full_table(gpu, ctx, path, preds):
     assert len(wk) > 0
     np.testing.assert_array_equal(k, wk)
     np.testing.assert_array_equal(s, ws)
+
+
+def _dense_star(rng_keys, n_keys, base, n_fact, seed=0, select_ends=True):
+    """A star build side whose keys are n_keys distinct values of [base, base + rng_keys)
+    (both ends included and, with select_ends, selected by segment == 1), and a fact
+    table whose fk also falls just outside that range."""
+    r = np.random.default_rng(seed)
+    inner = r.choice(np.arange(1, rng_keys - 1, dtype=np.int64), n_keys - 2, replace=False)
+    keys = np.concatenate([[0, rng_keys - 1], inner]) + base
+    seg = r.integers(0, 5, len(keys)).astype(np.int32)
+    if select_ends:
+        seg[:2] = 1
+    o = r.permutation(len(keys))
+    b = {"key": keys[o].astype(np.int32), "segment": seg[o]}
+    near = np.clip(base + r.integers(-20, rng_keys + 20, 64), -2 ** 31 + 1, 2 ** 31 - 1)
+    fk = np.concatenate([keys[r.integers(0, len(keys), n_fact - 64)], near]).astype(np.int32)
+    p = {"fk": fk[r.permutation(n_fact)], "date": r.integers(0, 2407, n_fact).astype(np.int32),
+         "price": r.integers(90_000, 10_500_001, n_fact).astype(np.int64)}
+    return b, p
+
+
+@pytest.mark.parametrize("path", ["fast", "fast_hash"])
+@pytest.mark.parametrize("rng_keys,base", [
+    (1 << 20, 0),                    # exact LDS filter, the largest such range
+    ((1 << 20) + 1, -(2 ** 31) + 5),  # paired filter bits, the bitmap read from the L2
+    (1 << 21, 2 ** 31 - (1 << 21)),  # the largest direct range, ending at INT32_MAX
+    ((1 << 21) + 1, 1000),           # one past it: hash table
+    (3_000, 7),                      # a small range
+])
+def test_star_direct_addressing_ranges(gpu, ctx, path, rng_keys, base):
+    b, p = _dense_star(rng_keys, min(rng_keys, 400_000), base, 1_500_001)
+    bd = {k: dev(v) for k, v in b.items()}
+    plan = gpu.star_plan(bd, max_load=0.2)  # reserves >= 2^21 slots for 400k keys
+    k, s = run(gpu, ctx, plan, [dev(p[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(b, p)
+    assert len(wk) > 1000 or rng_keys < 10_000
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "fast_hash"])
+def test_star_sparse_and_single_keys(gpu, ctx, path):
+    # keys spread over the whole int32 range (a hash table either way), then a
+    # dimension whose filter keeps a single key (a range of one)
+    b, p = gen.star_tables(50_000, 500_003)
+    sb, sp = dict(b), dict(p)
+    sb["key"] = (b["key"].astype(np.int64) * 40_503 - 2 ** 31 + 1).astype(np.int32)
+    sp["fk"] = (p["fk"].astype(np.int64) * 40_503 - 2 ** 31 + 1).astype(np.int32)
+    k, s = run(gpu, ctx, gpu.star_plan({k_: dev(v) for k_, v in sb.items()}), [dev(sp[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(sb, sp)
+    assert len(wk) > 1000
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+    one = dict(b)
+    one["segment"] = np.where(b["key"] == 777, 1, 0).astype(np.int32)
+    k, s = run(gpu, ctx, gpu.star_plan({k_: dev(v) for k_, v in one.items()}), [dev(p[c]) for c in FACT_STAR], path)
+    wk, ws = oracle.star_query(one, p)
+    assert len(wk) == 1
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "fast_hash"])
+def test_star_duplicate_and_sentinel_dimension_keys(gpu, ctx, path):
+    # keys 1..20000 shifted down to just above INT32_MIN, so that the reserved
+    # key INT32_MIN still leaves a range small enough for direct addressing
+    b, p = gen.star_tables(20_000, 100_000)
+    shift = -2 ** 31
+    for bad, status in [(5, gpu.ERR_DUP_KEY), (0, gpu.ERR_KEY)]:
+        d = dict(b)
+        d["key"] = (b["key"].astype(np.int64) + shift).astype(np.int32)
+        d["segment"] = b["segment"].copy()
+        i = int(np.flatnonzero(b["key"] == 11)[0])
+        d["key"][i] = bad + shift  # a second key 5, or INT32_MIN, both selected
+        d["segment"][i] = 1
+        d["segment"][np.flatnonzero(b["key"] == 5)[0]] = 1
+        fact = [dev((p["fk"].astype(np.int64) + shift).astype(np.int32)), dev(p["date"]), dev(p["price"])]
+        ctx.hash_join_only(path == "fast_hash")
+        try:
+            gpu.query(ctx, gpu.star_plan({k_: dev(v) for k_, v in d.items()}), fact)
+            with pytest.raises(gpu.PystError) as e:
+                ctx.check()
+        finally:
+            ctx.hash_join_only(False)
+        assert e.value.status == status
 
 
 def _chain(n=1_000_003, na=40_000, nb=4_000, zs=0.0):
