@@ -28,6 +28,7 @@ struct BatFrag {
   int64_t nb;
   int32_t *sel;            // block-local selection (nblk * kDimTile)
   int32_t *cnt;            // per-block selected counts
+  int32_t *kmin_b, *kmax_b;  // per-block selected key bounds (direct addressing allowed), else null
   int64_t nblk;
   TableDev t;              // keys-only table with slot sums
   double max_load;
@@ -89,6 +90,8 @@ __global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const 
   for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
   bool keep[ITEMS];
   eval_preds_items<ITEMS>(fr.bpred, rows, fr.nb, keep);
+  __shared__ int32_t s_min[NW], s_max[NW];
+  if (fr.kmin_b) wave_key_bounds<ITEMS>(fr.bkey, rows, keep, w, s_min, s_max);  // uniform
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll
@@ -104,6 +107,15 @@ __global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const 
     int tot = 0;
     for (int k = 0; k < NW; ++k) tot += s_cnt[k];
     fr.cnt[local] = tot;
+    if (fr.kmin_b) {
+      int32_t mn = INT32_MAX, mx = INT32_MIN;
+      for (int k = 0; k < NW; ++k) {
+        mn = min(mn, s_min[k]);
+        mx = max(mx, s_max[k]);
+      }
+      fr.kmin_b[local] = mn;
+      fr.kmax_b[local] = mx;
+    }
   }
   int32_t *out = fr.sel + local * kDimTile;
 #pragma unroll
@@ -113,24 +125,53 @@ __global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const 
   }
 }
 
+// As k_fast_table_init, per fragment: the table's size and mode (direct
+// addressing when the fragment allows it and its selected keys fit), cleared.
 __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const int64_t *pre, int nfrag) {
   PYST_BLOCK_FRAG(kPreInit)
-  __shared__ int64_t s_total;
+  __shared__ int64_t s_total, s_kmin, s_kmax;
   if (threadIdx.x < kWave) {
     int64_t part = 0;
-    for (int64_t b = threadIdx.x; b < fr.nblk; b += kWave) part += fr.cnt[b];
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+    for (int64_t b = threadIdx.x; b < fr.nblk; b += kWave) {
+      part += fr.cnt[b];
+      if (fr.kmin_b) {
+        mn = min(mn, fr.kmin_b[b]);
+        mx = max(mx, fr.kmax_b[b]);
+      }
+    }
     part = wave_sum(part);
-    if (threadIdx.x == 0) s_total = part;
+    mn = wave_min_i32(mn);
+    mx = wave_max_i32(mx);
+    if (threadIdx.x == 0) {
+      s_total = part;
+      s_kmin = mn;
+      s_kmax = mx;
+    }
   }
   __syncthreads();
   const TableDev &t = fr.t;
-  const int64_t cap = table_capacity(s_total, fr.max_load, t.cap_alloc);
+  const bool direct = fr.kmin_b && direct_fits(t, s_total, s_kmin, s_kmax);
+  const int64_t range = s_kmax - s_kmin + 1;
+  const int64_t cap = direct ? next_pow2(range < 64 ? 64 : range) : table_capacity(s_total, fr.max_load, t.cap_alloc);
   const int64_t tid = local * 256 + threadIdx.x, nthr = nloc * 256;
   if (tid == 0) {
     t.hdr[0] = cap;
     t.hdr[1] = s_total;
+    t.hdr[kHdrDirect] = direct;
+    t.hdr[kHdrKmin] = direct ? s_kmin : 0;
+    t.hdr[kHdrRange] = direct ? range : 0;
     *fr.d_ngroups = 0;
     if (fr.bp.next) *fr.bp.next = 0;
+  }
+  if (direct) {  // block-uniform: the bitmap and the slot sums
+    uint32_t *bm = static_cast<uint32_t *>(t.slots);
+    for (int64_t i = tid; i < (range + 31) / 32; i += nthr) bm[i] = 0;
+    for (int64_t i = tid; i < cap; i += nthr) {
+      t.sums[i] = 0;
+      t.flags[i] = 0;
+    }
+    return;
   }
   int32_t *keys = static_cast<int32_t *>(t.slots);
   const int64_t words = bloom_words(cap);
@@ -146,13 +187,19 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
 __global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
   PYST_BLOCK_FRAG(kPreBuild)
   (void)nloc;
-  build_tile(fr.bkey, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
+  if (fr.t.hdr[kHdrDirect]) build_tile_direct(fr.bkey, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
+  else build_tile(fr.bkey, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
 }
 
 // Each fragment's Bloom filter, from its finished table (words past the ones
 // its capacity uses stay clear and are never read).
 __global__ __launch_bounds__(256) void k_bat_bloom(const BatFrag *frags, const int64_t *pre, int nfrag) {
   PYST_BLOCK_FRAG(kPreBloom)
+  if (fr.t.hdr[kHdrDirect]) {  // the bitmap as the filter (fits the words reserved for the Bloom filter)
+    const int64_t words = direct_filter_words(fr.t.hdr[kHdrRange]);
+    for (int64_t w = local * 256 + threadIdx.x; w < words; w += nloc * 256) fr.t.bloom[w] = direct_filter_word(fr.t, w);
+    return;
+  }
   if (fr.t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use it
   const int64_t words = bloom_words(fr.t.hdr[0]);
   for (int64_t w = local * 256 + threadIdx.x; w < words; w += nloc * 256) bloom_build_word(fr.t, w);
@@ -212,16 +259,21 @@ __global__ __launch_bounds__(kFastBlock) void k_bat_fact_staged(const BatFrag *f
     }
   }
   if (threadIdx.x == 0) *sl.cnt = 0;
-  const bool use_bloom = fr.t.hdr[1] <= kBloomMaxKeys;
+  const bool direct = fr.t.hdr[kHdrDirect] != 0;
+  const bool use_bloom = direct || fr.t.hdr[1] <= kBloomMaxKeys;
   if (use_bloom) {
-    const int64_t words = bloom_words(fr.t.hdr[0]);
+    const int64_t words = direct ? direct_filter_words(fr.t.hdr[kHdrRange]) : bloom_words(fr.t.hdr[0]);
     for (int64_t i = threadIdx.x; i < words; i += kFastBlock) s_bloom[i] = gmem(fr.t.bloom)[i];
   }
   __syncthreads();
   const int64_t begin = local * fr.rows_per_unit;
   const int64_t end = begin + fr.rows_per_unit < fr.fa.n ? begin + fr.rows_per_unit : fr.fa.n;
-  star_range<3, V64, true, 4>(fr.fa, fr.t, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
-                              int64_t{kFastBlock} * 4, end, &bp, &sl);
+  if (direct)
+    star_direct<V64, true, 4>(fr.fa, fr.t, (const PYST_LDS uint32_t *)s_bloom, begin, int64_t{kFastBlock} * 4, end,
+                              &bp, &sl);
+  else
+    star_range<3, V64, true, 4>(fr.fa, fr.t, err, (const PYST_LDS uint32_t *)s_bloom, use_bloom, begin,
+                                int64_t{kFastBlock} * 4, end, &bp, &sl);
 }
 
 // Bucket b of a staged fragment per block: its pairs and direct sums added
@@ -235,7 +287,7 @@ __global__ __launch_bounds__(kFastBlock) void k_bat_sums(const BatFrag *frags, c
   __shared__ uint32_t s_wsum[kFastBlock / kWave];
   __shared__ int64_t s_base;
   bucket_sums_block(fr.t, fr.bp, static_cast<uint32_t>(local), fr.out_keys, fr.out_sums, fr.out_cap, fr.d_ngroups,
-                    err, s_sum, s_bits, s_wsum, &s_base, false);
+                    err, s_sum, s_bits, s_wsum, &s_base, true);
 }
 
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
@@ -364,7 +416,8 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
     b.t.slot_bytes = 4;
     bp->table_bytes_total += (table_bytes(cap_alloc, 4, true) + 255) / 256 * 256 +
                              (static_cast<size_t>(bloom_words(cap_alloc)) * 4 + 255) / 256 * 256;
-    bp->sel_bytes_total += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
+    bp->sel_bytes_total += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256 +
+                           static_cast<size_t>(2 * ((b.nblk + 63) / 64 * 64)) * 4;
     const int64_t fact_units = ceil_div(std::max<int64_t>(fa.n, 1), b.rows_per_unit);
     const int64_t blocks[kPreKinds] = {
         b.nblk,
@@ -445,11 +498,17 @@ static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfr
     b.t.bloom = reinterpret_cast<uint32_t *>(p);
     p += (static_cast<size_t>(bloom_words(b.t.cap_alloc)) * 4 + 255) / 256 * 256;
   }
+  // direct addressing needs staged sums (the per-row atomic pass probes hash tables only)
+  const bool allow_direct = bp.staged && !ctx_hash_join_only(ctx);
   for (int f = 0; f < nfrag; ++f) {
     BatFrag &b = bp.frags[f];
+    const int64_t nblk64 = (b.nblk + 63) / 64 * 64;
     b.cnt = reinterpret_cast<int32_t *>(p);
-    b.sel = b.cnt + (b.nblk + 63) / 64 * 64;
+    b.sel = b.cnt + nblk64;
     p += (static_cast<size_t>(b.nblk) * (kDimTile + 1) * 4 + 255 + 256) / 256 * 256;
+    b.kmin_b = allow_direct ? reinterpret_cast<int32_t *>(p) : nullptr;
+    b.kmax_b = allow_direct ? b.kmin_b + nblk64 : nullptr;
+    p += static_cast<size_t>(2 * nblk64) * 4;
   }
   for (int f = 0; f < nfrag && bp.staged; ++f) {  // pools: next counter, records, chunk tags, fills
     BatFrag &b = bp.frags[f];

@@ -137,6 +137,40 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
   return v;
 }
 
+// The least and greatest key of a wave's kept rows into s_min[w] / s_max[w].
+template <int ITEMS>
+__device__ __forceinline__ void wave_key_bounds(const int32_t *key, const int64_t (&rows)[ITEMS],
+                                                const bool (&keep)[ITEMS], int w, int32_t *s_min, int32_t *s_max) {
+  int32_t kv[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) kv[j] = keep[j] ? key[rows[j]] : 0;
+  int32_t mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (keep[j]) {
+      mn = min(mn, kv[j]);
+      mx = max(mx, kv[j]);
+    }
+  mn = wave_min_i32(mn);
+  mx = wave_max_i32(mx);
+  if (lane_id() == 0) {
+    s_min[w] = mn;
+    s_max[w] = mx;
+  }
+}
+
+// Whether a keys-only table whose selected keys (total of them) lie in [kmin, kmax] is direct-addressed.
+__device__ __forceinline__ bool direct_fits(const TableDev &t, int64_t total, int64_t kmin, int64_t kmax) {
+  const int64_t range = kmax - kmin + 1;
+  return t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc && range <= (int64_t{1} << kStageSlotBits);
+}
+
+// Words of a direct-addressed table's LDS filter: one bit per key up to 2^20
+// keys, else one bit per key pair.
+__host__ __device__ __forceinline__ int64_t direct_filter_words(int64_t range) {
+  return ((range > kFilterBits ? (range + 1) / 2 : range) + 31) / 32;
+}
+
 __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32_t *sel, int32_t *cnt,
                                                     const int32_t *key, int32_t *kmin_b, int32_t *kmax_b) {
   constexpr int NW = 256 / kWave, ITEMS = kDimTile / 256;
@@ -148,24 +182,7 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
   for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
   bool keep[ITEMS];
   eval_preds_items<ITEMS>(ps, rows, n, keep);
-  if (key) {  // uniform
-    int32_t kv[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) kv[j] = keep[j] ? key[rows[j]] : 0;
-    int32_t mn = INT32_MAX, mx = INT32_MIN;
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-      if (keep[j]) {
-        mn = min(mn, kv[j]);
-        mx = max(mx, kv[j]);
-      }
-    mn = wave_min_i32(mn);
-    mx = wave_max_i32(mx);
-    if (lane == 0) {
-      s_min[w] = mn;
-      s_max[w] = mx;
-    }
-  }
+  if (key) wave_key_bounds<ITEMS>(key, rows, keep, w, s_min, s_max);  // uniform
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll
@@ -230,9 +247,8 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
   }
   __syncthreads();
   const int64_t total = s_total;
-  const int64_t range = s_kmax - s_kmin + 1;  // <= 0: no key selected
-  const bool direct = kmin_b && t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc &&
-                      range <= (int64_t{1} << kStageSlotBits);
+  const int64_t range = s_kmax - s_kmin + 1;
+  const bool direct = kmin_b && direct_fits(t, total, s_kmin, s_kmax);
   const int64_t cap = direct ? next_pow2(range < 64 ? 64 : range) : table_capacity(total, max_load, t.cap_alloc);
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
@@ -481,19 +497,18 @@ __device__ __forceinline__ uint32_t pair_or16(uint32_t x) {
 // One thread per filter word.  A direct-addressed table's filter is its
 // bitmap (range <= 2^20 bits) or the bitmap with each bit pair ORed into one
 // (range <= 2^21): filter bit j stands for the keys kmin + 2j and kmin + 2j + 1.
+__device__ __forceinline__ uint32_t direct_filter_word(const TableDev &t, int64_t w) {
+  const int64_t range = t.hdr[kHdrRange], nwords = (range + 31) / 32;
+  const uint32_t *bm = static_cast<const uint32_t *>(t.slots);
+  if (range <= kFilterBits) return w < nwords ? bm[w] : 0u;
+  const uint32_t lo = 2 * w < nwords ? bm[2 * w] : 0u, hi = 2 * w + 1 < nwords ? bm[2 * w + 1] : 0u;
+  return pair_or16(lo) | (pair_or16(hi) << 16);
+}
+
 __global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
   if (t.hdr[kHdrDirect]) {
     const int64_t w = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
-    const int64_t range = t.hdr[kHdrRange], nwords = (range + 31) / 32;
-    const uint32_t *bm = static_cast<const uint32_t *>(t.slots);
-    uint32_t f;
-    if (range <= kFilterBits) {
-      f = w < nwords ? bm[w] : 0u;
-    } else {
-      const uint32_t lo = 2 * w < nwords ? bm[2 * w] : 0u, hi = 2 * w + 1 < nwords ? bm[2 * w + 1] : 0u;
-      f = pair_or16(lo) | (pair_or16(hi) << 16);
-    }
-    t.bloom[w] = f;
+    t.bloom[w] = direct_filter_word(t, w);
     return;
   }
   if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter

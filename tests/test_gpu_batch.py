@@ -40,12 +40,19 @@ def sorted_np(k, s):
     return k[o], s[o]
 
 
+@pytest.mark.parametrize("hash_only", [False, True])
 @pytest.mark.parametrize("tuning", [None, (16, 256, 0.5), (256, 1024, 0.7), (64, 512, 0.5), (1, 256, 0.0)])
-def test_batch_matches_oracle(gpu, ctx, tuning):
+def test_batch_matches_oracle(gpu, ctx, tuning, hash_only):
+    # staged tunings (1024-thread blocks) direct-address the fragments' dense
+    # dimension keys unless hash tables are forced
     frags, host = make_fragments(gpu, 40)
     batch = gpu.Batch(ctx, frags)
-    batch.run(tuning)
-    ctx.check()
+    ctx.hash_join_only(hash_only)
+    try:
+        batch.run(tuning)
+        ctx.check()
+    finally:
+        ctx.hash_join_only(False)
     for (k, s), (bt, pt) in zip(batch.results(), host):
         wk, ws = oracle.star_query(bt, pt)
         gk, gs = sorted_np(k, s)
@@ -138,3 +145,30 @@ def test_batch_graph_replays_match(gpu, ctx):
                 np.testing.assert_array_equal(gs, ws)
     finally:
         g.close()
+
+
+def test_batch_mixed_key_ranges(gpu, ctx):
+    # fragments whose dimension keys are dense, sparse (hash table) or span the
+    # largest direct range, in one staged batch
+    import torch
+    frags, host = [], []
+    for f in range(6):
+        bt, pt = gen.star_tables(20_000 + 7_000 * f, 300_001, workload=3, fragment=f)
+        if f % 3 == 1:  # sparse keys
+            bt["key"] = (bt["key"].astype(np.int64) * 65_537 - 2 ** 30).astype(np.int32)
+            pt["fk"] = (pt["fk"].astype(np.int64) * 65_537 - 2 ** 30).astype(np.int32)
+        elif f % 3 == 2:  # keys spread over [1, 2^21]
+            bt["key"] = (bt["key"].astype(np.int64) * 40).astype(np.int32)
+            pt["fk"] = (pt["fk"].astype(np.int64) * 40).astype(np.int32)
+        frags.append((gpu.star_plan({k: dev(v) for k, v in bt.items()}, max_load=0.02),
+                      [dev(pt[c]) for c in ("fk", "date", "price")]))
+        host.append((bt, pt))
+    batch = gpu.Batch(ctx, frags)
+    batch.run((8, 1024, 0.0))
+    ctx.check()
+    for (k, s), (bt, pt) in zip(batch.results(), host):
+        wk, ws = oracle.star_query(bt, pt)
+        assert len(wk) > 100
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, wk)
+        np.testing.assert_array_equal(gs, ws)
