@@ -165,6 +165,13 @@ __device__ __forceinline__ bool direct_fits(const TableDev &t, int64_t total, in
   return t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc && range <= (int64_t{1} << kStageSlotBits);
 }
 
+// Slots of a direct-addressed table: the range, rounded up to whole buckets of
+// sums (the table's reserved slots are a power of two >= the range, so they
+// hold that many).
+__host__ __device__ __forceinline__ int64_t direct_cap(int64_t range) {
+  return range <= kBucketSlots ? range : (range + kBucketSlots - 1) / kBucketSlots * kBucketSlots;
+}
+
 // Words of a direct-addressed table's LDS filter: one bit per key up to 2^20
 // keys, else one bit per key pair.
 __host__ __device__ __forceinline__ int64_t direct_filter_words(int64_t range) {
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
 // also clears the Bloom words and the caller's group/pair counters.  With the
 // per-block key bounds (kmin_b / kmax_b) it chooses direct addressing when the
 // selected keys' range allows it: the header then holds the mode, kmin and
-// the range, hdr[0] the power of two covering the range (the slot count the
+// the range, hdr[0] the range rounded up to whole buckets (the slot count the
 // sums and their buckets use), and the bitmap words are cleared instead of keys.
 __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblocks, int64_t n, double max_load,
                                   int64_t *zero0, int64_t *zero1, const int32_t *kmin_b, const int32_t *kmax_b) {
@@ -249,7 +256,7 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
   const int64_t total = s_total;
   const int64_t range = s_kmax - s_kmin + 1;
   const bool direct = kmin_b && direct_fits(t, total, s_kmin, s_kmax);
-  const int64_t cap = direct ? next_pow2(range < 64 ? 64 : range) : table_capacity(total, max_load, t.cap_alloc);
+  const int64_t cap = direct ? direct_cap(range) : table_capacity(total, max_load, t.cap_alloc);
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
   if (tid == 0) {
