@@ -155,12 +155,14 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
   const int64_t range = s_kmax - s_kmin + 1;
   const int64_t cap = direct ? direct_cap(range) : table_capacity(s_total, fr.max_load, t.cap_alloc);
   const int64_t tid = local * 256 + threadIdx.x, nthr = nloc * 256;
+  for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + i] = 0;
   if (tid == 0) {
     t.hdr[0] = cap;
     t.hdr[1] = s_total;
     t.hdr[kHdrDirect] = direct;
     t.hdr[kHdrKmin] = direct ? s_kmin : 0;
     t.hdr[kHdrRange] = direct ? range : 0;
+
     *fr.d_ngroups = 0;
     if (fr.bp.next) *fr.bp.next = 0;
   }

@@ -70,6 +70,20 @@ constexpr uint32_t kNoChunk = 0xffffffffu;
 // from the selected keys' minimum and maximum, and records the mode in the
 // table header (TableDev::hdr[kHdrDirect], [kHdrKmin], [kHdrRange]).
 constexpr int kHdrDirect = 2, kHdrKmin = 3, kHdrRange = 4;
+// Header byte kHdrAddedByte + b is set (by plain stores: no read, no atomic,
+// so nothing in the fact pass waits on it) when a pass adds a sum straight
+// into a slot of bucket b instead of staging it; the bucket sums then read
+// that bucket's slot flags.  Cleared by the table initializers.
+constexpr int kHdrAddedByte = 512;
+static_assert(kHdrAddedByte + kMaxSumBuckets <= static_cast<int>(kHdrBytes), "header bytes");
+
+// Only for tables of at most kMaxSumBuckets buckets (those with bucketed sums).
+__device__ __forceinline__ void mark_added(const TableDev &t, int64_t s) {
+  reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + (s >> kBucketLg)] = 1;
+}
+__device__ __forceinline__ bool bucket_added(const TableDev &t, uint32_t b) {
+  return reinterpret_cast<const uint8_t *>(t.hdr)[kHdrAddedByte + b] != 0;
+}
 constexpr int64_t kFilterBits = int64_t{32} << kBloomLgw;  // 2^20
 
 static_assert((int64_t{kMaxBuckets} << kBucketLg) == (int64_t{1} << kStageSlotBits), "staged slot bits");
@@ -259,6 +273,7 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
   const int64_t cap = direct ? direct_cap(range) : table_capacity(total, max_load, t.cap_alloc);
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + i] = 0;
   if (tid == 0) {
     t.hdr[0] = cap;
     t.hdr[1] = total;
@@ -687,6 +702,7 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
       atomicAdd(reinterpret_cast<unsigned long long *>(&t.sums[s]),
                 static_cast<unsigned long long>(static_cast<int64_t>(en) >> kStageSlotBits));
       t.flags[s] = 1;
+      mark_added(t, s);
       continue;
     }
     const uint32_t c = pos < CH ? sl.chunk[b] : sl.newbase[b] + (pos >> bp.chunk_lg) - 1;
@@ -959,6 +975,16 @@ __device__ __forceinline__ int32_t walk_run(__amdgpu_buffer_rsrc_t r0, int32_t m
   return -1;
 }
 
+// Steps until the next staging check: c pairs are staged, cprev were at the
+// last check `since` steps ago; after a flush the whole area is free.
+__device__ __forceinline__ uint32_t next_check(uint32_t c, uint32_t cprev, uint32_t since, bool flush) {
+  const uint32_t rate = (c - cprev) / since;
+  const uint32_t per = rate + rate / 8 + 1;
+  const uint32_t room = flush ? kStageCap : c < kStageCap ? kStageCap - c : 0;
+  const uint32_t fit = room / per;
+  return fit < 1 ? 1 : fit > kCheckMax ? kCheckMax : fit;
+}
+
 // The one-join fact pass (star query) over rows [begin, end), summing into the
 // join table's slots: AGG 0 adds with buffer atomics plus a group-exists flag,
 // AGG 3 stages (slot, value) pairs in LDS and moves them to the bucket pool.
@@ -1037,6 +1063,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
           } else {  // staging full: add directly (the second kernel adds these in)
             atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[es[e]]), static_cast<unsigned long long>(ev[e]));
             t0.flags[es[e]] = 1;
+            mark_added(t0, es[e]);
           }
         }
         off += static_cast<uint32_t>(__popcll(m[e]));
@@ -1049,6 +1076,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
                : static_cast<int64_t>(static_cast<uint64_t>(x) * static_cast<uint64_t>(a.vconst - static_cast<int64_t>(w)));
   };
   uint32_t since = 0, every = 2;  // steps since the last staging check; steps between checks
+  uint32_t cprev = 0;              // staged pairs at the last check (0 after a flush)
   // AGG 3 steps the whole block together (it meets at a barrier every
   // `every` steps); otherwise each wave runs on its own.
   for (; (AGG == 3 ? wbase - int64_t{wv} * WR : wbase) < end; wbase += step) {
@@ -1169,16 +1197,18 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
     }
     // Every `every` steps the block meets and moves its staged pairs to HBM
     // once there are kFlushAt of them (pairs past kStageCap in between were
-    // added directly).  The next interval is the number of steps whose pairs
-    // fill the staging area at the rate seen so far (all threads read the
-    // same count after the barrier, so it stays block-uniform).
+    // added directly).  The next interval is the number of steps whose pairs,
+    // at the rate of the last interval plus an eighth, fit in the room the
+    // staging area has left (all threads read the same count after the
+    // barrier, so it stays block-uniform).
     if (AGG == 3 && stage_cap > 0 && ++since == every) {  // block-uniform
       __syncthreads();
       const uint32_t c = *sl->cnt;
-      const uint32_t fit = kStageCap / (c / since + 1);
-      every = fit < 1 ? 1 : fit > kCheckMax ? kCheckMax : fit;
+      const bool flush = c >= kFlushAt;
+      every = next_check(c, cprev, since, flush);
       since = 0;
-      if (c >= kFlushAt) stage_flush(*sl, *bp, t0, nb);
+      cprev = flush ? 0 : c;
+      if (flush) stage_flush(*sl, *bp, t0, nb);
     }
     cur = nxt;
   }
@@ -1187,6 +1217,7 @@ __device__ __forceinline__ void star_range(const FastArgs &a, const TableDev &t0
     if (s >= 0) {
       atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[s]), static_cast<unsigned long long>(pval));
       t0.flags[s] = 1;
+      if (AGG == 3) mark_added(t0, s);  // (AGG 0's table may have more buckets than the header has bytes)
     }
   }
   if (AGG == 3 && stage_cap > 0) {
@@ -1237,6 +1268,7 @@ __device__ __forceinline__ void star_direct(const FastArgs &a, const TableDev &t
       } else {  // staging full: add directly (the second kernel adds these in)
         atomicAdd(reinterpret_cast<unsigned long long *>(&t0.sums[es]), static_cast<unsigned long long>(ev));
         t0.flags[es] = 1;
+        mark_added(t0, es);
       }
     }
   };
@@ -1260,6 +1292,8 @@ __device__ __forceinline__ void star_direct(const FastArgs &a, const TableDev &t
     return hit ? d : -1;
   };
   uint32_t since = 0, every = 2;  // steps since the last staging check; steps between checks
+  uint32_t cprev = 0;              // staged pairs at the last check (0 after a flush)
+  uint32_t lag = 1;                // the first interval's first step staged nothing (pairs go in a step late)
   // the previous step's first 64 live rows: slot, bitmap word, value, whether the lane holds one
   int32_t pd = 0;
   uint32_t pbw = 0;
@@ -1325,10 +1359,12 @@ __device__ __forceinline__ void star_direct(const FastArgs &a, const TableDev &t
     if (stage_cap > 0 && ++since == every) {  // block-uniform: as in star_range
       __syncthreads();
       const uint32_t c = *sl->cnt;
-      const uint32_t fit = kStageCap / (c / since + 1);
-      every = fit < 1 ? 1 : fit > kCheckMax ? kCheckMax : fit;
+      const bool flush = c >= kFlushAt;
+      every = next_check(c, cprev, since - lag, flush);
+      lag = 0;
       since = 0;
-      if (c >= kFlushAt) stage_flush(*sl, *bp, t0, nb);
+      cprev = flush ? 0 : c;
+      if (flush) stage_flush(*sl, *bp, t0, nb);
     }
     cur = nxt;
   }
@@ -1698,11 +1734,12 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
     }
   }
   __syncthreads();
-  for (uint32_t s = tid; s < span; s += kFastBlock)
-    if (t.flags[lo + s]) {
-      s_sum[s] += t.sums[lo + s];
-      atomicOr(&s_bits[s >> 5], 1u << (s & 31));
-    }
+  if (bucket_added(t, b))  // block-uniform: a slot of the bucket holds a sum of its own
+    for (uint32_t s = tid; s < span; s += kFastBlock)
+      if (t.flags[lo + s]) {
+        s_sum[s] += t.sums[lo + s];
+        atomicOr(&s_bits[s >> 5], 1u << (s & 31));
+      }
   __syncthreads();
   constexpr uint32_t kPer = kBucketSlots / kFastBlock;  // each thread writes out kPer consecutive slots
   const uint32_t s0 = tid * kPer;

@@ -53,7 +53,9 @@ __host__ __device__ inline int64_t table_capacity(int64_t cnt, double max_load, 
 
 inline int64_t table_capacity_host(int64_t n, double max_load) { return table_capacity(n, max_load, INT64_MAX); }
 
-constexpr size_t kHdrBytes = 256;
+// Header of every table: int64 words (capacity, count, mode, ...) in the
+// first 256 bytes; bytes [512, 1024) are one byte per bucket of slot sums.
+constexpr size_t kHdrBytes = 1024;
 
 inline size_t table_bytes(int64_t cap, int slot_bytes, bool with_sums) {
   size_t b = kHdrBytes + static_cast<size_t>(cap) * slot_bytes;

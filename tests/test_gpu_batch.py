@@ -172,3 +172,32 @@ def test_batch_mixed_key_ranges(gpu, ctx):
         gk, gs = sorted_np(k, s)
         np.testing.assert_array_equal(gk, wk)
         np.testing.assert_array_equal(gs, ws)
+
+
+@pytest.mark.parametrize("hash_only", [False, True])
+def test_batch_sums_added_directly(gpu, ctx, hash_only):
+    # every fact row matches (no predicate on either side): the pools, sized
+    # for an eighth of a fragment's rows, run out and the rest is added into
+    # the slot sums directly; one fragment's values are too wide to stage
+    frags, host = [], []
+    for f in range(4):
+        bt, pt = gen.star_tables(5_000 + 3_000 * f, 400_003, workload=3, fragment=200 + f)
+        if f == 3:
+            pt["price"] = (pt["price"].astype(np.uint64) << np.uint64(40)).view(np.int64)
+        plan = gpu.star_plan({k: dev(v) for k, v in bt.items()})
+        plan.joins[0]["preds"] = []
+        plan.preds = []
+        frags.append((plan, [dev(pt[c]) for c in ("fk", "date", "price")]))
+        host.append((bt, pt))
+    batch = gpu.Batch(ctx, frags)
+    ctx.hash_join_only(hash_only)
+    try:
+        batch.run((4, 1024, 0.5))
+        ctx.check()
+    finally:
+        ctx.hash_join_only(False)
+    for (k, s), (bt, pt) in zip(batch.results(), host):
+        wk, ws = oracle.star_query(bt, pt, build_preds=(), probe_preds=())
+        gk, gs = sorted_np(k, s)
+        np.testing.assert_array_equal(gk, wk)
+        np.testing.assert_array_equal(gs, ws)
