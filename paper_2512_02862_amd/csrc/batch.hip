@@ -155,7 +155,10 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
   const int64_t range = s_kmax - s_kmin + 1;
   const int64_t cap = direct ? direct_cap(range) : table_capacity(s_total, fr.max_load, t.cap_alloc);
   const int64_t tid = local * 256 + threadIdx.x, nthr = nloc * 256;
-  for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + i] = 0;
+  for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) {
+    reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + i] = 0;
+    if (fr.bp.next) fr.bp.next[i] = 0;
+  }
   if (tid == 0) {
     t.hdr[0] = cap;
     t.hdr[1] = s_total;
@@ -164,7 +167,6 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
     t.hdr[kHdrRange] = direct ? range : 0;
 
     *fr.d_ngroups = 0;
-    if (fr.bp.next) *fr.bp.next = 0;
   }
   if (direct) {  // block-uniform: the bitmap and the slot sums
     uint32_t *bm = static_cast<uint32_t *>(t.slots);
@@ -252,7 +254,6 @@ __global__ __launch_bounds__(kFastBlock) void k_bat_fact_staged(const BatFrag *f
   const uint32_t nb = bucket_count(fr.t.hdr[0]);
   if (nb <= bp.stride && threadIdx.x < bp.stride) {  // the unit's first chunks, one per bucket
     const uint32_t c = static_cast<uint32_t>(local) * bp.stride + threadIdx.x;
-    bp.bucket[c] = threadIdx.x < nb ? threadIdx.x : kNoChunk;
     bp.fill[c] = 0;
     if (threadIdx.x < nb) {
       sl.chunk[threadIdx.x] = c;
@@ -440,7 +441,7 @@ static pyst_status batch_layout(pyst_ctx *ctx, const pyst_fragment *fr, int nfra
       b.bp.blocks = static_cast<uint32_t>(fact_units);
       b.bp.stride = static_cast<uint32_t>(stride);
       bp->pool_bytes_total +=
-          256 + (static_cast<size_t>(nchunks) * ((size_t{8} << kBatchChunkLg) + 8) + 255) / 256 * 256;
+          kPoolHeadBytes + (static_cast<size_t>(nchunks) * ((size_t{8} << kBatchChunkLg) + 4) + 255) / 256 * 256;
     }
     for (int k = 0; k < kPreKinds; ++k) bp->pre[k * (nfrag + 1) + f + 1] = bp->pre[k * (nfrag + 1) + f] + blocks[k];
   }
@@ -512,14 +513,13 @@ static pyst_status batch_prepare(pyst_ctx *ctx, const pyst_fragment *fr, int nfr
     b.kmax_b = allow_direct ? b.kmin_b + nblk64 : nullptr;
     p += static_cast<size_t>(2 * nblk64) * 4;
   }
-  for (int f = 0; f < nfrag && bp.staged; ++f) {  // pools: next counter, records, chunk tags, fills
+  for (int f = 0; f < nfrag && bp.staged; ++f) {  // pools: per-bucket counters, records, fills
     BatFrag &b = bp.frags[f];
     const size_t nchunks = static_cast<size_t>(bp.pool_chunks[f]);
     b.bp.next = reinterpret_cast<uint32_t *>(p);
-    b.bp.rec = reinterpret_cast<uint64_t *>(p + 256);
-    b.bp.bucket = reinterpret_cast<uint32_t *>(b.bp.rec + (nchunks << kBatchChunkLg));
-    b.bp.fill = b.bp.bucket + nchunks;
-    p += 256 + (nchunks * ((size_t{8} << kBatchChunkLg) + 8) + 255) / 256 * 256;
+    b.bp.rec = reinterpret_cast<uint64_t *>(p + kPoolHeadBytes);
+    b.bp.fill = reinterpret_cast<uint32_t *>(b.bp.rec + (nchunks << kBatchChunkLg));
+    p += kPoolHeadBytes + (nchunks * ((size_t{8} << kBatchChunkLg) + 4) + 255) / 256 * 256;
   }
   // Descriptors go up through pinned staging (a pageable copy would stall other streams).
   char *stage = ctx_pinned_staging(ctx, meta);

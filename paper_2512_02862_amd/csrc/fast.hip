@@ -97,20 +97,33 @@ __device__ __forceinline__ bool fits_stage(int64_t v) {
   return t == 0 || t == -1;
 }
 
+// The chunks past the blocks' first ones are split evenly between the nb
+// buckets of the table (nb is known on the device only), so that bucket b's
+// later chunks are the first next[b] of its own region: the second kernel
+// reads them without searching the pool.  A bucket whose region is used up
+// adds its further pairs directly.
 struct BucketPool {
   uint64_t *rec;     // pair e of chunk c at [c * chunk + e]: value << kBucketLg | slot within the bucket
-  uint32_t *bucket;  // bucket of each chunk
   uint32_t *fill;    // pairs in each chunk
-  uint32_t *next;    // chunks handed out beyond the blocks' first ones (zeroed with the table)
+  uint32_t *next;    // [kMaxSumBuckets] chunks each bucket has taken from its region (zeroed with the table)
   uint32_t nchunks;  // chunks in the pool
   uint32_t blocks;   // fact-pass blocks; block k starts with chunks [k * stride, k * stride + nb)
   uint32_t stride;   // buckets a block's first chunks are reserved for; a table with more
                      // buckets than this (its size is only known on the device) is not staged
   uint32_t chunk_lg; // log2 of the pairs per chunk
 };
+constexpr size_t kPoolHeadBytes = kMaxSumBuckets * sizeof(uint32_t);  // the next[] counters ahead of the records
 
 __host__ __device__ inline uint32_t bucket_count(int64_t cap) {
   return cap > kBucketSlots ? static_cast<uint32_t>(cap >> kBucketLg) : 1u;
+}
+
+// Bucket b's region: chunks [region_first(bp, nb, b), + region_chunks(bp, nb)).
+__device__ __forceinline__ uint32_t region_chunks(const BucketPool &bp, uint32_t nb) {
+  return (bp.nchunks - bp.blocks * bp.stride) / nb;
+}
+__device__ __forceinline__ uint32_t region_first(const BucketPool &bp, uint32_t nb, uint32_t b) {
+  return bp.blocks * bp.stride + b * region_chunks(bp, nb);
 }
 
 // The Bloom filter reuses the join table's key hash h.  The word is the top
@@ -244,7 +257,8 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
 // the range, hdr[0] the range rounded up to whole buckets (the slot count the
 // sums and their buckets use), and the bitmap words are cleared instead of keys.
 __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblocks, int64_t n, double max_load,
-                                  int64_t *zero0, int64_t *zero1, const int32_t *kmin_b, const int32_t *kmax_b) {
+                                  int64_t *zero0, int64_t *zero1, const int32_t *kmin_b, const int32_t *kmax_b,
+                                  uint32_t *pool_next) {
   __shared__ int64_t s_total, s_kmin, s_kmax;
   if (threadIdx.x < kWave) {
     int64_t part = 0;
@@ -273,7 +287,10 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
   const int64_t cap = direct ? direct_cap(range) : table_capacity(total, max_load, t.cap_alloc);
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + i] = 0;
+  for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) {
+    reinterpret_cast<uint8_t *>(t.hdr)[kHdrAddedByte + i] = 0;
+    if (pool_next) pool_next[i] = 0;
+  }
   if (tid == 0) {
     t.hdr[0] = cap;
     t.hdr[1] = total;
@@ -678,16 +695,14 @@ __device__ __forceinline__ void stage_flush(const StageLds &sl, const BucketPool
     const uint32_t k = t > CH ? (t - 1) >> bp.chunk_lg : 0;  // chunks to add once the current one is full
     uint32_t first = 0;
     if (k) {
-      first = bp.blocks * bp.stride + atomicAdd(bp.next, k);
-      if (first + k > bp.nchunks) {  // chunks of this range that do exist are marked unused
-        for (uint32_t j = first; j < bp.nchunks; ++j) bp.bucket[j] = kNoChunk;
+      const uint32_t reg = region_chunks(bp, nb), used = atomicAdd(&bp.next[tid], k);
+      first = region_first(bp, nb, tid) + used;
+      if (used + k > reg) {  // the region is used up: its chunks of this range stay empty
+        for (uint32_t j = used; j < reg; ++j) bp.fill[region_first(bp, nb, tid) + j] = 0;
         first = kNoChunk;
       } else {
         bp.fill[sl.chunk[tid]] = CH;
-        for (uint32_t j = 0; j < k; ++j) {
-          bp.bucket[first + j] = tid;
-          if (j + 1 < k) bp.fill[first + j] = CH;
-        }
+        for (uint32_t j = 0; j + 1 < k; ++j) bp.fill[first + j] = CH;
       }
     }
     sl.newbase[tid] = first;
@@ -1621,7 +1636,6 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
     const uint32_t nb = bucket_count(t0.hdr[0]);
     if (nb <= bp.stride && threadIdx.x < bp.stride) {  // the block's first chunks, one per bucket
       const uint32_t c = blockIdx.x * bp.stride + threadIdx.x;
-      bp.bucket[c] = threadIdx.x < nb ? threadIdx.x : kNoChunk;
       bp.fill[c] = 0;
       if (threadIdx.x < nb) {
         sl.chunk[threadIdx.x] = c;
@@ -1706,9 +1720,7 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
   for (uint32_t i = tid; i < kBucketSlots / 32; i += kFastBlock) s_bits[i] = 0;
   __syncthreads();
   if (nb <= bp.stride) {  // pairs were staged
-    uint32_t total = bp.blocks * bp.stride + *bp.next;
-    total = total < bp.nchunks ? total : bp.nchunks;
-    // the blocks' first chunks of bucket b, then the chunks added later (found by their tags)
+    // the blocks' first chunks of bucket b, then the chunks it took from its region
     constexpr uint32_t NW = kFastBlock / kWave;
     for (uint32_t k = wv; k < bp.blocks; k += 4 * NW) {
       uint32_t cs[4];
@@ -1716,21 +1728,13 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
       for (int i = 0; i < 4; ++i) cs[i] = k + i * NW < bp.blocks ? (k + i * NW) * bp.stride + b : kNoChunk;
       add_chunks(bp, cs, lo, s_sum, s_bits);
     }
-    for (uint32_t c0 = bp.blocks * bp.stride + wv * kWave; c0 < total; c0 += kFastBlock) {
-      const uint32_t c = c0 + lane;
-      uint64_t m = __ballot(c < total && bp.bucket[c < total ? c : c0] == b);
-      while (m) {  // wave-uniform
-        uint32_t cs[4];
+    const uint32_t reg = region_chunks(bp, nb), first = region_first(bp, nb, b);
+    const uint32_t used = bp.next[b] < reg ? bp.next[b] : reg;
+    for (uint32_t k = wv; k < used; k += 4 * NW) {
+      uint32_t cs[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          cs[i] = kNoChunk;
-          if (m) {
-            cs[i] = c0 + static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
-            m &= m - 1;
-          }
-        }
-        add_chunks(bp, cs, lo, s_sum, s_bits);
-      }
+      for (int i = 0; i < 4; ++i) cs[i] = k + i * NW < used ? first + k + i * NW : kNoChunk;
+      add_chunks(bp, cs, lo, s_sum, s_bits);
     }
   }
   __syncthreads();
@@ -1988,22 +1992,21 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
     const int64_t stride = std::min<int64_t>(kMaxBuckets, bucket_count(cap_alloc));
     const int64_t nchunks = grid * stride + ceil_div(fa.n, int64_t{kChunk}) + 1;
     if (cap_alloc <= kBucketSlots * kMaxSumBuckets && nchunks < (int64_t{1} << 31))
-      pool = ctx_alloc(ctx, 256 + static_cast<size_t>(nchunks) * (size_t{kChunk} * 8 + 8), stream);
+      pool = ctx_alloc(ctx, kPoolHeadBytes + static_cast<size_t>(nchunks) * (size_t{kChunk} * 8 + 4), stream);
     if (pool) {
       char *p = static_cast<char *>(pool);
       bp.next = reinterpret_cast<uint32_t *>(p);  // zeroed by the table initializer
-      bp.rec = reinterpret_cast<uint64_t *>(p + 256);
-      bp.bucket = reinterpret_cast<uint32_t *>(bp.rec + static_cast<size_t>(nchunks) * kChunk);
-      bp.fill = bp.bucket + nchunks;
+      bp.rec = reinterpret_cast<uint64_t *>(p + kPoolHeadBytes);
+      bp.fill = reinterpret_cast<uint32_t *>(bp.rec + static_cast<size_t>(nchunks) * kChunk);
       bp.nchunks = static_cast<uint32_t>(nchunks);
       bp.chunk_lg = kChunkLg;
       bp.blocks = static_cast<uint32_t>(grid);
       bp.stride = static_cast<uint32_t>(stride);
     }
   }
-  int64_t *zero1 = pool ? reinterpret_cast<int64_t *>(bp.next) : s.po.count;
   if (st == PYST_OK)
-    st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, zero1, stream, pool != nullptr && !ctx_hash_join_only(ctx));
+    st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, pool ? nullptr : s.po.count, stream,
+                               pool != nullptr && !ctx_hash_join_only(ctx), pool ? bp.next : nullptr);
   if (pool) {
     if (st == PYST_OK) st = bucketed_sums(ctx, fa, d, bp, out_keys, out_sums, out_cap, d_ngroups, stream);
     ctx_free(ctx, pool, stream);
@@ -2020,7 +2023,8 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
 // with allow_direct (its consumers handle the direct-addressed mode) and keys
 // that allow it, direct-addressed.
 pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
-                                  int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct) {
+                                  int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct,
+                                  uint32_t *pool_next) {
   for (int j = 0; j < plan->njoins; ++j) {
     const pyst_join_spec &js = plan->joins[j];
     const int64_t nb = js.key.n;
@@ -2067,7 +2071,8 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
     }
     const int iblocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(cap_alloc, 256), 64), 2048));
     k_fast_table_init<<<iblocks, 256, 0, stream>>>(d->t[j], cnt, nblk, nb, js.max_load, j == 0 ? zero0 : nullptr,
-                                                   j == 0 ? zero1 : nullptr, kmin_b, kmax_b);
+                                                   j == 0 ? zero1 : nullptr, kmin_b, kmax_b,
+                                                   j == 0 ? pool_next : nullptr);
     PYST_LAUNCH_CHECK("k_fast_table_init");
     if (nb > 0) {
       const int32_t *key = static_cast<const int32_t *>(js.key.data);

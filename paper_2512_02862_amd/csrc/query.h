@@ -78,7 +78,8 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
                        int64_t *out_keys, int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                        hipStream_t stream);
 pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
-                                  int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct);
+                                  int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct,
+                                  uint32_t *pool_next);
 pyst_status fast_fact_pass(pyst_ctx *ctx, int njoins, int agg_mode, const FastArgs &a, const DimTables &d,
                            const GroupDev &g, const PairsOut &po, hipStream_t stream);
 pyst_status fast_finish(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, const DimTables &d, AggState *s,

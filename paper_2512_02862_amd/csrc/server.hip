@@ -232,7 +232,7 @@ static std::unique_ptr<DimEntry> build_entry(pyst_server *sv, const Request &r, 
   *ps = fill_u32(e->d_err, 1, 0u, st);
   if (*ps == PYST_OK) {
     ErrScope scope(sv->ctx, e->d_err);
-    *ps = fast_build_dimensions(sv->ctx, &r.pc.plan, r.q, &e->d, nullptr, nullptr, st, false);
+    *ps = fast_build_dimensions(sv->ctx, &r.pc.plan, r.q, &e->d, nullptr, nullptr, st, false, nullptr);
   }
   if (*ps != PYST_OK) {
     free_dimensions(sv->ctx, &e->d, st);

@@ -91,7 +91,7 @@ pyst_status streamed_query(pyst_ctx *ctx, const pyst_plan *plan, const pyst_col 
       st = group_init(s.g, nullptr, bound, 0, plan->group_max_load, stream);
     }
   }
-  if (st == PYST_OK) st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, nullptr, stream, false);
+  if (st == PYST_OK) st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, nullptr, stream, false, nullptr);
   // The copy stream must not overwrite ring memory before `stream` has reached this point.
   hipEvent_t start = nullptr;
   if (st == PYST_OK) {
