@@ -54,6 +54,8 @@ KERNEL_SOURCES = {  # the files that define each profiled kernel (name patterns 
     "k_move_scatter": ["agg.hip", "pyst_internal.h"],
     "k_bucket_groups": ["agg.hip", "pyst_internal.h"],
     "k_bat_fact_staged": ["batch.hip", "fast.hip", "pyst_internal.h", "table.h", "query.h"],
+    "k_part_hist_i32": ["ops.hip", "pyst_internal.h"],
+    "k_part_scatter": ["ops.hip", "pyst_internal.h"],
 }
 Q18_WORKLOAD = "q18_n60000000_g15000000"
 BATCH_WORKLOAD = "batch_512"
@@ -174,6 +176,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=30_000_000)
     ap.add_argument("--join-k", default="1,4,8", help="8-byte columns a side of the join microbenchmark")
+    ap.add_argument("--partition-fanouts", default="2,8,64", help="fanouts of the partition extra")
+    ap.add_argument("--join-legs", default="plain,partition,m2m",
+                    help="parts of the join extra: the materializing join, the same with its partition leg, "
+                         "the many-to-many join (counter runs take 'plain' alone)")
     ap.add_argument("--batch-fragments", type=int, default=512)
     ap.add_argument("--batch-max-rows", type=float, default=2e7, help="largest fragment probe size")
     ap.add_argument("--config4-rows", type=int, default=2_000_000_000, help="pinned host fact rows, streamed and served")
@@ -283,12 +289,13 @@ def main():
             result[name] = {"error": repr(e)}
         torch.cuda.empty_cache()
 
-    extra("partition", bench_partition, ctx, pyst, p, npr, log)
+    extra("partition", bench_partition, ctx, pyst, p, npr, log, [int(x) for x in args.partition_fanouts.split(",")])
     del b, p, fact
     torch.cuda.empty_cache()
     extra("chain", bench_chain, ctx, pyst, gen, log)
     extra("groupby", bench_groupby, ctx, pyst, gen, log)
-    extra("join", bench_join, ctx, pyst, gen, log, 60_000_000, 160_000_000, [int(x) for x in args.join_k.split(",")])
+    extra("join", bench_join, ctx, pyst, gen, log, 60_000_000, 160_000_000, [int(x) for x in args.join_k.split(",")],
+          2, args.join_legs.split(","))
     extra("batch", bench_batch, ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
     extra("config4", bench_config4, pyst, gen, log, args.config4_rows, args.config4_requests, 64_000_000, 32 << 30)
 
@@ -299,10 +306,13 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def bench_partition(ctx, pyst, p, npr, log):
+PART_WORKLOAD = "partition_f64_n60000000"  # counters of the fanout-64 partition (--partition-fanouts 64)
+
+
+def bench_partition(ctx, pyst, p, npr, log, fanouts=(2, 8, 64)):
     import torch
     out = {}
-    for fanout in (2, 8, 64):
+    for fanout in fanouts:
         log("partition fanout %d" % fanout)
 
         def step():
@@ -322,6 +332,9 @@ def bench_partition(ctx, pyst, p, npr, log):
         out["F%d" % fanout] = {"ms": ms, "rows_per_s": npr / (ms / 1e3), "gbs": alg / (ms / 1e3) / 1e9,
                               "frac_of_peak": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                               "scatter_kernel_us": sc_ms / max(sc_n, 1) * 1e3}
+        if fanout == 64:  # HBM bytes per launch from committed counters (null once the kernels changed)
+            out["F64"]["counter_traffic"] = {k: counter_traffic(k, PART_WORKLOAD)
+                                             for k in ("k_part_hist_i32", "k_part_scatter")}
         torch.cuda.empty_cache()
     return out
 
@@ -491,7 +504,8 @@ def bench_many_to_many(ctx, pyst, gen, log, nb, npr, ks=(1, 4)):
     return out
 
 
-def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8), fanout=2):
+def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8), fanout=2,
+               legs=("plain", "partition", "m2m")):
     """Build + probe + materialize of k 8-byte columns per side (one pyst_join_materialize call),
     and the same join with its partition leg (both sides partitioned first, fanout 2: two GPUs)."""
     import torch
@@ -537,10 +551,12 @@ def bench_join(ctx, pyst, gen, log, nb=60_000_000, npr=160_000_000, ks=(1, 4, 8)
             # gathers: the build side at k > 1, after packing its columns row-major
             "gather_us": g_us, "gather_gbs": gather_bytes / (g_us / 1e6) / 1e9 if g_us > 0 else None,
             "gather_rows_us": r_ms / r_n * 1e3 if r_n else None, "pack_rows_us": k_ms / k_n * 1e3 if k_n else None}
-        out["k%d" % k]["with_partition"] = bench_partitioned_join(ctx, pyst, log, bk, bc, pk, pc, fanout, m)
+        if "partition" in legs:
+            out["k%d" % k]["with_partition"] = bench_partitioned_join(ctx, pyst, log, bk, bc, pk, pc, fanout, m)
         del bk, pk, bc, pc
         torch.cuda.empty_cache()
-    out["many_to_many"] = bench_many_to_many(ctx, pyst, gen, log, nb, npr)
+    if "m2m" in legs:
+        out["many_to_many"] = bench_many_to_many(ctx, pyst, gen, log, nb, npr)
     # HBM bytes per launch from committed counters of the k = 4 run (null once the kernels changed)
     out["k4_counter_traffic"] = {"k_join_probe": counter_traffic("k_join_probe", JOIN_WORKLOAD),
                                  "k_gather_rows": counter_traffic("k_gather_rows<4", JOIN_WORKLOAD),
