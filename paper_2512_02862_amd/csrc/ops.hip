@@ -405,9 +405,11 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(PartArgs a, const int32_
   int32_t pos[ITEMS];
   uint16_t dst[ITEMS];
   int64_t keyv[ITEMS];
-  // The first two payload columns are loaded with the keys (one memory round
+  // The first payload columns are loaded with the keys (one memory round
   // trip per tile instead of one per column); later ones in the column loop.
-  constexpr int PRE = 2;
+  // (Two with 512 threads; one with 1024, whose 4 rows per thread then fit in
+  // 56 registers: two blocks of 16 waves per CU.)
+  constexpr int PRE = BLOCK >= 1024 ? 1 : 2;
   int64_t pre[PRE][ITEMS];
   {
     int64_t r64[ITEMS];
@@ -492,9 +494,13 @@ static void launch_partition(const PartArgs &a, int32_t *hist, int32_t *scan, in
     k_part_hist_i32<64><<<static_cast<unsigned>(ntiles), 256, 0, stream>>>(a, hist, ntiles);
   else if (hist_phase)
     k_part_hist<kPartBlock, kPartItems, FMAX><<<static_cast<unsigned>(ntiles), kPartBlock, 0, stream>>>(a, hist, ntiles);
-  else
-    // the same 4096-row tiles as the histogram, as 512 threads x 8 rows (fewer
-    // registers per thread with the payloads loaded up front)
+  else if (FMAX <= 256)
+    // the same 4096-row tiles as the histogram, as 1024 threads x 4 rows (few
+    // registers per thread: 32 waves per CU; at fanout 64, 524 against 567 us
+    // per 60M-row partition as 512 threads x 8 rows)
+    k_part_scatter<4 * kPartBlock, kPartItems / 4, FMAX><<<static_cast<unsigned>(ntiles), 4 * kPartBlock, 0, stream>>>(
+        a, scan, ntiles);
+  else  // 1024 destinations: the per-wave counters of 16 waves would not leave LDS for two blocks
     k_part_scatter<2 * kPartBlock, kPartItems / 2, FMAX><<<static_cast<unsigned>(ntiles), 2 * kPartBlock, 0, stream>>>(
         a, scan, ntiles);
 }
@@ -860,7 +866,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_probe(const void *key, const int
   using KeyT = std::conditional_t<K64, int64_t, int32_t>;              // probe column
   using CmpT = std::conditional_t<WIDE || K64, int64_t, int32_t>;      // key as held
   using StoredT = std::conditional_t<WIDE, int64_t, int32_t>;          // table payload
-  constexpr KeyT kColEmpty = K64 ? kEmpty64 : kEmpty32;
+  constexpr KeyT kColEmpty = K64 ? static_cast<KeyT>(kEmpty64) : static_cast<KeyT>(kEmpty32);
   CmpT kk[ITEMS];
   StoredT first_pay[ITEMS];
   int32_t c[ITEMS];
