@@ -53,14 +53,16 @@ __device__ __forceinline__ int frag_of(const int64_t *pre, int nfrag, int64_t b)
   return lo;
 }
 
-#define PYST_BLOCK_FRAG(kind)                                              \
+#define PYST_BLOCK_FRAG_AT(kind, blk)                                      \
   __shared__ int s_frag;                                                   \
-  if (threadIdx.x == 0) s_frag = frag_of(pre + (kind) * (nfrag + 1), nfrag, blockIdx.x); \
+  const int64_t blk_ = (blk);                                              \
+  if (threadIdx.x == 0) s_frag = frag_of(pre + (kind) * (nfrag + 1), nfrag, blk_); \
   __syncthreads();                                                         \
   const int f = s_frag;                                                    \
   const BatFrag &fr = frags[f];                                            \
-  const int64_t local = blockIdx.x - pre[(kind) * (nfrag + 1) + f];        \
+  const int64_t local = blk_ - pre[(kind) * (nfrag + 1) + f];              \
   const int64_t nloc = pre[(kind) * (nfrag + 1) + f + 1] - pre[(kind) * (nfrag + 1) + f];
+#define PYST_BLOCK_FRAG(kind) PYST_BLOCK_FRAG_AT(kind, blockIdx.x)
 
 // The fact pass lays its blocks out by fragment in the order kept after the
 // prefixes (pre[kPreKinds * (nfrag + 1) + i]: the fragment at position i),
@@ -165,12 +167,12 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
     t.hdr[kHdrDirect] = direct;
     t.hdr[kHdrKmin] = direct ? s_kmin : 0;
     t.hdr[kHdrRange] = direct ? range : 0;
+    t.hdr[kHdrDistinct] = 0;
 
     *fr.d_ngroups = 0;
   }
-  if (direct) {  // block-uniform: the bitmap and the slot sums
-    uint32_t *bm = static_cast<uint32_t *>(t.slots);
-    for (int64_t i = tid; i < (range + 31) / 32; i += nthr) bm[i] = 0;
+  if (direct) {  // block-uniform: the byte map and the slot sums (the bitmap is packed whole later)
+    direct_clear(t, range, tid, nthr);
     for (int64_t i = tid; i < cap; i += nthr) {
       t.sums[i] = 0;
       t.flags[i] = 0;
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
 
 // One dimension tile of one fragment per block (as k_fast_build).
 __global__ __launch_bounds__(256) void k_bat_build(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {
-  PYST_BLOCK_FRAG(kPreBuild)
+  PYST_BLOCK_FRAG_AT(kPreBuild, xcd_block(blockIdx.x, gridDim.x))
   (void)nloc;
   if (fr.t.hdr[kHdrDirect]) build_tile_direct(fr.bkey, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
   else build_tile(fr.bkey, fr.sel, fr.cnt, fr.nb, local, fr.t, err);
@@ -201,7 +203,13 @@ __global__ __launch_bounds__(256) void k_bat_bloom(const BatFrag *frags, const i
   PYST_BLOCK_FRAG(kPreBloom)
   if (fr.t.hdr[kHdrDirect]) {  // the bitmap as the filter (fits the words reserved for the Bloom filter)
     const int64_t words = direct_filter_words(fr.t.hdr[kHdrRange]);
-    for (int64_t w = local * 256 + threadIdx.x; w < words; w += nloc * 256) fr.t.bloom[w] = direct_filter_word(fr.t, w);
+    int keys = 0;
+    for (int64_t w = local * 256 + threadIdx.x; w < words; w += nloc * 256) {
+      int k;
+      fr.t.bloom[w] = direct_pack_word(fr.t, w, &k);
+      keys += k;
+    }
+    add_distinct(fr.t, keys);
     return;
   }
   if (fr.t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use it
@@ -252,6 +260,8 @@ __global__ __launch_bounds__(kFastBlock) void k_bat_fact_staged(const BatFrag *f
   sl.cnt = sl.newbase + kMaxBuckets;
   const BucketPool &bp = fr.bp;
   const uint32_t nb = bucket_count(fr.t.hdr[0]);
+  if (local == 0 && threadIdx.x == 0 && fr.t.hdr[kHdrDirect] && fr.t.hdr[kHdrDistinct] != fr.t.hdr[1])
+    latch(err, kErrDup);  // every fragment has a first unit
   if (nb <= bp.stride && threadIdx.x < bp.stride) {  // the unit's first chunks, one per bucket
     const uint32_t c = static_cast<uint32_t>(local) * bp.stride + threadIdx.x;
     bp.fill[c] = 0;

@@ -68,8 +68,13 @@ constexpr uint32_t kNoChunk = 0xffffffffu;
 // each pair of its bits ORed into one (range <= 2^21: the exact bit is read
 // from the bitmap in the L2).  The table initializer decides on the device,
 // from the selected keys' minimum and maximum, and records the mode in the
-// table header (TableDev::hdr[kHdrDirect], [kHdrKmin], [kHdrRange]).
-constexpr int kHdrDirect = 2, kHdrKmin = 3, kHdrRange = 4;
+// table header (TableDev::hdr[kHdrDirect], [kHdrKmin], [kHdrRange]).  The
+// build marks each key in a byte map (one plain byte store per key: no atomic,
+// and stores need no reply); the filter pass then packs the byte map into the
+// bitmap and the LDS filter and counts the distinct keys into
+// hdr[kHdrDistinct].  Fewer distinct keys than selected rows means a duplicate
+// key, which the fact pass reports.
+constexpr int kHdrDirect = 2, kHdrKmin = 3, kHdrRange = 4, kHdrDistinct = 5;
 // Header byte kHdrAddedByte + b is set (by plain stores: no read, no atomic,
 // so nothing in the fact pass waits on it) when a pass adds a sum straight
 // into a slot of bucket b instead of staging it; the bucket sums then read
@@ -186,10 +191,25 @@ __device__ __forceinline__ void wave_key_bounds(const int32_t *key, const int64_
   }
 }
 
+// A direct table's byte map sits in its key memory after the bitmap, 16-byte
+// aligned; the initializer clears whole 64-key groups of it (the most that one
+// filter word packs).
+__host__ __device__ __forceinline__ int64_t direct_bytemap_off(int64_t range) {
+  return ((range + 31) / 32 * 4 + 15) / 16 * 16;
+}
+__host__ __device__ __forceinline__ int64_t direct_bytemap_len(int64_t range) { return (range + 63) / 64 * 64; }
+
 // Whether a keys-only table whose selected keys (total of them) lie in [kmin, kmax] is direct-addressed.
 __device__ __forceinline__ bool direct_fits(const TableDev &t, int64_t total, int64_t kmin, int64_t kmax) {
   const int64_t range = kmax - kmin + 1;
-  return t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc && range <= (int64_t{1} << kStageSlotBits);
+  return t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc && range <= (int64_t{1} << kStageSlotBits) &&
+         direct_bytemap_off(range) + direct_bytemap_len(range) <= 4 * t.cap_alloc;
+}
+
+// Clears a direct table's byte map (threads tid, tid + nthr, ... of a grid).
+__device__ __forceinline__ void direct_clear(const TableDev &t, int64_t range, int64_t tid, int64_t nthr) {
+  uint4 *bytes = reinterpret_cast<uint4 *>(static_cast<char *>(t.slots) + direct_bytemap_off(range));
+  for (int64_t i = tid; i < direct_bytemap_len(range) / 16; i += nthr) bytes[i] = uint4{0u, 0u, 0u, 0u};
 }
 
 // Slots of a direct-addressed table: the range, rounded up to whole buckets of
@@ -297,12 +317,12 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
     t.hdr[kHdrDirect] = direct;
     t.hdr[kHdrKmin] = direct ? s_kmin : 0;
     t.hdr[kHdrRange] = direct ? range : 0;
+    t.hdr[kHdrDistinct] = 0;
     if (zero0) *zero0 = 0;
     if (zero1) *zero1 = 0;
   }
-  if (direct) {  // uniform: the bitmap, the slot sums, the filter
-    uint32_t *bm = static_cast<uint32_t *>(t.slots);
-    for (int64_t i = tid; i < (range + 31) / 32; i += nthr) bm[i] = 0;
+  if (direct) {  // uniform: the byte map, the slot sums, the filter (the bitmap is packed whole later)
+    direct_clear(t, range, tid, nthr);
     if (t.sums)
       for (int64_t i = tid; i < cap; i += nthr) {
         t.sums[i] = 0;
@@ -386,13 +406,13 @@ __device__ __forceinline__ void build_tile(const int32_t *key, const int32_t *se
   }
 }
 
-// The same tile into a direct-addressed table: one atomic OR per key sets its
-// bit (every key's OR is issued before any result is looked at); a bit that
-// was already set is a duplicate key.
+// The same tile into a direct-addressed table: one byte store per key marks
+// it in the byte map (duplicates are found when the byte map is packed).
 __device__ __forceinline__ void build_tile_direct(const int32_t *key, const int32_t *sel, const int32_t *cnt,
                                                   int64_t n, int64_t tile, const TableDev &t, uint32_t *err) {
   constexpr int ITEMS = kDimTile / 256;
   const uint32_t kmin = static_cast<uint32_t>(t.hdr[kHdrKmin]);
+  uint8_t *bytes = static_cast<uint8_t *>(t.slots) + direct_bytemap_off(t.hdr[kHdrRange]);
   const int64_t base = tile * kDimTile;
   const int64_t rest = n - base;
   const int64_t have = sel ? cnt[tile] : (rest < kDimTile ? rest : kDimTile);
@@ -407,21 +427,14 @@ __device__ __forceinline__ void build_tile_direct(const int32_t *key, const int3
   int32_t k[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) k[j] = v[j] ? key[row[j]] : kEmpty32;
-  uint32_t *bm = static_cast<uint32_t *>(t.slots);
-  uint32_t bit[ITEMS], old[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (v[j] && k[j] == kEmpty32) {
       latch(err, kErrKey);
       v[j] = false;
     }
-    const uint32_t d = static_cast<uint32_t>(k[j]) - kmin;  // < range: the range spans the selected keys
-    bit[j] = 1u << (d & 31);
-    old[j] = v[j] ? atomicOr(&bm[d >> 5], bit[j]) : 0u;
+    if (v[j]) bytes[static_cast<uint32_t>(k[j]) - kmin] = 1;  // < range: the range spans the selected keys
   }
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (v[j] && (old[j] & bit[j])) latch(err, kErrDup);
 }
 
 // Tables built here always went through k_fast_table_init, which set the mode.
@@ -533,21 +546,54 @@ __device__ __forceinline__ uint32_t pair_or16(uint32_t x) {
   return x;
 }
 
-// One thread per filter word.  A direct-addressed table's filter is its
-// bitmap (range <= 2^20 bits) or the bitmap with each bit pair ORed into one
-// (range <= 2^21): filter bit j stands for the keys kmin + 2j and kmin + 2j + 1.
-__device__ __forceinline__ uint32_t direct_filter_word(const TableDev &t, int64_t w) {
+// The 16 bytes of a byte map (each 0 or 1) as 16 bits, byte i -> bit i.
+__device__ __forceinline__ uint32_t pack_bytes16(uint4 q) {
+  auto p4 = [](uint32_t x) { return ((x & 0x01010101u) * 0x01020408u) >> 24; };
+  return p4(q.x) | (p4(q.y) << 4) | (p4(q.z) << 8) | (p4(q.w) << 12);
+}
+
+// One thread per filter word: packs the keys that filter word w covers from
+// the byte map into the bitmap and returns the word; *keys receives how many
+// keys it holds.  A direct-addressed table's filter is its bitmap (range <=
+// 2^20 bits) or the bitmap with each bit pair ORed into one (range <= 2^21):
+// filter bit j stands for the keys kmin + 2j and kmin + 2j + 1.
+__device__ __forceinline__ uint32_t direct_pack_word(const TableDev &t, int64_t w, int *keys) {
   const int64_t range = t.hdr[kHdrRange], nwords = (range + 31) / 32;
-  const uint32_t *bm = static_cast<const uint32_t *>(t.slots);
-  if (range <= kFilterBits) return w < nwords ? bm[w] : 0u;
-  const uint32_t lo = 2 * w < nwords ? bm[2 * w] : 0u, hi = 2 * w + 1 < nwords ? bm[2 * w + 1] : 0u;
-  return pair_or16(lo) | (pair_or16(hi) << 16);
+  uint32_t *bm = static_cast<uint32_t *>(t.slots);
+  const uint4 *bytes = reinterpret_cast<const uint4 *>(static_cast<const char *>(t.slots) + direct_bytemap_off(range));
+  const bool paired = range > kFilterBits;
+  uint32_t bits[2] = {0u, 0u};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t bw = paired ? 2 * w + h : w;
+    if ((h == 0 || paired) && bw < nwords) {  // its 32 bytes lie within the cleared 64-key groups
+      bits[h] = pack_bytes16(bytes[2 * bw]) | (pack_bytes16(bytes[2 * bw + 1]) << 16);
+      bm[bw] = bits[h];
+    }
+  }
+  *keys = __popc(bits[0]) + __popc(bits[1]);
+  return paired ? pair_or16(bits[0]) | (pair_or16(bits[1]) << 16) : bits[0];
+}
+
+// Adds a block's count of distinct keys to the table header (one atomic per block).
+__device__ __forceinline__ void add_distinct(const TableDev &t, int keys) {
+  __shared__ int s_k[256 / kWave];
+  const int v = wave_sum(keys);
+  if (lane_id() == 0) s_k[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;
+    for (int i = 0; i < static_cast<int>(blockDim.x) / kWave; ++i) sum += s_k[i];
+    if (sum) atomicAdd(reinterpret_cast<unsigned long long *>(&t.hdr[kHdrDistinct]), static_cast<unsigned long long>(sum));
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
-  if (t.hdr[kHdrDirect]) {
+  if (t.hdr[kHdrDirect]) {  // uniform
     const int64_t w = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
-    t.bloom[w] = direct_filter_word(t, w);
+    int keys;
+    t.bloom[w] = direct_pack_word(t, w, &keys);
+    add_distinct(t, keys);
     return;
   }
   if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter
@@ -1647,6 +1693,7 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
   }
   // (only the staged one-join pass, whose tables come from k_fast_table_init, meets direct addressing)
   const bool direct = NJ == 1 && AGG == 3 && t0.hdr[kHdrDirect] != 0;
+  if (direct && blockIdx.x == 0 && threadIdx.x == 0 && t0.hdr[kHdrDistinct] != t0.hdr[1]) latch(err, kErrDup);
   const bool use_bloom = direct || (t0.bloom != nullptr && t0.hdr[1] <= kBloomMaxKeys);
   if (use_bloom)
     for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];

@@ -201,3 +201,28 @@ def test_batch_sums_added_directly(gpu, ctx, hash_only):
         gk, gs = sorted_np(k, s)
         np.testing.assert_array_equal(gk, wk)
         np.testing.assert_array_equal(gs, ws)
+
+
+@pytest.mark.parametrize("hash_only", [False, True])
+def test_batch_duplicate_dimension_key(gpu, ctx, hash_only):
+    # one fragment of three repeats a selected dimension key: the batch reports
+    # a duplicate key whether its table is direct-addressed or hashed
+    frags = []
+    for f in range(3):
+        bt, pt = gen.star_tables(30_000, 200_001, workload=3, fragment=300 + f)
+        if f == 1:
+            i = int(np.flatnonzero(bt["key"] == 17)[0])
+            j = int(np.flatnonzero(bt["key"] == 23)[0])
+            bt["key"][i] = 23
+            bt["segment"][i] = bt["segment"][j] = 1
+        frags.append((gpu.star_plan({k: dev(v) for k, v in bt.items()}),
+                      [dev(pt[c]) for c in ("fk", "date", "price")]))
+    batch = gpu.Batch(ctx, frags)
+    ctx.hash_join_only(hash_only)
+    try:
+        batch.run((4, 1024, 0.5))
+        with pytest.raises(gpu.PystError) as e:
+            ctx.check()
+    finally:
+        ctx.hash_join_only(False)
+    assert e.value.status == gpu.ERR_DUP_KEY
