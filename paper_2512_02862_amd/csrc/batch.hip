@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
   }
   __syncthreads();
   const TableDev &t = fr.t;
-  const bool direct = fr.kmin_b && direct_fits(t, s_total, s_kmin, s_kmax);
+  const bool direct = fr.kmin_b && direct_fits(t, s_total, s_kmin, s_kmax, int64_t{1} << kStageSlotBits);
   const int64_t range = s_kmax - s_kmin + 1;
   const int64_t cap = direct ? direct_cap(range) : table_capacity(s_total, fr.max_load, t.cap_alloc);
   const int64_t tid = local * 256 + threadIdx.x, nthr = nloc * 256;

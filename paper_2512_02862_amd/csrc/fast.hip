@@ -199,11 +199,16 @@ __host__ __device__ __forceinline__ int64_t direct_bytemap_off(int64_t range) {
 }
 __host__ __device__ __forceinline__ int64_t direct_bytemap_len(int64_t range) { return (range + 63) / 64 * 64; }
 
-// Whether a keys-only table whose selected keys (total of them) lie in [kmin, kmax] is direct-addressed.
-__device__ __forceinline__ bool direct_fits(const TableDev &t, int64_t total, int64_t kmin, int64_t kmax) {
+// Whether a table whose selected keys (total of them) lie in [kmin, kmax] is
+// direct-addressed: a keys-only table (4-byte slots) becomes a bitmap, a
+// key + payload table (8-byte slots) keeps its slot format with key k in slot
+// k - kmin.  max_range: the largest range its consumer takes.
+__device__ __forceinline__ bool direct_fits(const TableDev &t, int64_t total, int64_t kmin, int64_t kmax,
+                                            int64_t max_range) {
   const int64_t range = kmax - kmin + 1;
-  return t.slot_bytes == 4 && total > 0 && range <= t.cap_alloc && range <= (int64_t{1} << kStageSlotBits) &&
-         direct_bytemap_off(range) + direct_bytemap_len(range) <= 4 * t.cap_alloc;
+  if (total <= 0 || range > t.cap_alloc || range > max_range) return false;
+  if (t.slot_bytes == 8) return true;
+  return t.slot_bytes == 4 && direct_bytemap_off(range) + direct_bytemap_len(range) <= 4 * t.cap_alloc;
 }
 
 // Clears a direct table's byte map (threads tid, tid + nthr, ... of a grid).
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
 // sums and their buckets use), and the bitmap words are cleared instead of keys.
 __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblocks, int64_t n, double max_load,
                                   int64_t *zero0, int64_t *zero1, const int32_t *kmin_b, const int32_t *kmax_b,
-                                  uint32_t *pool_next) {
+                                  int64_t max_range, uint32_t *pool_next) {
   __shared__ int64_t s_total, s_kmin, s_kmax;
   if (threadIdx.x < kWave) {
     int64_t part = 0;
@@ -303,8 +308,10 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
   __syncthreads();
   const int64_t total = s_total;
   const int64_t range = s_kmax - s_kmin + 1;
-  const bool direct = kmin_b && direct_fits(t, total, s_kmin, s_kmax);
-  const int64_t cap = direct ? direct_cap(range) : table_capacity(total, max_load, t.cap_alloc);
+  const bool direct = kmin_b && direct_fits(t, total, s_kmin, s_kmax, max_range);
+  const bool bitmap = direct && t.slot_bytes == 4;
+  // a direct key + payload table: the range rounded up to whole 16-byte groups
+  const int64_t cap = bitmap ? direct_cap(range) : direct ? (range + 1) / 2 * 2 : table_capacity(total, max_load, t.cap_alloc);
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < kMaxSumBuckets; i += nthr) {
@@ -321,7 +328,7 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
     if (zero0) *zero0 = 0;
     if (zero1) *zero1 = 0;
   }
-  if (direct) {  // uniform: the byte map, the slot sums, the filter (the bitmap is packed whole later)
+  if (bitmap) {  // uniform: the byte map, the slot sums, the filter (the bitmap is packed whole later)
     direct_clear(t, range, tid, nthr);
     if (t.sums)
       for (int64_t i = tid; i < cap; i += nthr) {
@@ -447,14 +454,19 @@ __global__ __launch_bounds__(256) void k_fast_build(const int32_t *key, const in
 // Build of a key + payload table (8-byte slots), one row per thread: the
 // slot is read first and claimed with a compare-and-swap where empty (a CAS
 // straight to a cold line measured slower; so did 16 rows per thread, whose
-// reads wait for each other before any claim).
+// reads wait for each other before any claim).  A direct-addressed table
+// takes one plain store per row into the key's own slot (the scattered
+// 8-byte stores bound it: four rows per thread measured the same).
 __global__ __launch_bounds__(256) void k_fast_build_payload(const int32_t *key, const int32_t *payload,
                                                             const int32_t *sel, const int32_t *cnt, int64_t n,
                                                             TableDev t, uint32_t *err) {
   const int64_t mask = t.hdr[0] - 1;
   uint64_t *slots = static_cast<uint64_t *>(t.slots);
   const uint64_t empty = static_cast<uint32_t>(kEmpty32);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const bool direct = t.hdr[kHdrDirect] != 0;  // uniform
+  const uint32_t kmin = static_cast<uint32_t>(t.hdr[kHdrKmin]);
+  const int64_t nthr = int64_t{gridDim.x} * blockDim.x, tid = blockIdx.x * int64_t{blockDim.x} + threadIdx.x;
+  for (int64_t i = tid; i < n; i += nthr) {
     int64_t row = i;
     if (sel) {
       if ((i % kDimTile) >= cnt[i / kDimTile]) continue;
@@ -467,6 +479,10 @@ __global__ __launch_bounds__(256) void k_fast_build_payload(const int32_t *key, 
     }
     const uint64_t packed = uint64_t{static_cast<uint32_t>(k)} |
                             (uint64_t{static_cast<uint32_t>(payload ? payload[row] : static_cast<int32_t>(row))} << 32);
+    if (direct) {  // a plain store into the key's own slot (k - kmin < range: the range spans the selected keys)
+      slots[static_cast<uint32_t>(k) - kmin] = packed;
+      continue;
+    }
     int64_t s = (table_hash32(k) & mask) & ~int64_t{1};
     bool done = false;
     for (int64_t step = 0; step <= mask; ++step) {
@@ -598,6 +614,30 @@ __global__ __launch_bounds__(256) void k_fast_bloom(TableDev t) {
   }
   if (t.hdr[1] > kBloomMaxKeys) return;  // the fact pass will not use the filter
   bloom_build_word(t, blockIdx.x * int64_t{blockDim.x} + threadIdx.x);
+}
+
+// Distinct keys of a direct-addressed key + payload table (slots not EMPTY)
+// into hdr[kHdrDistinct]: a duplicate key's rows share one slot, so the count
+// falls short of the selected rows.
+// Each thread reads four 16-byte groups (eight slots) at once; few blocks
+// (each adds its count with one atomic on the same header word, and those
+// atomics serialize).
+__global__ __launch_bounds__(256) void k_direct_count(TableDev t) {
+  if (!t.hdr[kHdrDirect]) return;  // uniform
+  constexpr int U = 4;
+  const int64_t ng = t.hdr[0] / 2;  // the slot count is even
+  const ulonglong2 *grp = static_cast<const ulonglong2 *>(t.slots);
+  const ulonglong2 none{static_cast<uint32_t>(kEmpty32), static_cast<uint32_t>(kEmpty32)};
+  int keys = 0;
+  for (int64_t i0 = blockIdx.x * int64_t{256 * U} + threadIdx.x; i0 < ng; i0 += int64_t{gridDim.x} * 256 * U) {
+    ulonglong2 q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = i0 + u * 256 < ng ? grp[i0 + u * 256] : none;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      keys += (static_cast<int32_t>(q[u].x) != kEmpty32) + (static_cast<int32_t>(q[u].y) != kEmpty32);
+  }
+  add_distinct(t, keys);
 }
 
 // ------------------------------------------------------------------ the fact pass
@@ -1458,6 +1498,13 @@ __device__ __forceinline__ void chain_range(const FastArgs &a, const TableDev &t
   const int bshift = bloom_shift(cap0);
   const __amdgpu_buffer_rsrc_t r0 = rsrc(t0.slots, cap0 * 4);
   const __amdgpu_buffer_rsrc_t r1 = rsrc(t1.slots, cap1 * SB1);
+  // Direct-addressed joins (uniform): join 0's LDS filter is then its exact
+  // bitmap (range <= kFilterBits), so a live row is found and join 0's table
+  // is never read; join 1 (8-byte slots) keeps key k in slot k - kmin1, one
+  // 16-byte load and no walk.
+  const bool dir0 = t0.hdr[kHdrDirect] != 0, dir1 = SB1 == 8 && t1.hdr[kHdrDirect] != 0;
+  const uint32_t kmin0 = static_cast<uint32_t>(t0.hdr[kHdrKmin]), range0 = static_cast<uint32_t>(t0.hdr[kHdrRange]);
+  const uint32_t kmin1 = static_cast<uint32_t>(t1.hdr[kHdrKmin]), range1 = static_cast<uint32_t>(t1.hdr[kHdrRange]);
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   int64_t wpos = 0, wend = 0;  // the wave's pair run, wave-uniform
@@ -1504,7 +1551,7 @@ __device__ __forceinline__ void chain_range(const FastArgs &a, const TableDev &t
     W.k1 = o[1];
     W.ok = w0 + static_cast<uint32_t>(lane) < n;
     W.s0 = static_cast<int32_t>(table_hash32(W.k0)) & mask0 & ~3;
-    W.q0 = __builtin_amdgcn_raw_buffer_load_b128(r0, W.ok ? W.s0 * 4 : kBufOob, 0, 0);
+    W.q0 = __builtin_amdgcn_raw_buffer_load_b128(r0, W.ok && !dir0 ? W.s0 * 4 : kBufOob, 0, 0);
     if (V64) {
       const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rv, W.ok ? W.crow * 8 : kBufOob, 0, kNonTemporal);
       W.x = static_cast<int64_t>((uint64_t{v.y} << 32) | v.x);
@@ -1560,8 +1607,8 @@ __device__ __forceinline__ void chain_range(const FastArgs &a, const TableDev &t
     for (int k = 0; k < K; ++k) {
       bool empty;
       const int h = match4(W[k].q0, W[k].k0, &empty);
-      slot0[k] = W[k].ok && h >= 0 ? W[k].s0 + h : -1;
-      need[k] = W[k].ok && h < 0 && !empty && groups0 > 1;
+      slot0[k] = W[k].ok && (dir0 || h >= 0) ? (dir0 ? 0 : W[k].s0 + h) : -1;
+      need[k] = W[k].ok && !dir0 && h < 0 && !empty && groups0 > 1;
       s[k] = W[k].s0;
     }
     for (int32_t g = groups0 - 1;; --g) {
@@ -1586,14 +1633,24 @@ __device__ __forceinline__ void chain_range(const FastArgs &a, const TableDev &t
     v4i32 q1[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      s[k] = static_cast<int32_t>(table_hash32(W[k].k1)) & mask1 & ~(GS - 1);
-      q1[k] = __builtin_amdgcn_raw_buffer_load_b128(r1, slot0[k] >= 0 ? s[k] * SB1 : kBufOob, 0, 0);
+      const uint32_t d1 = static_cast<uint32_t>(W[k].k1) - kmin1;
+      const bool go = slot0[k] >= 0 && (!dir1 || d1 < range1);
+      s[k] = dir1 ? static_cast<int32_t>(d1 & ~1u) : static_cast<int32_t>(table_hash32(W[k].k1)) & mask1 & ~(GS - 1);
+      q1[k] = __builtin_amdgcn_raw_buffer_load_b128(r1, go ? s[k] * SB1 : kBufOob, 0, 0);
     }
     int state[K];
     int32_t pl[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      state[k] = probe1(q1[k], W[k].k1, &pl[k]);
+      if (dir1) {  // the key's own slot: the first or the second of the group
+        const bool odd = (static_cast<uint32_t>(W[k].k1) - kmin1) & 1u;
+        const int32_t key = odd ? q1[k].z : q1[k].x;
+        pl[k] = odd ? q1[k].w : q1[k].y;
+        state[k] = key == W[k].k1 ? 1 : 0;  // a slot outside the range read as zeros: key 0 only if k1 is 0
+        if (static_cast<uint32_t>(W[k].k1) - kmin1 >= range1) state[k] = 0;
+      } else {
+        state[k] = probe1(q1[k], W[k].k1, &pl[k]);
+      }
       need[k] = slot0[k] >= 0 && state[k] < 0 && groups1 > 1;
     }
     for (int32_t g = groups1 - 1;; --g) {
@@ -1632,7 +1689,10 @@ __device__ __forceinline__ void chain_range(const FastArgs &a, const TableDev &t
                in_range(row_of(cur.c1, r), a.plo[1], a.pspan[1], a.pneg[1]);
       kv[0][r] = row_of(cur.f0, r);
       kv[1][r] = row_of(cur.f1, r);
-      if (use_bloom) {
+      if (dir0) {
+        const uint32_t d0 = static_cast<uint32_t>(kv[0][r]) - kmin0;
+        l = l && d0 < range0 && ((s_bloom[d0 >> 5] >> (d0 & 31)) & 1u);
+      } else if (use_bloom) {
         const uint32_t h = table_hash32(kv[0][r]);
         const uint32_t bits = bloom_bits(h);
         l = l && (s_bloom[bloom_word(h, cap0 - 1, bshift)] & bits) == bits;
@@ -1691,9 +1751,14 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
     }
     if (threadIdx.x == 0) *sl.cnt = 0;
   }
-  // (only the staged one-join pass, whose tables come from k_fast_table_init, meets direct addressing)
-  const bool direct = NJ == 1 && AGG == 3 && t0.hdr[kHdrDirect] != 0;
-  if (direct && blockIdx.x == 0 && threadIdx.x == 0 && t0.hdr[kHdrDistinct] != t0.hdr[1]) latch(err, kErrDup);
+  // Direct-addressed tables come from k_fast_table_init, for the staged one-join
+  // pass (join 0) and the two-join pair pass (both joins) only.
+  constexpr bool kMayDirect = (NJ == 1 && AGG == 3) || (NJ == 2 && AGG == 2);
+  const bool direct = kMayDirect && t0.hdr[kHdrDirect] != 0;
+  if (kMayDirect && blockIdx.x == 0 && threadIdx.x == 0) {  // duplicate keys seen while the tables were built
+    if (direct && t0.hdr[kHdrDistinct] != t0.hdr[1]) latch(err, kErrDup);
+    if (NJ == 2 && t1.hdr[kHdrDirect] != 0 && t1.hdr[kHdrDistinct] != t1.hdr[1]) latch(err, kErrDup);
+  }
   const bool use_bloom = direct || (t0.bloom != nullptr && t0.hdr[1] <= kBloomMaxKeys);
   if (use_bloom)
     for (int i = threadIdx.x; i < kBloomWords; i += kFastBlock) s_bloom[i] = gmem(t0.bloom)[i];
@@ -2053,7 +2118,9 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
   }
   if (st == PYST_OK)
     st = fast_build_dimensions(ctx, plan, q, &d, d_ngroups, pool ? nullptr : s.po.count, stream,
-                               pool != nullptr && !ctx_hash_join_only(ctx), pool ? bp.next : nullptr);
+                               (pool != nullptr || (plan->njoins == 2 && q.agg_mode == 2 && fa.n > 0)) &&
+                                   !ctx_hash_join_only(ctx),
+                               pool ? bp.next : nullptr);
   if (pool) {
     if (st == PYST_OK) st = bucketed_sums(ctx, fa, d, bp, out_keys, out_sums, out_cap, d_ngroups, stream);
     ctx_free(ctx, pool, stream);
@@ -2068,7 +2135,9 @@ pyst_status fast_query(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q
 
 // Dimension tables of the fast path: join 0 keys-only with a Bloom filter, or,
 // with allow_direct (its consumers handle the direct-addressed mode) and keys
-// that allow it, direct-addressed.
+// that allow it, direct-addressed: join 0 of the staged one-join pass (range
+// up to 2^kStageSlotBits), both joins of the two-join pair pass (join 0 up to
+// kFilterBits keys, so that its LDS filter is exact; join 1 with payloads).
 pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const QueryShape &q, DimTables *d,
                                   int64_t *zero0, int64_t *zero1, hipStream_t stream, bool allow_direct,
                                   uint32_t *pool_next) {
@@ -2088,7 +2157,10 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
     const int32_t *sel = nullptr;
     int32_t *cnt = nullptr, *kmin_b = nullptr, *kmax_b = nullptr;
     const int64_t nblk = std::max<int64_t>(1, ceil_div(nb, kDimTile));
-    const bool direct_ok = allow_direct && j == 0 && sb == 4 && sums && nb > 0 && js.key.dtype == PYST_I32;
+    const bool chain = plan->njoins == 2 && q.agg_mode == 2;
+    const bool direct_ok = allow_direct && nb > 0 && js.key.dtype == PYST_I32 &&
+                           ((j == 0 && sb == 4 && (sums || chain)) || (j == 1 && sb == 8 && chain));
+    const int64_t max_range = j == 1 ? INT64_MAX : sums ? (int64_t{1} << kStageSlotBits) : int64_t{kFilterBits};
     if (js.npreds > 0 || direct_ok) {  // (direct addressing needs the selected keys' bounds from the filter)
       const int64_t nblk64 = (nblk + 63) / 64 * 64;
       d->sel_mem[j] = ctx_alloc(ctx, static_cast<size_t>(nblk) * kDimTile * sizeof(int32_t) +
@@ -2118,17 +2190,23 @@ pyst_status fast_build_dimensions(pyst_ctx *ctx, const pyst_plan *plan, const Qu
     }
     const int iblocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(cap_alloc, 256), 64), 2048));
     k_fast_table_init<<<iblocks, 256, 0, stream>>>(d->t[j], cnt, nblk, nb, js.max_load, j == 0 ? zero0 : nullptr,
-                                                   j == 0 ? zero1 : nullptr, kmin_b, kmax_b,
+                                                   j == 0 ? zero1 : nullptr, kmin_b, kmax_b, max_range,
                                                    j == 0 ? pool_next : nullptr);
     PYST_LAUNCH_CHECK("k_fast_table_init");
     if (nb > 0) {
       const int32_t *key = static_cast<const int32_t *>(js.key.data);
       const int32_t *pay = static_cast<const int32_t *>(js.payload.data);
+      if (js.npreds == 0) sel = nullptr;  // the filter ran for the key bounds only: every row is selected
       if (sb == 4) {  // one block per dimension tile (the filter's tiles)
         k_fast_build<<<static_cast<unsigned>(nblk), 256, 0, stream>>>(key, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
       } else {
         const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(nb, 256), int64_t{1} << 20));
         k_fast_build_payload<<<blocks, 256, 0, stream>>>(key, pay, sel, cnt, nb, d->t[j], ctx_err_word(ctx));
+        if (direct_ok) {  // (a no-op unless the initializer chose direct addressing)
+          PYST_LAUNCH_CHECK("k_fast_build_payload");
+          k_direct_count<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(cap_alloc / 2, 256 * 4), 256)), 256, 0,
+                           stream>>>(d->t[j]);
+        }
       }
       PYST_LAUNCH_CHECK("k_fast_build");
       if (d->t[j].bloom) {  // keys-only (join 0)

@@ -291,7 +291,7 @@ def _chain(n=1_000_003, na=40_000, nb=4_000, zs=0.0):
     return a, b, f
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("zs", [0.0, 1.0])
 @pytest.mark.parametrize("max_groups", [0, 300_000])
 def test_chain_both_paths(gpu, ctx, path, zs, max_groups):
@@ -304,7 +304,7 @@ def test_chain_both_paths(gpu, ctx, path, zs, max_groups):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("preds", [True, False])
 def test_chain_nearly_full_tables(gpu, ctx, path, preds):
     # both join tables near load 0.92 (B keys-only, A key + payload, two slots
@@ -324,7 +324,7 @@ def test_chain_nearly_full_tables(gpu, ctx, path, preds):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_chain_group_by_two_join_keys(gpu, ctx, path):
     # GROUP BY (A.key, B.key): join 1 needs no payload (keys-only table)
     a, b, f = _chain(n=500_001)
@@ -342,7 +342,7 @@ def test_chain_group_by_two_join_keys(gpu, ctx, path):
     np.testing.assert_array_equal(s, ws)
 
 
-@pytest.mark.parametrize("path", ["fast", "generic"])
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 @pytest.mark.parametrize("n", [1, 5, 4097])
 def test_chain_small_and_empty(gpu, ctx, path, n):
     # a handful of fact rows (few or no pairs reach the group-by), and a
@@ -357,6 +357,64 @@ def test_chain_small_and_empty(gpu, ctx, path, n):
     plan.preds = [(2, "<", -5)]
     k, s = run(gpu, ctx, plan, fact, path)
     assert len(k) == 0 and len(oracle.chain_query(a, b, f, fact_preds=(("date", "<", -5),))[0]) == 0
+
+
+def _shift_keys(a, b, f, a_map, b_map):
+    a, b, f = dict(a), dict(b), dict(f)
+    a["key"], f["a_fk"] = a_map(a["key"]), a_map(f["a_fk"])
+    b["key"], f["b_fk"] = b_map(b["key"]), b_map(f["b_fk"])
+    return a, b, f
+
+
+def _affine(mul, add):
+    return lambda x: (x.astype(np.int64) * mul + add).astype(np.int32)
+
+
+@pytest.mark.parametrize("path", ["fast", "fast_hash"])
+@pytest.mark.parametrize("case", ["b_wide", "a_sparse", "top", "bottom"])
+def test_chain_direct_addressing_ranges(gpu, ctx, path, case):
+    # B's selected keys over more than 2^20 values (B hashed, A direct), A's
+    # keys sparse (A hashed, B direct), and both dense with the ranges ending
+    # at INT32_MAX or starting just above the reserved INT32_MIN; some probe
+    # keys fall just outside each range
+    a, b, f = _chain(n=700_001, na=40_000, nb=6_000)
+    na, nb = 40_000, 6_000
+    maps = {"b_wide": (_affine(1, 0), _affine(200, 0)),
+            "a_sparse": (_affine(65_537, -2 ** 30), _affine(1, 0)),
+            "top": (_affine(1, 2 ** 31 - 1 - na), _affine(1, 2 ** 31 - 1 - nb)),
+            "bottom": (_affine(1, -2 ** 31), _affine(1, -2 ** 31))}[case]
+    a, b, f = _shift_keys(a, b, f, *maps)
+    f["a_fk"][::97] = (int(a["key"].min()) - 1) if case != "bottom" else int(a["key"].max()) + 3
+    f["b_fk"][5::89] = (int(b["key"].max()) + 1) if case != "top" else int(b["key"].min()) - 2
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()})
+    k, s = run(gpu, ctx, plan, [dev(f[c]) for c in FACT_CHAIN], path)
+    wk, ws = oracle.chain_query(a, b, f)
+    assert len(wk) > 10_000
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
+@pytest.mark.parametrize("path", ["fast", "fast_hash"])
+@pytest.mark.parametrize("side", ["a", "b"])
+def test_chain_duplicate_dimension_key(gpu, ctx, path, side):
+    # a repeated key in A, or in B's selected rows: reported whether the table
+    # is direct-addressed or hashed
+    a, b, f = _chain(n=200_001, na=20_000, nb=3_000)
+    a, b = {k: v.copy() for k, v in a.items()}, {k: v.copy() for k, v in b.items()}
+    t = a if side == "a" else b
+    i, j = int(np.flatnonzero(t["key"] == 17)[0]), int(np.flatnonzero(t["key"] == 29)[0])
+    t["key"][i] = 29
+    if side == "b":
+        b["segment"][i] = b["segment"][j] = 1
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()})
+    ctx.hash_join_only(path == "fast_hash")
+    try:
+        gpu.query(ctx, plan, [dev(f[c]) for c in FACT_CHAIN])
+        with pytest.raises(gpu.PystError) as e:
+            ctx.check()
+    finally:
+        ctx.hash_join_only(False)
+    assert e.value.status == gpu.ERR_DUP_KEY
 
 
 def test_fast_query_capacity_error(gpu, ctx):
