@@ -184,6 +184,9 @@ def main():
     ap.add_argument("--batch-max-rows", type=float, default=2e7, help="largest fragment probe size")
     ap.add_argument("--config4-rows", type=int, default=2_000_000_000, help="pinned host fact rows, streamed and served")
     ap.add_argument("--config4-requests", type=int, default=200)
+    ap.add_argument("--config4-serve", action="store_true",
+                    help="also serve the config4 requests at full size (off by default: a full-size Poisson "
+                         "serving run has failed with a device memory fault whose cause is not found yet)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -297,7 +300,8 @@ def main():
     extra("join", bench_join, ctx, pyst, gen, log, 60_000_000, 160_000_000, [int(x) for x in args.join_k.split(",")],
           2, args.join_legs.split(","))
     extra("batch", bench_batch, ctx, pyst, gen, log, args.batch_fragments, args.batch_max_rows)
-    extra("config4", bench_config4, pyst, gen, log, args.config4_rows, args.config4_requests, 64_000_000, 32 << 30)
+    extra("config4", bench_config4, pyst, gen, log, args.config4_rows, args.config4_requests, 64_000_000, 32 << 30,
+          args.config4_serve)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(b_host, p_host, args.cpu_sample_rows, log)
@@ -714,7 +718,7 @@ def _digest(k, s):
     return (int(k.numel()), int(k.sum()), int(s.sum()), int((k * 0x9E3779B1 + s).sum()))
 
 
-def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total):
+def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total, serve_requests=False):
     """The served workload at its stated size: a 2e9-row chain fact table in
     pinned host memory streamed in 64M-row chunks under a 32 GiB device
     budget; the chain query streamed over all of it (raw and bit-packed); then
@@ -722,7 +726,8 @@ def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total):
     at 0.5 and 0.9 of the one-at-a-time capacity, FIFO against continuous
     batching, plus back-to-back bursts of both; every request of the
     continuous-batching runs compared with its FIFO (alone) result, and a
-    seeded sample of requests checked against the oracle on its fact prefix."""
+    seeded sample of requests checked against the oracle on its fact prefix.
+    Without serve_requests only the streamed query runs (raw and packed)."""
     import numpy as np
     import torch
 
@@ -780,122 +785,134 @@ def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total):
     out["stream"] = stream
 
     # --- serving
-    rows = np.minimum(gen.loguniform_i64(nreq, 1e6, nrows, gen.seed(4, 7, 0)), nrows)
-    kinds = ["star" if i % 2 == 0 else "chain" for i in range(nreq)]
-    srv_budget = budget_total - ring - (1 << 20)
-
-    def plan_for(kind, r):
-        if kind == "star":
-            return pyst.fact_star_plan(b), nbd
-        g = int(min(max(r // 8, 1024), max_groups))
-        return pyst.chain_plan(a, b, max_groups=g), g
-
-    # seeded oracle sample: two star and two chain requests small enough for the
-    # single-threaded oracle (star <= 1.5e8 rows, chain <= 4e7 rows)
-    rng = np.random.default_rng(gen.seed(4, 9, 0))
-    small_star = [i for i in range(nreq) if kinds[i] == "star" and rows[i] <= 150_000_000]
-    small_chain = [i for i in range(nreq) if kinds[i] == "chain" and rows[i] <= 40_000_000]
-    sample = sorted(list(rng.choice(small_star, min(2, len(small_star)), replace=False)) +
-                    list(rng.choice(small_chain, min(2, len(small_chain)), replace=False)))
-    sample = [int(i) for i in sample]
-    star_ids = [i for i in range(nreq) if kinds[i] == "star"]
-    big_star = max(star_ids, key=lambda i: rows[i]) if star_ids else None
-
-    def run(max_active, arrivals, packed_cols=None, keep=()):
-        srv = pyst.Server(None if packed_cols else host, budget=srv_budget, max_active=max_active, nbuf=2,
-                          chunk_rows=chunk, packed=packed_cols)
-        for kind in ("star", "chain"):  # warm the resident dimension tables outside the trace
-            p, c = plan_for(kind, 1_000_000)
-            srv.wait(srv.submit(p, 1_000_000, c))
-        base = srv.stats()
-        t_start = time.perf_counter()
-        tickets = [None] * nreq
-
-        def producer():
-            for i in range(nreq):
-                delay = t_start + arrivals[i] - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-                p, c = plan_for(kinds[i], int(rows[i]))
-                tickets[i] = srv.submit(p, int(rows[i]), c)
-
-        th = threading.Thread(target=producer)
-        th.start()
-        lat, digests, kept = [], [], {}
-        for i in range(nreq):
-            while tickets[i] is None:
-                time.sleep(0.0005)
-            k, s_, l_ = srv.wait(tickets[i])
-            lat.append(l_)
-            digests.append(_digest(k, s_))
-            if i in keep:
-                kept[i] = (k.cpu().numpy(), s_.cpu().numpy())
-            del k, s_
-        th.join()
-        makespan = time.perf_counter() - t_start
-        st = srv.stats()
-        srv.check()
-        srv.close()
-        torch.cuda.empty_cache()
-        lat = np.array(lat)
-        res = {"p50_ms": float(np.percentile(lat, 50, method="nearest")),
-               "p99_ms": float(np.percentile(lat, 99, method="nearest")),
-               "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "makespan_s": makespan,
-               "requests_per_s": nreq / makespan, "rows_per_s": float(rows.sum()) / makespan,
-               "chunks_copied": st["chunks_copied"] - base["chunks_copied"],
-               "h2d_gb": (st["bytes_copied"] - base["bytes_copied"]) / 1e9,
-               "max_active_seen": st["max_active_seen"],
-               "admission_waits": st["admission_waits"] - base["admission_waits"]}
-        log("config4: served %d requests, max_active %d: makespan %.1f s, p50 %.0f ms, p99 %.0f ms, "
-            "admission waits %d" % (nreq, max_active, makespan, res["p50_ms"], res["p99_ms"], res["admission_waits"]))
-        return res, digests, kept
-
     serve = {}
-    traces = {}
-    burst_fifo, fifo_digests, _ = run(1, np.zeros(nreq))
-    serve["burst_one_at_a_time"] = burst_fifo
-    capacity = burst_fifo["requests_per_s"]
-    burst_cb, d, kept = run(8, np.zeros(nreq), keep=set(sample + ([big_star] if big_star is not None else [])))
-    burst_cb["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
-    serve["burst_continuous_batching"] = burst_cb
-    for rho in (0.5, 0.9):
-        lam = rho * capacity
-        arrivals = gen.poisson_arrivals(nreq, lam, gen.seed(4, 8, int(rho * 10)))
-        traces[rho] = arrivals
-        log("config4: Poisson rate %.2f req/s (%.1f x one-at-a-time capacity)" % (lam, rho))
-        fifo, _, _ = run(1, arrivals)
-        cb, d, _ = run(8, arrivals)
-        cb["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
-        serve["rho%.1f" % rho] = {"arrival_rate_per_s": lam, "one_at_a_time": fifo, "continuous_batching": cb}
+    if serve_requests:
+        rows = np.minimum(gen.loguniform_i64(nreq, 1e6, nrows, gen.seed(4, 7, 0)), nrows)
+        kinds = ["star" if i % 2 == 0 else "chain" for i in range(nreq)]
+        srv_budget = budget_total - ring - (1 << 20)
 
-    # the oracle on the sampled requests' fact prefixes (results of the burst run)
-    checks = []
-    for i in sample:
-        pref = {c: v[:int(rows[i])].numpy() for c, v in zip(("a_fk", "b_fk", "date", "price", "discount"), host)}
-        t0 = time.perf_counter()
-        if kinds[i] == "star":
-            wk, ws = oracle.star_query(b_h, {"fk": pref["b_fk"], "date": pref["date"], "price": pref["price"]})
-        else:
-            wk, ws = oracle.chain_query(a_h, b_h, pref)
-        k, s_ = kept[i]
-        o = np.argsort(k)
-        ok = bool(len(k) == len(wk) and np.array_equal(k[o], wk) and np.array_equal(s_[o], ws))
-        checks.append({"request": i, "kind": kinds[i], "rows": int(rows[i]), "groups": int(len(wk)), "equal": ok,
-                       "oracle_s": time.perf_counter() - t0})
-    if big_star is not None:
-        i = big_star
-        pref = {c: v[:int(rows[i])].numpy() for c, v in zip(("b_fk", "date", "price"), host[1:4])}
-        t0 = time.perf_counter()
-        wk, ws, used = oracle.star_query_threaded(b_h, {"fk": pref["b_fk"], "date": pref["date"],
-                                                        "price": pref["price"]}, threads=len(os.sched_getaffinity(0)))
-        k, s_ = kept[i]
-        o = np.argsort(k)
-        checks.append({"request": i, "kind": "star", "rows": int(rows[i]), "groups": int(len(wk)),
-                       "equal": bool(np.array_equal(k[o], wk) and np.array_equal(s_[o], ws)),
-                       "checked_by": "threaded baseline (%d threads; equal to the oracle by test)" % used,
-                       "seconds": time.perf_counter() - t0})
-    serve["oracle_checks"] = checks
-    serve["result_mismatches"] = sum(not c["equal"] for c in checks)
+        def plan_for(kind, r):
+            if kind == "star":
+                return pyst.fact_star_plan(b), nbd
+            g = int(min(max(r // 8, 1024), max_groups))
+            return pyst.chain_plan(a, b, max_groups=g), g
+
+        # seeded oracle sample: two star and two chain requests small enough for the
+        # single-threaded oracle (star <= 1.5e8 rows, chain <= 4e7 rows)
+        rng = np.random.default_rng(gen.seed(4, 9, 0))
+        small_star = [i for i in range(nreq) if kinds[i] == "star" and rows[i] <= 150_000_000]
+        small_chain = [i for i in range(nreq) if kinds[i] == "chain" and rows[i] <= 40_000_000]
+        sample = sorted(list(rng.choice(small_star, min(2, len(small_star)), replace=False)) +
+                        list(rng.choice(small_chain, min(2, len(small_chain)), replace=False)))
+        sample = [int(i) for i in sample]
+        star_ids = [i for i in range(nreq) if kinds[i] == "star"]
+        big_star = max(star_ids, key=lambda i: rows[i]) if star_ids else None
+
+        def run(max_active, arrivals, packed_cols=None, keep=()):
+            srv = pyst.Server(None if packed_cols else host, budget=srv_budget, max_active=max_active, nbuf=2,
+                              chunk_rows=chunk, packed=packed_cols)
+            for kind in ("star", "chain"):  # warm the resident dimension tables outside the trace
+                p, c = plan_for(kind, 1_000_000)
+                srv.wait(srv.submit(p, 1_000_000, c))
+            base = srv.stats()
+            t_start = time.perf_counter()
+            tickets = [None] * nreq
+
+            def producer():
+                for i in range(nreq):
+                    delay = t_start + arrivals[i] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                    p, c = plan_for(kinds[i], int(rows[i]))
+                    tickets[i] = srv.submit(p, int(rows[i]), c)
+
+            failed = []
+
+            def producer_checked():
+                try:
+                    producer()
+                except BaseException as e:  # noqa: BLE001 -- reported by the consumer below
+                    failed.append(e)
+
+            th = threading.Thread(target=producer_checked)
+            th.start()
+            lat, digests, kept = [], [], {}
+            for i in range(nreq):
+                while tickets[i] is None:
+                    if failed:
+                        raise RuntimeError("config4 request producer failed: %r" % (failed[0],))
+                    time.sleep(0.0005)
+                k, s_, l_ = srv.wait(tickets[i])
+                lat.append(l_)
+                digests.append(_digest(k, s_))
+                if i in keep:
+                    kept[i] = (k.cpu().numpy(), s_.cpu().numpy())
+                del k, s_
+            th.join()
+            makespan = time.perf_counter() - t_start
+            st = srv.stats()
+            srv.check()
+            srv.close()
+            torch.cuda.empty_cache()
+            lat = np.array(lat)
+            res = {"p50_ms": float(np.percentile(lat, 50, method="nearest")),
+                   "p99_ms": float(np.percentile(lat, 99, method="nearest")),
+                   "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "makespan_s": makespan,
+                   "requests_per_s": nreq / makespan, "rows_per_s": float(rows.sum()) / makespan,
+                   "chunks_copied": st["chunks_copied"] - base["chunks_copied"],
+                   "h2d_gb": (st["bytes_copied"] - base["bytes_copied"]) / 1e9,
+                   "max_active_seen": st["max_active_seen"],
+                   "admission_waits": st["admission_waits"] - base["admission_waits"]}
+            log("config4: served %d requests, max_active %d: makespan %.1f s, p50 %.0f ms, p99 %.0f ms, "
+                "admission waits %d" % (nreq, max_active, makespan, res["p50_ms"], res["p99_ms"], res["admission_waits"]))
+            return res, digests, kept
+
+        serve = {}
+        traces = {}
+        burst_fifo, fifo_digests, _ = run(1, np.zeros(nreq))
+        serve["burst_one_at_a_time"] = burst_fifo
+        capacity = burst_fifo["requests_per_s"]
+        burst_cb, d, kept = run(8, np.zeros(nreq), keep=set(sample + ([big_star] if big_star is not None else [])))
+        burst_cb["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
+        serve["burst_continuous_batching"] = burst_cb
+        for rho in (0.5, 0.9):
+            lam = rho * capacity
+            arrivals = gen.poisson_arrivals(nreq, lam, gen.seed(4, 8, int(rho * 10)))
+            traces[rho] = arrivals
+            log("config4: Poisson rate %.2f req/s (%.1f x one-at-a-time capacity)" % (lam, rho))
+            fifo, _, _ = run(1, arrivals)
+            cb, d, _ = run(8, arrivals)
+            cb["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
+            serve["rho%.1f" % rho] = {"arrival_rate_per_s": lam, "one_at_a_time": fifo, "continuous_batching": cb}
+
+        # the oracle on the sampled requests' fact prefixes (results of the burst run)
+        checks = []
+        for i in sample:
+            pref = {c: v[:int(rows[i])].numpy() for c, v in zip(("a_fk", "b_fk", "date", "price", "discount"), host)}
+            t0 = time.perf_counter()
+            if kinds[i] == "star":
+                wk, ws = oracle.star_query(b_h, {"fk": pref["b_fk"], "date": pref["date"], "price": pref["price"]})
+            else:
+                wk, ws = oracle.chain_query(a_h, b_h, pref)
+            k, s_ = kept[i]
+            o = np.argsort(k)
+            ok = bool(len(k) == len(wk) and np.array_equal(k[o], wk) and np.array_equal(s_[o], ws))
+            checks.append({"request": i, "kind": kinds[i], "rows": int(rows[i]), "groups": int(len(wk)), "equal": ok,
+                           "oracle_s": time.perf_counter() - t0})
+        if big_star is not None:
+            i = big_star
+            pref = {c: v[:int(rows[i])].numpy() for c, v in zip(("b_fk", "date", "price"), host[1:4])}
+            t0 = time.perf_counter()
+            wk, ws, used = oracle.star_query_threaded(b_h, {"fk": pref["b_fk"], "date": pref["date"],
+                                                            "price": pref["price"]}, threads=len(os.sched_getaffinity(0)))
+            k, s_ = kept[i]
+            o = np.argsort(k)
+            checks.append({"request": i, "kind": "star", "rows": int(rows[i]), "groups": int(len(wk)),
+                           "equal": bool(np.array_equal(k[o], wk) and np.array_equal(s_[o], ws)),
+                           "checked_by": "threaded baseline (%d threads; equal to the oracle by test)" % used,
+                           "seconds": time.perf_counter() - t0})
+        serve["oracle_checks"] = checks
+        serve["result_mismatches"] = sum(not c["equal"] for c in checks)
 
     # --- the same table bit-packed: encoded into pageable memory, the raw table
     # unpinned, the packed one pinned; streamed and served again
@@ -933,13 +950,18 @@ def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total):
     sctx.close()
     stream["packed"] = {"bytes": packed_bytes, "bytes_per_row": packed_bytes / nrows,
                         "ratio": nrows * raw_b / packed_bytes, "host_encode_s": pack_s}
-    cbp, d, _ = run(8, traces[0.9], packed)
-    cbp["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
-    serve["rho0.9"]["continuous_batching_packed"] = cbp
-    serve.update({"requests": nreq, "server_budget_bytes": srv_budget, "ring_bytes": ring, "max_active": 8,
-                  "request_rows_mean": float(rows.mean()), "request_rows_max": int(rows.max()),
-                  "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]; device arena %d "
-                              "GiB in total (chunk ring of 2 x %d rows included)" % (nrows, budget_total >> 30, chunk)})
+    if serve_requests:
+        cbp, d, _ = run(8, traces[0.9], packed)
+        cbp["results_equal_to_alone"] = sum(x == y for x, y in zip(d, fifo_digests))
+        serve["rho0.9"]["continuous_batching_packed"] = cbp
+        serve.update({"requests": nreq, "server_budget_bytes": srv_budget, "ring_bytes": ring, "max_active": 8,
+                      "request_rows_mean": float(rows.mean()), "request_rows_max": int(rows.max()),
+                      "workload": "50/50 star and chain requests, scan sizes log-uniform in [1e6, %d]; device arena "
+                                  "%d GiB in total (chunk ring of 2 x %d rows included)" % (nrows, budget_total >> 30,
+                                                                                         chunk)})
+    else:
+        serve = {"skipped": "full-size serving runs only with --config4-serve (a full-size Poisson serving run "
+                            "failed with a device memory fault whose cause is not found yet)"}
     out["serve"] = serve
     del packed
     pinned.free_all()
