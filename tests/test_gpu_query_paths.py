@@ -394,6 +394,22 @@ def test_chain_direct_addressing_ranges(gpu, ctx, path, case):
     np.testing.assert_array_equal(s, ws)
 
 
+@pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
+def test_chain_filtered_payload_join(gpu, ctx, path):
+    # a predicate on A as well: A's table holds only the selected keys (its
+    # build goes through the filter's selection) and the probe of an A key
+    # that was filtered out must miss, direct-addressed or hashed
+    a, b, f = _chain(n=600_001, na=50_000, nb=5_000)
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()})
+    plan.joins[1]["cols"] = [plan.joins[1]["key"], plan.joins[1]["payload"]]
+    plan.joins[1]["preds"] = [(1, "<", 900)]
+    k, s = run(gpu, ctx, plan, [dev(f[c]) for c in FACT_CHAIN], path)
+    wk, ws = oracle.chain_query(a, b, f, a_preds=(("date", "<", 900),))
+    assert len(wk) > 5_000
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
 @pytest.mark.parametrize("path", ["fast", "fast_hash"])
 @pytest.mark.parametrize("side", ["a", "b"])
 def test_chain_duplicate_dimension_key(gpu, ctx, path, side):
