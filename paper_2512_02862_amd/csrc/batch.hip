@@ -90,10 +90,12 @@ __global__ __launch_bounds__(256) void k_bat_filter(const BatFrag *frags, const 
   int64_t rows[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
+  int32_t kv[ITEMS];
+  if (fr.kmin_b) load_keys<ITEMS>(fr.bkey, rows, fr.nb, kv);  // uniform
   bool keep[ITEMS];
   eval_preds_items<ITEMS>(fr.bpred, rows, fr.nb, keep);
   __shared__ int32_t s_min[NW], s_max[NW];
-  if (fr.kmin_b) wave_key_bounds<ITEMS>(fr.bkey, rows, keep, w, s_min, s_max);  // uniform
+  if (fr.kmin_b) wave_key_bounds<ITEMS>(kv, keep, w, s_min, s_max);  // uniform
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll

@@ -169,13 +169,19 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
   return v;
 }
 
+// The keys of a filter tile's rows (rows past n read as 0), loaded before the
+// predicate columns so that both are in flight together.
+template <int ITEMS>
+__device__ __forceinline__ void load_keys(const int32_t *key, const int64_t (&rows)[ITEMS], int64_t n,
+                                          int32_t (&kv)[ITEMS]) {
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) kv[j] = rows[j] < n ? key[rows[j]] : 0;
+}
+
 // The least and greatest key of a wave's kept rows into s_min[w] / s_max[w].
 template <int ITEMS>
-__device__ __forceinline__ void wave_key_bounds(const int32_t *key, const int64_t (&rows)[ITEMS],
-                                                const bool (&keep)[ITEMS], int w, int32_t *s_min, int32_t *s_max) {
-  int32_t kv[ITEMS];
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) kv[j] = keep[j] ? key[rows[j]] : 0;
+__device__ __forceinline__ void wave_key_bounds(const int32_t (&kv)[ITEMS], const bool (&keep)[ITEMS], int w,
+                                                int32_t *s_min, int32_t *s_max) {
   int32_t mn = INT32_MAX, mx = INT32_MIN;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
@@ -239,9 +245,11 @@ __global__ __launch_bounds__(256) void k_dim_filter(PredSet ps, int64_t n, int32
   int64_t rows[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) rows[j] = wbase + int64_t{j} * kWave + lane;
+  int32_t kv[ITEMS];
+  if (key) load_keys<ITEMS>(key, rows, n, kv);  // uniform
   bool keep[ITEMS];
   eval_preds_items<ITEMS>(ps, rows, n, keep);
-  if (key) wave_key_bounds<ITEMS>(key, rows, keep, w, s_min, s_max);  // uniform
+  if (key) wave_key_bounds<ITEMS>(kv, keep, w, s_min, s_max);  // uniform
   uint64_t m[ITEMS];
   int c = 0;
 #pragma unroll
