@@ -140,8 +140,14 @@ pyst_status pyst_ctx_timing(pyst_ctx *ctx, int enable);
 /* PYST_OPT_HASH_JOIN_ONLY != 0 keeps pyst_query's join tables hash tables:
    without it, a one-join query grouped by the join key direct-addresses its
    dimension table (key k in slot k - min key) when the selected dimension
-   keys span at most 2^21 values and no more than the table's reserved slots.
-   Both compute the same result; tests compare them. */
+   keys span at most 2^21 values and no more than the table's reserved slots,
+   and a two-join query whose pairs are grouped (the chain of Sec. 6.1)
+   direct-addresses its first join when the selected keys span at most 2^20
+   values and its second (key + payload) join when its keys span no more than
+   that table's reserved slots.  The choice is made on the device from the
+   selected keys' least and greatest value.  Both compute the same result;
+   tests compare them.  Duplicate dimension keys are reported
+   (PYST_ERR_DUP_KEY) in either mode. */
 #define PYST_OPT_HASH_JOIN_ONLY 4
 pyst_status pyst_ctx_option(pyst_ctx *ctx, int key, int64_t value);
 pyst_status pyst_ctx_kernel_time(pyst_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
