@@ -394,6 +394,48 @@ def test_chain_direct_addressing_ranges(gpu, ctx, path, case):
     np.testing.assert_array_equal(s, ws)
 
 
+def _chain_ranges(b_range, a_range, n_fact=500_001, nb=6_000, na=40_000, seed=3):
+    """Chain tables whose selected B keys span exactly b_range values and whose
+    A keys span exactly a_range values (both ends present, B's ends selected);
+    some fact keys fall just outside each range."""
+    r = np.random.default_rng(seed)
+
+    def keys(n, rng_, base):
+        inner = r.choice(np.arange(1, rng_ - 1, dtype=np.int64), n - 2, replace=False)
+        return (np.concatenate([[0, rng_ - 1], inner]) + base).astype(np.int32)
+
+    bk, ak = keys(nb, b_range, 11), keys(na, a_range, -500)
+    bseg = r.integers(0, 5, nb).astype(np.int32)
+    bseg[:2] = 1
+    b = {"key": bk, "segment": bseg}
+    a = {"key": ak, "date": r.integers(0, 2407, na).astype(np.int32)}
+    fa = ak[r.integers(0, na, n_fact)]
+    fb = bk[r.integers(0, nb, n_fact)]
+    fa[::101] = ak.min() - 1
+    fa[50::101] = ak.max() + 1
+    fb[7::97] = bk.max() + 1
+    f = {"a_fk": fa, "b_fk": fb, "date": r.integers(0, 2407, n_fact).astype(np.int32),
+         "price": r.integers(90_000, 10_500_001, n_fact).astype(np.int64),
+         "discount": r.integers(0, 11, n_fact).astype(np.int32)}
+    return a, b, f
+
+
+@pytest.mark.parametrize("path", ["fast", "fast_hash"])
+@pytest.mark.parametrize("b_range,a_range", [
+    (1 << 20, 1 << 17),              # both at their direct limits (A reserves 2^17 slots for 40k keys)
+    ((1 << 20) + 1, (1 << 17) + 1),  # one past each: both hashed
+    ((1 << 20) - 1, (1 << 17) - 1),  # odd ranges: A's last 16-byte group holds one slot
+])
+def test_chain_direct_range_limits(gpu, ctx, path, b_range, a_range):
+    a, b, f = _chain_ranges(b_range, a_range)
+    plan = gpu.chain_plan({k: dev(v) for k, v in a.items()}, {k: dev(v) for k, v in b.items()})
+    k, s = run(gpu, ctx, plan, [dev(f[c]) for c in FACT_CHAIN], path)
+    wk, ws = oracle.chain_query(a, b, f)
+    assert len(wk) > 5_000
+    np.testing.assert_array_equal(k, wk)
+    np.testing.assert_array_equal(s, ws)
+
+
 @pytest.mark.parametrize("path", ["fast", "fast_hash", "generic"])
 def test_chain_filtered_payload_join(gpu, ctx, path):
     # a predicate on A as well: A's table holds only the selected keys (its
