@@ -147,6 +147,32 @@ def to_dev(d):
     return {k: torch.from_numpy(v).cuda() for k, v in d.items()}
 
 
+def hbm_ceiling(pyst):
+    """The HBM peak three ways: the published figure the roofline uses, the one
+    the device's properties imply, and a measured streaming copy (a 4 GiB
+    device-to-device copy, 2 bytes moved per byte copied, best of 10)."""
+    import torch
+    clk, bits, props = pyst.device_hbm(0)
+    src = torch.empty(1 << 29, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    best = None
+    for _ in range(12):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    nbytes = 2 * src.numel() * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"published_gbs": HBM_PEAK_GBS, "device_props_gbs": props, "mem_clock_khz": clk, "bus_bits": bits,
+            "measured_copy_gbs": nbytes / (best / 1e3) / 1e9,
+            "copy": "torch device-to-device copy of 4 GiB, best of 12, read + write bytes"}
+
+
 def timed_loop(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -271,6 +297,7 @@ def main():
         },
         "query_hbm": {"algorithmic_bytes": query_bytes, "gbs": query_bytes / (ms_per_step / 1e3) / 1e9,
                       "frac_of_peak": query_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "hbm_ceiling": hbm_ceiling(pyst),
         "roofline": {
             "kernel": "k_fast_fact (fused filter + probe + SUM)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

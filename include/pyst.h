@@ -117,6 +117,14 @@ size_t pyst_ctx_budget(const pyst_ctx *ctx);
 /* Message describing the last error returned on the calling thread. */
 const char *pyst_last_error(void);
 
+/* The device's memory clock (kHz) and bus width (bits) as its properties
+   report them, and the HBM peak they imply (GB/s) at HBM3 / HBM3E's 4
+   transfers a pin per reported clock: the properties-derived peak recorded
+   beside the published one as the roofline of the measurements on this
+   hardware (Sec. 6 reports its numbers against the A100's own peaks).
+   Errors: PYST_ERR_ARG (a NULL output), PYST_ERR_HIP (a bad device). */
+pyst_status pyst_device_hbm(int device, int64_t *mem_clock_khz, int32_t *bus_bits, double *peak_gbs);
+
 /* Kernel timing for measurement.  When enabled, the library records a pair of
    HIP events on the launch stream around its timed regions: "fact_pass" (the
    fused probe + aggregation kernel of pyst_query), "partition" (the whole of

@@ -418,6 +418,19 @@ pyst_status pyst_ctx_kernel_time(pyst_ctx *c, const char *name, double *total_ms
 }
 size_t pyst_ctx_budget(const pyst_ctx *c) { return c ? c->budget : 0; }
 
+pyst_status pyst_device_hbm(int device, int64_t *mem_clock_khz, int32_t *bus_bits, double *peak_gbs) {
+  if (!mem_clock_khz || !bus_bits || !peak_gbs) return set_error(PYST_ERR_ARG, "pyst_device_hbm: NULL argument");
+  int clock = 0, bits = 0;
+  hipError_t e = hipDeviceGetAttribute(&clock, hipDeviceAttributeMemoryClockRate, device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&bits, hipDeviceAttributeMemoryBusWidth, device);
+  if (e != hipSuccess) return hip_error(e, "pyst_device_hbm");
+  *mem_clock_khz = clock;
+  *bus_bits = bits;
+  // HBM3 / HBM3E move 4 transfers a pin per reported memory clock (2.0 GHz -> 8 Gb/s on this device)
+  *peak_gbs = 4.0 * static_cast<double>(clock) * 1e3 * (static_cast<double>(bits) / 8.0) / 1e9;
+  return PYST_OK;
+}
+
 pyst_status pyst_ctx_check(pyst_ctx *c, hipStream_t stream) {
   if (!c) return set_error(PYST_ERR_ARG, "pyst_ctx_check: ctx is NULL");
   hipError_t e = hipMemcpyAsync(c->h_err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);

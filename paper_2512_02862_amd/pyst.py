@@ -36,6 +36,7 @@ EXPORTS = [
     "pyst_batch_graph_create", "pyst_batch_graph_launch", "pyst_batch_graph_destroy",
     "pyst_server_create", "pyst_server_create_packed", "pyst_server_submit", "pyst_server_wait", "pyst_server_poll", "pyst_server_get_stats", "pyst_server_check",
     "pyst_server_destroy", "pyst_server_forget_tables", "pyst_server_option", "pyst_partition_noalloc",
+    "pyst_device_hbm",
 ]
 
 
@@ -162,6 +163,7 @@ def load(path: str = LIB_PATH):
         "pyst_server_forget_tables": ([p, p], i32),
         "pyst_server_option": ([p, i32, i64], i32),
         "pyst_ctx_kernel_time": ([p, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
+        "pyst_device_hbm": ([i32, P(i64), P(i32), P(ctypes.c_double)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -169,6 +171,14 @@ def load(path: str = LIB_PATH):
         f.restype = res
     _lib = lib
     return lib
+
+
+def device_hbm(device=0):
+    """(memory clock kHz, bus width bits, implied HBM peak GB/s) from the device's properties."""
+    lib = load()
+    clk, bits, peak = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib.pyst_device_hbm(int(device), ctypes.byref(clk), ctypes.byref(bits), ctypes.byref(peak)))
+    return clk.value, bits.value, peak.value
 
 
 def _check(status):
