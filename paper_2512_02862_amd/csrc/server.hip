@@ -31,10 +31,17 @@
 
 namespace pyst {
 
-__global__ void k_req_init(TableDev t, int64_t *d_ngroups) {
-  const int64_t cap = t.hdr[0];
+// Clears a request's group counter and, for slot sums, the sums and flags of
+// the table's slots -- never past the request's own arrays (t.cap_alloc
+// slots): a header claiming more slots latches kErrIndex instead.
+__global__ void k_req_init(TableDev t, int64_t *d_ngroups, uint32_t *err) {
+  int64_t cap = t.hdr[0];
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (tid == 0) *d_ngroups = 0;
+  if (t.sums && (cap < 0 || cap > t.cap_alloc)) {
+    if (tid == 0) latch(err, kErrIndex);
+    cap = cap < 0 ? 0 : t.cap_alloc;
+  }
   if (t.sums)
     for (int64_t i = tid; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
       t.sums[i] = 0;
@@ -292,7 +299,8 @@ static bool admit(pyst_server *sv, const std::shared_ptr<Request> &r) {
     }
     r->d.t[0].sums = static_cast<uint64_t *>(r->sums_mem);
     r->d.t[0].flags = reinterpret_cast<uint8_t *>(r->d.t[0].sums + cap);
-    k_req_init<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(cap, 256), 2048)), 256, 0, st>>>(r->d.t[0], r->d_ngroups);
+    k_req_init<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(cap, 256), 2048)), 256, 0, st>>>(r->d.t[0], r->d_ngroups,
+                                                                                          ctx_err_word(sv->ctx));
   } else {
     const int64_t bound = std::min<int64_t>(r->pc.plan.max_groups, std::max<int64_t>(r->rows, 1));
     const int64_t cap = table_capacity_host(bound, r->pc.plan.group_max_load);
@@ -306,7 +314,7 @@ static bool admit(pyst_server *sv, const std::shared_ptr<Request> &r) {
     (void)group_init(r->s.g, nullptr, bound, 0, r->pc.plan.group_max_load, st);
     TableDev t{};
     t.hdr = r->d.t[0].hdr;
-    k_req_init<<<1, 64, 0, st>>>(t, r->d_ngroups);
+    k_req_init<<<1, 64, 0, st>>>(t, r->d_ngroups, ctx_err_word(sv->ctx));
   }
   r->nchunks = ceil_div(r->rows, sv->cfg.chunk_rows);
   r->remaining = r->nchunks;
