@@ -298,11 +298,11 @@ __global__ __launch_bounds__(kFastBlock) void k_bat_sums(const BatFrag *frags, c
   PYST_BLOCK_FRAG(kPreCompact)
   (void)nloc;
   __shared__ uint64_t s_sum[kBucketSlots];
-  __shared__ uint32_t s_bits[kBucketSlots / 32];
+  __shared__ uint32_t s_pres[kBucketSlots / 4];
   __shared__ uint32_t s_wsum[kFastBlock / kWave];
   __shared__ int64_t s_base;
   bucket_sums_block(fr.t, fr.bp, static_cast<uint32_t>(local), fr.out_keys, fr.out_sums, fr.out_cap, fr.d_ngroups,
-                    err, s_sum, s_bits, s_wsum, &s_base, true);
+                    err, s_sum, s_pres, s_wsum, &s_base, true);
 }
 
 __global__ __launch_bounds__(256) void k_bat_compact(const BatFrag *frags, const int64_t *pre, int nfrag, uint32_t *err) {

@@ -1785,10 +1785,10 @@ __global__ __launch_bounds__(kFastBlock) void k_fast_fact(FastArgs a, TableDev t
 }
 
 // Adds the pairs of up to 4 chunks (kNoChunk: none) into the LDS sums of their
-// bucket.  One wave; every lane loads its pairs of all 4 chunks before any add,
+// bucket and marks their slots present (s_pres: one byte per slot).  One wave; every lane loads its pairs of all 4 chunks before any add,
 // so 4 chunks cost one memory round trip per 256 pairs each.
 __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t (&c)[4], int64_t lo, uint64_t *s_sum,
-                                           uint32_t *s_bits) {
+                                           uint32_t *s_pres) {
   constexpr int U = 4;
   uint32_t f[4], fmax = 0;
   size_t base[4];
@@ -1813,7 +1813,7 @@ __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t 
       const uint32_t s = static_cast<uint32_t>(q[u]) & (kBucketSlots - 1);
       atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[s]),
                 static_cast<unsigned long long>(static_cast<int64_t>(q[u]) >> kBucketLg));
-      atomicOr(&s_bits[s >> 5], 1u << (s & 31));
+      reinterpret_cast<uint8_t *>(s_pres)[s] = 1;  // idempotent: a plain byte store, no atomic
     }
   }
 }
@@ -1821,14 +1821,14 @@ __device__ __forceinline__ void add_chunks(const BucketPool &bp, const uint32_t 
 // Second kernel of the bucketed slot sums: block b adds up the pairs of bucket
 // b in LDS, adds the sums the fact pass made directly, and writes the groups
 // present with one counter atomic.  *d_ngroups must be zero on entry.  The LDS
-// arrays come from the calling kernel (s_sum: kBucketSlots, s_bits:
-// kBucketSlots / 32, s_wsum: kFastBlock / kWave, s_base: 1); blockDim.x is
+// arrays come from the calling kernel (s_sum: kBucketSlots, s_pres:
+// kBucketSlots / 4 words of presence bytes, s_wsum: kFastBlock / kWave, s_base: 1); blockDim.x is
 // kFastBlock.  may_direct: the table's header records its mode (tables from
 // k_fast_table_init); a direct-addressed slot s holds the key kmin + s.
 __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const BucketPool &bp, uint32_t b,
                                                   int64_t *out_keys, int64_t *out_sums, int64_t out_cap,
                                                   int64_t *d_ngroups, uint32_t *err, uint64_t *s_sum,
-                                                  uint32_t *s_bits, uint32_t *s_wsum, int64_t *s_base,
+                                                  uint32_t *s_pres, uint32_t *s_wsum, int64_t *s_base,
                                                   bool may_direct) {
   const int64_t cap = t.hdr[0];
   const uint32_t nb = bucket_count(cap);
@@ -1837,7 +1837,7 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
   const int64_t lo = int64_t{b} << kBucketLg;
   const uint32_t span = static_cast<uint32_t>(cap - lo < kBucketSlots ? cap - lo : kBucketSlots);
   for (uint32_t i = tid; i < kBucketSlots; i += kFastBlock) s_sum[i] = 0;
-  for (uint32_t i = tid; i < kBucketSlots / 32; i += kFastBlock) s_bits[i] = 0;
+  for (uint32_t i = tid; i < kBucketSlots / 4; i += kFastBlock) s_pres[i] = 0;
   __syncthreads();
   if (nb <= bp.stride) {  // pairs were staged
     // the blocks' first chunks of bucket b, then the chunks it took from its region
@@ -1846,7 +1846,7 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
       uint32_t cs[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) cs[i] = k + i * NW < bp.blocks ? (k + i * NW) * bp.stride + b : kNoChunk;
-      add_chunks(bp, cs, lo, s_sum, s_bits);
+      add_chunks(bp, cs, lo, s_sum, s_pres);
     }
     const uint32_t reg = region_chunks(bp, nb), first = region_first(bp, nb, b);
     const uint32_t used = bp.next[b] < reg ? bp.next[b] : reg;
@@ -1854,7 +1854,7 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
       uint32_t cs[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) cs[i] = k + i * NW < used ? first + k + i * NW : kNoChunk;
-      add_chunks(bp, cs, lo, s_sum, s_bits);
+      add_chunks(bp, cs, lo, s_sum, s_pres);
     }
   }
   __syncthreads();
@@ -1862,12 +1862,14 @@ __device__ __forceinline__ void bucket_sums_block(const TableDev &t, const Bucke
     for (uint32_t s = tid; s < span; s += kFastBlock)
       if (t.flags[lo + s]) {
         s_sum[s] += t.sums[lo + s];
-        atomicOr(&s_bits[s >> 5], 1u << (s & 31));
+        reinterpret_cast<uint8_t *>(s_pres)[s] = 1;
       }
   __syncthreads();
   constexpr uint32_t kPer = kBucketSlots / kFastBlock;  // each thread writes out kPer consecutive slots
   const uint32_t s0 = tid * kPer;
-  uint32_t m = (s_bits[s0 >> 5] >> (s0 & 31)) & ((1u << kPer) - 1);
+  static_assert(kPer == 8, "a thread's slots are two words of presence bytes");
+  const uint32_t p0 = s_pres[s0 / 4], p1 = s_pres[s0 / 4 + 1];  // byte i -> bit i
+  uint32_t m = (((p0 & 0x01010101u) * 0x01020408u) >> 24) | ((((p1 & 0x01010101u) * 0x01020408u) >> 24) << 4);
   const uint32_t c = static_cast<uint32_t>(__popc(m));
   const uint32_t incl = wave_inclusive_scan(c);
   if (lane == kWave - 1) s_wsum[wv] = incl;
@@ -1903,10 +1905,10 @@ __global__ __launch_bounds__(kFastBlock) void k_bucket_sums(TableDev t, BucketPo
                                                            int64_t *out_sums, int64_t out_cap, int64_t *d_ngroups,
                                                            uint32_t *err) {
   __shared__ uint64_t s_sum[kBucketSlots];
-  __shared__ uint32_t s_bits[kBucketSlots / 32];
+  __shared__ uint32_t s_pres[kBucketSlots / 4];
   __shared__ uint32_t s_wsum[kFastBlock / kWave];
   __shared__ int64_t s_base;
-  bucket_sums_block(t, bp, blockIdx.x, out_keys, out_sums, out_cap, d_ngroups, err, s_sum, s_bits, s_wsum, &s_base,
+  bucket_sums_block(t, bp, blockIdx.x, out_keys, out_sums, out_cap, d_ngroups, err, s_sum, s_pres, s_wsum, &s_base,
                     true);
 }
 
