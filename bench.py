@@ -297,7 +297,7 @@ def main():
         },
         "query_hbm": {"algorithmic_bytes": query_bytes, "gbs": query_bytes / (ms_per_step / 1e3) / 1e9,
                       "frac_of_peak": query_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
-        "hbm_ceiling": hbm_ceiling(pyst),
+        "hbm_ceiling": None if args.no_extras else hbm_ceiling(pyst),  # (kept out of --no-extras profile runs)
         "roofline": {
             "kernel": "k_fast_fact (fused filter + probe + SUM)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
