@@ -175,20 +175,16 @@ __global__ __launch_bounds__(256) void k_bat_init(const BatFrag *frags, const in
   }
   if (direct) {  // block-uniform: the byte map and the slot sums (the bitmap is packed whole later)
     direct_clear(t, range, tid, nthr);
-    for (int64_t i = tid; i < cap; i += nthr) {
-      t.sums[i] = 0;
-      t.flags[i] = 0;
-    }
+    clear_sums(t, cap, tid, nthr);
     return;
   }
-  int32_t *keys = static_cast<int32_t *>(t.slots);
+  // 16-byte stores (a hashed table's capacity is a power of two >= 64)
+  uint4 *keys = static_cast<uint4 *>(t.slots);
+  const uint32_t e = static_cast<uint32_t>(kEmpty32);
+  for (int64_t i = tid; i < cap / 4; i += nthr) keys[i] = uint4{e, e, e, e};
+  clear_sums(t, cap, tid, nthr);
   const int64_t words = bloom_words(cap);
-  for (int64_t i = tid; i < cap; i += nthr) {
-    keys[i] = kEmpty32;
-    t.sums[i] = 0;
-    t.flags[i] = 0;
-    if (i < words) t.bloom[i] = 0;
-  }
+  for (int64_t i = tid; i < words; i += nthr) t.bloom[i] = 0;
 }
 
 // One dimension tile of one fragment per block (as k_fast_build).

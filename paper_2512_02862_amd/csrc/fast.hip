@@ -217,6 +217,15 @@ __device__ __forceinline__ bool direct_fits(const TableDev &t, int64_t total, in
   return t.slot_bytes == 4 && direct_bytemap_off(range) + direct_bytemap_len(range) <= 4 * t.cap_alloc;
 }
 
+// Clears the slot sums and flags of slots [0, cap) (and at most one sum and 15
+// flags past them, still inside the cap_alloc slots: cap_alloc is a power of
+// two >= 64) with 16-byte stores, threads tid, tid + nthr, ... of a grid.
+__device__ __forceinline__ void clear_sums(const TableDev &t, int64_t cap, int64_t tid, int64_t nthr) {
+  uint4 *sums = reinterpret_cast<uint4 *>(t.sums), *flags = reinterpret_cast<uint4 *>(t.flags);
+  for (int64_t i = tid; i < (cap + 1) / 2; i += nthr) sums[i] = uint4{0u, 0u, 0u, 0u};
+  for (int64_t i = tid; i < (cap + 15) / 16; i += nthr) flags[i] = uint4{0u, 0u, 0u, 0u};
+}
+
 // Clears a direct table's byte map (threads tid, tid + nthr, ... of a grid).
 __device__ __forceinline__ void direct_clear(const TableDev &t, int64_t range, int64_t tid, int64_t nthr) {
   uint4 *bytes = reinterpret_cast<uint4 *>(static_cast<char *>(t.slots) + direct_bytemap_off(range));
@@ -338,11 +347,7 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
   }
   if (bitmap) {  // uniform: the byte map, the slot sums, the filter (the bitmap is packed whole later)
     direct_clear(t, range, tid, nthr);
-    if (t.sums)
-      for (int64_t i = tid; i < cap; i += nthr) {
-        t.sums[i] = 0;
-        t.flags[i] = 0;
-      }
+    if (t.sums) clear_sums(t, cap, tid, nthr);
     if (t.bloom)
       for (int64_t i = tid; i < kBloomWords; i += nthr) t.bloom[i] = 0;
     return;
@@ -352,11 +357,7 @@ __global__ void k_fast_table_init(TableDev t, const int32_t *cnt, int64_t nblock
                                            : uint64_t{static_cast<uint32_t>(kEmpty32)};
   uint64_t *p = static_cast<uint64_t *>(t.slots);
   for (int64_t i = tid; i < words; i += nthr) p[i] = fillv;
-  if (t.sums)
-    for (int64_t i = tid; i < cap; i += nthr) {
-      t.sums[i] = 0;
-      t.flags[i] = 0;
-    }
+  if (t.sums) clear_sums(t, cap, tid, nthr);
   if (t.bloom)
     for (int64_t i = tid; i < kBloomWords; i += nthr) t.bloom[i] = 0;
 }
