@@ -807,6 +807,22 @@ def bench_config4(pyst, gen, log, want_rows, nreq, chunk, budget_total, serve_re
         stream_digest = _digest(k[:int(ng.item())], s_[:int(ng.item())])
         del k, s_
     torch.cuda.empty_cache()
+    # the chunked path against the oracle: a 200M-row prefix of the same pinned
+    # table streamed in the configured chunks (three full ones and a partial one)
+    pre = min(nrows, 200_000_000)
+    k, s_, ng = pyst.query_streamed(sctx, plan, [t[:pre] for t in host], chunk_rows=chunk, nbuf=2, out_cap=max_groups)
+    sctx.check()
+    m = int(ng.item())
+    got_k, got_s = k[:m].cpu().numpy(), s_[:m].cpu().numpy()
+    del k, s_
+    t0 = time.perf_counter()
+    wk, ws = oracle.chain_query(a_h, b_h, {c: t[:pre].numpy() for c, t in zip(names, host)})
+    o = np.argsort(got_k)
+    stream["oracle_check"] = {
+        "rows": pre, "chunk_rows": chunk, "groups": int(len(wk)), "oracle_s": time.perf_counter() - t0,
+        "equal": bool(len(got_k) == len(wk) and np.array_equal(got_k[o], wk) and np.array_equal(got_s[o], ws))}
+    log("config4: streamed %d-row prefix equal to the oracle: %s" % (pre, stream["oracle_check"]["equal"]))
+    del got_k, got_s, wk, ws
     stream["workload"] = "chain query, fact %d rows (24 B/row) from pinned host, %d-row chunks, %d GiB arena" % (
         nrows, chunk, budget_total >> 30)
     out["stream"] = stream
